@@ -1,0 +1,212 @@
+/*
+ * krr.h -- C ABI of the MI355X (gfx950) random-features-preconditioned kernel ridge
+ * regression library (libkrr.so).
+ *
+ * Method: Avron, Clarkson, Woodruff, "Faster Kernel Ridge Regression Using Sketching
+ * and Preconditioning" (arXiv 1611.03220). The library solves Eq. 1,
+ *     (K + lambda I_n) c = y,   K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))   (Sec. 5),
+ * by PCG (Alg. 1, step 9) with the preconditioner Z Z^T + lambda_p I_n built from random
+ * Fourier features Z = sqrt(2/s) cos(X W + b) (Sec. 2.2) and applied through its
+ * Woodbury form lambda_p^{-1} (I - U^T U), U = C^{-1} Z^T, C C^T = Z^T Z + lambda_p I_s
+ * (Sec. 3.1; Alg. 1, steps 6-7). The kernel matrix is never stored: every product
+ * recomputes it tile by tile from X.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (HIP global memory) owned by the caller,
+ *     except those documented as host pointers. Matrices are row-major with an explicit
+ *     leading dimension (elements between consecutive rows, >= the row length).
+ *   - Points X are FP32 (n x d). Right-hand sides, solutions and kernel-product operands
+ *     are FP64. Features Z and the preconditioner factor U^T are FP32.
+ *   - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued on it.
+ *   - No entry point allocates device memory. Scratch space is the caller's `ws` buffer
+ *     (device, 256-byte aligned) of at least krr_workspace_bytes(...) bytes; the library
+ *     does not keep a reference to it after the call returns.
+ *   - Every call returns a krr_status. On failure the outputs are undefined unless stated
+ *     otherwise, and krr_last_error() describes the failure. No exception or abort
+ *     crosses the ABI.
+ *   - Calls are thread-safe as long as concurrent calls use distinct workspaces.
+ */
+#ifndef KRR_H
+#define KRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum krr_status {
+  KRR_OK = 0,
+  KRR_E_ARG = 1,        /* invalid argument: null pointer, bad size or stride, lambda <= 0,
+                           sigma <= 0, s >= n, tol <= 0 (the paper assumes lambda > 0, s < n,
+                           epsilon > 0: Sec. 2.1, Sec. 3.1, Alg. 1) */
+  KRR_E_NOT_SPD = 2,    /* Z^T Z + lambda_p I not numerically positive definite (info set) */
+  KRR_E_NO_CONV = 3,    /* PCG reached max_iter; alpha holds the last iterate, report filled */
+  KRR_E_BREAKDOWN = 4,  /* non-finite data or <p, A p> <= 0 in some column; that column frozen */
+  KRR_E_HIP = 5,        /* a HIP runtime call failed */
+  KRR_E_WORKSPACE = 6   /* ws is NULL, misaligned or smaller than krr_workspace_bytes() */
+} krr_status;
+
+/* Arithmetic of the kernel product K V (Sec. 3.1: the dominant per-iteration cost). */
+typedef enum krr_prec {
+  KRR_PREC_FP64 = 0,   /* FP64 distances, FP64 exp, FP64 sums ("plain FP64 path") */
+  KRR_PREC_F16X3 = 1,  /* distances on MFMA from FP16 hi+lo splits of the (power-of-two
+                          scaled) points, 3 products hi*hi + hi*lo + lo*hi, FP32 accumulate;
+                          FP32 exp2; FP32 products with V, FP64 sums across tiles (default) */
+  KRR_PREC_BF16X3 = 2  /* as F16X3 with BF16 hi+lo splits (16 instead of 22 mantissa bits) */
+} krr_prec;
+
+/* Operation codes for krr_workspace_bytes. */
+typedef enum krr_op {
+  KRR_OP_FEATURES = 0,
+  KRR_OP_PRECOND_FACTOR = 1,
+  KRR_OP_KERNEL_MATMAT = 2,
+  KRR_OP_PCG_SOLVE = 3,
+  KRR_OP_GRAD = 4
+} krr_op;
+
+/*
+ * krr_workspace_bytes -- size of the device workspace an operation needs.
+ *   op   : a krr_op code.
+ *   n1   : points (rows) of the operation; n2: columns of a cross kernel product
+ *          (KRR_OP_KERNEL_MATMAT; pass n2 = n1 otherwise).
+ *   d, s, m : dimension, feature count, right-hand sides (0 where not used).
+ *   prec : a krr_prec (kernel-product arithmetic).
+ * Returns 0 for an unknown op.
+ */
+size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_t s, int64_t m,
+                           int32_t prec);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* krr_last_error(void);
+
+/* Library version string. */
+const char* krr_version(void);
+
+/*
+ * krr_features -- random Fourier features, Alg. 1 steps 4-5 (feature map of Sec. 2.2):
+ *     Z[i, l] = sqrt(2/s) * cos( sum_k X[i, k] W[k, l] + b[l] ).
+ * The scale is sqrt(2/s) (not the printed s^{-1/2}): with it E[z(x)^T z(y)] = k(x, y).
+ *   X  : n x d FP32, leading dimension ldx >= d.
+ *   W  : d x s FP32 row-major (leading dimension s); columns w_l ~ N(0, sigma^-2 I) drawn by
+ *        the caller.
+ *   b  : s FP32 offsets in [0, 2 pi), drawn by the caller.
+ *   Z  : n x s FP32 output, leading dimension ldz >= s.
+ * The product X W runs on MFMA from FP16 hi+lo splits (power-of-two scaled, three
+ * products, FP32 accumulate); cos is the accurate FP32 cosine. Asynchronous on `stream`.
+ * Errors: KRR_E_ARG, KRR_E_WORKSPACE.
+ */
+krr_status krr_features(const float* X, int64_t n, int64_t d, int64_t ldx, const float* W,
+                        const float* b, int64_t s, float* Z, int64_t ldz, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/*
+ * krr_precond_factor -- preconditioner set-up, Alg. 1 steps 6-7 (Woodbury form, Sec. 3.1):
+ *     G = Z^T Z + lambda_p I_s,  C C^T = G (C lower, FP64),  Ut = Z C^{-T}  (= U^T, n x s).
+ * Then (Z Z^T + lambda_p I)^{-1} v = (v - Ut (Ut^T v)) / lambda_p.
+ *   Z   : n x s FP32, leading dimension ldz >= s (s < n).
+ *   lambda_p : > 0 (Alg. 1 uses lambda_p = lambda; Table 2 varies it).
+ *   C   : s x s FP64 output, row-major, leading dimension s; lower triangle is the factor,
+ *         the strict upper triangle is set to zero.
+ *   Ut  : n x s FP32 output, leading dimension ldu >= s: row i is (C^{-1} z_i)^T.
+ *   info: HOST pointer; 0 on success, else the 1-based index of the first non-positive
+ *         pivot (then KRR_E_NOT_SPD is returned and C, Ut are undefined).
+ * The Gram product runs on MFMA from FP16 hi+lo splits with FP64 sums; the Cholesky and
+ * the triangular inverse run in FP64; Ut is formed by one GEMM with C^{-1} (GEMM instead
+ * of per-iteration triangular solves, as Sec. 3.1 argues). Synchronises `stream`.
+ */
+krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
+                              double* C, float* Ut, int64_t ldu, void* ws, size_t ws_bytes,
+                              int64_t* info, void* stream);
+
+/*
+ * krr_kernel_matmat -- matrix-free kernel product (the per-iteration product of Alg. 1
+ * step 9; Sec. 3.1 cost discussion):
+ *     OUT[i, :] = sum_j k(x1_i, x2_j) V[j, :] + shift * V[i, :],
+ * with k the Gaussian kernel of Sec. 5, or, with deriv = 1, its sigma-derivative
+ * dk/dsigma = k * ||x1_i - x2_j||^2 / sigma^3.
+ *   X1 : n1 x d FP32 (ldx1 >= d);  X2 : n2 x d FP32 (ldx2 >= d).
+ *   V  : n2 x m FP64 (ldv >= m);   OUT: n1 x m FP64 (ldo >= m), must not alias V.
+ *   shift : requires n1 == n2 when non-zero (square case: shift = lambda gives (K + lambda I) V).
+ *   prec  : a krr_prec. Squared distances are clamped at zero.
+ * Asynchronous on `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE.
+ */
+krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const float* X2, int64_t n2,
+                             int64_t ldx2, int64_t d, double sigma, double shift, const double* V,
+                             int64_t m, int64_t ldv, double* OUT, int64_t ldo, int32_t deriv,
+                             int32_t prec, void* ws, size_t ws_bytes, void* stream);
+
+/* Options of krr_pcg_solve (zero-initialise, then set what you need; see krr_pcg_defaults). */
+typedef struct krr_pcg_opts {
+  double tol;            /* stop when ||y_j - A c_j|| <= tol ||y_j|| for every column j (Sec. 5),
+                            tracked on the recursive residual */
+  int32_t max_iter;      /* iteration cap (the paper's ablation uses 1000) */
+  int32_t prec;          /* krr_prec of the kernel products */
+  int32_t use_precond;   /* 1: preconditioner from Ut (Alg. 1); 0: plain CG (Table 4 baseline) */
+  int32_t check_every;   /* read the convergence count back to the host every k iterations */
+  double lambda_p;       /* regulariser Ut was built with; <= 0 means lambda */
+  int32_t true_residual; /* 1: at exit, compute the FP64 true residual per column */
+  int32_t refine;        /* max outer refinement steps driven by the FP64 true residual
+                            (0 = none); each step solves A delta = y - A c by PCG */
+  int32_t warm_start;    /* 0: start from zero as in Thm. 1 (alpha's input is ignored);
+                            1: start from the alpha passed in (resume a saved iterate) */
+} krr_pcg_opts;
+
+/* Report of krr_pcg_solve. Host arrays may be NULL; when given they hold m entries. */
+typedef struct krr_pcg_report {
+  int32_t iters;           /* PCG iterations (summed over refinement steps) */
+  int32_t converged_cols;  /* columns meeting tol on the recursive residual */
+  int32_t breakdown_cols;  /* columns frozen by breakdown */
+  int32_t refine_steps;    /* outer refinement steps taken */
+  double* relres_rec;      /* host[m]: recursive ||r_j|| / ||y_j|| at exit */
+  double* relres_true;     /* host[m]: FP64 ||y_j - (K + lambda I) c_j|| / ||y_j|| (if requested) */
+  double* history;         /* host[history_cap]: max relative recursive residual per iteration */
+  int32_t history_cap;
+  int32_t history_len;
+} krr_pcg_report;
+
+/* Fill `o` with the defaults: tol 1e-6, max_iter 1000, F16X3, preconditioned, check every
+ * iteration, lambda_p = lambda, true residual on, no refinement, zero start. */
+void krr_pcg_defaults(krr_pcg_opts* o);
+
+/*
+ * krr_pcg_solve -- Alg. 1 step 9: solve (K + lambda I_n) alpha = Y by PCG with the
+ * preconditioner (Z Z^T + lambda_p I)^{-1} = (I - Ut Ut^T) / lambda_p, one independent
+ * PCG recurrence per right-hand side (columns freeze once converged; Sec. 5).
+ *   X     : n x d FP32 (ldx >= d).   sigma > 0, lambda > 0.
+ *   Ut, s, ldu : output of krr_precond_factor (ignored when opts->use_precond == 0).
+ *   Y     : n x m FP64 right-hand sides (ldy >= m).
+ *   alpha : n x m FP64 (lda >= m). On entry the starting point when opts->warm_start is 1
+ *           (else ignored: the iteration starts from zero as in Thm. 1); on exit the
+ *           solution.
+ *   opts  : HOST pointer (NULL = defaults).  rep: HOST pointer (may be NULL).
+ * CG scalars (inner products, step lengths) and the iterates x, r are FP64; the kernel
+ * product uses opts->prec. Synchronises `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE,
+ * KRR_E_NO_CONV (alpha holds the last iterate, report filled), KRR_E_BREAKDOWN.
+ */
+krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, double sigma,
+                         double lambda, const float* Ut, int64_t s, int64_t ldu, const double* Y,
+                         int64_t ldy, double* alpha, int64_t lda, int64_t m,
+                         const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/*
+ * krr_grad -- hyper-parameter gradients of a loss through the solve of Eq. 1 (adjoint
+ * method). Given alpha = A^{-1} Y and the adjoint abar = A^{-1} Gbar (A = K + lambda I):
+ *     dL_dsigma  = - sum_ij <abar_i, alpha_j> dk(x_i, x_j)/dsigma   (= -<abar, (dK/dsigma) alpha>)
+ *     dL_dlambda = - <abar, alpha>.
+ *   X : n x d FP32 (ldx >= d).  alpha, abar : n x m FP64 (leading dimension ld >= m).
+ *   dL_dsigma, dL_dlambda : HOST pointers.
+ * The sigma term is one matrix-free product with dK/dsigma (krr_kernel_matmat, deriv = 1)
+ * followed by an FP64 inner product. Synchronises `stream`.
+ */
+krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double sigma,
+                    const double* alpha, const double* abar, int64_t m, int64_t ld,
+                    double* dL_dsigma, double* dL_dlambda, int32_t prec, void* ws, size_t ws_bytes,
+                    void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRR_H */

@@ -1,0 +1,76 @@
+// Shared device/host definitions for libkrr (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace krr {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+
+// Padding of the prepared point arrays: rows to a multiple of ROW_PAD, the contraction
+// (feature) dimension to a multiple of K_STEP (one 16x16x32 MFMA step).
+constexpr int ROW_PAD = 64;
+constexpr int K_STEP = 32;
+
+__host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Largest finite magnitude we let a scaled operand reach before the hi/lo split: the hi
+// part must stay below the FP16 maximum (65504) with margin.
+constexpr float SPLIT_TARGET = 16384.0f;
+
+// ---------------------------------------------------------------- element traits
+// Split a float into hi + lo of a 16-bit MFMA type: hi = rn(x), lo = rn(x - hi).
+template <typename T> struct Elem;
+template <> struct Elem<_Float16> {
+  typedef half8 vec8;
+  __device__ static inline void split(float x, _Float16& hi, _Float16& lo) {
+    hi = (_Float16)x;
+    lo = (_Float16)(x - (float)hi);
+  }
+  __device__ static inline f32x4 mfma(vec8 a, vec8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Elem<__bf16> {
+  typedef bf16x8 vec8;
+  __device__ static inline void split(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+  }
+  __device__ static inline f32x4 mfma(vec8 a, vec8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+// Power of two q with q * amax <= SPLIT_TARGET (amax > 0 finite), else 1.
+__device__ inline float split_scale(float amax) {
+  if (!(amax > 0.0f) || !(amax < 3.0e38f)) return 1.0f;
+  int e;
+  frexpf(SPLIT_TARGET / amax, &e);  // SPLIT_TARGET/amax = f * 2^e, f in [0.5, 1)
+  return ldexpf(1.0f, e - 1);
+}
+
+// Positive floats order like their bit patterns: atomic max through unsigned ints.
+__device__ inline void atomic_max_pos(float* addr, float v) {
+  if (v > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(addr), __float_as_uint(v));
+}
+
+template <typename T> __device__ inline T wave_sum(T v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+}  // namespace krr
+
+// ------------------------------------------------------------------ host helpers
+#define KRR_LAUNCH_CHECK()                                    \
+  do {                                                        \
+    hipError_t e_ = hipGetLastError();                        \
+    if (e_ != hipSuccess) return e_;                          \
+  } while (0)

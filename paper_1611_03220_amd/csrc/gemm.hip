@@ -1,0 +1,207 @@
+// Dense products of the set-up steps (a2, a3):
+//   * gemm_nt_f16x3: C[M x N] = s * sum_k A[i, k] B[j, k] on MFMA from FP16 hi/lo splits
+//     (three products), FP32 accumulate within a k split, with epilogues
+//       EPI_PART64 : FP64 partial per k split (Gram Z^T Z; summed in fixed order later)
+//       EPI_F32    : FP32 store (Ut = Z C^{-T})
+//       EPI_COS    : amp * cos(C + b[j]) (random Fourier features, Sec. 2.2)
+//   * dgemm: FP64 C = beta C + alpha op(A) op(B) with general strides (Cholesky trailing
+//     updates and the triangular inverse).
+#include "kernels.hpp"
+
+namespace krr {
+
+constexpr int G_BM = 64, G_BN = 64, G_BK = 32;
+constexpr int G_LDS = G_BK + 8;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_nt_f16x3_kernel(
+    const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo, int64_t lda,
+    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo, int64_t ldb, int64_t M,
+    int64_t N, int64_t K, int64_t k_per_split, int lower_only, int tri_b,
+    const float* __restrict__ qa, const float* __restrict__ qb, double alpha,
+    double* __restrict__ out64, int64_t out64_stride, float* __restrict__ out32, int64_t ldc,
+    const float* __restrict__ bias, float amp) {
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (lower_only && bj > bi) return;
+  __shared__ __attribute__((aligned(16))) _Float16 sAh[2][G_BM * G_LDS], sAl[2][G_BM * G_LDS];
+  __shared__ __attribute__((aligned(16))) _Float16 sBh[2][G_BN * G_LDS], sBl[2][G_BN * G_LDS];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wr = w >> 1, wc = w & 1;  // wave owns a 32 x 32 quadrant
+  const int64_t row0 = bi * G_BM, col0 = bj * G_BN;
+  int64_t k_begin = (int64_t)blockIdx.z * k_per_split;
+  int64_t k_end = k_begin + k_per_split < K ? k_begin + k_per_split : K;
+  if (tri_b) {  // B lower triangular in (j, k): entries with k > j vanish
+    const int64_t kmax = round_up(col0 + G_BN, G_BK);
+    if (k_end > kmax) k_end = kmax;
+  }
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  // each operand tile is 64 rows x 32 halves = 256 chunks of 16 bytes: one per thread
+  const int lrow = tid >> 2, lc8 = (tid & 3) * 8;
+  uint4 rah, ral, rbh, rbl;
+  auto gload = [&](int64_t k0) {
+    const int64_t oa = (row0 + lrow) * lda + k0 + lc8;
+    const int64_t ob = (col0 + lrow) * ldb + k0 + lc8;
+    rah = *reinterpret_cast<const uint4*>(Ahi + oa);
+    ral = *reinterpret_cast<const uint4*>(Alo + oa);
+    rbh = *reinterpret_cast<const uint4*>(Bhi + ob);
+    rbl = *reinterpret_cast<const uint4*>(Blo + ob);
+  };
+  auto lstore = [&](int buf) {
+    *reinterpret_cast<uint4*>(&sAh[buf][lrow * G_LDS + lc8]) = rah;
+    *reinterpret_cast<uint4*>(&sAl[buf][lrow * G_LDS + lc8]) = ral;
+    *reinterpret_cast<uint4*>(&sBh[buf][lrow * G_LDS + lc8]) = rbh;
+    *reinterpret_cast<uint4*>(&sBl[buf][lrow * G_LDS + lc8]) = rbl;
+  };
+  if (k_begin < k_end) {
+    gload(k_begin);
+    lstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = k_begin; k0 < k_end; k0 += G_BK) {
+    if (k0 + G_BK < k_end) gload(k0 + G_BK);
+    half8 fah[2], fal[2], fbh[2], fbl[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int r = 32 * wr + 16 * a + li;
+      fah[a] = *reinterpret_cast<const half8*>(&sAh[buf][r * G_LDS + 8 * lg]);
+      fal[a] = *reinterpret_cast<const half8*>(&sAl[buf][r * G_LDS + 8 * lg]);
+      const int c = 32 * wc + 16 * a + li;
+      fbh[a] = *reinterpret_cast<const half8*>(&sBh[buf][c * G_LDS + 8 * lg]);
+      fbl[a] = *reinterpret_cast<const half8*>(&sBl[buf][c * G_LDS + 8 * lg]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fal[a], fbh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fah[a], fbl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fah[a], fbh[b], acc[a][b], 0, 0, 0);
+      }
+    if (k0 + G_BK < k_end) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  const float sa = split_scale(*qa), sb = split_scale(*qb);
+  const double scale = alpha / ((double)sa * (double)sb);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = row0 + 32 * wr + 16 * a + 4 * lg + r;
+        const int64_t j = col0 + 32 * wc + 16 * b + li;
+        if (i < M && j < N) {
+          const double v = (double)acc[a][b][r] * scale;
+          if (EPI == EPI_PART64) out64[(int64_t)blockIdx.z * out64_stride + i * ldc + j] = v;
+          else if (EPI == EPI_F32) out32[i * ldc + j] = (float)v;
+          else out32[i * ldc + j] = amp * cosf((float)v + bias[j]);
+        }
+      }
+}
+
+hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M, int64_t N,
+                         int64_t K, int nsplit, int epi, int lower_only, int tri_b, double alpha,
+                         double* out64, int64_t out64_stride, float* out32, int64_t ldc,
+                         const float* bias, float amp, hipStream_t st) {
+  if (K % G_BK) return hipErrorInvalidValue;
+  const int64_t kps = round_up(ceil_div(K, nsplit), G_BK);
+  dim3 grid(ceil_div(N, G_BN), ceil_div(M, G_BM), nsplit);
+#define KRR_G(E)                                                                               \
+  gemm_nt_f16x3_kernel<E><<<grid, 256, 0, st>>>(A.hi, A.lo, A.ld, B.hi, B.lo, B.ld, M, N, K,   \
+                                                kps, lower_only, tri_b, A.amax, B.amax, alpha,  \
+                                                out64, out64_stride, out32, ldc, bias, amp)
+  if (epi == EPI_PART64) KRR_G(EPI_PART64);
+  else if (epi == EPI_F32) KRR_G(EPI_F32);
+  else KRR_G(EPI_COS);
+#undef KRR_G
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------------------------- FP64 GEMM
+// C[i, j] = beta C[i, j] + alpha sum_k A(i, k) B(k, j), A(i, k) = A[i*sai + k*sak],
+// B(k, j) = B[k*sbk + j*sbj]; batched over blockIdx.z with element strides bA, bB, bC.
+// 64 x 64 tile, k chunks of 16, each thread 4 x 4 outputs. lower_only skips tiles that lie
+// strictly above the block diagonal and entries with j > i.
+constexpr int D_BK = 16;
+__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K,
+                                                    double alpha, const double* __restrict__ A,
+                                                    int64_t sai, int64_t sak, int64_t bA,
+                                                    const double* __restrict__ B, int64_t sbk,
+                                                    int64_t sbj, int64_t bB, double beta,
+                                                    double* __restrict__ C, int64_t ldc,
+                                                    int64_t bC, int lower_only) {
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (lower_only && bj > bi) return;
+  A += (int64_t)blockIdx.z * bA;
+  B += (int64_t)blockIdx.z * bB;
+  C += (int64_t)blockIdx.z * bC;
+  __shared__ double sA[D_BK][64 + 1];
+  __shared__ double sB[D_BK][64 + 1];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int64_t row0 = bi * 64, col0 = bj * 64;
+  double acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+  for (int64_t k0 = 0; k0 < K; k0 += D_BK) {
+    for (int e = tid; e < 64 * D_BK; e += 256) {
+      // A tile: prefer consecutive threads along the unit-stride index
+      int rr, kk;
+      if (sak == 1) { rr = e / D_BK; kk = e % D_BK; } else { kk = e / 64; rr = e % 64; }
+      const int64_t gi = row0 + rr, gk = k0 + kk;
+      sA[kk][rr] = (gi < M && gk < K) ? A[gi * sai + gk * sak] : 0.0;
+      int cc, k2;
+      if (sbk == 1) { cc = e / D_BK; k2 = e % D_BK; } else { k2 = e / 64; cc = e % 64; }
+      const int64_t gj = col0 + cc, gk2 = k0 + k2;
+      sB[k2][cc] = (gj < N && gk2 < K) ? B[gk2 * sbk + gj * sbj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < D_BK; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = sA[kk][ty * 4 + r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = sB[kk][tx + 16 * q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = fma(a[r], b[q], acc[r][q]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = row0 + ty * 4 + r, j = col0 + tx + 16 * q;
+      if (i < M && j < N && (!lower_only || j <= i)) {
+        const double prev = beta != 0.0 ? C[i * ldc + j] : 0.0;
+        C[i * ldc + j] = beta * prev + alpha * acc[r][q];
+      }
+    }
+}
+
+hipError_t dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai,
+                 int64_t sak, int64_t bA, const double* B, int64_t sbk, int64_t sbj, int64_t bB,
+                 double beta, double* C, int64_t ldc, int64_t bC, int batch, int lower_only,
+                 hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid(ceil_div(N, 64), ceil_div(M, 64), batch);
+  dgemm_kernel<<<grid, 256, 0, st>>>(M, N, K, alpha, A, sai, sak, bA, B, sbk, sbj, bB, beta, C,
+                                     ldc, bC, lower_only);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+}  // namespace krr

@@ -1,0 +1,119 @@
+// Internal launcher declarations of libkrr (not part of the C ABI).
+#pragma once
+#include <algorithm>
+#include "common.hpp"
+
+namespace krr {
+
+template <typename T> struct MixedPoints {
+  const T* hi;
+  const T* lo;
+  int64_t n;      // valid rows (arrays hold round_up(n, ROW_PAD) rows)
+  int64_t Kp;     // padded augmented width (multiple of 32)
+  const float* qinv2;  // device scalar 1/q^2
+};
+
+struct F64Points {
+  const double* X;   // round_up(n, 64) x dp
+  const double* nu;  // round_up(n, 64)
+  int64_t n;
+  int64_t dp;        // multiple of 32
+};
+
+struct SplitOperand {
+  const _Float16* hi;
+  const _Float16* lo;
+  int64_t ld;          // elements per row (the padded contraction length)
+  const float* amax;   // device max |entry| of the unsplit operand (scale source)
+};
+
+struct CGScalars {
+  double *ynorm, *rnorm, *rho, *alpha, *beta;
+  int *active, *broken, *col_iters, *count;
+};
+
+enum { EPI_PART64 = 0, EPI_F32 = 1, EPI_COS = 2 };
+
+// prep.hip
+hipError_t fill_f32(float* p, int64_t count, float v, hipStream_t st);
+hipError_t fill_f64(double* p, int64_t count, double v, hipStream_t st);
+hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st);
+hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float* stats,
+                       hipStream_t st);
+template <typename T>
+hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                       int64_t Kp, double c2, const float* stats, int side, T* hi, T* lo,
+                       float* qinv2, hipStream_t st);
+hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                           int64_t dp, double* X64, double* nu, hipStream_t st);
+hipError_t vec_to_f32(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
+                      int64_t ldo, float* out, hipStream_t st);
+hipError_t vec_pad_f64(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
+                       int64_t ldo, double* out, hipStream_t st);
+template <typename S>
+hipError_t absmax(const S* src, int64_t rows, int64_t cols, int64_t ld, float* amax,
+                  hipStream_t st);
+template <typename S, typename T>
+hipError_t split_operand(const S* src, int64_t rows, int64_t cols, int64_t ld, const float* amax,
+                         int transpose, int64_t out_rows, int64_t out_cols, T* hi, T* lo,
+                         hipStream_t st);
+
+// matmat.hip
+template <typename T>
+hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
+                        int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
+                        int64_t ldp, int nsplit, hipStream_t st);
+hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
+                      int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
+                      int nsplit, hipStream_t st);
+template <typename VS>
+hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, int64_t n,
+                           int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,
+                           double* out, int64_t ldo, hipStream_t st);
+
+// gemm.hip
+hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M, int64_t N,
+                         int64_t K, int nsplit, int epi, int lower_only, int tri_b, double alpha,
+                         double* out64, int64_t out64_stride, float* out32, int64_t ldc,
+                         const float* bias, float amp, hipStream_t st);
+hipError_t dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai,
+                 int64_t sak, int64_t bA, const double* B, int64_t sbk, int64_t sbj, int64_t bB,
+                 double beta, double* C, int64_t ldc, int64_t bC, int batch, int lower_only,
+                 hipStream_t st);
+
+// chol.hip
+hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st);
+hipError_t tri_inverse_doubling(const double* C, int64_t s_pad, double* Cinv, double* tmp,
+                                hipStream_t st);
+hipError_t gram_finalize(const double* part, int nsplit, int64_t s, int64_t ldp, int64_t pstride,
+                         double lambda_p, int64_t s_pad, double* G, hipStream_t st);
+hipError_t copy_lower(const double* a, int64_t lda, int64_t s, double* C, hipStream_t st);
+
+// cg.hip
+template <typename TA, typename TB>
+hipError_t dot_partial(const TA* a, int64_t lda, const TB* b, int64_t ldb, int64_t n, int64_t m,
+                       double* part, int nblk, hipStream_t st);
+hipError_t cg_init_scalars(const double* part_yy, const double* part_rr, const double* part_rz,
+                           int nblk, int64_t m, double tol, CGScalars& S, hipStream_t st);
+hipError_t cg_alpha(const double* part_pq, int nblk, int64_t m, CGScalars& S, hipStream_t st);
+hipError_t cg_conv(const double* part_rr, int nblk, int64_t m, double tol, int it, CGScalars& S,
+                   double* hist_slot, hipStream_t st);
+hipError_t cg_beta(const double* part_rz, const double* part_rr, int nblk, int64_t m,
+                   CGScalars& S, hipStream_t st);
+template <typename TP>
+hipError_t cg_update_xr(double* x, int64_t ldx, double* r, const TP* p, int64_t ldp,
+                        const double* q, const double* alpha, int64_t n, int64_t m,
+                        double* part_rr, int nblk, hipStream_t st);
+hipError_t cg_update_p(const double* z, double* p, float* pf, int64_t ldpf, const double* beta,
+                       const int* active, int init, int64_t n, int64_t m, hipStream_t st);
+hipError_t residual_from(const double* y, int64_t ldy, const double* ax, int64_t n, int64_t m,
+                         double* r, hipStream_t st);
+hipError_t copy2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n, int64_t m,
+                  hipStream_t st);
+hipError_t add2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n, int64_t m,
+                 hipStream_t st);
+hipError_t precond_apply(const float* Ut, int64_t ldu, int64_t n, int64_t s, int64_t m,
+                         double lambda_p, const double* r, double* z, double* part, int nchunk,
+                         double* T, hipStream_t st);
+
+}  // namespace krr

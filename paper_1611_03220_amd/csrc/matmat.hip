@@ -1,0 +1,392 @@
+// Matrix-free Gaussian kernel products (hot-path step a4): OUT = K(X1, X2) V.
+//
+// Mixed kernel (F16X3 / BF16X3): each 64-thread wave owns 16 output rows i; the block
+// (4 waves, 64 rows) sweeps a range of 64-column tiles j. Per 16x16 (i, j) block, three
+// 16x16x32 MFMAs per 32-wide k step form <a_i, b_j> = q^2 log2 k_ij from hi/lo splits
+// (lo*hi, hi*lo, hi*hi). The epilogue is VALU: log2 k = min(S / q^2, 0), k = exp2(log2 k)
+// (times -log2 k / (c sigma^3) for dk/dsigma), then k * V[j, c] accumulated in FP32 over
+// FLUSH tiles and added into FP64 accumulators (cross-tile sums in FP64). The row operands
+// a_i live in registers for the whole sweep; b_j tiles and V rows are double-buffered
+// through LDS.
+//
+// MFMA 16x16x32 lane layout (gfx950): A operand lane l holds A[l%16][8(l/16)+t], B operand
+// B[8(l/16)+t][l%16], result C[4(l/16)+r][l%16], t = 0..7, r = 0..3.
+#include "kernels.hpp"
+
+namespace krr {
+
+constexpr int MM_BM = 64;   // rows per block (4 waves x 16)
+constexpr int MM_BN = 64;   // columns per tile
+constexpr int MM_FLUSH = 4; // tiles between FP32 -> FP64 flushes (16 terms per lane)
+
+template <typename T, int KS, int MC, bool DERIV>
+__global__ __launch_bounds__(256) void matmat_mixed_kernel(
+    const T* __restrict__ Ahi, const T* __restrict__ Alo, const T* __restrict__ Bhi,
+    const T* __restrict__ Blo, const float* __restrict__ Vf, int64_t ldvf, int64_t n1,
+    int64_t n2, int c0, const float* __restrict__ qinv2_ptr, float dscale,
+    double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split) {
+  typedef typename Elem<T>::vec8 vec8;
+  constexpr int KP = KS * 32;
+  constexpr int LDS_K = KP + 8;  // padded row (halves) to spread LDS banks
+  constexpr int CHUNKS = MM_BN * KP / 8;  // 16-byte chunks per operand tile
+  constexpr int CPT = (CHUNKS + 255) / 256;
+  constexpr int VEL = MM_BN * MC;  // V floats per tile
+  constexpr int VPT = (VEL + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) T sBh[2][MM_BN * LDS_K];
+  __shared__ __attribute__((aligned(16))) T sBl[2][MM_BN * LDS_K];
+  __shared__ float sV[2][MM_BN * MC];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * MM_BM + 16 * w;
+  const int64_t ntiles = ceil_div(n2, MM_BN);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+  const float qinv2 = *qinv2_ptr;
+
+  // row operands in registers
+  vec8 ah[KS], al[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int64_t off = (i0 + li) * KP + ks * 32 + 8 * lg;
+    ah[ks] = *reinterpret_cast<const vec8*>(Ahi + off);
+    al[ks] = *reinterpret_cast<const vec8*>(Alo + off);
+  }
+
+  float acc[4][MC];
+  double acc64[4][MC];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < MC; ++c) { acc[r][c] = 0.0f; acc64[r][c] = 0.0; }
+
+  uint4 rh[CPT], rl[CPT];
+  float rv[VPT];
+  auto gload = [&](int64_t t) {
+    const int64_t j0 = t * MM_BN;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < CHUNKS) {
+        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
+        const int64_t off = (j0 + row) * KP + col8 * 8;
+        rh[u] = *reinterpret_cast<const uint4*>(Bhi + off);
+        rl[u] = *reinterpret_cast<const uint4*>(Blo + off);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < VEL) {
+        const int row = e / MC, c = e % MC;
+        rv[u] = (j0 + row < n2) ? Vf[(j0 + row) * ldvf + c0 + c] : 0.0f;
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < CHUNKS) {
+        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
+        *reinterpret_cast<uint4*>(&sBh[buf][row * LDS_K + col8 * 8]) = rh[u];
+        *reinterpret_cast<uint4*>(&sBl[buf][row * LDS_K + col8 * 8]) = rl[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < VEL) sV[buf][e] = rv[u];
+    }
+  };
+
+  if (t_begin < t_end) {
+    gload(t_begin);
+    lstore(0);
+  }
+  __syncthreads();
+  int since_flush = 0;
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int buf = (int)((t - t_begin) & 1);
+    if (t + 1 < t_end) gload(t + 1);
+#pragma unroll
+    for (int jb = 0; jb < MM_BN / 16; ++jb) {
+      f32x4 S = {0.0f, 0.0f, 0.0f, 0.0f};
+      const T* bh = &sBh[buf][(16 * jb + li) * LDS_K + 8 * lg];
+      const T* bl = &sBl[buf][(16 * jb + li) * LDS_K + 8 * lg];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const vec8 bhv = *reinterpret_cast<const vec8*>(bh + ks * 32);
+        const vec8 blv = *reinterpret_cast<const vec8*>(bl + ks * 32);
+        S = Elem<T>::mfma(al[ks], bhv, S);
+        S = Elem<T>::mfma(ah[ks], blv, S);
+        S = Elem<T>::mfma(ah[ks], bhv, S);
+      }
+      float v[MC];
+#pragma unroll
+      for (int c = 0; c < MC; ++c) v[c] = sV[buf][(16 * jb + li) * MC + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float l2 = fminf(S[r] * qinv2, 0.0f);
+        float p = __builtin_amdgcn_exp2f(l2);
+        if (DERIV) p = p * (-l2) * dscale;
+#pragma unroll
+        for (int c = 0; c < MC; ++c) acc[r][c] = fmaf(p, v[c], acc[r][c]);
+      }
+    }
+    if (++since_flush == MM_FLUSH) {
+      since_flush = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < MC; ++c) { acc64[r][c] += (double)acc[r][c]; acc[r][c] = 0.0f; }
+    }
+    if (t + 1 < t_end) lstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+      double s = acc64[r][c] + (double)acc[r][c];
+      // lanes sharing lg hold the same rows and different j: reduce over lane bits 0..3
+      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+      acc64[r][c] = s;
+    }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int c = 0; c < MC; ++c) {
+    if (li == c) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 4 * lg + r;
+        if (i < n1) pout[i * ldp + c0 + c] = acc64[r][c];
+      }
+    }
+  }
+}
+
+template <typename T, int KS, int MC>
+static hipError_t launch_mixed_mc(const MixedPoints<T>& A, const MixedPoints<T>& B,
+                                  const float* Vf, int64_t ldvf, int c0, bool deriv, float dscale,
+                                  double* part, int64_t ldp, int64_t part_stride, int nsplit,
+                                  int tiles_per_split, hipStream_t st) {
+  dim3 grid(ceil_div(A.n, MM_BM), nsplit);
+  if (deriv)
+    matmat_mixed_kernel<T, KS, MC, true><<<grid, 256, 0, st>>>(
+        A.hi, A.lo, B.hi, B.lo, Vf, ldvf, A.n, B.n, c0, A.qinv2, dscale, part, ldp, part_stride,
+        tiles_per_split);
+  else
+    matmat_mixed_kernel<T, KS, MC, false><<<grid, 256, 0, st>>>(
+        A.hi, A.lo, B.hi, B.lo, Vf, ldvf, A.n, B.n, c0, A.qinv2, dscale, part, ldp, part_stride,
+        tiles_per_split);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+template <typename T, int KS>
+static hipError_t launch_mixed_ks(const MixedPoints<T>& A, const MixedPoints<T>& B,
+                                  const float* Vf, int64_t ldvf, int64_t m, bool deriv,
+                                  float dscale, double* part, int64_t ldp, int64_t part_stride,
+                                  int nsplit, int tiles_per_split, hipStream_t st) {
+  for (int64_t c0 = 0; c0 < m; c0 += 8) {
+    const int mc = (int)std::min<int64_t>(8, m - c0);
+    hipError_t e;
+    switch (mc) {
+#define KRR_MC(N)                                                                              \
+  case N:                                                                                      \
+    e = launch_mixed_mc<T, KS, N>(A, B, Vf, ldvf, (int)c0, deriv, dscale, part, ldp,           \
+                                  part_stride, nsplit, tiles_per_split, st);                   \
+    break;
+      KRR_MC(1) KRR_MC(2) KRR_MC(3) KRR_MC(4) KRR_MC(5) KRR_MC(6) KRR_MC(7) KRR_MC(8)
+#undef KRR_MC
+      default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
+                        int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
+                        int64_t ldp, int nsplit, hipStream_t st) {
+  if (A.Kp != B.Kp) return hipErrorInvalidValue;
+  const int64_t ntiles = ceil_div(B.n, MM_BN);
+  const int tps = (int)ceil_div(ntiles, nsplit);
+  const int64_t part_stride = round_up(A.n, MM_BM) * ldp;
+  switch (A.Kp / 32) {
+#define KRR_KS(N)                                                                             \
+  case N:                                                                                     \
+    return launch_mixed_ks<T, N>(A, B, Vf, ldvf, m, deriv, dscale, part, ldp, part_stride,    \
+                                 nsplit, tps, st);
+    KRR_KS(1) KRR_KS(2) KRR_KS(3) KRR_KS(4) KRR_KS(5) KRR_KS(6) KRR_KS(7) KRR_KS(8)
+#undef KRR_KS
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t matmat_mixed<_Float16>(const MixedPoints<_Float16>&,
+                                           const MixedPoints<_Float16>&, const float*, int64_t,
+                                           int64_t, bool, float, double*, int64_t, int,
+                                           hipStream_t);
+template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const MixedPoints<__bf16>&,
+                                         const float*, int64_t, int64_t, bool, float, double*,
+                                         int64_t, int, hipStream_t);
+
+// ------------------------------------------------------------------- FP64 path
+// Block: 64 rows x 64-column tiles; thread (ty, tx) = (t/16, t%16) owns rows 4ty..4ty+3 and
+// columns tx, tx+16, tx+32, tx+48 of each tile. Distances from FP64 norms and an FP64 dot
+// product staged through LDS in 32-wide k chunks, FP64 exp, FP64 accumulation.
+constexpr int F64_BK = 32;
+
+template <int MC>
+__global__ __launch_bounds__(256) void matmat_f64_kernel(
+    const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
+    const double* __restrict__ nub, int64_t dp, const double* __restrict__ V, int64_t ldv,
+    int64_t n1, int64_t n2, int c0, double c, int deriv, double dscale, double* __restrict__ part,
+    int64_t ldp, int64_t part_stride, int tiles_per_split) {
+  __shared__ double sA[64][F64_BK + 1];
+  __shared__ double sB[64][F64_BK + 1];
+  __shared__ double sV[64][MC];
+  __shared__ double snb[64];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int64_t ntiles = ceil_div(n2, 64);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+  double acc[4][MC];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < MC; ++q) acc[r][q] = 0.0;
+  double na[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) na[r] = nua[i0 + 4 * ty + r];
+
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int64_t j0 = t * 64;
+    double g[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[r][q] = 0.0;
+    for (int64_t k0 = 0; k0 < dp; k0 += F64_BK) {
+      __syncthreads();
+      for (int e = tid; e < 64 * F64_BK; e += 256) {
+        const int rr = e / F64_BK, kk = e % F64_BK;
+        sA[rr][kk] = Xa[(i0 + rr) * dp + k0 + kk];
+        sB[rr][kk] = Xb[(j0 + rr) * dp + k0 + kk];
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int kk = 0; kk < F64_BK; ++kk) {
+        double a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = sA[4 * ty + r][kk];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = sB[tx + 16 * q][kk];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g[r][q] = fma(a[r], b[q], g[r][q]);
+      }
+    }
+    for (int e = tid; e < 64 * MC; e += 256) {
+      const int rr = e / MC, q = e % MC;
+      sV[rr][q] = (j0 + rr < n2) ? V[(j0 + rr) * ldv + c0 + q] : 0.0;
+    }
+    if (tid < 64) snb[tid] = nub[j0 + tid];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jj = tx + 16 * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double D = na[r] + snb[jj] - 2.0 * g[r][q];
+        D = D > 0.0 ? D : 0.0;
+        double p = exp(-D * c);
+        if (deriv) p *= D * dscale;
+#pragma unroll
+        for (int u = 0; u < MC; ++u) acc[r][u] = fma(p, sV[jj][u], acc[r][u]);
+      }
+    }
+  }
+  // reduce over the 16 threads (tx) sharing rows: consecutive lanes of one wave
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int u = 0; u < MC; ++u) {
+      double s = acc[r][u];
+      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+      acc[r][u] = s;
+    }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int u = 0; u < MC; ++u)
+    if (tx == u) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 4 * ty + r;
+        if (i < n1) pout[i * ldp + c0 + u] = acc[r][u];
+      }
+    }
+}
+
+hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
+                      int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
+                      int nsplit, hipStream_t st) {
+  if (A.dp != B.dp) return hipErrorInvalidValue;
+  const int64_t ntiles = ceil_div(B.n, 64);
+  const int tps = (int)ceil_div(ntiles, nsplit);
+  const int64_t part_stride = round_up(A.n, 64) * ldp;
+  dim3 grid(ceil_div(A.n, 64), nsplit);
+  for (int64_t c0 = 0; c0 < m; c0 += 8) {
+    const int mc = (int)std::min<int64_t>(8, m - c0);
+    switch (mc) {
+#define KRR_MC(N)                                                                              \
+  case N:                                                                                      \
+    matmat_f64_kernel<N><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, A.dp, V, ldv, A.n, B.n,   \
+                                               (int)c0, c, deriv ? 1 : 0, dscale, part, ldp,   \
+                                               part_stride, tps);                              \
+    break;
+      KRR_MC(1) KRR_MC(2) KRR_MC(3) KRR_MC(4) KRR_MC(5) KRR_MC(6) KRR_MC(7) KRR_MC(8)
+#undef KRR_MC
+    }
+    KRR_LAUNCH_CHECK();
+  }
+  return hipSuccess;
+}
+
+// OUT[i, c] = sum_s part[s][i][c] (fixed order) + shift * Vs[i, c]
+template <typename VS>
+__global__ void matmat_finalize_kernel(const double* __restrict__ part, int64_t part_stride,
+                                       int nsplit, int64_t n, int64_t m, int64_t ldp,
+                                       double shift, const VS* __restrict__ Vs, int64_t ldvs,
+                                       double* __restrict__ out, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * m) return;
+  const int64_t i = e / m, c = e % m;
+  double s = 0.0;
+  for (int k = 0; k < nsplit; ++k) s += part[k * part_stride + i * ldp + c];
+  if (shift != 0.0) s += shift * (double)Vs[i * ldvs + c];
+  out[i * ldo + c] = s;
+}
+
+template <typename VS>
+hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, int64_t n,
+                           int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,
+                           double* out, int64_t ldo, hipStream_t st) {
+  matmat_finalize_kernel<VS><<<ceil_div(n * m, 256), 256, 0, st>>>(
+      part, part_stride, nsplit, n, m, ldp, shift, Vs, ldvs, out, ldo);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+template hipError_t matmat_finalize<double>(const double*, int64_t, int, int64_t, int64_t,
+                                            int64_t, double, const double*, int64_t, double*,
+                                            int64_t, hipStream_t);
+template hipError_t matmat_finalize<float>(const double*, int64_t, int, int64_t, int64_t, int64_t,
+                                           double, const float*, int64_t, double*, int64_t,
+                                           hipStream_t);
+
+}  // namespace krr

@@ -1,0 +1,284 @@
+// Point preparation (hot-path step a1) and operand splitting for the MFMA products.
+//
+// The Gaussian kernel (Sec. 5) is evaluated through the norm expansion
+//   -||x_i - x_j||^2 c = 2c <x_i, x_j> - c nu_i - c nu_j,   nu = ||x||^2, c = log2(e)/(2 sigma^2),
+// which becomes ONE inner product of augmented rows
+//   a_i = q [sqrt(2c) x_i, -c nu_i, 1],   b_j = q [sqrt(2c) x_j, 1, -c nu_j],
+// so that <a_i, b_j> = q^2 log2 k(x_i, x_j). q is a power of two that keeps every entry
+// below 2^14, so the FP16 hi/lo split loses no range (exact scaling, undone in the epilogue).
+#include "kernels.hpp"
+
+namespace krr {
+
+__global__ void fill_f32_kernel(float* p, int64_t count, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, int64_t count, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+__global__ void fill_i32_kernel(int* p, int64_t count, int v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+hipError_t fill_f32(float* p, int64_t count, float v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  fill_f32_kernel<<<ceil_div(count, 256), 256, 0, st>>>(p, count, v);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+hipError_t fill_f64(double* p, int64_t count, double v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  fill_f64_kernel<<<ceil_div(count, 256), 256, 0, st>>>(p, count, v);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  fill_i32_kernel<<<ceil_div(count, 256), 256, 0, st>>>(p, count, v);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// One wave per row: stats[0] = max |x_ik|, stats[1] = max ||x_i||^2 (atomic max on the
+// float bit pattern, valid for non-negative values; stats must start at 0).
+__global__ __launch_bounds__(256) void point_stats_kernel(const float* __restrict__ X, int64_t n,
+                                                          int64_t d, int64_t ldx, float* stats) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const float* x = X + row * ldx;
+  double nu = 0.0;
+  float amax = 0.0f;
+  for (int64_t k = lane; k < d; k += 64) {
+    float v = x[k];
+    nu += (double)v * (double)v;
+    amax = fmaxf(amax, fabsf(v));
+  }
+  nu = wave_sum(nu);
+  for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+  if (lane == 0) {
+    atomic_max_pos(&stats[0], amax);
+    atomic_max_pos(&stats[1], (float)nu);
+  }
+}
+
+hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float* stats,
+                       hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  point_stats_kernel<<<ceil_div(n, 4), 256, 0, st>>>(X, n, d, ldx, stats);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// Augmented, scaled, split rows (one wave per row). side 0 writes a_i, side 1 writes b_j.
+// Rows n..rows_pad-1 and columns d+2..Kp-1 are zero. Thread 0 of block 0 also stores
+// 1/q^2 into *qinv2 (identical for both sides: q depends only on the shared stats).
+template <typename T>
+__global__ __launch_bounds__(256) void prep_points_kernel(
+    const float* __restrict__ X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad, int64_t Kp,
+    double c2, const float* __restrict__ stats, int side, T* __restrict__ hi, T* __restrict__ lo,
+    float* __restrict__ qinv2) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const double t = sqrt(2.0 * c2);
+  const float amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(c2 * stats[1])), 1.0f);
+  const float q = split_scale(amax);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && qinv2) *qinv2 = 1.0f / (q * q);
+  if (row >= rows_pad) return;
+  T* h = hi + row * Kp;
+  T* l = lo + row * Kp;
+  if (row >= n) {
+    for (int64_t k = lane; k < Kp; k += 64) { h[k] = (T)0.0f; l[k] = (T)0.0f; }
+    return;
+  }
+  const float* x = X + row * ldx;
+  double nu = 0.0;
+  for (int64_t k = lane; k < d; k += 64) nu += (double)x[k] * (double)x[k];
+  nu = wave_sum(nu);
+  const double qt = (double)q * t;
+  const double qnu = -(double)q * c2 * nu;
+  for (int64_t k = lane; k < Kp; k += 64) {
+    double v;
+    if (k < d) v = qt * (double)x[k];
+    else if (k == d) v = side == 0 ? qnu : (double)q;
+    else if (k == d + 1) v = side == 0 ? (double)q : qnu;
+    else v = 0.0;
+    T a, b;
+    Elem<T>::split((float)v, a, b);
+    h[k] = a;
+    l[k] = b;
+  }
+}
+
+template <typename T>
+hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                       int64_t Kp, double c2, const float* stats, int side, T* hi, T* lo,
+                       float* qinv2, hipStream_t st) {
+  prep_points_kernel<T><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, Kp, c2,
+                                                               stats, side, hi, lo, qinv2);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+template hipError_t prep_points<_Float16>(const float*, int64_t, int64_t, int64_t, int64_t,
+                                          int64_t, double, const float*, int, _Float16*,
+                                          _Float16*, float*, hipStream_t);
+template hipError_t prep_points<__bf16>(const float*, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                        double, const float*, int, __bf16*, __bf16*, float*,
+                                        hipStream_t);
+
+// FP64 points for the plain FP64 path: X64 (rows_pad x dp, zero padded) and nu (rows_pad).
+__global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __restrict__ X,
+                                                              int64_t n, int64_t d, int64_t ldx,
+                                                              int64_t rows_pad, int64_t dp,
+                                                              double* __restrict__ X64,
+                                                              double* __restrict__ nu) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_pad) return;
+  double s = 0.0;
+  for (int64_t k = lane; k < dp; k += 64) {
+    double v = (row < n && k < d) ? (double)X[row * ldx + k] : 0.0;
+    X64[row * dp + k] = v;
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if (lane == 0) nu[row] = s;
+}
+
+hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                           int64_t dp, double* X64, double* nu, hipStream_t st) {
+  prep_points_f64_kernel<<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, dp, X64,
+                                                                nu);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// V (FP64, n x m, ldv) -> FP32 (rows_pad x ldo), zero padded rows and columns.
+__global__ void vec_to_f32_kernel(const double* __restrict__ V, int64_t n, int64_t m, int64_t ldv,
+                                  int64_t rows_pad, int64_t ldo, float* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows_pad * ldo) return;
+  int64_t i = e / ldo, c = e % ldo;
+  out[e] = (i < n && c < m) ? (float)V[i * ldv + c] : 0.0f;
+}
+
+hipError_t vec_to_f32(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
+                      int64_t ldo, float* out, hipStream_t st) {
+  vec_to_f32_kernel<<<ceil_div(rows_pad * ldo, 256), 256, 0, st>>>(V, n, m, ldv, rows_pad, ldo,
+                                                                   out);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// V (FP64) -> FP64 copy (rows_pad x ldo), zero padded.
+__global__ void vec_pad_f64_kernel(const double* __restrict__ V, int64_t n, int64_t m, int64_t ldv,
+                                   int64_t rows_pad, int64_t ldo, double* __restrict__ out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows_pad * ldo) return;
+  int64_t i = e / ldo, c = e % ldo;
+  out[e] = (i < n && c < m) ? V[i * ldv + c] : 0.0;
+}
+
+hipError_t vec_pad_f64(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
+                       int64_t ldo, double* out, hipStream_t st) {
+  vec_pad_f64_kernel<<<ceil_div(rows_pad * ldo, 256), 256, 0, st>>>(V, n, m, ldv, rows_pad, ldo,
+                                                                    out);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// ------------------------------------------------- generic operand splitting (GEMMs)
+// max |src| over a rows x cols FP32 or FP64 matrix -> atomic max into *amax (starts at 0).
+template <typename S>
+__global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, int64_t rows,
+                                                     int64_t cols, int64_t ld, float* amax) {
+  float m = 0.0f;
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t r = e / cols, c = e % cols;
+    m = fmaxf(m, (float)fabs((double)src[r * ld + c]));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  __shared__ float red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) atomic_max_pos(amax, fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
+
+template <typename S>
+hipError_t absmax(const S* src, int64_t rows, int64_t cols, int64_t ld, float* amax,
+                  hipStream_t st) {
+  int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(rows * cols, 256)));
+  absmax_kernel<S><<<blocks, 256, 0, st>>>(src, rows, cols, ld, amax);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+template hipError_t absmax<float>(const float*, int64_t, int64_t, int64_t, float*, hipStream_t);
+template hipError_t absmax<double>(const double*, int64_t, int64_t, int64_t, float*, hipStream_t);
+
+// dst (rows_pad x cols_pad, k contiguous) = split(q * src), q = split_scale(*amax).
+// transpose = 0: dst[r][c] = src[r][c]; transpose = 1: dst[c][r] = src[r][c] (dst is
+// cols_pad x rows_pad). Padding is zero. LDS-tiled 32 x 32 so both sides coalesce.
+template <typename S, typename T>
+__global__ __launch_bounds__(256) void split_kernel(const S* __restrict__ src, int64_t rows,
+                                                    int64_t cols, int64_t ld,
+                                                    const float* __restrict__ amax, int transpose,
+                                                    int64_t out_rows, int64_t out_cols,
+                                                    T* __restrict__ hi, T* __restrict__ lo) {
+  __shared__ float tile[32][33];
+  const float q = split_scale(*amax);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  // block covers output tile (orow0.., ocol0..)
+  const int64_t orow0 = (int64_t)blockIdx.y * 32, ocol0 = (int64_t)blockIdx.x * 32;
+  if (!transpose) {
+    for (int yy = ty; yy < 32; yy += 8) {
+      int64_t r = orow0 + yy, c = ocol0 + tx;
+      if (r < out_rows && c < out_cols) {
+        float v = (r < rows && c < cols) ? (float)((double)q * (double)src[r * ld + c]) : 0.0f;
+        T a, b;
+        Elem<T>::split(v, a, b);
+        hi[r * out_cols + c] = a;
+        lo[r * out_cols + c] = b;
+      }
+    }
+  } else {
+    // output row = source column, output col = source row
+    for (int yy = ty; yy < 32; yy += 8) {
+      int64_t sr = ocol0 + yy, sc = orow0 + tx;  // source tile, coalesced along sc
+      tile[yy][tx] = (sr < rows && sc < cols) ? (float)((double)q * (double)src[sr * ld + sc]) : 0.0f;
+    }
+    __syncthreads();
+    for (int yy = ty; yy < 32; yy += 8) {
+      int64_t r = orow0 + yy, c = ocol0 + tx;
+      if (r < out_rows && c < out_cols) {
+        T a, b;
+        Elem<T>::split(tile[tx][yy], a, b);
+        hi[r * out_cols + c] = a;
+        lo[r * out_cols + c] = b;
+      }
+    }
+  }
+}
+
+template <typename S, typename T>
+hipError_t split_operand(const S* src, int64_t rows, int64_t cols, int64_t ld, const float* amax,
+                         int transpose, int64_t out_rows, int64_t out_cols, T* hi, T* lo,
+                         hipStream_t st) {
+  dim3 grid(ceil_div(out_cols, 32), ceil_div(out_rows, 32));
+  split_kernel<S, T><<<grid, 256, 0, st>>>(src, rows, cols, ld, amax, transpose, out_rows,
+                                           out_cols, hi, lo);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+template hipError_t split_operand<float, _Float16>(const float*, int64_t, int64_t, int64_t,
+                                                   const float*, int, int64_t, int64_t, _Float16*,
+                                                   _Float16*, hipStream_t);
+template hipError_t split_operand<double, _Float16>(const double*, int64_t, int64_t, int64_t,
+                                                    const float*, int, int64_t, int64_t,
+                                                    _Float16*, _Float16*, hipStream_t);
+
+}  // namespace krr

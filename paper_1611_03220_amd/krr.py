@@ -1,0 +1,285 @@
+"""Python binding of libkrr (ctypes). Argument marshalling only: every step runs in the
+HIP library. Tensors are torch device tensors; the library enqueues on torch's current
+stream. Loading fails loudly when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkrr.so")
+
+OK, E_ARG, E_NOT_SPD, E_NO_CONV, E_BREAKDOWN, E_HIP, E_WORKSPACE = range(7)
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_NOT_SPD", 3: "E_NO_CONV", 4: "E_BREAKDOWN",
+                5: "E_HIP", 6: "E_WORKSPACE"}
+PREC = {"fp64": 0, "f16x3": 1, "bf16x3": 2}
+OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD = range(5)
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+class KRRError(RuntimeError):
+    def __init__(self, status: int, msg: str, report=None, info: int = 0):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.report = report
+        self.info = info
+
+
+class PCGOpts(ctypes.Structure):
+    _fields_ = [("tol", _dbl), ("max_iter", _i32), ("prec", _i32), ("use_precond", _i32),
+                ("check_every", _i32), ("lambda_p", _dbl), ("true_residual", _i32),
+                ("refine", _i32), ("warm_start", _i32)]
+
+
+class PCGReport(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("converged_cols", _i32), ("breakdown_cols", _i32),
+                ("refine_steps", _i32), ("relres_rec", ctypes.POINTER(_dbl)),
+                ("relres_true", ctypes.POINTER(_dbl)), ("history", ctypes.POINTER(_dbl)),
+                ("history_cap", _i32), ("history_len", _i32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libkrr.so (built by ``paper_1611_03220_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libkrr.so not found at {LIB_PATH}: run paper_1611_03220_amd.build.build()")
+    import torch.cuda  # noqa: F401  (the HIP runtime torch loaded is the one libkrr binds to)
+    L = ctypes.CDLL(LIB_PATH)
+    L.krr_workspace_bytes.restype = _sz
+    L.krr_workspace_bytes.argtypes = [_i32, _i64, _i64, _i64, _i64, _i64, _i32]
+    L.krr_last_error.restype = ctypes.c_char_p
+    L.krr_version.restype = ctypes.c_char_p
+    L.krr_pcg_defaults.argtypes = [ctypes.POINTER(PCGOpts)]
+    L.krr_features.restype = _i32
+    L.krr_features.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _sz, _vp]
+    L.krr_precond_factor.restype = _i32
+    L.krr_precond_factor.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _vp, _sz,
+                                     ctypes.POINTER(_i64), _vp]
+    L.krr_kernel_matmat.restype = _i32
+    L.krr_kernel_matmat.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _dbl, _vp, _i64,
+                                    _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]
+    L.krr_pcg_solve.restype = _i32
+    L.krr_pcg_solve.argtypes = [_vp, _i64, _i64, _i64, _dbl, _dbl, _vp, _i64, _i64, _vp, _i64,
+                                _vp, _i64, _i64, ctypes.POINTER(PCGOpts),
+                                ctypes.POINTER(PCGReport), _vp, _sz, _vp]
+    L.krr_grad.restype = _i32
+    L.krr_grad.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64,
+                           ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _i32, _vp, _sz, _vp]
+    _lib = L
+    return L
+
+
+EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_defaults",
+            "krr_features", "krr_precond_factor", "krr_kernel_matmat", "krr_pcg_solve",
+            "krr_grad"]
+
+
+def last_error() -> str:
+    return lib().krr_last_error().decode()
+
+
+def version() -> str:
+    return lib().krr_version().decode()
+
+
+def workspace_bytes(op: int, n1: int, n2: int, d: int, s: int, m: int, prec: int) -> int:
+    return int(lib().krr_workspace_bytes(op, n1, n2, d, s, m, prec))
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check(t: torch.Tensor, dtype, name: str, cols: int | None = None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 2 and t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must be row-major with unit column stride")
+    if cols is not None and t.shape[-1] != cols:
+        raise ValueError(f"{name} has {t.shape[-1]} columns, expected {cols}")
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2:
+        return 1
+    return max(t.stride(0), t.shape[1])
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _raise(status: int, report=None, info: int = 0):
+    if status != OK:
+        raise KRRError(status, last_error(), report, info)
+
+
+# ---------------------------------------------------------------- entry points
+def features(X: torch.Tensor, W: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """Z = sqrt(2/s) cos(X W + b) (n x s, FP32)."""
+    _check(X, torch.float32, "X")
+    _check(W, torch.float32, "W")
+    _check(b, torch.float32, "b")
+    n, d = X.shape
+    s = W.shape[1]
+    if W.shape[0] != d or W.stride(0) != s or b.numel() != s:
+        raise ValueError("W must be d x s contiguous and b of length s")
+    Z = torch.empty((n, s), dtype=torch.float32, device=X.device)
+    ws = _ws(workspace_bytes(OP_FEATURES, n, n, d, s, 0, 1), X.device)
+    st = lib().krr_features(X.data_ptr(), n, d, _ld(X), W.data_ptr(), b.data_ptr(), s,
+                            Z.data_ptr(), s, ws.data_ptr(), ws.numel(), _stream())
+    _raise(st)
+    return Z
+
+
+def precond_factor(Z: torch.Tensor, lambda_p: float):
+    """(C, Ut) with C C^T = Z^T Z + lambda_p I (FP64 s x s) and Ut = Z C^{-T} (FP32 n x s)."""
+    _check(Z, torch.float32, "Z")
+    n, s = Z.shape
+    C = torch.empty((s, s), dtype=torch.float64, device=Z.device)
+    Ut = torch.empty((n, s), dtype=torch.float32, device=Z.device)
+    ws = _ws(workspace_bytes(OP_PRECOND_FACTOR, n, n, 0, s, 0, 1), Z.device)
+    info = _i64(0)
+    st = lib().krr_precond_factor(Z.data_ptr(), n, s, _ld(Z), float(lambda_p), C.data_ptr(),
+                                  Ut.data_ptr(), s, ws.data_ptr(), ws.numel(), ctypes.byref(info),
+                                  _stream())
+    _raise(st, info=info.value)
+    return C, Ut
+
+
+def kernel_matmat(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Tensor,
+                  shift: float = 0.0, deriv: bool = False, prec="f16x3",
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """OUT = K(X1, X2) V + shift V (deriv: dK/dsigma instead of K). FP64 V and OUT."""
+    _check(X1, torch.float32, "X1")
+    _check(X2, torch.float32, "X2")
+    vec = V.dim() == 1
+    V2 = V[:, None] if vec else V
+    _check(V2, torch.float64, "V")
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    m = V2.shape[1]
+    if X2.shape[1] != d or V2.shape[0] != n2:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((n1, m), dtype=torch.float64, device=X1.device)
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_KERNEL_MATMAT, n1, n2, d, 0, m, p), X1.device)
+    st = lib().krr_kernel_matmat(X1.data_ptr(), n1, _ld(X1), X2.data_ptr(), n2, _ld(X2), d,
+                                 float(sigma), float(shift), V2.data_ptr(), m, _ld(V2),
+                                 out.data_ptr(), _ld(out), int(bool(deriv)), p, ws.data_ptr(),
+                                 ws.numel(), _stream())
+    _raise(st)
+    return out[:, 0] if vec else out
+
+
+@dataclasses.dataclass
+class SolveReport:
+    status: int
+    iters: int
+    converged_cols: int
+    breakdown_cols: int
+    refine_steps: int
+    relres_rec: list
+    relres_true: list
+    history: list
+
+
+def pcg_solve(X: torch.Tensor, sigma: float, lam: float, Ut: torch.Tensor | None,
+              Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000, prec="f16x3",
+              use_precond: bool = True, lambda_p: float | None = None, check_every: int = 1,
+              true_residual: bool = True, refine: int = 0, alpha0: torch.Tensor | None = None,
+              raise_on_error: bool = True, history_cap: int = 4096):
+    """Solve (K + lam I) alpha = Y by PCG. Returns (alpha, SolveReport)."""
+    _check(X, torch.float32, "X")
+    vec = Y.dim() == 1
+    Y2 = Y[:, None] if vec else Y
+    _check(Y2, torch.float64, "Y")
+    n, d = X.shape
+    m = Y2.shape[1]
+    if Y2.shape[0] != n:
+        raise ValueError("Y rows must match X")
+    if use_precond:
+        if Ut is None:
+            raise ValueError("use_precond needs Ut")
+        _check(Ut, torch.float32, "Ut")
+        s, ldu, uptr = Ut.shape[1], _ld(Ut), Ut.data_ptr()
+    else:
+        s, ldu, uptr = 0, 0, None
+    p = _prec(prec)
+    alpha = torch.zeros((n, m), dtype=torch.float64, device=X.device)
+    if alpha0 is not None:
+        alpha.copy_(alpha0.reshape(n, m))
+    opts = PCGOpts()
+    lib().krr_pcg_defaults(ctypes.byref(opts))
+    opts.tol, opts.max_iter, opts.prec = float(tol), int(max_iter), p
+    opts.use_precond, opts.check_every = int(bool(use_precond)), int(check_every)
+    opts.lambda_p = float(lambda_p) if lambda_p else 0.0
+    opts.true_residual, opts.refine = int(bool(true_residual)), int(refine)
+    opts.warm_start = int(alpha0 is not None)
+    rec = (_dbl * m)()
+    tru = (_dbl * m)()
+    hist = (_dbl * history_cap)()
+    rep = PCGReport()
+    rep.relres_rec = ctypes.cast(rec, ctypes.POINTER(_dbl))
+    rep.relres_true = ctypes.cast(tru, ctypes.POINTER(_dbl))
+    rep.history = ctypes.cast(hist, ctypes.POINTER(_dbl))
+    rep.history_cap = history_cap
+    ws = _ws(workspace_bytes(OP_PCG_SOLVE, n, n, d, s, m, p), X.device)
+    st = lib().krr_pcg_solve(X.data_ptr(), n, d, _ld(X), float(sigma), float(lam), uptr, s, ldu,
+                             Y2.data_ptr(), _ld(Y2), alpha.data_ptr(), m, m, ctypes.byref(opts),
+                             ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream())
+    report = SolveReport(st, rep.iters, rep.converged_cols, rep.breakdown_cols, rep.refine_steps,
+                         [rec[i] for i in range(m)], [tru[i] for i in range(m)],
+                         [hist[i] for i in range(rep.history_len)])
+    if raise_on_error and st not in (OK,):
+        if st in (E_NO_CONV, E_BREAKDOWN):
+            raise KRRError(st, last_error(), report)
+        _raise(st, report)
+    return (alpha[:, 0] if vec else alpha), report
+
+
+def grad(X: torch.Tensor, sigma: float, alpha: torch.Tensor, abar: torch.Tensor, prec="f16x3"):
+    """(-<abar, dK/dsigma alpha>, -<abar, alpha>)."""
+    _check(X, torch.float32, "X")
+    a2 = alpha[:, None] if alpha.dim() == 1 else alpha
+    b2 = abar[:, None] if abar.dim() == 1 else abar
+    _check(a2, torch.float64, "alpha")
+    _check(b2, torch.float64, "abar")
+    if a2.shape != b2.shape or a2.stride() != b2.stride():
+        raise ValueError("alpha and abar must have the same shape and layout")
+    n, d = X.shape
+    m = a2.shape[1]
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_GRAD, n, n, d, 0, m, p), X.device)
+    ds, dl = _dbl(0.0), _dbl(0.0)
+    st = lib().krr_grad(X.data_ptr(), n, d, _ld(X), float(sigma), a2.data_ptr(), b2.data_ptr(), m,
+                        _ld(a2), ctypes.byref(ds), ctypes.byref(dl), p, ws.data_ptr(), ws.numel(),
+                        _stream())
+    _raise(st)
+    return ds.value, dl.value
+
+
+def rff_scale(s: int) -> float:
+    return math.sqrt(2.0 / s)

@@ -91,7 +91,7 @@ def plain_fp64(n: int = 2000, d: int = 8, s: int = 200, lam_per_n: float = 1e-3,
     X = rng_for(cfg, 0, salt).standard_normal((n, d)).astype(np.float32)
     u = rng_for(cfg, 1, salt).standard_normal(d) / math.sqrt(d)
     eps = rng_for(cfg, 4, salt).standard_normal(n)
-    Y = (np.sin(X.astype(np.float64) @ u) + 0.1 * eps)[:, None]
+    Y = np.ascontiguousarray((np.sin(X.astype(np.float64) @ u) + 0.1 * eps)[:, None])
     sigma = math.sqrt(d)
     W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt))
     return Workload("plain_fp64", X, Y, sigma, lam_per_n * n, s, W, b, tol)
