@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the random-features-preconditioned KRR solve on one MI355X.
+
+One step is the whole hot path on the multi-RHS workload (n = 65536 points, d = 54,
+7 one-vs-all right-hand sides, s = 2048 random Fourier features, lambda = 1e-4 n, sigma
+= median pairwise distance, tolerance 1e-6): features (Alg. 1 steps 4-5), preconditioner
+factorisation (steps 6-7), mixed-precision PCG to 1e-6 (step 9) and the FP64 true
+residual at exit. Inputs are seeded synthetic data resident in HBM before timing.
+
+Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algorithmic
+kernel-product flops 2 n^2 (d + m) of all products in the timed steps divided by the
+timed wall time. `roofline` describes the dominant kernel (the fused kernel product),
+timed with HIP events inside the library on the stream it runs on. `fp64_path` is the
+same solve with the plain FP64 kernel product (time to tolerance), measured once after
+the timed steps. `cpu_baseline` times the CPU FP64 oracle's kernel product on a row
+sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts used by the roofline model
+PEAK_MFMA_F16 = 2.5e15          # dense FP16/BF16 MFMA flop/s
+PEAK_HBM = 8.0e12               # bytes/s
+CUS, CLOCK = 256, 2.4e9
+PEAK_EXP = CUS * 32 * CLOCK     # FP32 transcendental ops/s: half of the 64-lane VALU rate
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=65536, help="points (65536 is the benchmark workload)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path solve")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, seconds):
+    """Time the oracle's FP64 kernel product on a growing row sample for ~`seconds`."""
+    import numpy as np
+    import oracle as O
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    V = np.random.default_rng(0).standard_normal((w.n, w.m))
+    rows_done, t_used, rows = 0, 0.0, 8
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        while t_used < seconds:
+            idx = np.arange(rows_done, rows_done + rows) % w.n
+            t0 = time.perf_counter()
+            O.kernel_matmat(w.X, w.X, w.sigma, V, rows=idx)
+            t_used += time.perf_counter() - t0
+            rows_done += rows
+            rows = min(rows * 2, 256)
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    flops = 2.0 * rows_done * w.n * (w.d + w.m)
+    return {"value": flops / t_used / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 difference-form kernel product K[rows, :] V for {rows_done} of "
+                      f"{w.n} rows (d={w.d}, m={w.m}), {t_used:.1f} s, one thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU "
+              "by design, see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+
+    dev = torch.device("cuda:0")
+    w = WL.mixture_multi_rhs(n=args.n)
+    X = torch.from_numpy(w.X).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+    W = torch.from_numpy(w.W).to(dev)
+    b = torch.from_numpy(w.b).to(dev)
+    torch.cuda.synchronize()
+
+    def step(prec):
+        Z = krr.features(X, W, b)
+        _, Ut = krr.precond_factor(Z, w.lam)
+        alpha, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, prec=prec,
+                                   true_residual=True, raise_on_error=False)
+        return alpha, rep
+
+    for _ in range(args.warmup):
+        step("f16x3")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = [step("f16x3")[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    n, d, m = w.n, w.d, w.m
+    flops_mm = 2.0 * n * n * (d + m)
+    calls = sum(r.matmat_calls for r in reps)
+    mm_ms = sum(r.matmat_ms for r in reps)
+    avg_launch_s = mm_ms / max(calls, 1) / 1e3
+    pairs = float(n) * n
+    kp = int(math.ceil((d + 2) / 32.0) * 32)
+    exec_mfma = pairs * 3 * 2 * kp
+    t_mfma = flops_mm / PEAK_MFMA_F16
+    t_exp = pairs / PEAK_EXP
+    roof = {"bound": "alu", "achieved": pairs / avg_launch_s / 1e12, "peak": PEAK_EXP / 1e12,
+            "unit": "TFLOP/s", "frac": (pairs / avg_launch_s) / PEAK_EXP, "traffic": None,
+            "kernel": "matmat_mixed_kernel (FP16 hi/lo split MFMA distances + exp2 + V accumulate)",
+            "op_counted": "one FP32 exp per kernel entry (n^2 per launch)",
+            "avg_launch_ms": avg_launch_s * 1e3, "launches": calls,
+            "algorithmic_mfma_tflops": flops_mm / avg_launch_s / 1e12,
+            "executed_mfma_tflops": exec_mfma / avg_launch_s / 1e12,
+            "model_ms": {"mfma_algorithmic": t_mfma * 1e3, "exp": t_exp * 1e3}}
+    relres_true = max(max(r.relres_true) for r in reps)
+    iters = [r.iters for r in reps]
+    out = {
+        "metric": "kernel matmat TFLOP/s + time-to-1e-6 residual PCG solve, mixed vs FP64 path",
+        "value": calls * flops_mm / wall / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f16x3-split MFMA + f32 exp, f64 CG scalars", "data": "synthetic",
+        "config": {"workload": "multi-RHS Gaussian mixture", "n": n, "d": d, "m": m, "s": w.s,
+                   "lambda": w.lam, "sigma": w.sigma, "tol": w.tol, "parallelism": "single GPU"},
+        "time_to_tol_mixed_s": wall / args.steps,
+        "iterations": iters,
+        "relres_true_max": relres_true,
+        "kernel_matmat_tflops": flops_mm / avg_launch_s / 1e12,
+        "roofline": roof,
+    }
+    if not args.no_fp64:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, r64 = step("fp64")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t1
+        out["fp64_path"] = {"time_to_tol_s": t64, "iterations": r64.iters,
+                            "relres_true_max": max(r64.relres_true),
+                            "kernel_matmat_tflops": flops_mm * r64.matmat_calls / max(r64.matmat_ms, 1e-9) * 1e-9,
+                            "speedup_mixed_vs_fp64": t64 / (wall / args.steps)}
+        print(f"[bench] fp64 path {t64:.3f} s", file=sys.stderr, flush=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -161,9 +161,12 @@ typedef struct krr_pcg_report {
   int32_t refine_steps;    /* outer refinement steps taken */
   double* relres_rec;      /* host[m]: recursive ||r_j|| / ||y_j|| at exit */
   double* relres_true;     /* host[m]: FP64 ||y_j - (K + lambda I) c_j|| / ||y_j|| (if requested) */
-  double* history;         /* host[history_cap]: max relative recursive residual per iteration */
+  double* history;         /* host[history_cap]: max relative recursive residual at each check */
   int32_t history_cap;
   int32_t history_len;
+  int32_t matmat_calls;    /* kernel products in the solve precision (iterations, warm start) */
+  double matmat_ms;        /* summed device time of those products (HIP events on `stream`);
+                              the FP64 true-residual products are not included */
 } krr_pcg_report;
 
 /* Fill `o` with the defaults: tol 1e-6, max_iter 1000, F16X3, preconditioned, check every

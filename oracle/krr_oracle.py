@@ -51,10 +51,12 @@ def sq_dists(X1: np.ndarray, X2: np.ndarray, block: int = 256) -> np.ndarray:
     """Squared Euclidean distances D_ij = sum_k (x1_ik - x2_jk)^2 in FP64.
 
     Difference form, evaluated block by block (Sec. 5 defines the Gaussian kernel on
-    ||x - z||^2).
+    ||x - z||^2). The block of rows is capped so the difference array stays near 2^24
+    elements.
     """
     X1 = np.asarray(X1, np.float64)
     X2 = np.asarray(X2, np.float64)
+    block = max(1, min(block, (1 << 24) // max(1, X2.shape[0] * X2.shape[1])))
     D = np.empty((X1.shape[0], X2.shape[0]))
     for a in range(0, X1.shape[0], block):
         diff = X1[a:a + block, None, :] - X2[None, :, :]

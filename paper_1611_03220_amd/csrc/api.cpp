@@ -54,11 +54,19 @@ constexpr int NBLK = 256;  // blocks of the column-wise reductions
 bool prec_ok(int32_t p) { return p == KRR_PREC_FP64 || p == KRR_PREC_F16X3 || p == KRR_PREC_BF16X3; }
 
 int64_t kp_for(int64_t d) { return round_up(d + 2, K_STEP); }
+// The F16X3 product with MFMA accumulation (one more augmented column, up to 32 columns
+// of V per pass) serves d + 3 <= 128; other mixed cases use the VALU-accumulate kernel.
+bool use_pv(int prec, int64_t d) {
+  return prec == KRR_PREC_F16X3 && round_up(d + 2 + (PSHIFT > 0), K_STEP) <= 128;
+}
+int64_t kp_for(int prec, int64_t d) {
+  return use_pv(prec, d) ? round_up(d + 2 + (PSHIFT > 0), K_STEP) : kp_for(d);
+}
 int64_t dp_for(int64_t d) { return round_up(d, 32); }
 
 // Split of the column sweep over blockIdx.y so that small row counts still fill the chip.
 int choose_nsplit(int64_t n1, int64_t n2) {
-  const int64_t rowblocks = ceil_div(n1, 64);
+  const int64_t rowblocks = ceil_div(n1, 128);
   const int64_t tiles = ceil_div(n2, 64);
   int64_t ns = ceil_div(2048, rowblocks);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, tiles / 4));
@@ -68,6 +76,10 @@ int choose_nsplit(int64_t n1, int64_t n2) {
 // --------------------------------------------------------- kernel-product context
 struct MatmatCtx {
   int prec = KRR_PREC_F16X3;
+  bool pv = false;          // MFMA-accumulate kernel
+  _Float16 *Vth = nullptr, *Vtl = nullptr;  // [mpad][rp2] split V^T (pv)
+  float *colmax = nullptr, *vscale = nullptr;
+  int64_t mpad = 0;
   int64_t n1 = 0, n2 = 0, d = 0, m = 0;
   int64_t rp1 = 0, rp2 = 0, Kp = 0, dp = 0;
   int nsplit = 1;
@@ -95,7 +107,15 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     if (square) { c.XB = c.XA; c.nuB = c.nuA; }
     else { c.XB = b.take<double>(c.rp2 * c.dp); c.nuB = b.take<double>(c.rp2); }
   } else {
-    c.Kp = kp_for(d);
+    c.pv = use_pv(prec, d);
+    c.Kp = kp_for(prec, d);
+    if (c.pv) {
+      c.mpad = round_up(std::min<int64_t>(m, 32), 16);
+      c.Vth = b.take<_Float16>(c.mpad * c.rp2);
+      c.Vtl = b.take<_Float16>(c.mpad * c.rp2);
+      c.colmax = b.take<float>(m);
+      c.vscale = b.take<float>(c.mpad);
+    }
     c.Ahi = b.take<uint16_t>(c.rp1 * c.Kp);
     c.Alo = b.take<uint16_t>(c.rp1 * c.Kp);
     c.Bhi = b.take<uint16_t>(c.rp2 * c.Kp);
@@ -121,38 +141,56 @@ hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const flo
   if (X2 && (e = point_stats(X2, c.n2, c.d, ldx2, c.stats, st))) return e;
   const float* Xb = X2 ? X2 : X1;
   const int64_t ldb = X2 ? ldx2 : ldx1;
+  const int ps = c.pv ? PSHIFT : 0;
   if (c.prec == KRR_PREC_F16X3) {
-    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0,
+    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0, ps,
                                    (_Float16*)c.Ahi, (_Float16*)c.Alo, c.stats + 2, st)))
       return e;
-    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1,
+    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1, ps,
                                  (_Float16*)c.Bhi, (_Float16*)c.Blo, nullptr, st);
   }
-  if ((e = prep_points<__bf16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0, (__bf16*)c.Ahi,
-                               (__bf16*)c.Alo, c.stats + 2, st)))
+  if ((e = prep_points<__bf16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0, 0,
+                               (__bf16*)c.Ahi, (__bf16*)c.Alo, c.stats + 2, st)))
     return e;
-  return prep_points<__bf16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1, (__bf16*)c.Bhi,
+  return prep_points<__bf16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1, 0, (__bf16*)c.Bhi,
                              (__bf16*)c.Blo, nullptr, st);
 }
 
 // Partial sums of K V (or dK/dsigma V) into c.part. V is FP32 (mixed) or FP64 (FP64 path).
-hipError_t run_matmat(const MatmatCtx& c, const float* Vf, const double* V64, int64_t ldv,
-                      bool deriv, hipStream_t st) {
+// On the MFMA-accumulate path Vf (n2 x ldv) is split in place: on return it holds exactly the
+// vector the product used.
+hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t ldv, bool deriv,
+                      hipStream_t st) {
   const double sig3 = c.sigma * c.sigma * c.sigma;
   if (c.prec == KRR_PREC_FP64) {
     F64Points A{c.XA, c.nuA, c.n1, c.dp}, B{c.XB, c.nuB, c.n2, c.dp};
     return matmat_f64(A, B, V64, ldv, c.m, deriv, 1.0 / (2.0 * c.sigma * c.sigma), 1.0 / sig3,
-                      c.part, c.m, c.nsplit, st);
+                      c.part, c.m, c.part_stride, c.nsplit, st);
   }
   const float dscale = (float)(1.0 / (c.c2 * sig3));  // dk/dsigma = k * (-log2 k) / (c2 sigma^3)
   if (c.prec == KRR_PREC_F16X3) {
     MixedPoints<_Float16> A{(const _Float16*)c.Ahi, (const _Float16*)c.Alo, c.n1, c.Kp, c.stats + 2};
     MixedPoints<_Float16> B{(const _Float16*)c.Bhi, (const _Float16*)c.Blo, c.n2, c.Kp, c.stats + 2};
-    return matmat_mixed<_Float16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.nsplit, st);
+    if (c.pv) {
+      for (int64_t c0 = 0; c0 < c.m; c0 += 32) {
+        const int64_t mc = std::min<int64_t>(32, c.m - c0);
+        const int64_t mp = round_up(mc, 16);
+        hipError_t e = vec_split_t(Vf + c0, c.n2, mc, ldv, c.rp2, mp, c.colmax, PSHIFT, c.Vth,
+                                   c.Vtl, c.vscale, st);
+        if (e != hipSuccess) return e;
+        SplitRhs V{c.Vth, c.Vtl, c.vscale, c.rp2, mp};
+        e = matmat_f16pv(A, B, V, mc, deriv, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+    return matmat_mixed<_Float16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.part_stride,
+                                  c.nsplit, st);
   }
   MixedPoints<__bf16> A{(const __bf16*)c.Ahi, (const __bf16*)c.Alo, c.n1, c.Kp, c.stats + 2};
   MixedPoints<__bf16> B{(const __bf16*)c.Bhi, (const __bf16*)c.Blo, c.n2, c.Kp, c.stats + 2};
-  return matmat_mixed<__bf16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.nsplit, st);
+  return matmat_mixed<__bf16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.part_stride,
+                              c.nsplit, st);
 }
 
 krr_status check_ws(void* ws, size_t ws_bytes, size_t need) {
@@ -441,6 +479,60 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
 // ------------------------------------------------------------------------ PCG
 namespace {
 
+// Device time of the kernel products of one solve: HIP event pairs on the solve's stream,
+// harvested at synchronisation points.
+struct MMTimer {
+  static constexpr int CAP = 32;
+  hipEvent_t a[CAP], b[CAP];
+  int used = 0, created = 0, calls = 0;
+  double ms = 0.0;
+  hipError_t init() {
+    for (; created < CAP; ++created) {
+      hipError_t e = hipEventCreate(&a[created]);
+      if (e != hipSuccess) return e;
+      e = hipEventCreate(&b[created]);
+      if (e != hipSuccess) { (void)hipEventDestroy(a[created]); return e; }
+    }
+    return hipSuccess;
+  }
+  ~MMTimer() {
+    for (int i = 0; i < created; ++i) { (void)hipEventDestroy(a[i]); (void)hipEventDestroy(b[i]); }
+  }
+  hipError_t harvest() {
+    if (used == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(b[used - 1]);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < used; ++i) {
+      float t = 0.0f;
+      if ((e = hipEventElapsedTime(&t, a[i], b[i])) != hipSuccess) return e;
+      ms += t;
+    }
+    used = 0;
+    return hipSuccess;
+  }
+  hipError_t begin(hipStream_t st) {
+    if (used == CAP) {
+      hipError_t e = harvest();
+      if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(a[used], st);
+  }
+  hipError_t end(hipStream_t st) {
+    hipError_t e = hipEventRecord(b[used], st);
+    ++used;
+    ++calls;
+    return e;
+  }
+};
+
+hipError_t timed_matmat(MMTimer* tm, const MatmatCtx& c, float* Vf, const double* V64,
+                        int64_t ldv, bool deriv, hipStream_t st) {
+  hipError_t e;
+  if (tm && (e = tm->begin(st)) != hipSuccess) return e;
+  if ((e = run_matmat(c, Vf, V64, ldv, deriv, st)) != hipSuccess) return e;
+  return tm ? tm->end(st) : hipSuccess;
+}
+
 hipError_t fill2d_zero(double* a, int64_t lda, int64_t n, int64_t m, hipStream_t st) {
   if (lda == m) return fill_f64(a, n * m, 0.0, st);
   for (int64_t i = 0; i < n; ++i) {  // strided: one small fill per row is acceptable here
@@ -457,6 +549,7 @@ struct SolveArgs {
   double lambda, lambda_p, tol;
   int use_precond, max_iter, check_every;
   bool mixed;
+  MMTimer* tm;
 };
 
 // One PCG run on A x = rhs (rhs n x m contiguous, x strided), starting from x.
@@ -474,10 +567,10 @@ krr_status pcg_core(const SolveArgs& a, const double* rhs, int64_t ldr, double* 
       // FP32 copy of x for the product (row stride m)
       CHECK_HIP(copy2d(x, ldx, L.p, m, n, m, st));
       CHECK_HIP(cg_update_p(L.p, L.p, L.pf, ldpf, L.beta, L.active, 1, n, m, st));
-      CHECK_HIP(run_matmat(L.mm, L.pf, nullptr, ldpf, false, st));
+      CHECK_HIP(timed_matmat(a.tm, L.mm, L.pf, nullptr, ldpf, false, st));
     } else {
       CHECK_HIP(copy2d(x, ldx, L.p, m, n, m, st));
-      CHECK_HIP(run_matmat(L.mm, nullptr, L.p, m, false, st));
+      CHECK_HIP(timed_matmat(a.tm, L.mm, nullptr, L.p, m, false, st));
     }
     CHECK_HIP(matmat_finalize<double>(L.mm.part, L.mm.part_stride, L.mm.nsplit, n, m, m, a.lambda,
                                       L.p, m, L.ax, m, st));
@@ -504,12 +597,12 @@ krr_status pcg_core(const SolveArgs& a, const double* rhs, int64_t ldr, double* 
     ++it;
     // q = (K + lambda I) p
     if (a.mixed) {
-      CHECK_HIP(run_matmat(L.mm, L.pf, nullptr, ldpf, false, st));
+      CHECK_HIP(timed_matmat(a.tm, L.mm, L.pf, nullptr, ldpf, false, st));
       CHECK_HIP(matmat_finalize<float>(L.mm.part, L.mm.part_stride, L.mm.nsplit, n, m, m, a.lambda,
                                        L.pf, ldpf, L.q, m, st));
       CHECK_HIP(dot_partial<float, double>(L.pf, ldpf, L.q, m, n, m, L.part_pq, NBLK, st));
     } else {
-      CHECK_HIP(run_matmat(L.mm, nullptr, L.p, m, false, st));
+      CHECK_HIP(timed_matmat(a.tm, L.mm, nullptr, L.p, m, false, st));
       CHECK_HIP(matmat_finalize<double>(L.mm.part, L.mm.part_stride, L.mm.nsplit, n, m, m, a.lambda,
                                         L.p, m, L.q, m, st));
       CHECK_HIP(dot_partial<double, double>(L.p, m, L.q, m, n, m, L.part_pq, NBLK, st));
@@ -547,7 +640,7 @@ krr_status true_residual(PCGLayout& L, const SolveArgs& a, const double* Y, int6
   MatmatCtx& c = a.mixed ? L.mm64 : L.mm;
   const int64_t n = a.n, m = a.m;
   CHECK_HIP(copy2d(x, ldx, L.delta, m, n, m, st));
-  CHECK_HIP(run_matmat(c, nullptr, L.delta, m, false, st));
+  CHECK_HIP(run_matmat(c, nullptr, L.delta, m, false, st));  // FP64 check: not timed
   CHECK_HIP(matmat_finalize<double>(c.part, c.part_stride, c.nsplit, n, m, m, a.lambda, L.delta, m,
                                     L.ax, m, st));
   CHECK_HIP(residual_from(Y, ldy, L.ax, n, m, L.rhs, st));
@@ -606,8 +699,10 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
   if (mixed && (o.true_residual || o.refine > 0))
     CHECK_HIP(prepare_points(L.mm64, X, ldx, nullptr, 0, sigma, st));
 
+  MMTimer timer;
+  CHECK_HIP(timer.init());
   SolveArgs a{&L, n, m, s, ldu, Ut, lambda, lambda_p, o.tol, o.use_precond, o.max_iter,
-              o.check_every, mixed};
+              o.check_every, mixed, &timer};
   std::vector<double> hist;
   int iters = 0;
   if (!o.warm_start) CHECK_HIP(fill2d_zero(alpha, lda, n, m, st));
@@ -647,6 +742,7 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
       CHECK_ST(true_residual(L, a, Y, ldy, alpha, lda, rel_true, st));
     }
   }
+  CHECK_HIP(timer.harvest());
   int conv = 0, brk = 0;
   for (int64_t c = 0; c < m; ++c) {
     if (broken0[c]) ++brk;
@@ -664,6 +760,8 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
     if (rep->history && rep->history_cap > 0)
       for (; hl < rep->history_cap && hl < (int)hist.size(); ++hl) rep->history[hl] = hist[hl];
     rep->history_len = hl;
+    rep->matmat_calls = timer.calls;
+    rep->matmat_ms = timer.ms;
   }
   if (brk > 0) return fail(KRR_E_BREAKDOWN, "krr_pcg_solve: %d column(s) broke down", brk);
   bool ok;

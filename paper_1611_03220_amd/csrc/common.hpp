@@ -14,7 +14,7 @@ constexpr int WAVE = 64;
 
 // Padding of the prepared point arrays: rows to a multiple of ROW_PAD, the contraction
 // (feature) dimension to a multiple of K_STEP (one 16x16x32 MFMA step).
-constexpr int ROW_PAD = 64;
+constexpr int ROW_PAD = 128;
 constexpr int K_STEP = 32;
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }

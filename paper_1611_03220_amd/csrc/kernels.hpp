@@ -42,8 +42,11 @@ hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float*
                        hipStream_t st);
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                       int64_t Kp, double c2, const float* stats, int side, T* hi, T* lo,
-                       float* qinv2, hipStream_t st);
+                       int64_t Kp, double c2, const float* stats, int side, int pshift, T* hi,
+                       T* lo, float* qinv2, hipStream_t st);
+hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
+                       float* colmax, int pshift, _Float16* hi, _Float16* lo, float* vscale,
+                       hipStream_t st);
 hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                            int64_t dp, double* X64, double* nu, hipStream_t st);
 hipError_t vec_to_f32(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
@@ -59,13 +62,27 @@ hipError_t split_operand(const S* src, int64_t rows, int64_t cols, int64_t ld, c
                          hipStream_t st);
 
 // matmat.hip
+struct SplitRhs {          // right-hand sides prepared for the MFMA accumulation
+  const _Float16* hi;      // [mpad][rows_pad] V^T, scaled per column
+  const _Float16* lo;
+  const float* vscale;     // [mpad] 1 / (column scale * 2^pshift)
+  int64_t rows_pad, mpad;
+};
+// Exponent shift of the MFMA-accumulate products. Folding a shift into the augmented
+// contraction makes the FP32 accumulator carry log2 k + shift, whose rounding is relative
+// to the shift; measured, that raised the solve's residual floor, so no shift is applied:
+// k in (0, 1] is split directly (absolute error <= 2^-25 where k is below FP16's normal range).
+constexpr int PSHIFT = 0;
+hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
+                        const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
 template <typename T>
 hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
                         int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
-                        int64_t ldp, int nsplit, hipStream_t st);
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
-                      int nsplit, hipStream_t st);
+                      int64_t part_stride, int nsplit, hipStream_t st);
 template <typename VS>
 hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, int64_t n,
                            int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,

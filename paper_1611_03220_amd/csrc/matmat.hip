@@ -211,11 +211,10 @@ static hipError_t launch_mixed_ks(const MixedPoints<T>& A, const MixedPoints<T>&
 template <typename T>
 hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
                         int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
-                        int64_t ldp, int nsplit, hipStream_t st) {
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
   if (A.Kp != B.Kp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, MM_BN);
   const int tps = (int)ceil_div(ntiles, nsplit);
-  const int64_t part_stride = round_up(A.n, MM_BM) * ldp;
   switch (A.Kp / 32) {
 #define KRR_KS(N)                                                                             \
   case N:                                                                                     \
@@ -228,11 +227,276 @@ hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const 
 }
 template hipError_t matmat_mixed<_Float16>(const MixedPoints<_Float16>&,
                                            const MixedPoints<_Float16>&, const float*, int64_t,
-                                           int64_t, bool, float, double*, int64_t, int,
+                                           int64_t, bool, float, double*, int64_t, int64_t, int,
                                            hipStream_t);
 template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const MixedPoints<__bf16>&,
                                          const float*, int64_t, int64_t, bool, float, double*,
-                                         int64_t, int, hipStream_t);
+                                         int64_t, int64_t, int, hipStream_t);
+
+// ----------------------------------------------- F16X3 kernel with MFMA accumulation
+// Same product as above, with the accumulation over j on MFMA too. Each wave owns 32 rows
+// (two 16-row blocks) and reads 32-column halves ("j-pairs") of the 64-column tile:
+//   S^T[j][i] = <b_j, a_i> on MFMA with the column operand b_j (from LDS) as A and the
+//   row operand a_i (registers) as B, so lane l holds S^T[4(l/16)+r][l%16]: rows i = l%16
+//   and four consecutive j -- exactly the A-operand layout of the next product once two
+//   16-column blocks are concatenated along k;
+//   P' = exp2(S / q^2) = k 2^PSHIFT (PSHIFT = 0: no shift, see kernels.hpp), split
+//   into FP16 hi + lo (both rounded to nearest, so the error is unbiased) and multiplied on
+//   MFMA with the FP16
+//   hi/lo split of V^T (three products), FP32 accumulate, FP64 sums every MM2_FLUSH tiles.
+// The distance products of the second j-pair are issued before the first j-pair's
+// epilogue so MFMA and VALU work of one wave overlap.
+constexpr int MM2_BM = 128;   // rows per block (4 waves x 32)
+constexpr int MM2_FLUSH = 2;  // tiles between FP32 -> FP64 flushes
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+template <int KS, int NCT, bool DERIV>
+__global__ __launch_bounds__(256) void matmat_f16pv_kernel(
+    const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
+    const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
+    const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
+    const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
+    int64_t part_stride, int tiles_per_split) {
+  constexpr int KP = KS * 32;
+  constexpr int LDS_K = KP + 8;
+  constexpr int BCH = MM_BN * KP / 8;       // 16-byte chunks per B operand tile
+  constexpr int BCPT = (BCH + 255) / 256;
+  constexpr int VR = NCT * 16;              // V^T rows (columns of V) per tile
+  constexpr int LDS_J = MM_BN + 8;          // padded V^T row (halves)
+  constexpr int VCH = VR * MM_BN / 8;       // 16-byte chunks per V^T tile
+  constexpr int VCPT = (VCH + 255) / 256;
+
+  __shared__ __attribute__((aligned(16))) _Float16 sBh[2][MM_BN * LDS_K];
+  __shared__ __attribute__((aligned(16))) _Float16 sBl[2][MM_BN * LDS_K];
+  __shared__ __attribute__((aligned(16))) _Float16 sVh[2][VR * LDS_J];
+  __shared__ __attribute__((aligned(16))) _Float16 sVl[2][VR * LDS_J];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * MM2_BM + 32 * w;
+  const int64_t ntiles = ceil_div(n2, MM_BN);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+  const float qinv2 = *qinv2_ptr;
+
+  // row operands (B operand of the distance product) for the two 16-row blocks
+  half8 ah[2][KS], al[2][KS];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int64_t off = (i0 + 16 * ib + li) * KP + ks * 32 + 8 * lg;
+      ah[ib][ks] = *reinterpret_cast<const half8*>(Ahi + off);
+      al[ib][ks] = *reinterpret_cast<const half8*>(Alo + off);
+    }
+
+  f32x4 acc[2][NCT];
+  double acc64[2][NCT][4];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[ib][ct][r] = 0.0;
+    }
+
+  uint4 rbh[BCPT], rbl[BCPT], rvh[VCPT], rvl[VCPT];
+  auto gload = [&](int64_t t) {
+    const int64_t j0 = t * MM_BN;
+#pragma unroll
+    for (int u = 0; u < BCPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < BCH) {
+        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
+        const int64_t off = (j0 + row) * KP + col8 * 8;
+        rbh[u] = *reinterpret_cast<const uint4*>(Bhi + off);
+        rbl[u] = *reinterpret_cast<const uint4*>(Blo + off);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VCPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < VCH) {
+        const int c = ch / (MM_BN / 8), j8 = ch % (MM_BN / 8);
+        const int64_t off = (int64_t)c * ldvt + j0 + j8 * 8;
+        rvh[u] = *reinterpret_cast<const uint4*>(Vth + off);
+        rvl[u] = *reinterpret_cast<const uint4*>(Vtl + off);
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < BCPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < BCH) {
+        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
+        *reinterpret_cast<uint4*>(&sBh[buf][row * LDS_K + col8 * 8]) = rbh[u];
+        *reinterpret_cast<uint4*>(&sBl[buf][row * LDS_K + col8 * 8]) = rbl[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VCPT; ++u) {
+      const int ch = tid + 256 * u;
+      if (ch < VCH) {
+        const int c = ch / (MM_BN / 8), j8 = ch % (MM_BN / 8);
+        *reinterpret_cast<uint4*>(&sVh[buf][c * LDS_J + j8 * 8]) = rvh[u];
+        *reinterpret_cast<uint4*>(&sVl[buf][c * LDS_J + j8 * 8]) = rvl[u];
+      }
+    }
+  };
+  // distance products of j-pair jp (columns 32 jp .. 32 jp + 31 of the tile in `buf`)
+  auto dist = [&](int buf, int jp, f32x4 (&S)[2][2]) {
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) S[jb][ib] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      half8 bh[2], bl[2];
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb) {
+        const _Float16* p = &sBh[buf][(32 * jp + 16 * jb + li) * LDS_K + ks * 32 + 8 * lg];
+        bh[jb] = *reinterpret_cast<const half8*>(p);
+        bl[jb] = *reinterpret_cast<const half8*>(
+            &sBl[buf][(32 * jp + 16 * jb + li) * LDS_K + ks * 32 + 8 * lg]);
+      }
+      // four independent accumulation chains, small terms first
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+          S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[jb], ah[ib][ks], S[jb][ib], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+          S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[jb], al[ib][ks], S[jb][ib], 0, 0, 0);
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+          S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh[jb], ah[ib][ks], S[jb][ib], 0, 0, 0);
+    }
+  };
+  // exp2, split and accumulate j-pair jp on MFMA
+  auto epi = [&](int buf, int jp, const f32x4 (&S)[2][2]) {
+    half8 vh[NCT], vl[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int c = 16 * ct + li;
+      const half4 h0 = *reinterpret_cast<const half4*>(&sVh[buf][c * LDS_J + 32 * jp + 4 * lg]);
+      const half4 h1 = *reinterpret_cast<const half4*>(&sVh[buf][c * LDS_J + 32 * jp + 16 + 4 * lg]);
+      const half4 l0 = *reinterpret_cast<const half4*>(&sVl[buf][c * LDS_J + 32 * jp + 4 * lg]);
+      const half4 l1 = *reinterpret_cast<const half4*>(&sVl[buf][c * LDS_J + 32 * jp + 16 + 4 * lg]);
+      vh[ct] = half8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+      vl[ct] = half8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+    }
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      half8 ph, pl;
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
+          float l2a = S[jb][ib][r] * qinv2, l2b = S[jb][ib][r + 1] * qinv2;
+          float pa = __builtin_amdgcn_exp2f(l2a), pb = __builtin_amdgcn_exp2f(l2b);
+          if (DERIV) {
+            pa *= ((float)PSHIFT - l2a) * dscale;
+            pb *= ((float)PSHIFT - l2b) * dscale;
+          }
+          // round-to-nearest split (v_cvt_pk_f16_f32): unbiased, |error| <= 2^-22 |p|
+          const half2v h = half2v{(_Float16)pa, (_Float16)pb};
+          const half2v l = half2v{(_Float16)(pa - (float)h[0]), (_Float16)(pb - (float)h[1])};
+          ph[4 * jb + r] = h[0];
+          ph[4 * jb + r + 1] = h[1];
+          pl[4 * jb + r] = l[0];
+          pl[4 * jb + r + 1] = l[1];
+        }
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) {
+        acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl, vh[ct], acc[ib][ct], 0, 0, 0);
+        acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
+        acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vh[ct], acc[ib][ct], 0, 0, 0);
+      }
+    }
+  };
+
+  if (t_begin < t_end) {
+    gload(t_begin);
+    lstore(0);
+  }
+  __syncthreads();
+  int since_flush = 0;
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int buf = (int)((t - t_begin) & 1);
+    if (t + 1 < t_end) gload(t + 1);
+    f32x4 S0[2][2], S1[2][2];
+    dist(buf, 0, S0);
+    dist(buf, 1, S1);
+    epi(buf, 0, S0);
+    epi(buf, 1, S1);
+    if (++since_flush == MM2_FLUSH || t + 1 == t_end) {
+      since_flush = 0;
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc64[ib][ct][r] += (double)acc[ib][ct][r];
+          acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+    }
+    if (t + 1 < t_end) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // lane holds OUT[i0 + 16 ib + 4 lg + r][16 ct + li]
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t c = 16 * ct + li;
+    if (c < m) {
+      const double vs = (double)vscale[c];
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i0 + 16 * ib + 4 * lg + r;
+          if (i < n1) pout[i * ldp + c] = acc64[ib][ct][r] * vs;
+        }
+    }
+  }
+}
+
+hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
+                        const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
+  if (A.Kp != B.Kp || V.mpad < round_up(m, 16) || V.mpad > 32) return hipErrorInvalidValue;
+  if (part_stride < round_up(A.n, MM2_BM) * ldp) return hipErrorInvalidValue;
+  const int64_t ntiles = ceil_div(B.n, MM_BN);
+  const int tps = (int)ceil_div(ntiles, nsplit);
+  dim3 grid(ceil_div(A.n, MM2_BM), nsplit);
+  const int nct = (int)(V.mpad / 16);
+#define KRR_PV(KS_, NCT_)                                                                     \
+  if (A.Kp == KS_ * 32 && nct == NCT_) {                                                      \
+    if (deriv)                                                                                \
+      matmat_f16pv_kernel<KS_, NCT_, true><<<grid, 256, 0, st>>>(                             \
+          A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
+          dscale, part, ldp, part_stride, tps);                                               \
+    else                                                                                      \
+      matmat_f16pv_kernel<KS_, NCT_, false><<<grid, 256, 0, st>>>(                            \
+          A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
+          dscale, part, ldp, part_stride, tps);                                               \
+    KRR_LAUNCH_CHECK();                                                                       \
+    return hipSuccess;                                                                        \
+  }
+  KRR_PV(1, 1) KRR_PV(2, 1) KRR_PV(3, 1) KRR_PV(4, 1)
+  KRR_PV(1, 2) KRR_PV(2, 2) KRR_PV(3, 2) KRR_PV(4, 2)
+#undef KRR_PV
+  return hipErrorInvalidValue;
+}
 
 // ------------------------------------------------------------------- FP64 path
 // Block: 64 rows x 64-column tiles; thread (ty, tx) = (t/16, t%16) owns rows 4ty..4ty+3 and
@@ -335,11 +599,10 @@ __global__ __launch_bounds__(256) void matmat_f64_kernel(
 
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
-                      int nsplit, hipStream_t st) {
+                      int64_t part_stride, int nsplit, hipStream_t st) {
   if (A.dp != B.dp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, 64);
   const int tps = (int)ceil_div(ntiles, nsplit);
-  const int64_t part_stride = round_up(A.n, 64) * ldp;
   dim3 grid(ceil_div(A.n, 64), nsplit);
   for (int64_t c0 = 0; c0 < m; c0 += 8) {
     const int mc = (int)std::min<int64_t>(8, m - c0);

@@ -74,17 +74,20 @@ hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float*
 }
 
 // Augmented, scaled, split rows (one wave per row). side 0 writes a_i, side 1 writes b_j.
-// Rows n..rows_pad-1 and columns d+2..Kp-1 are zero. Thread 0 of block 0 also stores
-// 1/q^2 into *qinv2 (identical for both sides: q depends only on the shared stats).
+// With pshift > 0 a third augmented column (a: q, b: q * pshift) adds pshift to every
+// log2 k, i.e. the products return k * 2^pshift. Rows n..rows_pad-1 and the remaining
+// columns up to Kp are zero. Thread 0 of block 0 also stores 1/q^2 into *qinv2 (identical
+// for both sides: q depends only on the shared stats).
 template <typename T>
 __global__ __launch_bounds__(256) void prep_points_kernel(
     const float* __restrict__ X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad, int64_t Kp,
-    double c2, const float* __restrict__ stats, int side, T* __restrict__ hi, T* __restrict__ lo,
-    float* __restrict__ qinv2) {
+    double c2, const float* __restrict__ stats, int side, int pshift, T* __restrict__ hi,
+    T* __restrict__ lo, float* __restrict__ qinv2) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const double t = sqrt(2.0 * c2);
-  const float amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(c2 * stats[1])), 1.0f);
+  const float amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(c2 * stats[1])),
+                           fmaxf(1.0f, (float)pshift));
   const float q = split_scale(amax);
   if (blockIdx.x == 0 && threadIdx.x == 0 && qinv2) *qinv2 = 1.0f / (q * q);
   if (row >= rows_pad) return;
@@ -105,6 +108,7 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
     if (k < d) v = qt * (double)x[k];
     else if (k == d) v = side == 0 ? qnu : (double)q;
     else if (k == d + 1) v = side == 0 ? (double)q : qnu;
+    else if (k == d + 2 && pshift > 0) v = side == 0 ? (double)q : (double)q * pshift;
     else v = 0.0;
     T a, b;
     Elem<T>::split((float)v, a, b);
@@ -115,19 +119,97 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
 
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                       int64_t Kp, double c2, const float* stats, int side, T* hi, T* lo,
-                       float* qinv2, hipStream_t st) {
+                       int64_t Kp, double c2, const float* stats, int side, int pshift, T* hi,
+                       T* lo, float* qinv2, hipStream_t st) {
   prep_points_kernel<T><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, Kp, c2,
-                                                               stats, side, hi, lo, qinv2);
+                                                               stats, side, pshift, hi, lo, qinv2);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 template hipError_t prep_points<_Float16>(const float*, int64_t, int64_t, int64_t, int64_t,
-                                          int64_t, double, const float*, int, _Float16*,
+                                          int64_t, double, const float*, int, int, _Float16*,
                                           _Float16*, float*, hipStream_t);
 template hipError_t prep_points<__bf16>(const float*, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                        double, const float*, int, __bf16*, __bf16*, float*,
+                                        double, const float*, int, int, __bf16*, __bf16*, float*,
                                         hipStream_t);
+
+// ------------------------------------------- right-hand sides for the MFMA accumulation
+// colmax[c] = max_i |V[i, c]| (atomic max on the float bit pattern; colmax starts at 0).
+__global__ __launch_bounds__(256) void vec_colmax_kernel(const float* __restrict__ V, int64_t n,
+                                                         int64_t m, int64_t ldv,
+                                                         float* __restrict__ colmax) {
+  __shared__ float sh[256];
+  const int tid = threadIdx.x;
+  for (int64_t cbase = 0; cbase < m; cbase += 256) {
+    const int64_t mc = m - cbase < 256 ? m - cbase : 256;
+    const int rif = (int)(256 / mc);
+    const int ro = tid / (int)mc;
+    const int64_t c = cbase + tid % mc;
+    float mx = 0.0f;
+    if (ro < rif)
+      for (int64_t i = (int64_t)blockIdx.x * rif + ro; i < n; i += (int64_t)gridDim.x * rif)
+        mx = fmaxf(mx, fabsf(V[i * ldv + c]));
+    sh[tid] = ro < rif ? mx : 0.0f;
+    __syncthreads();
+    if (tid < mc) {
+      float r = 0.0f;
+      for (int k = 0; k < rif; ++k) r = fmaxf(r, sh[k * mc + tid]);
+      atomic_max_pos(&colmax[cbase + tid], r);
+    }
+    __syncthreads();
+  }
+}
+
+// Vt_hi/Vt_lo[c][j] = split(qv_c V[j, c]) (FP16, c < mpad, j < rows_pad, zero padded) with
+// qv_c = split_scale(colmax[c]); V[j, c] is overwritten by the value the split represents
+// exactly, (hi + lo) / qv_c, so later updates use the vector the products saw.
+// vscale[c] = 1 / (qv_c 2^pshift) undoes both the V scale and the 2^pshift of the kernel.
+__global__ __launch_bounds__(256) void vec_split_t_kernel(float* __restrict__ V, int64_t n,
+                                                          int64_t m, int64_t ldv, int64_t rows_pad,
+                                                          int64_t mpad,
+                                                          const float* __restrict__ colmax,
+                                                          int pshift, _Float16* __restrict__ hi,
+                                                          _Float16* __restrict__ lo,
+                                                          float* __restrict__ vscale) {
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t j0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  // load V[j0 + yy][c0 + tx]
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t j = j0 + yy, c = c0 + tx;
+    tile[yy][tx] = (j < n && c < m) ? V[j * ldv + c] : 0.0f;
+  }
+  __syncthreads();
+  // write Vt[c0 + yy][j0 + tx] (coalesced along j)
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int64_t c = c0 + yy, j = j0 + tx;
+    if (c < mpad && j < rows_pad) {
+      const float qv = c < m ? split_scale(colmax[c]) : 1.0f;
+      const float v = tile[tx][yy] * qv;
+      _Float16 h, l;
+      Elem<_Float16>::split(v, h, l);
+      hi[c * rows_pad + j] = h;
+      lo[c * rows_pad + j] = l;
+      if (j < n && c < m) V[j * ldv + c] = ((float)h + (float)l) / qv;
+      if (j == 0) vscale[c] = c < m ? 1.0f / (qv * ldexpf(1.0f, pshift)) : 0.0f;
+    }
+  }
+}
+
+hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
+                       float* colmax, int pshift, _Float16* hi, _Float16* lo, float* vscale,
+                       hipStream_t st) {
+  hipError_t e = fill_f32(colmax, m, 0.0f, st);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(n, 256)));
+  vec_colmax_kernel<<<blocks, 256, 0, st>>>(V, n, m, ldv, colmax);
+  KRR_LAUNCH_CHECK();
+  dim3 grid(ceil_div(rows_pad, 32), ceil_div(mpad, 32));
+  vec_split_t_kernel<<<grid, 256, 0, st>>>(V, n, m, ldv, rows_pad, mpad, colmax, pshift, hi, lo,
+                                           vscale);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
 
 // FP64 points for the plain FP64 path: X64 (rows_pad x dp, zero padded) and nu (rows_pad).
 __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __restrict__ X,

@@ -45,7 +45,8 @@ class PCGReport(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged_cols", _i32), ("breakdown_cols", _i32),
                 ("refine_steps", _i32), ("relres_rec", ctypes.POINTER(_dbl)),
                 ("relres_true", ctypes.POINTER(_dbl)), ("history", ctypes.POINTER(_dbl)),
-                ("history_cap", _i32), ("history_len", _i32)]
+                ("history_cap", _i32), ("history_len", _i32), ("matmat_calls", _i32),
+                ("matmat_ms", _dbl)]
 
 
 _lib = None
@@ -204,6 +205,8 @@ class SolveReport:
     relres_rec: list
     relres_true: list
     history: list
+    matmat_calls: int = 0
+    matmat_ms: float = 0.0
 
 
 def pcg_solve(X: torch.Tensor, sigma: float, lam: float, Ut: torch.Tensor | None,
@@ -252,7 +255,8 @@ def pcg_solve(X: torch.Tensor, sigma: float, lam: float, Ut: torch.Tensor | None
                              ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream())
     report = SolveReport(st, rep.iters, rep.converged_cols, rep.breakdown_cols, rep.refine_steps,
                          [rec[i] for i in range(m)], [tru[i] for i in range(m)],
-                         [hist[i] for i in range(rep.history_len)])
+                         [hist[i] for i in range(rep.history_len)], rep.matmat_calls,
+                         rep.matmat_ms)
     if raise_on_error and st not in (OK,):
         if st in (E_NO_CONV, E_BREAKDOWN):
             raise KRRError(st, last_error(), report)
