@@ -48,6 +48,16 @@ template <> struct Elem<__bf16> {
   }
 };
 
+// Scale of the point operands: 1 when the largest entry already lies in [2^-3, 2^14]
+// (products then need no rescaling), else the power of two of split_scale.
+__device__ inline float point_scale(float amax) {
+  if (amax >= 0.125f && amax <= SPLIT_TARGET) return 1.0f;
+  if (!(amax > 0.0f) || !(amax < 3.0e38f)) return 1.0f;
+  int e;
+  frexpf(SPLIT_TARGET / amax, &e);
+  return ldexpf(1.0f, e - 1);
+}
+
 // Power of two q with q * amax <= SPLIT_TARGET (amax > 0 finite), else 1.
 __device__ inline float split_scale(float amax) {
   if (!(amax > 0.0f) || !(amax < 3.0e38f)) return 1.0f;

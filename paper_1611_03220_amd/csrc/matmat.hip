@@ -18,6 +18,7 @@ namespace krr {
 constexpr int MM_BM = 64;   // rows per block (4 waves x 16)
 constexpr int MM_BN = 64;   // columns per tile
 constexpr int MM_FLUSH = 4; // tiles between FP32 -> FP64 flushes (16 terms per lane)
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
 
 template <typename T, int KS, int MC, bool DERIV>
 __global__ __launch_bounds__(256) void matmat_mixed_kernel(
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(256) void matmat_mixed_kernel(
 #pragma unroll
     for (int c = 0; c < MC; ++c) { acc[r][c] = 0.0f; acc64[r][c] = 0.0; }
 
-  uint4 rh[CPT], rl[CPT];
+  u32x4v rh[CPT], rl[CPT];
   float rv[VPT];
   auto gload = [&](int64_t t) {
     const int64_t j0 = t * MM_BN;
@@ -71,8 +72,8 @@ __global__ __launch_bounds__(256) void matmat_mixed_kernel(
       if (ch < CHUNKS) {
         const int row = ch / (KP / 8), col8 = ch % (KP / 8);
         const int64_t off = (j0 + row) * KP + col8 * 8;
-        rh[u] = *reinterpret_cast<const uint4*>(Bhi + off);
-        rl[u] = *reinterpret_cast<const uint4*>(Blo + off);
+        rh[u] = *reinterpret_cast<const u32x4v*>(Bhi + off);
+        rl[u] = *reinterpret_cast<const u32x4v*>(Blo + off);
       }
     }
 #pragma unroll
@@ -90,8 +91,8 @@ __global__ __launch_bounds__(256) void matmat_mixed_kernel(
       const int ch = tid + 256 * u;
       if (ch < CHUNKS) {
         const int row = ch / (KP / 8), col8 = ch % (KP / 8);
-        *reinterpret_cast<uint4*>(&sBh[buf][row * LDS_K + col8 * 8]) = rh[u];
-        *reinterpret_cast<uint4*>(&sBl[buf][row * LDS_K + col8 * 8]) = rl[u];
+        *reinterpret_cast<u32x4v*>(&sBh[buf][row * LDS_K + col8 * 8]) = rh[u];
+        *reinterpret_cast<u32x4v*>(&sBl[buf][row * LDS_K + col8 * 8]) = rl[u];
       }
     }
 #pragma unroll
@@ -237,41 +238,61 @@ template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const Mixed
 // Same product as above, with the accumulation over j on MFMA too. Each wave owns 32 rows
 // (two 16-row blocks) and reads 32-column halves ("j-pairs") of the 64-column tile:
 //   S^T[j][i] = <b_j, a_i> on MFMA with the column operand b_j (from LDS) as A and the
-//   row operand a_i (registers) as B, so lane l holds S^T[4(l/16)+r][l%16]: rows i = l%16
-//   and four consecutive j -- exactly the A-operand layout of the next product once two
-//   16-column blocks are concatenated along k;
-//   P' = exp2(S / q^2) = k 2^PSHIFT (PSHIFT = 0: no shift, see kernels.hpp), split
-//   into FP16 hi + lo (both rounded to nearest, so the error is unbiased) and multiplied on
-//   MFMA with the FP16
-//   hi/lo split of V^T (three products), FP32 accumulate, FP64 sums every MM2_FLUSH tiles.
+//   row operand a_i (registers) as B, so lane l holds S^T[4(l/16)+r][l%16]: row i = l%16
+//   and four consecutive j -- the A-operand layout of the next product once two 16-column
+//   blocks are concatenated along k;
+//   P = exp2(S / q^2) = k, split into FP16 hi + lo (both rounded to nearest: the error is
+//   unbiased), multiplied on MFMA with the FP16 hi/lo split of V^T (three products), FP32
+//   accumulate, FP64 sums every MM2_FLUSH tiles.
 // The distance products of the second j-pair are issued before the first j-pair's
-// epilogue so MFMA and VALU work of one wave overlap.
+// epilogue so one wave's MFMA and VALU work overlap. LDS tiles are XOR-swizzled (no
+// padding, no bank conflicts on the fragment reads). When q = 1 (operands already in
+// FP16's comfortable range) the kernel skips the 1/q^2 scaling: a uniform branch at entry
+// selects that instantiation of the body.
 constexpr int MM2_BM = 128;   // rows per block (4 waves x 32)
 constexpr int MM2_FLUSH = 2;  // tiles between FP32 -> FP64 flushes
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-template <int KS, int NCT, bool DERIV>
-__global__ __launch_bounds__(256) void matmat_f16pv_kernel(
-    const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+// p - (float)h.x and p - (float)h.y in one mixed-precision FMA each
+__device__ inline float sub_half_lo(half2v h, float p) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(p));
+  return r;
+}
+__device__ inline float sub_half_hi(half2v h, float p) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(p));
+  return r;
+}
+
+template <int KS, int NCT>
+struct PVSmem {
+  static constexpr int KP = KS * 32;
+  _Float16 Bh[2][MM_BN * KP];
+  _Float16 Bl[2][MM_BN * KP];
+  _Float16 Vh[2][NCT * 16 * MM_BN];
+  _Float16 Vl[2][NCT * 16 * MM_BN];
+};
+
+template <int KS, int NCT, bool UNIT, bool DERIV>
+__device__ __forceinline__ void f16pv_body(
+    PVSmem<KS, NCT>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
-    const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split) {
+    float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
+    int tiles_per_split) {
   constexpr int KP = KS * 32;
-  constexpr int LDS_K = KP + 8;
-  constexpr int BCH = MM_BN * KP / 8;       // 16-byte chunks per B operand tile
+  constexpr int CPR = KP / 8;                 // 16-byte chunks per B row
+  constexpr int SWZ = (KS == 1 || KS == 3) ? 3 : 7;
+  constexpr int BCH = MM_BN * CPR;
   constexpr int BCPT = (BCH + 255) / 256;
-  constexpr int VR = NCT * 16;              // V^T rows (columns of V) per tile
-  constexpr int LDS_J = MM_BN + 8;          // padded V^T row (halves)
-  constexpr int VCH = VR * MM_BN / 8;       // 16-byte chunks per V^T tile
+  constexpr int VR = NCT * 16;
+  constexpr int VCH = VR * MM_BN / 8;
   constexpr int VCPT = (VCH + 255) / 256;
-
-  __shared__ __attribute__((aligned(16))) _Float16 sBh[2][MM_BN * LDS_K];
-  __shared__ __attribute__((aligned(16))) _Float16 sBl[2][MM_BN * LDS_K];
-  __shared__ __attribute__((aligned(16))) _Float16 sVh[2][VR * LDS_J];
-  __shared__ __attribute__((aligned(16))) _Float16 sVl[2][VR * LDS_J];
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -279,9 +300,7 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
   const int64_t ntiles = ceil_div(n2, MM_BN);
   const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
-  const float qinv2 = *qinv2_ptr;
 
-  // row operands (B operand of the distance product) for the two 16-row blocks
   half8 ah[2][KS], al[2][KS];
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
@@ -303,72 +322,66 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
       for (int r = 0; r < 4; ++r) acc64[ib][ct][r] = 0.0;
     }
 
-  uint4 rbh[BCPT], rbl[BCPT], rvh[VCPT], rvl[VCPT];
-  auto gload = [&](int64_t t) {
-    const int64_t j0 = t * MM_BN;
-#pragma unroll
-    for (int u = 0; u < BCPT; ++u) {
-      const int ch = tid + 256 * u;
-      if (ch < BCH) {
-        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
-        const int64_t off = (j0 + row) * KP + col8 * 8;
-        rbh[u] = *reinterpret_cast<const uint4*>(Bhi + off);
-        rbl[u] = *reinterpret_cast<const uint4*>(Blo + off);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < VCPT; ++u) {
-      const int ch = tid + 256 * u;
-      if (ch < VCH) {
-        const int c = ch / (MM_BN / 8), j8 = ch % (MM_BN / 8);
-        const int64_t off = (int64_t)c * ldvt + j0 + j8 * 8;
-        rvh[u] = *reinterpret_cast<const uint4*>(Vth + off);
-        rvl[u] = *reinterpret_cast<const uint4*>(Vtl + off);
-      }
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < BCPT; ++u) {
-      const int ch = tid + 256 * u;
-      if (ch < BCH) {
-        const int row = ch / (KP / 8), col8 = ch % (KP / 8);
-        *reinterpret_cast<uint4*>(&sBh[buf][row * LDS_K + col8 * 8]) = rbh[u];
-        *reinterpret_cast<uint4*>(&sBl[buf][row * LDS_K + col8 * 8]) = rbl[u];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < VCPT; ++u) {
-      const int ch = tid + 256 * u;
-      if (ch < VCH) {
-        const int c = ch / (MM_BN / 8), j8 = ch % (MM_BN / 8);
-        *reinterpret_cast<uint4*>(&sVh[buf][c * LDS_J + j8 * 8]) = rvh[u];
-        *reinterpret_cast<uint4*>(&sVl[buf][c * LDS_J + j8 * 8]) = rvl[u];
-      }
-    }
-  };
-  // distance products of j-pair jp (columns 32 jp .. 32 jp + 31 of the tile in `buf`)
-  auto dist = [&](int buf, int jp, f32x4 (&S)[2][2]) {
-#pragma unroll
-    for (int jb = 0; jb < 2; ++jb)
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib) S[jb][ib] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // per-thread global sources (advance by one tile per step) and LDS destinations.
+  // B tiles have 8 KP chunks of 16 bytes (a multiple of 256: every thread loads BCPT);
+  // V^T tiles have 128 NCT chunks (threads below VCH load one each).
+  static_assert(BCH % 256 == 0 && VCPT == 1, "tile shape");
+  const _Float16* gbh = Bhi + (t_begin * MM_BN) * KP;
+  const _Float16* gbl = Blo + (t_begin * MM_BN) * KP;
+  static_assert(BCPT <= 4, "at most four B chunks per thread");
+  int gbo[4] = {0, 0, 0, 0}, sbo[4] = {0, 0, 0, 0};
+  // constant indices only (keeps the per-thread arrays in registers)
+#define KRR_PV_INIT(u)                                                     \
+  if (u < BCPT) {                                                          \
+    const int ch = tid + 256 * u;                                          \
+    const int row = ch / CPR, col = ch % CPR;                              \
+    gbo[u] = row * KP + col * 8;                                           \
+    sbo[u] = row * KP + ((col ^ (row & SWZ)) * 8);                         \
+  }
+  KRR_PV_INIT(0) KRR_PV_INIT(1) KRR_PV_INIT(2) KRR_PV_INIT(3)
+#undef KRR_PV_INIT
+  const bool vload = tid < VCH;
+  const int vch = vload ? tid : 0;
+  const int vc = vch / (MM_BN / 8), vj8 = vch % (MM_BN / 8);
+  const _Float16* gvh = Vth + (int64_t)vc * ldvt + t_begin * MM_BN + vj8 * 8;
+  const _Float16* gvl = Vtl + (int64_t)vc * ldvt + t_begin * MM_BN + vj8 * 8;
+  // 8-byte units of a V^T row are swizzled by the row index (16 units per row)
+  const int svo0 = vc * MM_BN + (((2 * vj8) ^ (vc & 15)) * 4);
+  const int svo1 = vc * MM_BN + (((2 * vj8 + 1) ^ (vc & 15)) * 4);
+  // prefetch registers as native vectors in named variables (an array of HIP's uint4
+  // struct is left in scratch memory by the compiler)
+  u32x4 rbh0 = {}, rbh1 = {}, rbh2 = {}, rbh3 = {}, rbl0 = {}, rbl1 = {}, rbl2 = {}, rbl3 = {};
+  u32x4 rvh = {}, rvl = {};
+#define KRR_PV_LD(u)                                                       \
+  if (u < BCPT) {                                                          \
+    rbh##u = *reinterpret_cast<const u32x4*>(gbh + gbo[u]);                \
+    rbl##u = *reinterpret_cast<const u32x4*>(gbl + gbo[u]);                \
+  }
+#define KRR_PV_ST(u, b)                                                    \
+  if (u < BCPT) {                                                          \
+    *reinterpret_cast<u32x4*>(&sm.Bh[b][sbo[u]]) = rbh##u;                 \
+    *reinterpret_cast<u32x4*>(&sm.Bl[b][sbo[u]]) = rbl##u;                 \
+  }
+  // distance products of j-pair jp (tile columns 32 jp .. 32 jp + 31)
+  auto dist = [&](int buf, int jp, f32x4 (&S)[2][2]) __attribute__((always_inline)) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       half8 bh[2], bl[2];
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb) {
-        const _Float16* p = &sBh[buf][(32 * jp + 16 * jb + li) * LDS_K + ks * 32 + 8 * lg];
-        bh[jb] = *reinterpret_cast<const half8*>(p);
-        bl[jb] = *reinterpret_cast<const half8*>(
-            &sBl[buf][(32 * jp + 16 * jb + li) * LDS_K + ks * 32 + 8 * lg]);
+        const int row = 32 * jp + 16 * jb + li;
+        const int o = row * KP + (((4 * ks + lg) ^ (row & SWZ)) * 8);
+        bh[jb] = *reinterpret_cast<const half8*>(&sm.Bh[buf][o]);
+        bl[jb] = *reinterpret_cast<const half8*>(&sm.Bl[buf][o]);
       }
       // four independent accumulation chains, small terms first
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
-          S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[jb], ah[ib][ks], S[jb][ib], 0, 0, 0);
+        for (int ib = 0; ib < 2; ++ib) {
+          const f32x4 c0 = ks == 0 ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : S[jb][ib];
+          S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl[jb], ah[ib][ks], c0, 0, 0, 0);
+        }
 #pragma unroll
       for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
@@ -382,15 +395,16 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
     }
   };
   // exp2, split and accumulate j-pair jp on MFMA
-  auto epi = [&](int buf, int jp, const f32x4 (&S)[2][2]) {
+  auto epi = [&](int buf, int jp, const f32x4 (&S)[2][2]) __attribute__((always_inline)) {
     half8 vh[NCT], vl[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
       const int c = 16 * ct + li;
-      const half4 h0 = *reinterpret_cast<const half4*>(&sVh[buf][c * LDS_J + 32 * jp + 4 * lg]);
-      const half4 h1 = *reinterpret_cast<const half4*>(&sVh[buf][c * LDS_J + 32 * jp + 16 + 4 * lg]);
-      const half4 l0 = *reinterpret_cast<const half4*>(&sVl[buf][c * LDS_J + 32 * jp + 4 * lg]);
-      const half4 l1 = *reinterpret_cast<const half4*>(&sVl[buf][c * LDS_J + 32 * jp + 16 + 4 * lg]);
+      const int u0 = ((8 * jp + lg) ^ (c & 15)) * 4, u1 = ((8 * jp + 4 + lg) ^ (c & 15)) * 4;
+      const half4 h0 = *reinterpret_cast<const half4*>(&sm.Vh[buf][c * MM_BN + u0]);
+      const half4 h1 = *reinterpret_cast<const half4*>(&sm.Vh[buf][c * MM_BN + u1]);
+      const half4 l0 = *reinterpret_cast<const half4*>(&sm.Vl[buf][c * MM_BN + u0]);
+      const half4 l1 = *reinterpret_cast<const half4*>(&sm.Vl[buf][c * MM_BN + u1]);
       vh[ct] = half8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
       vl[ct] = half8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
     }
@@ -401,15 +415,17 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
       for (int jb = 0; jb < 2; ++jb)
 #pragma unroll
         for (int r = 0; r < 4; r += 2) {
-          float l2a = S[jb][ib][r] * qinv2, l2b = S[jb][ib][r + 1] * qinv2;
+          float l2a = S[jb][ib][r], l2b = S[jb][ib][r + 1];
+          if (!UNIT) { l2a *= qinv2; l2b *= qinv2; }
           float pa = __builtin_amdgcn_exp2f(l2a), pb = __builtin_amdgcn_exp2f(l2b);
           if (DERIV) {
-            pa *= ((float)PSHIFT - l2a) * dscale;
-            pb *= ((float)PSHIFT - l2b) * dscale;
+            pa *= -l2a * dscale;
+            pb *= -l2b * dscale;
           }
-          // round-to-nearest split (v_cvt_pk_f16_f32): unbiased, |error| <= 2^-22 |p|
+          // round-to-nearest split: |(hi + lo) - p| <= 2^-22 |p| (2^-25 absolute below the
+          // FP16 normal range), unbiased
           const half2v h = half2v{(_Float16)pa, (_Float16)pb};
-          const half2v l = half2v{(_Float16)(pa - (float)h[0]), (_Float16)(pb - (float)h[1])};
+          const half2v l = half2v{(_Float16)sub_half_lo(h, pa), (_Float16)sub_half_hi(h, pb)};
           ph[4 * jb + r] = h[0];
           ph[4 * jb + r + 1] = h[1];
           pl[4 * jb + r] = l[0];
@@ -425,14 +441,39 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
   };
 
   if (t_begin < t_end) {
-    gload(t_begin);
-    lstore(0);
+    KRR_PV_LD(0) KRR_PV_LD(1) KRR_PV_LD(2) KRR_PV_LD(3)
+    gbh += MM_BN * KP;
+    gbl += MM_BN * KP;
+    if (vload) {
+      rvh = *reinterpret_cast<const u32x4*>(gvh);
+      rvl = *reinterpret_cast<const u32x4*>(gvl);
+    }
+    gvh += MM_BN;
+    gvl += MM_BN;
+    KRR_PV_ST(0, 0) KRR_PV_ST(1, 0) KRR_PV_ST(2, 0) KRR_PV_ST(3, 0)
+    if (vload) {
+      *reinterpret_cast<u32x2*>(&sm.Vh[0][svo0]) = u32x2{rvh.x, rvh.y};
+      *reinterpret_cast<u32x2*>(&sm.Vh[0][svo1]) = u32x2{rvh.z, rvh.w};
+      *reinterpret_cast<u32x2*>(&sm.Vl[0][svo0]) = u32x2{rvl.x, rvl.y};
+      *reinterpret_cast<u32x2*>(&sm.Vl[0][svo1]) = u32x2{rvl.z, rvl.w};
+    }
   }
   __syncthreads();
   int since_flush = 0;
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int buf = (int)((t - t_begin) & 1);
-    if (t + 1 < t_end) gload(t + 1);
+    const bool more = t + 1 < t_end;
+    if (more) {
+    KRR_PV_LD(0) KRR_PV_LD(1) KRR_PV_LD(2) KRR_PV_LD(3)
+    gbh += MM_BN * KP;
+    gbl += MM_BN * KP;
+    if (vload) {
+      rvh = *reinterpret_cast<const u32x4*>(gvh);
+      rvl = *reinterpret_cast<const u32x4*>(gvl);
+    }
+    gvh += MM_BN;
+    gvl += MM_BN;
+    }
     f32x4 S0[2][2], S1[2][2];
     dist(buf, 0, S0);
     dist(buf, 1, S1);
@@ -449,9 +490,19 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
           acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         }
     }
-    if (t + 1 < t_end) lstore(buf ^ 1);
+    if (more) {
+    KRR_PV_ST(0, buf ^ 1) KRR_PV_ST(1, buf ^ 1) KRR_PV_ST(2, buf ^ 1) KRR_PV_ST(3, buf ^ 1)
+    if (vload) {
+      *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo0]) = u32x2{rvh.x, rvh.y};
+      *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo1]) = u32x2{rvh.z, rvh.w};
+      *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo0]) = u32x2{rvl.x, rvl.y};
+      *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo1]) = u32x2{rvl.z, rvl.w};
+    }
+    }
     __syncthreads();
   }
+#undef KRR_PV_LD
+#undef KRR_PV_ST
   // lane holds OUT[i0 + 16 ib + 4 lg + r][16 ct + li]
   double* pout = part + (int64_t)blockIdx.y * part_stride;
 #pragma unroll
@@ -468,6 +519,24 @@ __global__ __launch_bounds__(256) void matmat_f16pv_kernel(
         }
     }
   }
+}
+
+template <int KS, int NCT, bool DERIV>
+__global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16pv_kernel(
+    const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
+    const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
+    const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
+    const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
+    int64_t part_stride, int tiles_per_split) {
+  __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT> sm;
+  const float qinv2 = *qinv2_ptr;
+  if (qinv2 == 1.0f)
+    f16pv_body<KS, NCT, true, DERIV>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                     qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+  else
+    f16pv_body<KS, NCT, false, DERIV>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                      qinv2, dscale, part, ldp, part_stride, tiles_per_split);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,

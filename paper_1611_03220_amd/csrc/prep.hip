@@ -5,7 +5,8 @@
 // which becomes ONE inner product of augmented rows
 //   a_i = q [sqrt(2c) x_i, -c nu_i, 1],   b_j = q [sqrt(2c) x_j, 1, -c nu_j],
 // so that <a_i, b_j> = q^2 log2 k(x_i, x_j). q is a power of two that keeps every entry
-// below 2^14, so the FP16 hi/lo split loses no range (exact scaling, undone in the epilogue).
+// below 2^14, so the FP16 hi/lo split loses no range (exact scaling, undone in the
+// epilogue); q = 1 whenever the entries already lie in [2^-3, 2^14].
 #include "kernels.hpp"
 
 namespace krr {
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
   const double t = sqrt(2.0 * c2);
   const float amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(c2 * stats[1])),
                            fmaxf(1.0f, (float)pshift));
-  const float q = split_scale(amax);
+  const float q = point_scale(amax);
   if (blockIdx.x == 0 && threadIdx.x == 0 && qinv2) *qinv2 = 1.0f / (q * q);
   if (row >= rows_pad) return;
   T* h = hi + row * Kp;
