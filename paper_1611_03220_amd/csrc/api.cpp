@@ -62,7 +62,8 @@ bool use_pv(int prec, int64_t d) {
 int64_t kp_for(int prec, int64_t d) {
   return use_pv(prec, d) ? round_up(d + 2 + (PSHIFT > 0), K_STEP) : kp_for(d);
 }
-int64_t dp_for(int64_t d) { return round_up(d, 32); }
+// FP64 point width: multiples of 8 up to 128 (FP64 MFMA kernel), else of 32 (VALU kernel)
+int64_t dp_for(int64_t d) { return round_up(d, 8) <= 128 ? round_up(d, 8) : round_up(d, 32); }
 
 // Split of the column sweep over blockIdx.y so that small row counts still fill the chip.
 int choose_nsplit(int64_t n1, int64_t n2) {

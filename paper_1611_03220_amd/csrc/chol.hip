@@ -14,59 +14,53 @@ namespace krr {
 constexpr int NB = 64;
 
 // Factor the diagonal block at (k0, k0) of A (lda) in place (lower, strict upper zeroed)
-// and write its inverse into Ainv (same offsets, ld lda_inv). *info receives the 1-based
-// global index of the first non-positive (or non-finite) pivot if it is still 0.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
-                                                         int64_t k0, double* __restrict__ Ainv,
-                                                         int64_t ldi, int* __restrict__ info) {
+// and write its inverse into Ainv (same offsets, ld lda_inv). One wave: lane r owns row r.
+// *info receives the 1-based global index of the first non-positive (or non-finite) pivot
+// if it is still 0.
+__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
+                                                        int64_t k0, double* __restrict__ Ainv,
+                                                        int64_t ldi, int* __restrict__ info) {
   __shared__ double L[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    L[r][c] = (c <= r) ? A[(k0 + r) * lda + k0 + c] : 0.0;
-  }
+  const int r = threadIdx.x;
+  for (int i = 0; i < NB; ++i) L[i][r] = (r <= i) ? A[(k0 + i) * lda + k0 + r] : 0.0;
   __syncthreads();
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      const double dj = L[j][j];
-      if (!(dj > 0.0) || !(dj < INFINITY)) {
-        if (*info == 0) *info = (int)(k0 + j + 1);
-      }
-      L[j][j] = sqrt(dj);
+    const double dj = L[j][j];
+    if (r == 0 && (!(dj > 0.0) || !(dj < INFINITY)) && *info == 0) *info = (int)(k0 + j + 1);
+    const double ljj = sqrt(dj);
+    double lrj = 0.0;
+    if (r > j) {
+      lrj = L[r][j] / ljj;
+      L[r][j] = lrj;
     }
     __syncthreads();
-    const double piv = L[j][j];
-    for (int r = j + 1 + tid; r < NB; r += 256) L[r][j] /= piv;
-    __syncthreads();
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e / NB, c = e % NB;
-      if (c > j && r >= c) L[r][c] -= L[r][j] * L[c][j];
-    }
+    if (r == j) L[j][j] = ljj;
+    if (r > j)
+      for (int c = j + 1; c <= r; ++c) L[r][c] -= lrj * L[c][j];
     __syncthreads();
   }
-  // inverse of the lower triangular block, one column per thread
-  if (tid < NB) {
-    const int c = tid;
-    for (int r = 0; r < NB; ++r) {
-      if (r < c) { X[r][c] = 0.0; continue; }
-      double s = (r == c) ? 1.0 : 0.0;
-      for (int k = c; k < r; ++k) s -= L[r][k] * X[k][c];
-      X[r][c] = s / L[r][r];
+  // inverse of the lower triangular block: lane c computes column c by forward substitution
+  {
+    const int c = r;
+    for (int i = 0; i < NB; ++i) {
+      if (i < c) { X[i][c] = 0.0; continue; }
+      double sacc = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) sacc -= L[i][k] * X[k][c];
+      X[i][c] = sacc / L[i][i];
     }
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e / NB, c = e % NB;
-    A[(k0 + r) * lda + k0 + c] = L[r][c];
-    Ainv[(k0 + r) * ldi + k0 + c] = X[r][c];
+  for (int i = 0; i < NB; ++i) {
+    A[(k0 + i) * lda + k0 + r] = L[i][r];
+    Ainv[(k0 + i) * ldi + k0 + r] = X[i][r];
   }
 }
 
 // G (s_pad x s_pad, lower part used) -> C in place; Cinv diagonal blocks filled.
 hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st) {
   for (int64_t k0 = 0; k0 < s_pad; k0 += NB) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(G, s_pad, k0, Cinv, s_pad, info);
+    potrf_diag_kernel<<<1, 64, 0, st>>>(G, s_pad, k0, Cinv, s_pad, info);
     KRR_LAUNCH_CHECK();
     const int64_t rest = s_pad - k0 - NB;
     if (rest <= 0) break;

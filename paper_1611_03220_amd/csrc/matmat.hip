@@ -666,6 +666,115 @@ __global__ __launch_bounds__(256) void matmat_f64_kernel(
     }
 }
 
+// FP64 kernel product on FP64 MFMA (16x16x4). Lane layout (gfx950): A operand lane l holds
+// A[l%16][l/16], B operand B[l/16][l%16], result register r holds C[l/16 + 4r][l%16].
+// Each wave owns 16 rows i whose coordinates stay in registers as the B operand; the
+// column points x_j stream through LDS in 32-point tiles. Per 16-column block:
+//   G^T[j][i] = <x_j, x_i> (KD MFMAs), D = nu_i + nu_j - 2 G, k = exp(-D c) (FP64, VALU),
+//   OUT[i][:] += sum_j k V[j][:] on MFMA with k as the A operand (contraction over 4 j per
+//   MFMA: register r of G^T supplies j = l/16 + 4r), FP64 accumulation throughout.
+constexpr int F64M_TJ = 32;  // columns per LDS tile
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+template <int KD, int NCT>
+__global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
+    const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
+    const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
+    int64_t n2, int64_t m, int c0, double c, int deriv, double dscale, double* __restrict__ part,
+    int64_t ldp, int64_t part_stride, int tiles_per_split) {
+  constexpr int DP = 4 * KD;
+  constexpr int LX = DP + 1;           // padded row of the column tile (doubles)
+  constexpr int VC = 16 * NCT;
+  constexpr int LV = VC + 1;
+  __shared__ double sX[2][F64M_TJ * LX];
+  __shared__ double sV[2][F64M_TJ * LV];
+  __shared__ double sN[2][F64M_TJ];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int64_t ntiles = ceil_div(n2, F64M_TJ);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+
+  double xi[KD];
+#pragma unroll
+  for (int sk = 0; sk < KD; ++sk) xi[sk] = Xa[(i0 + li) * DP + 4 * sk + lg];
+  const double nui = nua[i0 + li];
+  d4v acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  auto load_tile = [&](int64_t t, int buf) __attribute__((always_inline)) {
+    const int64_t j0 = t * F64M_TJ;
+    for (int e = tid; e < F64M_TJ * DP; e += 256) {
+      const int r = e / DP, k = e % DP;
+      sX[buf][r * LX + k] = Xb[(j0 + r) * DP + k];
+    }
+    for (int e = tid; e < F64M_TJ * VC; e += 256) {
+      const int r = e / VC, cc = e % VC;
+      const int64_t j = j0 + r;
+      sV[buf][r * LV + cc] = (j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
+    }
+    if (tid < F64M_TJ) sN[buf][tid] = nub[j0 + tid];
+  };
+
+  if (t_begin < t_end) load_tile(t_begin, 0);
+  __syncthreads();
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int buf = (int)((t - t_begin) & 1);
+    if (t + 1 < t_end) load_tile(t + 1, buf ^ 1);
+#pragma unroll
+    for (int jb = 0; jb < F64M_TJ / 16; ++jb) {
+      d4v g = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sk = 0; sk < KD; ++sk) {
+        const double a = sX[buf][(16 * jb + li) * LX + 4 * sk + lg];
+        g = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xi[sk], g, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = 16 * jb + lg + 4 * r;
+        double D = nui + sN[buf][jj] - 2.0 * g[r];
+        D = D > 0.0 ? D : 0.0;
+        double p = exp(-D * c);
+        if (deriv) p *= D * dscale;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li], acc[ct],
+                                                         0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t cc = c0 + 16 * ct + li;
+    if (cc < m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + lg + 4 * r;
+        if (i < n1) pout[i * ldp + cc] = acc[ct][r];
+      }
+    }
+  }
+}
+
+template <int KD>
+static void launch_f64mfma(dim3 grid, hipStream_t st, const F64Points& A, const F64Points& B,
+                           const double* V, int64_t ldv, int64_t m, int c0, int nct, double c,
+                           int deriv, double dscale, double* part, int64_t ldp,
+                           int64_t part_stride, int tps) {
+  if (nct == 1)
+    matmat_f64mfma_kernel<KD, 1><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, V, ldv, A.n, B.n, m,
+                                                       c0, c, deriv, dscale, part, ldp,
+                                                       part_stride, tps);
+  else
+    matmat_f64mfma_kernel<KD, 2><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, V, ldv, A.n, B.n, m,
+                                                       c0, c, deriv, dscale, part, ldp,
+                                                       part_stride, tps);
+}
+
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
                       int64_t part_stride, int nsplit, hipStream_t st) {
@@ -673,6 +782,27 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
   const int64_t ntiles = ceil_div(B.n, 64);
   const int tps = (int)ceil_div(ntiles, nsplit);
   dim3 grid(ceil_div(A.n, 64), nsplit);
+  if (A.dp <= 128 && A.dp % 8 == 0) {
+    // FP64 MFMA kernel: 32-point column tiles, up to 32 right-hand sides per pass
+    const int64_t ntj = ceil_div(B.n, F64M_TJ);
+    const int tpsm = (int)ceil_div(ntj, nsplit);
+    for (int64_t c0 = 0; c0 < m; c0 += 32) {
+      const int nct = m - c0 > 16 ? 2 : 1;
+      switch (A.dp / 4) {
+#define KRR_KD(K)                                                                            \
+  case K:                                                                                    \
+    launch_f64mfma<K>(grid, st, A, B, V, ldv, m, (int)c0, nct, c, deriv ? 1 : 0, dscale, part, \
+                      ldp, part_stride, tpsm);                                               \
+    break;
+        KRR_KD(2) KRR_KD(4) KRR_KD(6) KRR_KD(8) KRR_KD(10) KRR_KD(12) KRR_KD(14) KRR_KD(16)
+        KRR_KD(18) KRR_KD(20) KRR_KD(22) KRR_KD(24) KRR_KD(26) KRR_KD(28) KRR_KD(30) KRR_KD(32)
+#undef KRR_KD
+        default: return hipErrorInvalidValue;
+      }
+      KRR_LAUNCH_CHECK();
+    }
+    return hipSuccess;
+  }
   for (int64_t c0 = 0; c0 < m; c0 += 8) {
     const int mc = (int)std::min<int64_t>(8, m - c0);
     switch (mc) {

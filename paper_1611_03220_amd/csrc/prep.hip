@@ -43,33 +43,39 @@ hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st) {
   return hipSuccess;
 }
 
-// One wave per row: stats[0] = max |x_ik|, stats[1] = max ||x_i||^2 (atomic max on the
-// float bit pattern, valid for non-negative values; stats must start at 0).
+// stats[0] = max |x_ik|, stats[1] = max ||x_i||^2 over all rows: each wave walks rows with a
+// grid stride, the block reduces its four waves, one atomic max per block and statistic
+// (atomic max on the float bit pattern, valid for non-negative values; stats start at 0).
 __global__ __launch_bounds__(256) void point_stats_kernel(const float* __restrict__ X, int64_t n,
                                                           int64_t d, int64_t ldx, float* stats) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n) return;
-  const float* x = X + row * ldx;
-  double nu = 0.0;
-  float amax = 0.0f;
-  for (int64_t k = lane; k < d; k += 64) {
-    float v = x[k];
-    nu += (double)v * (double)v;
-    amax = fmaxf(amax, fabsf(v));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float amax = 0.0f, numax = 0.0f;
+  for (int64_t row = (int64_t)blockIdx.x * 4 + w; row < n; row += (int64_t)gridDim.x * 4) {
+    const float* x = X + row * ldx;
+    double nu = 0.0;
+    for (int64_t k = lane; k < d; k += 64) {
+      const float v = x[k];
+      nu += (double)v * (double)v;
+      amax = fmaxf(amax, fabsf(v));
+    }
+    nu = wave_sum(nu);
+    numax = fmaxf(numax, (float)nu);
   }
-  nu = wave_sum(nu);
   for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
-  if (lane == 0) {
-    atomic_max_pos(&stats[0], amax);
-    atomic_max_pos(&stats[1], (float)nu);
+  __shared__ float red[2][4];
+  if (lane == 0) { red[0][w] = amax; red[1][w] = numax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomic_max_pos(&stats[0], fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3])));
+    atomic_max_pos(&stats[1], fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3])));
   }
 }
 
 hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float* stats,
                        hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  point_stats_kernel<<<ceil_div(n, 4), 256, 0, st>>>(X, n, d, ldx, stats);
+  const int64_t blocks = std::min<int64_t>(1024, ceil_div(n, 4));
+  point_stats_kernel<<<blocks, 256, 0, st>>>(X, n, d, ldx, stats);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
