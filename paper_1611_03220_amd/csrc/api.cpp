@@ -54,11 +54,10 @@ constexpr int NBLK = 256;  // blocks of the column-wise reductions
 bool prec_ok(int32_t p) { return p == KRR_PREC_FP64 || p == KRR_PREC_F16X3 || p == KRR_PREC_BF16X3; }
 
 int64_t kp_for(int64_t d) { return round_up(d + 2, K_STEP); }
-// The F16X3 product with MFMA accumulation (one more augmented column, up to 32 columns
-// of V per pass) serves d + 3 <= 128; other mixed cases use the VALU-accumulate kernel.
-bool use_pv(int prec, int64_t d) {
-  return prec == KRR_PREC_F16X3 && round_up(d + 2 + (PSHIFT > 0), K_STEP) <= 128;
-}
+// The F16X3 product uses MFMA accumulation (up to 32 columns of V per pass) for every d;
+// the BF16X3 product keeps the VALU-accumulate kernel.
+// (d + 3 <= 128: row operands in registers; larger d: both operands through LDS)
+bool use_pv(int prec, int64_t d) { return prec == KRR_PREC_F16X3; }
 int64_t kp_for(int prec, int64_t d) {
   return use_pv(prec, d) ? round_up(d + 2 + (PSHIFT > 0), K_STEP) : kp_for(d);
 }
@@ -456,8 +455,8 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(KRR_E_ARG, "krr_kernel_matmat: sigma must be > 0");
   if (shift != 0.0 && n1 != n2) return fail(KRR_E_ARG, "krr_kernel_matmat: shift needs n1 == n2");
   if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_kernel_matmat: unknown precision %d", prec);
-  if (prec != KRR_PREC_FP64 && kp_for(d) > 256)
-    return fail(KRR_E_ARG, "krr_kernel_matmat: mixed precision supports d <= 254 (d=%lld)", (long long)d);
+  if (prec == KRR_PREC_BF16X3 && kp_for(d) > 256)
+    return fail(KRR_E_ARG, "krr_kernel_matmat: BF16X3 supports d <= 254 (d=%lld)", (long long)d);
   const size_t need = krr_workspace_bytes(KRR_OP_KERNEL_MATMAT, n1, n2, d, 0, m, prec);
   CHECK_ST(check_ws(ws, ws_bytes, need));
   Bump bb(ws);
@@ -679,8 +678,8 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
   if (!(o.tol > 0.0)) return fail(KRR_E_ARG, "krr_pcg_solve: tol must be > 0");
   if (o.max_iter < 1) return fail(KRR_E_ARG, "krr_pcg_solve: max_iter must be >= 1");
   if (!prec_ok(o.prec)) return fail(KRR_E_ARG, "krr_pcg_solve: unknown precision %d", o.prec);
-  if (o.prec != KRR_PREC_FP64 && kp_for(d) > 256)
-    return fail(KRR_E_ARG, "krr_pcg_solve: mixed precision supports d <= 254 (d=%lld)", (long long)d);
+  if (o.prec == KRR_PREC_BF16X3 && kp_for(d) > 256)
+    return fail(KRR_E_ARG, "krr_pcg_solve: BF16X3 supports d <= 254 (d=%lld)", (long long)d);
   if (o.use_precond) {
     if (!Ut || s < 1 || s >= n || ldu < s)
       return fail(KRR_E_ARG, "krr_pcg_solve: preconditioner needs Ut with 1 <= s < n, ldu >= s");
@@ -786,8 +785,8 @@ krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double si
   if (n < 1 || d < 1 || m < 1 || ldx < d || ld < m) return fail(KRR_E_ARG, "krr_grad: bad sizes");
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(KRR_E_ARG, "krr_grad: sigma must be > 0");
   if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_grad: unknown precision %d", prec);
-  if (prec != KRR_PREC_FP64 && kp_for(d) > 256)
-    return fail(KRR_E_ARG, "krr_grad: mixed precision supports d <= 254 (d=%lld)", (long long)d);
+  if (prec == KRR_PREC_BF16X3 && kp_for(d) > 256)
+    return fail(KRR_E_ARG, "krr_grad: BF16X3 supports d <= 254 (d=%lld)", (long long)d);
   const size_t need = krr_workspace_bytes(KRR_OP_GRAD, n, n, d, 0, m, prec);
   CHECK_ST(check_ws(ws, ws_bytes, need));
   Bump bb(ws);

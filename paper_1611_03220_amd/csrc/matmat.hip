@@ -539,6 +539,229 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16
                                       qinv2, dscale, part, ldp, part_stride, tiles_per_split);
 }
 
+// Large-d variant: the row operands no longer fit in registers, so both operands stream
+// through LDS in 32-wide k chunks. Block: 128 rows (4 waves x 32) against 64-column tiles;
+// per tile, KC = Kp/32 chunk steps accumulate S^T for the wave's 2 x 4 blocks of 16 x 16,
+// then the same epilogue as above (exp2, FP16 hi/lo split, MFMA accumulation against V^T).
+// Chunk rows are 64 bytes; their 16-byte pieces are XOR-swizzled with (row >> 1) & 3 so
+// fragment reads are conflict-free.
+constexpr int BD_BM = 128;
+template <int NCT, bool UNIT, bool DERIV>
+__device__ __forceinline__ void f16pv_bigd_body(
+    _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
+    const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
+    const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
+    float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
+    int tiles_per_split) {
+  constexpr int ACH = BD_BM * 4;            // 16-byte chunks in an A chunk-tile (per array)
+  constexpr int BCH = MM_BN * 4;
+  constexpr int VR = NCT * 16;
+  constexpr int VCH = VR * MM_BN / 8;
+  static_assert(ACH == 512 && BCH == 256 && VCH <= 256, "tile shape");
+  // LDS layout (halves): A[2][2][128*32], B[2][2][64*32], V[2][2][VR*64]
+  _Float16* sA = smem;
+  _Float16* sB = sA + 2 * 2 * BD_BM * 32;
+  _Float16* sV = sB + 2 * 2 * MM_BN * 32;
+  auto A_at = [&](int buf, int hl) { return sA + (buf * 2 + hl) * BD_BM * 32; };
+  auto B_at = [&](int buf, int hl) { return sB + (buf * 2 + hl) * MM_BN * 32; };
+  auto V_at = [&](int buf, int hl) { return sV + (buf * 2 + hl) * VR * MM_BN; };
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t blk_i0 = (int64_t)blockIdx.x * BD_BM;
+  const int64_t i0 = blk_i0 + 32 * w;
+  const int64_t ntiles = ceil_div(n2, MM_BN);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+  const int KC = KP / 32;
+  const int64_t nsteps = (t_end - t_begin) * KC;
+
+  f32x4 acc[2][NCT];
+  double acc64[2][NCT][4];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc64[ib][ct][r] = 0.0;
+    }
+  f32x4 S[4][2];
+
+  // chunk loaders: A rows blk_i0 + ch/4 (two chunks per thread), B rows j0 + ch/4 (one)
+  const int arow0 = tid >> 2, arow1 = (tid + 256) >> 2, acol = tid & 3;
+  const int brow = tid >> 2, bcol = tid & 3;
+  const int sa0 = arow0 * 32 + ((acol ^ ((arow0 >> 1) & 3)) * 8);
+  const int sa1 = arow1 * 32 + ((acol ^ ((arow1 >> 1) & 3)) * 8);
+  const int sb0 = brow * 32 + ((bcol ^ ((brow >> 1) & 3)) * 8);
+  const bool vload = tid < VCH;
+  const int vc = vload ? tid / (MM_BN / 8) : 0, vj8 = vload ? tid % (MM_BN / 8) : 0;
+  const int svo0 = vc * MM_BN + (((2 * vj8) ^ (vc & 15)) * 4);
+  const int svo1 = vc * MM_BN + (((2 * vj8 + 1) ^ (vc & 15)) * 4);
+  u32x4 ra0h = {}, ra0l = {}, ra1h = {}, ra1l = {}, rbh = {}, rbl = {}, rvh = {}, rvl = {};
+  auto gload = [&](int64_t q) __attribute__((always_inline)) {
+    const int64_t t = t_begin + q / KC;
+    const int kc = (int)(q % KC);
+    const int64_t ko = (int64_t)kc * 32;
+    ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko + acol * 8);
+    ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko + acol * 8);
+    ra1h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow1) * KP + ko + acol * 8);
+    ra1l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow1) * KP + ko + acol * 8);
+    rbh = *reinterpret_cast<const u32x4*>(Bhi + (t * MM_BN + brow) * KP + ko + bcol * 8);
+    rbl = *reinterpret_cast<const u32x4*>(Blo + (t * MM_BN + brow) * KP + ko + bcol * 8);
+    if (kc == 0 && vload) {
+      rvh = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc * ldvt + t * MM_BN + vj8 * 8);
+      rvl = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc * ldvt + t * MM_BN + vj8 * 8);
+    }
+  };
+  auto lstore = [&](int64_t q) __attribute__((always_inline)) {
+    const int buf = (int)(q & 1);
+    const int kc = (int)(q % KC);
+    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa0) = ra0h;
+    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa0) = ra0l;
+    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa1) = ra1h;
+    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa1) = ra1l;
+    *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb0) = rbh;
+    *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb0) = rbl;
+    if (kc == 0 && vload) {
+      const int vb = (int)((q / KC) & 1);
+      *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo0) = u32x2{rvh.x, rvh.y};
+      *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo1) = u32x2{rvh.z, rvh.w};
+      *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo0) = u32x2{rvl.x, rvl.y};
+      *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo1) = u32x2{rvl.z, rvl.w};
+    }
+  };
+
+  if (nsteps > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  int since_flush = 0;
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const int buf = (int)(q & 1);
+    const int kc = (int)(q % KC);
+    if (q + 1 < nsteps) gload(q + 1);
+    // fragments of this chunk: rows of the wave (B operand) and the tile's columns (A operand)
+    half8 ah[2], al[2];
+#pragma unroll
+    for (int ib = 0; ib < 2; ++ib) {
+      const int row = 32 * w + 16 * ib + li;
+      const int o = row * 32 + ((lg ^ ((row >> 1) & 3)) * 8);
+      ah[ib] = *reinterpret_cast<const half8*>(A_at(buf, 0) + o);
+      al[ib] = *reinterpret_cast<const half8*>(A_at(buf, 1) + o);
+    }
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+      const int row = 16 * jb + li;
+      const int o = row * 32 + ((lg ^ ((row >> 1) & 3)) * 8);
+      const half8 bh = *reinterpret_cast<const half8*>(B_at(buf, 0) + o);
+      const half8 bl = *reinterpret_cast<const half8*>(B_at(buf, 1) + o);
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib) {
+        const f32x4 c0 = kc == 0 ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : S[jb][ib];
+        f32x4 v = __builtin_amdgcn_mfma_f32_16x16x32_f16(bl, ah[ib], c0, 0, 0, 0);
+        v = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh, al[ib], v, 0, 0, 0);
+        S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh, ah[ib], v, 0, 0, 0);
+      }
+    }
+    if (kc == KC - 1) {
+      const int vb = (int)((q / KC) & 1);
+#pragma unroll
+      for (int jp = 0; jp < 2; ++jp) {
+        half8 vh[NCT], vl[NCT];
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int c = 16 * ct + li;
+          const int u0 = ((8 * jp + lg) ^ (c & 15)) * 4, u1 = ((8 * jp + 4 + lg) ^ (c & 15)) * 4;
+          const half4 h0 = *reinterpret_cast<const half4*>(V_at(vb, 0) + c * MM_BN + u0);
+          const half4 h1 = *reinterpret_cast<const half4*>(V_at(vb, 0) + c * MM_BN + u1);
+          const half4 l0 = *reinterpret_cast<const half4*>(V_at(vb, 1) + c * MM_BN + u0);
+          const half4 l1 = *reinterpret_cast<const half4*>(V_at(vb, 1) + c * MM_BN + u1);
+          vh[ct] = half8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+          vl[ct] = half8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+        }
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+          half8 ph, pl;
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int r = 0; r < 4; r += 2) {
+              float l2a = S[2 * jp + jj][ib][r], l2b = S[2 * jp + jj][ib][r + 1];
+              if (!UNIT) { l2a *= qinv2; l2b *= qinv2; }
+              float pa = __builtin_amdgcn_exp2f(l2a), pb = __builtin_amdgcn_exp2f(l2b);
+              if (DERIV) {
+                pa *= -l2a * dscale;
+                pb *= -l2b * dscale;
+              }
+              const half2v h = half2v{(_Float16)pa, (_Float16)pb};
+              const half2v l = half2v{(_Float16)sub_half_lo(h, pa), (_Float16)sub_half_hi(h, pb)};
+              ph[4 * jj + r] = h[0];
+              ph[4 * jj + r + 1] = h[1];
+              pl[4 * jj + r] = l[0];
+              pl[4 * jj + r + 1] = l[1];
+            }
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl, vh[ct], acc[ib][ct], 0, 0, 0);
+            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
+            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vh[ct], acc[ib][ct], 0, 0, 0);
+          }
+        }
+      }
+      if (++since_flush == MM2_FLUSH || q + 1 == nsteps) {
+        since_flush = 0;
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[ib][ct][r] += (double)acc[ib][ct][r];
+            acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          }
+      }
+    }
+    if (q + 1 < nsteps) lstore(q + 1);
+    __syncthreads();
+  }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t c = 16 * ct + li;
+    if (c < m) {
+      const double vs = (double)vscale[c];
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i0 + 16 * ib + 4 * lg + r;
+          if (i < n1) pout[i * ldp + c] = acc64[ib][ct][r] * vs;
+        }
+    }
+  }
+}
+
+template <int NCT, bool DERIV>
+__global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
+    const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
+    const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
+    const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
+    const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
+    int64_t part_stride, int tiles_per_split) {
+  __shared__ __attribute__((aligned(16)))
+  _Float16 smem[2 * 2 * BD_BM * 32 + 2 * 2 * MM_BN * 32 + 2 * 2 * NCT * 16 * MM_BN];
+  const float qinv2 = *qinv2_ptr;
+  if (qinv2 == 1.0f)
+    f16pv_bigd_body<NCT, true, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                      KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+  else
+    f16pv_bigd_body<NCT, false, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                       KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+}
+
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
                         const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
@@ -548,6 +771,22 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   const int tps = (int)ceil_div(ntiles, nsplit);
   dim3 grid(ceil_div(A.n, MM2_BM), nsplit);
   const int nct = (int)(V.mpad / 16);
+  if (A.Kp > 128) {
+    const int kp = (int)A.Kp;
+    if (nct == 1) {
+      if (deriv)
+        matmat_f16pv_bigd_kernel<1, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+      else
+        matmat_f16pv_bigd_kernel<1, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+    } else {
+      if (deriv)
+        matmat_f16pv_bigd_kernel<2, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+      else
+        matmat_f16pv_bigd_kernel<2, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+    }
+    KRR_LAUNCH_CHECK();
+    return hipSuccess;
+  }
 #define KRR_PV(KS_, NCT_)                                                                     \
   if (A.Kp == KS_ * 32 && nct == NCT_) {                                                      \
     if (deriv)                                                                                \

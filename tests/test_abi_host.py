@@ -97,9 +97,9 @@ def test_argument_validation_before_device_work():
     st = L.krr_precond_factor(fake, 10, 4, 4, -1.0, fake, fake, 4, fake, 1 << 30,
                               ctypes.byref(info), null)
     assert st == krr.E_ARG and "lambda_p" in krr.last_error()
-    # mixed precision dimension limit
+    # dimension limit of the BF16X3 (VALU-accumulate) product
     st = L.krr_kernel_matmat(fake, 10, 300, fake, 10, 300, 300, 1.0, 0.0, fake, 1, 1, fake, 1, 0,
-                             1, fake, 1 << 40, null)
+                             2, fake, 1 << 40, null)
     assert st == krr.E_ARG and "254" in krr.last_error()
 
 

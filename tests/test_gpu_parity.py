@@ -324,3 +324,78 @@ def test_grad_parity(dev, prec):
     tol = 1e-12 if prec == "fp64" else 1e-5
     assert abs(ds - ref_s) <= tol * scale
     assert dl == pytest.approx(ref_l, rel=1e-13)
+
+
+# ------------------------------------------------------------ large d, many RHS
+@pytest.mark.parametrize("case", [(150, 333, 300, 5), (200, 257, 440, 40), (64, 128, 130, 33)])
+def test_matmat_large_d_and_many_columns(dev, case):
+    """d beyond the register-resident kernel (both operands through LDS) and m > 32
+    (several column passes)."""
+    n1, n2, d, m = case
+    rng = np.random.default_rng(d + m)
+    X1 = rng.standard_normal((n1, d)).astype(np.float32)
+    X2 = rng.standard_normal((n2, d)).astype(np.float32)
+    V = rng.standard_normal((n2, m))
+    sigma = 0.8 * math.sqrt(d)
+    for deriv in (False, True):
+        got = krr.kernel_matmat(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), deriv=deriv).cpu().numpy()
+        ref = O.kernel_matmat(X1, X2, sigma, V, deriv=deriv)
+        tau = _tau("f16x3", X1, X2, sigma, d)
+        if deriv:
+            c = math.log2(math.e) / (2 * sigma ** 2)
+            Kd = O.gaussian_kernel(X1, X2, sigma)
+            bound = tau * (np.abs(O.gaussian_kernel_dsigma(X1, X2, sigma)) @ np.abs(V)) \
+                + ((tau / LN2) / c * Kd / sigma ** 3) @ np.abs(V)
+        else:
+            bound = tau * _abs_bound(X1, X2, sigma, V, False)
+        assert np.all(np.abs(got - ref) <= bound), (deriv, np.max(np.abs(got - ref) / bound))
+
+
+# -------------------------------------------------------- differentiation
+def _diff_workload():
+    return WL.correlated_differentiation(n=3072, n_val=384, d=440, k=147, s=256)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
+def test_validation_gradient_matches_oracle(dev, prec):
+    """The differentiation workload's recipe (d = 440, 147 classes) at n = 3072 + 384:
+    validation loss and its sigma / lambda gradients through the adjoint PCG against the
+    oracle's dense FP64 adjoint gradients (spec bound: 1e-4 relative)."""
+    from paper_1611_03220_amd import autograd as KA
+    w = _diff_workload()
+    Xtr, Xv = _t(w.X, dev), _t(w.Xv, dev)
+    Ytr, Yv = _t(w.Y, dev), _t(w.Yv, dev)
+    Z = krr.features(Xtr, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(w.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    L = KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, prec=prec, tol=1e-9, refine=3)
+    L.backward()
+    ref = O.validation_loss_and_grads(w.X, w.Y, w.Xv, w.Yv, w.sigma, w.lam)
+    assert float(L) == pytest.approx(ref["loss"], rel=1e-6)
+    assert float(sig.grad) == pytest.approx(ref["dL_dsigma"], rel=1e-4)
+    assert float(lam.grad) == pytest.approx(ref["dL_dlambda"], rel=1e-4)
+
+
+def test_validation_gradient_central_differences(dev):
+    """Central differences of the GPU FP64 loss in log sigma and log lambda (h = 1e-4) agree
+    with the adjoint gradient of the mixed path."""
+    from paper_1611_03220_amd import autograd as KA
+    w = WL.correlated_differentiation(n=2048, n_val=256, d=440, k=20, s=192)
+    Xtr, Xv = _t(w.X, dev), _t(w.Xv, dev)
+    Ytr, Yv = _t(w.Y, dev), _t(w.Yv, dev)
+    Z = krr.features(Xtr, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+
+    def loss(s_, l_, prec):
+        return float(KA.validation_loss(Xtr, Ytr, Xv, Yv, s_, l_, Ut, prec=prec, tol=1e-12,
+                                        max_iter=2000))
+
+    sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(w.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, prec="f16x3", tol=1e-9, refine=3).backward()
+    h = 1e-4
+    fd_s = (loss(w.sigma * math.exp(h), w.lam, "fp64") - loss(w.sigma * math.exp(-h), w.lam, "fp64")) / (2 * h) / w.sigma
+    fd_l = (loss(w.sigma, w.lam * math.exp(h), "fp64") - loss(w.sigma, w.lam * math.exp(-h), "fp64")) / (2 * h) / w.lam
+    assert float(sig.grad) == pytest.approx(fd_s, rel=1e-4)
+    assert float(lam.grad) == pytest.approx(fd_l, rel=1e-4)
