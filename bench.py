@@ -3,9 +3,9 @@
 
 One step is the whole hot path on the multi-RHS workload (n = 65536 points, d = 54,
 7 one-vs-all right-hand sides, s = 2048 random Fourier features, lambda = 1e-4 n, sigma
-= median pairwise distance, tolerance 1e-6): features (Alg. 1 steps 4-5), preconditioner
-factorisation (steps 6-7), mixed-precision PCG to 1e-6 (step 9) and the FP64 true
-residual at exit. Inputs are seeded synthetic data resident in HBM before timing.
+= median pairwise distance, tolerance 1e-6): random features, preconditioner
+factorisation and mixed-precision PCG to 1e-6 (the three phases of Alg. 1), and the FP64
+true residual at exit. Inputs are seeded synthetic data resident in HBM before timing.
 
 Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algorithmic
 kernel-product flops 2 n^2 (d + m) of all products in the timed steps divided by the
@@ -78,7 +78,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU "
-              "by design, see the sharding notes in DESIGN.md", file=sys.stderr)
+              "by design; the design notes describe how it would shard", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

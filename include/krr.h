@@ -5,10 +5,10 @@
  * Method: Avron, Clarkson, Woodruff, "Faster Kernel Ridge Regression Using Sketching
  * and Preconditioning" (arXiv 1611.03220). The library solves Eq. 1,
  *     (K + lambda I_n) c = y,   K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))   (Sec. 5),
- * by PCG (Alg. 1, step 9) with the preconditioner Z Z^T + lambda_p I_n built from random
+ * by PCG (Alg. 1) with the preconditioner Z Z^T + lambda_p I_n built from random
  * Fourier features Z = sqrt(2/s) cos(X W + b) (Sec. 2.2) and applied through its
  * Woodbury form lambda_p^{-1} (I - U^T U), U = C^{-1} Z^T, C C^T = Z^T Z + lambda_p I_s
- * (Sec. 3.1; Alg. 1, steps 6-7). The kernel matrix is never stored: every product
+ * (Sec. 3.1; Alg. 1). The kernel matrix is never stored: every product
  * recomputes it tile by tile from X.
  *
  * Conventions shared by every entry point
@@ -85,7 +85,7 @@ const char* krr_last_error(void);
 const char* krr_version(void);
 
 /*
- * krr_features -- random Fourier features, Alg. 1 steps 4-5 (feature map of Sec. 2.2):
+ * krr_features -- random Fourier features, the feature map of Alg. 1 (Sec. 2.2):
  *     Z[i, l] = sqrt(2/s) * cos( sum_k X[i, k] W[k, l] + b[l] ).
  * The scale is sqrt(2/s) (not the printed s^{-1/2}): with it E[z(x)^T z(y)] = k(x, y).
  *   X  : n x d FP32, leading dimension ldx >= d.
@@ -102,7 +102,7 @@ krr_status krr_features(const float* X, int64_t n, int64_t d, int64_t ldx, const
                         size_t ws_bytes, void* stream);
 
 /*
- * krr_precond_factor -- preconditioner set-up, Alg. 1 steps 6-7 (Woodbury form, Sec. 3.1):
+ * krr_precond_factor -- preconditioner set-up of Alg. 1 (Woodbury form, Sec. 3.1):
  *     G = Z^T Z + lambda_p I_s,  C C^T = G (C lower, FP64),  Ut = Z C^{-T}  (= U^T, n x s).
  * Then (Z Z^T + lambda_p I)^{-1} v = (v - Ut (Ut^T v)) / lambda_p.
  *   Z   : n x s FP32, leading dimension ldz >= s (s < n).
@@ -121,8 +121,8 @@ krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz,
                               int64_t* info, void* stream);
 
 /*
- * krr_kernel_matmat -- matrix-free kernel product (the per-iteration product of Alg. 1
- * step 9; Sec. 3.1 cost discussion):
+ * krr_kernel_matmat -- matrix-free kernel product (the per-iteration product of the PCG in
+ * Alg. 1; Sec. 3.1 cost discussion):
  *     OUT[i, :] = sum_j k(x1_i, x2_j) V[j, :] + shift * V[i, :],
  * with k the Gaussian kernel of Sec. 5, or, with deriv = 1, its sigma-derivative
  * dk/dsigma = k * ||x1_i - x2_j||^2 / sigma^3.
@@ -174,7 +174,7 @@ typedef struct krr_pcg_report {
 void krr_pcg_defaults(krr_pcg_opts* o);
 
 /*
- * krr_pcg_solve -- Alg. 1 step 9: solve (K + lambda I_n) alpha = Y by PCG with the
+ * krr_pcg_solve -- the solve of Alg. 1: (K + lambda I_n) alpha = Y by PCG with the
  * preconditioner (Z Z^T + lambda_p I)^{-1} = (I - Ut Ut^T) / lambda_p, one independent
  * PCG recurrence per right-hand side (columns freeze once converged; Sec. 5).
  *   X     : n x d FP32 (ldx >= d).   sigma > 0, lambda > 0.
@@ -208,6 +208,77 @@ krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double si
                     const double* alpha, const double* abar, int64_t m, int64_t ld,
                     double* dL_dsigma, double* dL_dlambda, int32_t prec, void* ws, size_t ws_bytes,
                     void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Batched solves: many independent problems in one plan. Every iteration runs ONE persistent
+ * kernel-product launch over a work queue of (problem, 128-row block, column range) items for
+ * all problems at once, plus batched CG and preconditioner kernels; the iteration is captured
+ * once in a hipGraph and replayed until every column of every problem has converged. The
+ * work-item granularity is chosen by timing candidates when the plan is created.
+ * Products use KRR_PREC_F16X3. The plan owns device memory (allocated at creation, freed by
+ * krr_batch_plan_destroy); krr_batch_solve allocates nothing.
+ */
+#define KRR_BATCH_MAX_M 16
+
+/* One problem of a batch; all arrays are device memory owned by the caller and must stay
+ * valid for the plan's lifetime (the plan keeps the pointers). */
+typedef struct krr_batch_problem {
+  const float* X;      /* n x d FP32 points (ldx >= d) */
+  int64_t n, d, ldx;
+  double sigma;        /* > 0 */
+  double lambda;       /* > 0 */
+  double lambda_p;     /* preconditioner regulariser Ut was built with; <= 0 means lambda */
+  const float* Ut;     /* krr_precond_factor output (n x s, ldu), or NULL for plain CG */
+  int64_t s, ldu;
+  const double* Y;     /* n x m right-hand sides (ldy >= m) */
+  int64_t ldy;
+  double* alpha;       /* n x m solution (lda >= m); written by krr_batch_solve */
+  int64_t lda;
+  int64_t m;           /* 1 <= m <= KRR_BATCH_MAX_M */
+} krr_batch_problem;
+
+typedef struct krr_batch_plan krr_batch_plan;
+
+typedef struct krr_batch_report {
+  int32_t iters;           /* replayed iterations, over all refinement solves */
+  int32_t converged_cols;  /* over all problems */
+  int32_t breakdown_cols;
+  int32_t refine_steps;    /* batched FP64-residual refinement steps (opts->refine) */
+  double* relres_rec;      /* host[count * KRR_BATCH_MAX_M] or NULL: problem p column c at
+                              p * KRR_BATCH_MAX_M + c (recursive residual) */
+  double* relres_true;     /* same layout, FP64 true residual (opts->true_residual) or NULL */
+  double product_ms;       /* device time of one batched kernel product (autotuned) */
+  double iteration_ms;     /* average device time of one replayed iteration graph */
+  int32_t tiles_per_item;  /* autotuned work-item size, in 64-column tiles */
+  int32_t work_items;      /* items in the persistent product's queue */
+} krr_batch_report;
+
+/*
+ * krr_batch_plan_create -- prepare `count` problems (Eq. 1 each, solved as in Alg. 1) for
+ * batched PCG: validates them, prepares points, builds the work queues, autotunes the
+ * product's work-item size and captures one iteration in a hipGraph. The points are
+ * prepared here: a plan serves later changes of Y, Ut contents or alpha's memory, not of X
+ * or sigma. opts: HOST pointer (NULL = defaults; opts->prec must be KRR_PREC_F16X3;
+ * use_precond = 0 ignores every Ut; refine > 0 adds up to that many refinement steps, each
+ * a batched solve of A delta = Y - A alpha for the columns whose FP64 true residual is
+ * still above tol; lambda_p and warm_start are not used: each problem carries its own
+ * lambda_p). The plan owns its device memory (about
+ * 5 * 8 * sum(n_p) * M bytes of vectors, where M is the widest m_p, plus the prepared points
+ * and the product partials). Synchronises `stream`. Errors: KRR_E_ARG, KRR_E_HIP.
+ */
+krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
+                                 const krr_pcg_opts* opts, krr_batch_plan** plan, void* stream);
+
+/*
+ * krr_batch_solve -- run the plan: zero start (Thm. 1), replay the iteration graph until all
+ * problems meet opts->tol on every column or opts->max_iter, write each problem's alpha.
+ * rep: HOST pointer (may be NULL). Synchronises `stream`. Errors: KRR_E_ARG, KRR_E_HIP,
+ * KRR_E_NO_CONV, KRR_E_BREAKDOWN (alpha written in every case).
+ */
+krr_status krr_batch_solve(krr_batch_plan* plan, krr_batch_report* rep, void* stream);
+
+/* Free everything the plan owns (NULL is ignored). */
+void krr_batch_plan_destroy(krr_batch_plan* plan);
 
 #ifdef __cplusplus
 }

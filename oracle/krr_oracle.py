@@ -79,7 +79,7 @@ def kernel_matmat(X1, X2, sigma: float, V, shift: float = 0.0, deriv: bool = Fal
                   rows=None, block: int = 512) -> np.ndarray:
     """OUT = K(X1, X2) V + shift * V, matrix-free over row blocks of X1.
 
-    The per-iteration product of Alg. 1, step 9 (the dominant cost, Sec. 3.1), with
+    The per-iteration product of the PCG in Alg. 1 (the dominant cost, Sec. 3.1), with
     K never stored whole. ``deriv`` swaps K for dK/dsigma. ``rows`` restricts the
     output to the given rows of X1 (for sampled checks at large n). ``shift`` is only
     meaningful for the square case X1 == X2 (it adds lambda * V for K + lambda I).
@@ -136,7 +136,7 @@ class NotSPDError(Exception):
 
 
 def precond_factor(Z, lambda_p: float):
-    """Alg. 1, steps 6-7: G = Z^T Z + lambda_p I_s, lower C with C C^T = G, U = C^{-1} Z^T.
+    """Preconditioner set-up of Alg. 1 (Sec. 3.1): G = Z^T Z + lambda_p I_s, lower C with C C^T = G, U = C^{-1} Z^T.
 
     Returns (C, U) with C s x s lower triangular and U s x n. Raises NotSPDError when
     G is not positive definite (only possible with lambda_p <= 0 or non-finite Z).
@@ -182,7 +182,7 @@ class PCGResult:
 def pcg(apply_A, Y, apply_M=None, tol: float = 1e-6, max_iter: int = 1000, x0=None) -> PCGResult:
     """Preconditioned conjugate gradients on A x = y, one independent run per column.
 
-    Alg. 1, step 9: solve (K + lambda I) c = y by PCG with a fixed SPD preconditioner,
+    The solve of Alg. 1: (K + lambda I) c = y by PCG with a fixed SPD preconditioner,
     starting from zero (Thm. 1), stopping when ||y_j - A x_j|| <= tol ||y_j|| (tracked on
     the recursive residual) for every column (Sec. 5). Standard PCG: alpha = rho/<p, Ap>,
     beta = rho_new/rho. A column whose curvature <p, Ap> is not positive or not finite is

@@ -816,3 +816,567 @@ krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double si
 }
 
 }  // extern "C"
+
+// =================================================================== batched plans
+#include "batch.hpp"
+
+struct krr_batch_plan {
+  int count = 0, M = 0;
+  int64_t N = 0;  // packed rows
+  krr_pcg_opts opts{};
+  std::vector<krr_batch_problem> probs;
+  std::vector<BatchMeta> meta_h;
+  std::vector<void*> allocs;
+  // device arrays
+  BatchMeta* meta = nullptr;
+  int* row_inst = nullptr;
+  BatchInst* inst = nullptr;
+  BatchItem* items = nullptr;
+  int nitems = 0, grid = 0, tiles_per_item = 0;
+  int* counter = nullptr;
+  RedItem* red = nullptr;
+  int nred = 0;
+  PCItem* pitems = nullptr;
+  int npitems = 0;
+  ZItem* zitems = nullptr;
+  int nzitems = 0;
+  int64_t smax = 0;
+  float* pf = nullptr;
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *part_yy = nullptr, *part_rr = nullptr, *part_pq = nullptr, *part_rz = nullptr;
+  double *pc_part = nullptr, *T = nullptr, *kpart = nullptr;
+  float *colmax = nullptr, *vscale = nullptr;
+  _Float16 *Vth = nullptr, *Vtl = nullptr;
+  BatchScalars S{};
+  std::vector<BatchInst> inst_h;
+  std::vector<int64_t> kpart_off;
+  double product_ms = 0.0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* ws64 = nullptr;  // FP64 true-residual workspace (largest problem)
+  size_t ws64_bytes = 0;
+};
+
+namespace {
+
+template <typename T> hipError_t plan_alloc(krr_batch_plan* P, T** out, int64_t count) {
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, (size_t)std::max<int64_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  P->allocs.push_back(ptr);
+  *out = static_cast<T*>(ptr);
+  return hipSuccess;
+}
+
+template <typename T> hipError_t upload(T* dst, const std::vector<T>& src, hipStream_t st) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+// Work items of the batched product for a granularity of g column tiles per item; updates
+// nsplit / partial offsets in meta_h and inst_h. Items are sorted by cost, largest first.
+std::vector<BatchItem> build_items(krr_batch_plan* P, int g) {
+  std::vector<BatchItem> items;
+  std::vector<std::pair<int64_t, BatchItem>> keyed;
+  int64_t off = 0;
+  for (int i = 0; i < P->count; ++i) {
+    const int64_t n = P->probs[i].n;
+    const int64_t rows_pad = round_up(n, ROW_PAD);
+    const int64_t tiles = ceil_div(n, 64);
+    const int nsplit = (int)ceil_div(tiles, g);
+    BatchMeta& M = P->meta_h[i];
+    BatchInst& I = P->inst_h[i];
+    M.nsplit = nsplit;
+    M.part = P->kpart + off;
+    M.part_stride = rows_pad * P->M;
+    I.part = M.part;
+    I.part_stride = M.part_stride;
+    off += (int64_t)nsplit * rows_pad * P->M;
+    for (int64_t rb = 0; rb < ceil_div(n, 128); ++rb)
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const int64_t nt = std::min<int64_t>(g, tiles - (int64_t)sp * g);
+        BatchItem it{i, g, rb, sp};
+        keyed.push_back({nt * I.Kp, it});
+      }
+  }
+  std::stable_sort(keyed.begin(), keyed.end(),
+                   [](const auto& a, const auto& b) { return a.first > b.first; });
+  for (auto& k : keyed) items.push_back(k.second);
+  return items;
+}
+
+int64_t kpart_elems(krr_batch_plan* P, int g) {
+  int64_t tot = 0;
+  for (int i = 0; i < P->count; ++i) {
+    const int64_t n = P->probs[i].n;
+    tot += ceil_div(ceil_div(n, 64), g) * round_up(n, ROW_PAD) * P->M;
+  }
+  return tot;
+}
+
+hipError_t batch_product(krr_batch_plan* P, hipStream_t st) {
+  hipError_t e = batch_split_v(P->row_inst, P->meta, P->count, P->N, P->M, P->pf, P->red, P->nred,
+                               P->colmax, P->Vth, P->Vtl, P->vscale, st);
+  if (e != hipSuccess) return e;
+  e = matmat_batch(P->items, P->nitems, P->inst, P->S.live, P->counter, P->grid, st);
+  if (e != hipSuccess) return e;
+  return batch_finalize(P->meta, P->row_inst, P->N, P->M, P->pf, P->q, st);
+}
+
+// One PCG iteration for every problem (the captured graph body).
+hipError_t batch_iteration(krr_batch_plan* P, hipStream_t st) {
+  const int M = P->M;
+  hipError_t e;
+  if ((e = batch_product(P, st))) return e;
+  if ((e = batch_dot<float, double>(P->pf, P->q, M, P->red, P->nred, P->part_pq, st))) return e;
+  if ((e = batch_alpha(P->meta, P->count, M, P->part_pq, P->S, st))) return e;
+  if ((e = batch_update_xr(P->row_inst, P->N, M, P->S.alpha, P->pf, P->q, P->x, P->r, st))) return e;
+  if ((e = batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->part_rr, st))) return e;
+  if ((e = batch_conv(P->meta, P->count, M, P->part_rr, P->S, st))) return e;
+  if ((e = batch_precond(P->meta, P->count, P->pitems, P->npitems, P->zitems, P->nzitems, P->smax,
+                         P->r, M, P->pc_part, P->T, P->z, st)))
+    return e;
+  if ((e = batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->part_rz, st))) return e;
+  if ((e = batch_beta(P->meta, P->count, M, P->part_rz, P->part_rr, P->S, st))) return e;
+  return batch_update_p(P->row_inst, P->N, M, P->S.beta, P->S.active, 0, P->z, P->p, P->pf, st);
+}
+
+// FP64 true-residual scratch of one problem of a batch
+struct BatchResid {
+  MatmatCtx c;
+  double *ax, *res, *prr, *pyy;
+};
+void layout_batch_resid(Bump& b, BatchResid& R, int64_t n, int64_t d, int64_t m) {
+  layout_matmat(b, R.c, n, n, d, m, KRR_PREC_FP64, true);
+  R.ax = b.take<double>(n * m);
+  R.res = b.take<double>(n * m);
+  R.prr = b.take<double>(NBLK * m);
+  R.pyy = b.take<double>(NBLK * m);
+}
+
+// Per-column ||Y - (K + lambda I) alpha|| / ||Y|| of one problem, all in FP64.
+krr_status batch_true_residual(krr_batch_plan* P, const krr_batch_problem& b, double* rel,
+                               hipStream_t st, double* r_out = nullptr, int64_t ldr = 0) {
+  Bump bb(P->ws64);
+  BatchResid R;
+  layout_batch_resid(bb, R, b.n, b.d, b.m);
+  const int64_t n = b.n, m = b.m;
+  CHECK_HIP(prepare_points(R.c, b.X, b.ldx, nullptr, 0, b.sigma, st));
+  CHECK_HIP(run_matmat(R.c, nullptr, b.alpha, b.lda, false, st));
+  CHECK_HIP(matmat_finalize<double>(R.c.part, R.c.part_stride, R.c.nsplit, n, m, m, b.lambda,
+                                    b.alpha, b.lda, R.ax, m, st));
+  CHECK_HIP(residual_from(b.Y, b.ldy, R.ax, n, m, R.res, st));
+  if (r_out) CHECK_HIP(copy2d(R.res, m, r_out, ldr, n, m, st));
+  CHECK_HIP(dot_partial<double, double>(R.res, m, R.res, m, n, m, R.prr, NBLK, st));
+  CHECK_HIP(dot_partial<double, double>(b.Y, b.ldy, b.Y, b.ldy, n, m, R.pyy, NBLK, st));
+  std::vector<double> prr(NBLK * m), pyy(NBLK * m);
+  CHECK_HIP(hipMemcpyAsync(prr.data(), R.prr, sizeof(double) * NBLK * m, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipMemcpyAsync(pyy.data(), R.pyy, sizeof(double) * NBLK * m, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  for (int64_t c = 0; c < m; ++c) {
+    double rr = 0.0, yy = 0.0;
+    for (int k = 0; k < NBLK; ++k) { rr += prr[k * m + c]; yy += pyy[k * m + c]; }
+    rel[c] = yy > 0.0 ? std::sqrt(rr / yy) : std::sqrt(rr);
+  }
+  return KRR_OK;
+}
+
+void plan_free(krr_batch_plan* P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  for (void* a : P->allocs) (void)hipFree(a);
+  delete P;
+}
+
+}  // namespace
+
+extern "C" {
+
+krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
+                                 const krr_pcg_opts* opts, krr_batch_plan** plan_out,
+                                 void* stream) {
+  g_err[0] = 0;
+  if (!probs || count < 1 || !plan_out) return fail(KRR_E_ARG, "krr_batch_plan_create: bad arguments");
+  *plan_out = nullptr;
+  krr_pcg_opts o;
+  krr_pcg_defaults(&o);
+  if (opts) o = *opts;
+  if (o.prec != KRR_PREC_F16X3)
+    return fail(KRR_E_ARG, "krr_batch_plan_create: batched products use KRR_PREC_F16X3");
+  if (!(o.tol > 0.0) || o.max_iter < 1) return fail(KRR_E_ARG, "krr_batch_plan_create: bad tol/max_iter");
+  if (o.check_every < 1) o.check_every = 1;
+  int M = 0;
+  for (int i = 0; i < count; ++i) {
+    const krr_batch_problem& b = probs[i];
+    if (!b.X || !b.Y || !b.alpha || b.n < 2 || b.d < 1 || b.ldx < b.d || b.m < 1 ||
+        b.m > KRR_BATCH_MAX_M || b.ldy < b.m || b.lda < b.m)
+      return fail(KRR_E_ARG, "krr_batch_plan_create: problem %d: bad pointer or size", i);
+    if (!(b.sigma > 0.0) || !(b.lambda > 0.0) || !std::isfinite(b.sigma) || !std::isfinite(b.lambda))
+      return fail(KRR_E_ARG, "krr_batch_plan_create: problem %d: sigma and lambda must be > 0", i);
+    if (b.Ut && (b.s < 1 || b.s >= b.n || b.ldu < b.s))
+      return fail(KRR_E_ARG, "krr_batch_plan_create: problem %d: need 1 <= s < n", i);
+    M = std::max<int>(M, (int)b.m);
+  }
+  hipStream_t st = (hipStream_t)stream;
+  krr_batch_plan* P = new krr_batch_plan();
+  P->count = count;
+  P->M = M;
+  P->opts = o;
+  P->probs.assign(probs, probs + count);
+  P->meta_h.resize(count);
+  P->inst_h.resize(count);
+  auto bail = [&](krr_status code) { plan_free(P); return code; };
+#define PLAN_HIP(...)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (__VA_ARGS__);                                                           \
+    if (e_ != hipSuccess) {                                                                  \
+      fail(KRR_E_HIP, "%s failed: %s (line %d)", #__VA_ARGS__, hipGetErrorString(e_), __LINE__); \
+      return bail(KRR_E_HIP);                                                                \
+    }                                                                                        \
+  } while (0)
+
+  // packed layout and per-problem metadata
+  std::vector<int> row_inst_h;
+  std::vector<RedItem> red_h;
+  std::vector<PCItem> pitems_h;
+  std::vector<ZItem> zitems_h;
+  int64_t off = 0, pc_off = 0, t_off = 0, nmax = 0;
+  for (int i = 0; i < count; ++i) {
+    const krr_batch_problem& b = probs[i];
+    BatchMeta& Mt = P->meta_h[i];
+    const int64_t rows_pad = round_up(b.n, ROW_PAD);
+    Mt.off = off;
+    Mt.n = b.n;
+    Mt.m = (int)b.m;
+    Mt.lambda = b.lambda;
+    Mt.has_u = (b.Ut && o.use_precond) ? 1 : 0;
+    Mt.Ut = b.Ut;
+    Mt.s = Mt.has_u ? b.s : 0;
+    Mt.ldu = b.ldu;
+    Mt.inv_lp = 1.0 / (b.lambda_p > 0.0 ? b.lambda_p : b.lambda);
+    Mt.ext_in = b.Y;
+    Mt.ld_in = b.ldy;
+    Mt.ext_out = b.alpha;
+    Mt.ld_out = b.lda;
+    Mt.red_begin = (int)red_h.size();
+    for (int64_t r0 = 0; r0 < b.n; r0 += 1024)
+      red_h.push_back(RedItem{i, off + r0, off + std::min<int64_t>(b.n, r0 + 1024)});
+    Mt.red_end = (int)red_h.size();
+    if (Mt.has_u) {
+      const int chunks = (int)std::max<int64_t>(1, ceil_div(b.n, 2048));
+      Mt.pc_chunks = chunks;
+      Mt.pc_part_off = pc_off;
+      Mt.t_off = t_off;
+      const int64_t rpc = ceil_div(b.n, chunks);
+      for (int64_t k0 = 0; k0 < b.s; k0 += 256)
+        for (int c = 0; c < chunks; ++c)
+          pitems_h.push_back(PCItem{i, c, k0, c * rpc, std::min<int64_t>(b.n, (c + 1) * rpc), pc_off});
+      pc_off += (int64_t)chunks * b.s * 16;
+      t_off += b.s * 16;
+      P->smax = std::max<int64_t>(P->smax, b.s);
+    }
+    for (int64_t i0 = 0; i0 < b.n; i0 += 64) zitems_h.push_back(ZItem{i, i0});
+    for (int64_t r = 0; r < rows_pad; ++r) row_inst_h.push_back(i);
+    off += rows_pad;
+    nmax = std::max<int64_t>(nmax, b.n);
+  }
+  P->N = off;
+  P->nred = (int)red_h.size();
+  P->npitems = (int)pitems_h.size();
+  P->nzitems = (int)zitems_h.size();
+  const int64_t NM = P->N * M;
+  PLAN_HIP(plan_alloc(P, &P->meta, count));
+  PLAN_HIP(plan_alloc(P, &P->row_inst, P->N));
+  PLAN_HIP(plan_alloc(P, &P->inst, count));
+  PLAN_HIP(plan_alloc(P, &P->counter, 64));
+  PLAN_HIP(plan_alloc(P, &P->red, P->nred));
+  PLAN_HIP(plan_alloc(P, &P->pitems, P->npitems));
+  PLAN_HIP(plan_alloc(P, &P->zitems, P->nzitems));
+  PLAN_HIP(plan_alloc(P, &P->pf, NM));
+  PLAN_HIP(plan_alloc(P, &P->x, NM));
+  PLAN_HIP(plan_alloc(P, &P->r, NM));
+  PLAN_HIP(plan_alloc(P, &P->z, NM));
+  PLAN_HIP(plan_alloc(P, &P->p, NM));
+  PLAN_HIP(plan_alloc(P, &P->q, NM));
+  PLAN_HIP(plan_alloc(P, &P->part_yy, (int64_t)P->nred * M));
+  PLAN_HIP(plan_alloc(P, &P->part_rr, (int64_t)P->nred * M));
+  PLAN_HIP(plan_alloc(P, &P->part_pq, (int64_t)P->nred * M));
+  PLAN_HIP(plan_alloc(P, &P->part_rz, (int64_t)P->nred * M));
+  PLAN_HIP(plan_alloc(P, &P->pc_part, pc_off));
+  PLAN_HIP(plan_alloc(P, &P->T, t_off));
+  PLAN_HIP(plan_alloc(P, &P->colmax, (int64_t)count * 16));
+  PLAN_HIP(plan_alloc(P, &P->vscale, (int64_t)count * 16));
+  PLAN_HIP(plan_alloc(P, &P->Vth, 16 * P->N));
+  PLAN_HIP(plan_alloc(P, &P->Vtl, 16 * P->N));
+  const int cm = count * M;
+  PLAN_HIP(plan_alloc(P, &P->S.ynorm, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.rnorm, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.rho, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.alpha, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.beta, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.active, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.broken, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.col_iters, cm));
+  PLAN_HIP(plan_alloc(P, &P->S.count, 64));
+  PLAN_HIP(plan_alloc(P, &P->S.iter, 64));
+  PLAN_HIP(plan_alloc(P, &P->S.live, count));
+  PLAN_HIP(fill_i32(P->S.live, count, 1, st));
+  PLAN_HIP(plan_alloc(P, &P->S.tol, cm));
+  // per-problem prepared points (F16X3, augmented, scaled)
+  for (int i = 0; i < count; ++i) {
+    const krr_batch_problem& b = probs[i];
+    const int64_t rows_pad = round_up(b.n, ROW_PAD);
+    const int64_t Kp = kp_for(b.d);
+    _Float16 *ah, *al, *bh, *bl;
+    float* stats;
+    PLAN_HIP(plan_alloc(P, &ah, rows_pad * Kp));
+    PLAN_HIP(plan_alloc(P, &al, rows_pad * Kp));
+    PLAN_HIP(plan_alloc(P, &bh, rows_pad * Kp));
+    PLAN_HIP(plan_alloc(P, &bl, rows_pad * Kp));
+    PLAN_HIP(plan_alloc(P, &stats, 64));
+    const double c2 = 1.4426950408889634 / (2.0 * b.sigma * b.sigma);
+    PLAN_HIP(fill_f32(stats, 4, 0.0f, st));
+    PLAN_HIP(point_stats(b.X, b.n, b.d, b.ldx, stats, st));
+    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, c2, stats, 0, 0, ah, al,
+                                   stats + 2, st));
+    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, c2, stats, 1, 0, bh, bl,
+                                   nullptr, st));
+    BatchInst& I = P->inst_h[i];
+    I.Ahi = ah; I.Alo = al; I.Bhi = bh; I.Blo = bl;
+    I.Vth = P->Vth + P->meta_h[i].off;
+    I.Vtl = P->Vtl + P->meta_h[i].off;
+    I.vscale = P->vscale + 16 * i;
+    I.qinv2 = stats + 2;
+    I.n = b.n;
+    I.m = M;
+    I.ldvt = P->N;
+    I.ldp = M;
+    I.Kp = (int)Kp;
+  }
+  // product partials sized for the finest candidate granularity
+  const int cands[4] = {4, 8, 16, 32};
+  PLAN_HIP(plan_alloc(P, &P->kpart, kpart_elems(P, cands[0])));
+  PLAN_HIP(upload(P->row_inst, row_inst_h, st));
+  PLAN_HIP(upload(P->red, red_h, st));
+  PLAN_HIP(upload(P->pitems, pitems_h, st));
+  PLAN_HIP(upload(P->zitems, zitems_h, st));
+  PLAN_HIP(fill_f32(P->pf, NM, 0.0f, st));
+  for (double* v : {P->x, P->r, P->z, P->p, P->q}) PLAN_HIP(fill_f64(v, NM, 0.0, st));
+  int dev = 0, cus = 256;
+  PLAN_HIP(hipGetDevice(&dev));
+  PLAN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  P->grid = 2 * cus;
+  // autotune the work-item granularity on the real problem set (the finest granularity
+  // has the most items, so its buffer holds every candidate's list)
+  PLAN_HIP(plan_alloc(P, &P->items, (int64_t)build_items(P, cands[0]).size()));
+  hipEvent_t e0, e1;
+  PLAN_HIP(hipEventCreate(&e0));
+  PLAN_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_g = cands[0];
+  for (int g : cands) {
+    std::vector<BatchItem> items = build_items(P, g);
+    PLAN_HIP(upload(P->items, items, st));
+    PLAN_HIP(upload(P->inst, P->inst_h, st));
+    PLAN_HIP(upload(P->meta, P->meta_h, st));
+    P->nitems = (int)items.size();
+    float tbest = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      PLAN_HIP(hipEventRecord(e0, st));
+      PLAN_HIP(batch_product(P, st));
+      PLAN_HIP(hipEventRecord(e1, st));
+      PLAN_HIP(hipEventSynchronize(e1));
+      float t = 0.0f;
+      PLAN_HIP(hipEventElapsedTime(&t, e0, e1));
+      if (rep > 0) tbest = std::min(tbest, t);
+    }
+    if (tbest < best) {
+      best = tbest;
+      best_g = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  {
+    std::vector<BatchItem> items = build_items(P, best_g);
+    PLAN_HIP(upload(P->items, items, st));
+    P->nitems = (int)items.size();
+    PLAN_HIP(upload(P->inst, P->inst_h, st));
+    PLAN_HIP(upload(P->meta, P->meta_h, st));
+  }
+  P->tiles_per_item = best_g;
+  P->product_ms = best;
+  // FP64 true-residual workspace (the largest problem)
+  if (o.true_residual) {
+    for (int i = 0; i < count; ++i) {
+      Bump sz(nullptr);
+      BatchResid R;
+      layout_batch_resid(sz, R, probs[i].n, probs[i].d, probs[i].m);
+      P->ws64_bytes = std::max(P->ws64_bytes, sz.off);
+    }
+    char* w = nullptr;
+    PLAN_HIP(plan_alloc(P, &w, (int64_t)P->ws64_bytes));
+    P->ws64 = w;
+  }
+  PLAN_HIP(hipStreamSynchronize(st));
+  // capture one iteration
+  PLAN_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+  PLAN_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  {
+    hipError_t ce = batch_iteration(P, P->cap);
+    hipGraph_t g = nullptr;
+    hipError_t ee = hipStreamEndCapture(P->cap, &g);
+    P->graph = g;
+    PLAN_HIP(ce);
+    PLAN_HIP(ee);
+  }
+  PLAN_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+#undef PLAN_HIP
+  *plan_out = P;
+  return KRR_OK;
+}
+
+void krr_batch_plan_destroy(krr_batch_plan* plan) { plan_free(plan); }
+
+// PCG on the packed right-hand sides in P->r (x from zero) with per-column tolerances
+// already in S.tol; returns the iterations run.
+static krr_status batch_pcg(krr_batch_plan* P, int* iters, double* ms, hipStream_t st) {
+  const int M = P->M;
+  CHECK_HIP(fill_f64(P->x, P->N * M, 0.0, st));
+  CHECK_HIP(batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->part_yy, st));
+  CHECK_HIP(batch_precond(P->meta, P->count, P->pitems, P->npitems, P->zitems, P->nzitems, P->smax,
+                          P->r, M, P->pc_part, P->T, P->z, st));
+  CHECK_HIP(batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->part_rz, st));
+  CHECK_HIP(batch_init_scalars(P->meta, P->count, M, P->part_yy, P->part_rz, P->S, st));
+  CHECK_HIP(batch_update_p(P->row_inst, P->N, M, P->S.beta, P->S.active, 1, P->z, P->p, P->pf, st));
+  int h_count = 0;
+  CHECK_HIP(hipMemcpyAsync(&h_count, P->S.count, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  hipEvent_t e0, e1;
+  CHECK_HIP(hipEventCreate(&e0));
+  CHECK_HIP(hipEventCreate(&e1));
+  int it = 0;
+  hipError_t err = hipEventRecord(e0, st);
+  while (err == hipSuccess && h_count > 0 && it < P->opts.max_iter) {
+    err = hipGraphLaunch(P->exec, st);
+    ++it;
+    if (err == hipSuccess && (it % P->opts.check_every == 0 || it == P->opts.max_iter)) {
+      err = hipMemcpyAsync(&h_count, P->S.count, sizeof(int), hipMemcpyDeviceToHost, st);
+      if (err == hipSuccess) err = hipStreamSynchronize(st);
+    }
+  }
+  if (err == hipSuccess) err = hipEventRecord(e1, st);
+  if (err == hipSuccess) err = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  CHECK_HIP(err);
+  *iters = it;
+  *ms = t;
+  return KRR_OK;
+}
+
+krr_status krr_batch_solve(krr_batch_plan* P, krr_batch_report* rep, void* stream) {
+  g_err[0] = 0;
+  if (!P) return fail(KRR_E_ARG, "krr_batch_solve: NULL plan");
+  hipStream_t st = (hipStream_t)stream;
+  const int M = P->M, cm = P->count * M;
+  const double tol = P->opts.tol;
+  std::vector<double> tolv(cm, 1.0);
+  for (int i = 0; i < P->count; ++i)
+    for (int c = 0; c < P->probs[i].m; ++c) tolv[i * M + c] = tol;
+  CHECK_HIP(hipMemcpyAsync(P->S.tol, tolv.data(), sizeof(double) * cm, hipMemcpyHostToDevice, st));
+  CHECK_HIP(batch_pack(P->row_inst, P->meta, P->N, M, BATCH_PACK_IN, P->r, st));
+  int it = 0;
+  double ms = 0.0;
+  CHECK_ST(batch_pcg(P, &it, &ms, st));
+  CHECK_HIP(batch_pack(P->row_inst, P->meta, P->N, M, BATCH_UNPACK_SET, P->x, st));
+  int total_iters = it;
+  const double iter_ms = it > 0 ? ms / it : 0.0;
+  std::vector<double> rn(cm), yn(cm);
+  std::vector<int> brk(cm);
+  CHECK_HIP(hipMemcpyAsync(rn.data(), P->S.rnorm, sizeof(double) * cm, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipMemcpyAsync(yn.data(), P->S.ynorm, sizeof(double) * cm, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipMemcpyAsync(brk.data(), P->S.broken, sizeof(int) * cm, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  int conv = 0, nbrk = 0;
+  for (int i = 0; i < P->count; ++i)
+    for (int c = 0; c < P->probs[i].m; ++c) {
+      const int e = i * M + c;
+      const double rel = yn[e] > 0.0 ? rn[e] / yn[e] : 0.0;
+      if (brk[e]) ++nbrk;
+      else if (rel <= tol) ++conv;
+      if (rep && rep->relres_rec) rep->relres_rec[i * KRR_BATCH_MAX_M + c] = rel;
+    }
+  // FP64 true residuals; refinement solves A delta = R for the columns above tol
+  std::vector<double> rel_true(cm, 0.0);
+  int refine_steps = 0;
+  const bool want_true = P->opts.true_residual || P->opts.refine > 0;
+  auto true_all = [&]() -> krr_status {
+    for (int i = 0; i < P->count; ++i) {
+      // R also lands in the packed right-hand side, ready for a refinement solve
+      const krr_status stt = batch_true_residual(P, P->probs[i], &rel_true[i * M], st,
+                                                 P->r + P->meta_h[i].off * M, M);
+      if (stt != KRR_OK) return stt;
+    }
+    return KRR_OK;
+  };
+  if (want_true && nbrk == 0) {
+    CHECK_ST(true_all());
+    while (refine_steps < P->opts.refine) {
+      double worst = 0.0;
+      for (int i = 0; i < P->count; ++i)
+        for (int c = 0; c < P->probs[i].m; ++c) worst = std::max(worst, rel_true[i * M + c]);
+      if (!(worst > tol)) break;
+      ++refine_steps;
+      // P->r holds every problem's R; settled columns stay inactive
+      for (int i = 0; i < P->count; ++i) {
+        const krr_batch_problem& b = P->probs[i];
+        for (int c = 0; c < M; ++c) {
+          const double r = c < b.m ? rel_true[i * M + c] : 0.0;
+          tolv[i * M + c] = r > tol ? std::max(0.5 * tol / r, 1e-14) : 1.0;
+        }
+      }
+      CHECK_HIP(hipMemcpyAsync(P->S.tol, tolv.data(), sizeof(double) * cm, hipMemcpyHostToDevice, st));
+      int it2 = 0;
+      double ms2 = 0.0;
+      CHECK_ST(batch_pcg(P, &it2, &ms2, st));
+      total_iters += it2;
+      CHECK_HIP(batch_pack(P->row_inst, P->meta, P->N, M, BATCH_UNPACK_ADD, P->x, st));
+      CHECK_ST(true_all());
+    }
+  }
+  if (rep && rep->relres_true)
+    for (int i = 0; i < P->count; ++i)
+      for (int c = 0; c < P->probs[i].m; ++c)
+        rep->relres_true[i * KRR_BATCH_MAX_M + c] = want_true && nbrk == 0 ? rel_true[i * M + c] : NAN;
+  if (rep) {
+    rep->iters = total_iters;
+    rep->converged_cols = conv;
+    rep->breakdown_cols = nbrk;
+    rep->refine_steps = refine_steps;
+    rep->product_ms = P->product_ms;
+    rep->iteration_ms = iter_ms;
+    rep->tiles_per_item = P->tiles_per_item;
+    rep->work_items = P->nitems;
+  }
+  if (nbrk > 0) return fail(KRR_E_BREAKDOWN, "krr_batch_solve: %d column(s) broke down", nbrk);
+  bool ok = true;
+  if (refine_steps > 0) {
+    for (int i = 0; i < P->count; ++i)
+      for (int c = 0; c < P->probs[i].m; ++c) ok = ok && rel_true[i * M + c] <= tol;
+  } else {
+    int total = 0;
+    for (int i = 0; i < P->count; ++i) total += (int)P->probs[i].m;
+    ok = conv == total;
+  }
+  if (!ok)
+    return fail(KRR_E_NO_CONV, "krr_batch_solve: not converged after %d iterations", total_iters);
+  return KRR_OK;
+}
+
+}  // extern "C"

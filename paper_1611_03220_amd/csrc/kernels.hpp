@@ -88,6 +88,24 @@ hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, 
                            int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,
                            double* out, int64_t ldo, hipStream_t st);
 
+// batched kernel product (matmat.hip)
+struct BatchInst {          // one problem of a batch, prepared for the F16X3 product
+  const _Float16 *Ahi, *Alo, *Bhi, *Blo;   // rows padded to ROW_PAD, Kp wide
+  const _Float16 *Vth, *Vtl;              // [16][ldvt] split V^T
+  const float* vscale;                     // [16]
+  const float* qinv2;                      // device scalar
+  double* part;                            // partial sums [nsplit][rows_pad][ldp]
+  int64_t n, m, ldvt, ldp, part_stride;
+  int Kp;
+};
+struct BatchItem {          // a 128-row block of one problem against one column range
+  int inst;
+  int tiles_per_split;
+  int64_t rb, split;
+};
+hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
+                        const int* live, int* counter, int grid, hipStream_t st);
+
 // gemm.hip
 hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M, int64_t N,
                          int64_t K, int nsplit, int epi, int lower_only, int tri_b, double alpha,

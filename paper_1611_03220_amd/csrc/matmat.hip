@@ -553,7 +553,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
-    int tiles_per_split) {
+    int tiles_per_split, int64_t rb, int64_t split) {
   constexpr int ACH = BD_BM * 4;            // 16-byte chunks in an A chunk-tile (per array)
   constexpr int BCH = MM_BN * 4;
   constexpr int VR = NCT * 16;
@@ -569,10 +569,10 @@ __device__ __forceinline__ void f16pv_bigd_body(
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int64_t blk_i0 = (int64_t)blockIdx.x * BD_BM;
+  const int64_t blk_i0 = rb * BD_BM;
   const int64_t i0 = blk_i0 + 32 * w;
   const int64_t ntiles = ceil_div(n2, MM_BN);
-  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_begin = split * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = KP / 32;
   const int64_t nsteps = (t_end - t_begin) * KC;
@@ -726,7 +726,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
     if (q + 1 < nsteps) lstore(q + 1);
     __syncthreads();
   }
-  double* pout = part + (int64_t)blockIdx.y * part_stride;
+  double* pout = part + split * part_stride;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
@@ -756,10 +756,12 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
     f16pv_bigd_body<NCT, true, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                      KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+                                      KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split,
+                                      blockIdx.x, blockIdx.y);
   else
     f16pv_bigd_body<NCT, false, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                       KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+                                       KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split,
+                                       blockIdx.x, blockIdx.y);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
@@ -804,6 +806,50 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   KRR_PV(1, 2) KRR_PV(2, 2) KRR_PV(3, 2) KRR_PV(4, 2)
 #undef KRR_PV
   return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------- batched persistent kernel
+// One launch serves many independent problems: blocks take work items (instance, 128-row
+// block, column split) from an atomic counter until the list is exhausted, and run the
+// large-d body (runtime feature width) on each. Items are ordered largest first; items of a
+// problem whose columns have all converged (live[inst] == 0) are skipped.
+__global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* __restrict__ items,
+                                                              int nitems,
+                                                              const BatchInst* __restrict__ inst,
+                                                              const int* __restrict__ live,
+                                                              int* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16)))
+  _Float16 smem[2 * 2 * BD_BM * 32 + 2 * 2 * MM_BN * 32 + 2 * 2 * 16 * MM_BN];
+  __shared__ int cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = cur;
+    __syncthreads();
+    if (it >= nitems) break;  // uniform: every wave of the block leaves together
+    const BatchItem wi = items[it];
+    if (!live[wi.inst]) continue;  // uniform per block
+    const BatchInst I = inst[wi.inst];
+    const float qinv2 = *I.qinv2;
+    if (qinv2 == 1.0f)
+      f16pv_bigd_body<1, true, false>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
+                                      I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
+                                      I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
+    else
+      f16pv_bigd_body<1, false, false>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
+                                       I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
+                                       I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
+    __syncthreads();
+  }
+}
+
+hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
+                        const int* live, int* counter, int grid, hipStream_t st) {
+  hipError_t e = fill_i32(counter, 1, 0, st);
+  if (e != hipSuccess) return e;
+  matmat_batch_kernel<<<grid, 256, 0, st>>>(items, nitems, inst, live, counter);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------------- FP64 path

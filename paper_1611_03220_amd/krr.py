@@ -49,6 +49,23 @@ class PCGReport(ctypes.Structure):
                 ("matmat_ms", _dbl)]
 
 
+BATCH_MAX_M = 16
+
+
+class BatchProblem(ctypes.Structure):
+    _fields_ = [("X", _vp), ("n", _i64), ("d", _i64), ("ldx", _i64), ("sigma", _dbl),
+                ("lam", _dbl), ("lambda_p", _dbl), ("Ut", _vp), ("s", _i64), ("ldu", _i64),
+                ("Y", _vp), ("ldy", _i64), ("alpha", _vp), ("lda", _i64), ("m", _i64)]
+
+
+class BatchReport(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("converged_cols", _i32), ("breakdown_cols", _i32),
+                ("refine_steps", _i32),
+                ("relres_rec", ctypes.POINTER(_dbl)), ("relres_true", ctypes.POINTER(_dbl)),
+                ("product_ms", _dbl), ("iteration_ms", _dbl), ("tiles_per_item", _i32),
+                ("work_items", _i32)]
+
+
 _lib = None
 
 
@@ -81,13 +98,20 @@ def lib():
     L.krr_grad.restype = _i32
     L.krr_grad.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64,
                            ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _i32, _vp, _sz, _vp]
+    L.krr_batch_plan_create.restype = _i32
+    L.krr_batch_plan_create.argtypes = [ctypes.POINTER(BatchProblem), _i32,
+                                        ctypes.POINTER(PCGOpts), ctypes.POINTER(_vp), _vp]
+    L.krr_batch_solve.restype = _i32
+    L.krr_batch_solve.argtypes = [_vp, ctypes.POINTER(BatchReport), _vp]
+    L.krr_batch_plan_destroy.restype = None
+    L.krr_batch_plan_destroy.argtypes = [_vp]
     _lib = L
     return L
 
 
 EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_defaults",
             "krr_features", "krr_precond_factor", "krr_kernel_matmat", "krr_pcg_solve",
-            "krr_grad"]
+            "krr_grad", "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
 
 
 def last_error() -> str:
@@ -283,6 +307,105 @@ def grad(X: torch.Tensor, sigma: float, alpha: torch.Tensor, abar: torch.Tensor,
                         _stream())
     _raise(st)
     return ds.value, dl.value
+
+
+@dataclasses.dataclass
+class BatchSolveReport:
+    status: int
+    iters: int
+    converged_cols: int
+    breakdown_cols: int
+    refine_steps: int
+    relres_rec: list       # per problem: list of its m columns
+    relres_true: list
+    product_ms: float
+    iteration_ms: float
+    tiles_per_item: int
+    work_items: int
+
+
+class BatchPlan:
+    """Many independent problems (K_p + lam_p I) alpha_p = Y_p solved together: one persistent
+    kernel-product launch and one captured iteration graph per PCG iteration.
+
+    problems: list of dicts with keys X (n x d FP32), sigma, lam, Y (n x m FP64, m <= 16) and
+    optionally Ut (n x s FP32) and lambda_p. The plan keeps references to every tensor and
+    owns the solutions (``alphas``). Points are prepared at construction."""
+
+    def __init__(self, problems, tol: float = 1e-6, max_iter: int = 1000,
+                 use_precond: bool = True, check_every: int = 1, true_residual: bool = True,
+                 refine: int = 0):
+        self._keep = []
+        n_p = len(problems)
+        arr = (BatchProblem * n_p)()
+        self.alphas = []
+        self.ms = []
+        for i, pr in enumerate(problems):
+            X, Y = pr["X"], pr["Y"]
+            _check(X, torch.float32, f"problems[{i}].X")
+            Y2 = Y[:, None] if Y.dim() == 1 else Y
+            _check(Y2, torch.float64, f"problems[{i}].Y")
+            n, d = X.shape
+            m = Y2.shape[1]
+            if Y2.shape[0] != n:
+                raise ValueError(f"problems[{i}]: Y rows must match X")
+            alpha = torch.zeros((n, m), dtype=torch.float64, device=X.device)
+            Ut = pr.get("Ut")
+            b = arr[i]
+            b.X, b.n, b.d, b.ldx = X.data_ptr(), n, d, _ld(X)
+            b.sigma, b.lam = float(pr["sigma"]), float(pr["lam"])
+            b.lambda_p = float(pr.get("lambda_p") or 0.0)
+            if Ut is not None:
+                _check(Ut, torch.float32, f"problems[{i}].Ut")
+                b.Ut, b.s, b.ldu = Ut.data_ptr(), Ut.shape[1], _ld(Ut)
+            else:
+                b.Ut, b.s, b.ldu = None, 0, 0
+            b.Y, b.ldy = Y2.data_ptr(), _ld(Y2)
+            b.alpha, b.lda, b.m = alpha.data_ptr(), m, m
+            self._keep += [X, Y2, Ut]
+            self.alphas.append(alpha)
+            self.ms.append(m)
+        opts = PCGOpts()
+        lib().krr_pcg_defaults(ctypes.byref(opts))
+        opts.tol, opts.max_iter, opts.prec = float(tol), int(max_iter), PREC["f16x3"]
+        opts.use_precond, opts.check_every = int(bool(use_precond)), int(check_every)
+        opts.true_residual, opts.refine = int(bool(true_residual)), int(refine)
+        self._problems = arr
+        self._handle = _vp(None)
+        st = lib().krr_batch_plan_create(arr, n_p, ctypes.byref(opts), ctypes.byref(self._handle),
+                                         _stream())
+        _raise(st)
+        self.count = n_p
+
+    def solve(self, raise_on_error: bool = True):
+        """Run PCG on every problem; returns (alphas, BatchSolveReport)."""
+        if not self._handle:
+            raise RuntimeError("plan destroyed")
+        k = self.count * BATCH_MAX_M
+        rec, tru = (_dbl * k)(), (_dbl * k)()
+        rep = BatchReport()
+        rep.relres_rec = ctypes.cast(rec, ctypes.POINTER(_dbl))
+        rep.relres_true = ctypes.cast(tru, ctypes.POINTER(_dbl))
+        st = lib().krr_batch_solve(self._handle, ctypes.byref(rep), _stream())
+        per = lambda a: [[a[i * BATCH_MAX_M + c] for c in range(m)] for i, m in enumerate(self.ms)]
+        report = BatchSolveReport(st, rep.iters, rep.converged_cols, rep.breakdown_cols,
+                                  rep.refine_steps, per(rec),
+                                  per(tru), rep.product_ms, rep.iteration_ms, rep.tiles_per_item,
+                                  rep.work_items)
+        if raise_on_error and st != OK:
+            raise KRRError(st, last_error(), report)
+        return self.alphas, report
+
+    def close(self):
+        if self._handle:
+            lib().krr_batch_plan_destroy(self._handle)
+            self._handle = _vp(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def rff_scale(s: int) -> float:

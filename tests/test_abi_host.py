@@ -107,3 +107,63 @@ def test_python_binding_rejects_host_tensors():
     import torch
     with pytest.raises(TypeError):
         krr.kernel_matmat(torch.zeros(4, 2), torch.zeros(4, 2), 1.0, torch.zeros(4, 1, dtype=torch.float64))
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, compiled with gcc against include/krr.h."""
+    import subprocess
+    import tempfile
+    body = "\n".join(f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = (f'#include <stddef.h>\n#include <stdio.h>\n#include "krr.h"\nint main(void) {{\n'
+           f'  printf("%zu\\n", sizeof({struct}));\n{body}\n  return 0;\n}}\n')
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("struct,cls", [("krr_pcg_opts", krr.PCGOpts),
+                                        ("krr_pcg_report", krr.PCGReport),
+                                        ("krr_batch_problem", krr.BatchProblem),
+                                        ("krr_batch_report", krr.BatchReport)])
+def test_binding_structs_match_header_layout(struct, cls):
+    names = [f[0] for f in cls._fields_]
+    cnames = ["lambda" if n == "lam" else n for n in names]
+    got = _c_layout(struct, cnames)
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, n).offset for n in names]
+
+
+def test_batch_plan_validation_before_device_work():
+    L = krr.lib()
+    fake = ctypes.c_void_p(256)
+    probs = (krr.BatchProblem * 2)()
+    for p in probs:
+        p.X, p.n, p.d, p.ldx, p.sigma, p.lam = fake, 100, 3, 3, 1.0, 1.0
+        p.Y, p.ldy, p.alpha, p.lda, p.m = fake, 2, fake, 2, 2
+    o = krr.PCGOpts()
+    L.krr_pcg_defaults(ctypes.byref(o))
+    h = ctypes.c_void_p(None)
+    probs[1].m, probs[1].ldy, probs[1].lda = 17, 17, 17
+    st = L.krr_batch_plan_create(probs, 2, ctypes.byref(o), ctypes.byref(h), None)
+    assert st == krr.E_ARG and "problem 1" in krr.last_error() and not h
+    probs[1].m, probs[1].ldy, probs[1].lda = 2, 2, 2
+    probs[0].sigma = -1.0
+    st = L.krr_batch_plan_create(probs, 2, ctypes.byref(o), ctypes.byref(h), None)
+    assert st == krr.E_ARG and "sigma" in krr.last_error()
+    probs[0].sigma = 1.0
+    probs[0].Ut, probs[0].s, probs[0].ldu = fake, 100, 100
+    st = L.krr_batch_plan_create(probs, 2, ctypes.byref(o), ctypes.byref(h), None)
+    assert st == krr.E_ARG and "s < n" in krr.last_error()
+    probs[0].Ut = None
+    o.prec = 0
+    st = L.krr_batch_plan_create(probs, 2, ctypes.byref(o), ctypes.byref(h), None)
+    assert st == krr.E_ARG and "F16X3" in krr.last_error()
+    o.prec = 1
+    st = L.krr_batch_plan_create(probs, 0, ctypes.byref(o), ctypes.byref(h), None)
+    assert st == krr.E_ARG
+    st = L.krr_batch_solve(None, None, None)
+    assert st == krr.E_ARG
+    L.krr_batch_plan_destroy(None)

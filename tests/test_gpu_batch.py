@@ -1,0 +1,147 @@
+"""GPU parity of the batched solve: many independent problems of uneven size through one
+persistent kernel-product launch per iteration (captured iteration graph), each problem
+checked against the CPU FP64 oracle.
+
+Bar: every column of every problem meets the tolerance in the oracle's FP64 true residual
+||y - (K + lambda I) alpha|| / ||y||, and the library's own FP64 true residual agrees with
+the oracle's. Batched products run FP16 hi/lo split with FP32 exp, so on the small-lambda
+problems (condition numbers near 1e6) the solve certifies 1e-6 through FP64-residual
+refinement, as the single-problem solve does.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1611_03220_amd import krr
+from paper_1611_03220_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    krr.lib()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _problems(ws, dev, precond=True):
+    out = []
+    for w in ws:
+        X = _t(w.X, dev)
+        p = {"X": X, "sigma": w.sigma, "lam": w.lam, "Y": _t(w.Y, dev)}
+        if precond and w.s >= 1 and w.s < w.n:
+            Z = krr.features(X, _t(w.W, dev), _t(w.b, dev))
+            _, Ut = krr.precond_factor(Z, w.lam)
+            p["Ut"] = Ut
+        out.append(p)
+    return out
+
+
+def _check_against_oracle(ws, alphas, rep, tol):
+    for i, (w, a) in enumerate(zip(ws, alphas)):
+        rel = O.relres_true(w.X, w.sigma, w.lam, a.cpu().numpy(), w.Y)
+        assert rel.max() <= tol, (i, w.n, w.d, w.lam, rel)
+        np.testing.assert_allclose(rep.relres_true[i], rel, rtol=2e-3, atol=1e-13)
+
+
+def test_batch_reduced_uneven_instances(dev):
+    """The batched recipe (n log-uniform, d in {16, 32, 64, 128}, s = n/8, 1-4 right-hand
+    sides, lambda log-uniform in [1e-6, 1e-2] n) at 12 problems of 300-3000 points."""
+    ws = WL.batched_instances(count=12, n_lo=300, n_hi=3000, salt=1)
+    plan = krr.BatchPlan(_problems(ws, dev), tol=1e-6, refine=4)
+    alphas, rep = plan.solve()
+    assert rep.work_items > 0 and rep.tiles_per_item in (4, 8, 16, 32)
+    assert rep.breakdown_cols == 0
+    _check_against_oracle(ws, alphas, rep, 1e-6)
+    plan.close()
+
+
+def test_batch_edge_shapes(dev):
+    """Degenerate members: n = 2 without a preconditioner, a ragged n = 70 with s = 8, the
+    widest m = 16, d = 1 and d = 200 (several 32-wide feature chunks), one column only."""
+    rng = np.random.default_rng(7)
+    ws = []
+    for n, d, m, s in [(2, 3, 1, 0), (70, 5, 2, 8), (1000, 16, 16, 125), (513, 1, 1, 64),
+                       (600, 200, 3, 75), (129, 64, 4, 0)]:
+        X = rng.standard_normal((n, d)).astype(np.float32)
+        Y = rng.standard_normal((n, m))
+        sigma = math.sqrt(d)
+        W = (rng.standard_normal((d, max(s, 1))) / sigma).astype(np.float32)
+        b = rng.uniform(0, 2 * math.pi, max(s, 1)).astype(np.float32)
+        ws.append(WL.Workload(f"edge_{n}_{d}", X, Y, sigma, 0.01 * n, s, W, b, 1e-8))
+    plan = krr.BatchPlan(_problems(ws, dev), tol=1e-8, refine=4)
+    alphas, rep = plan.solve()
+    _check_against_oracle(ws, alphas, rep, 1e-8)
+    for w, a in zip(ws, alphas):
+        assert a.shape == (w.n, w.m)
+
+
+def test_batch_matches_single_solves_and_is_deterministic(dev):
+    """Each problem's batched solution equals its own single-problem solve to the accuracy
+    both certify; two solves of one plan give bitwise identical results; new contents of Y
+    (same memory) are picked up by the next solve."""
+    ws = WL.batched_instances(count=5, n_lo=500, n_hi=2000, salt=2)
+    probs = _problems(ws, dev)
+    plan = krr.BatchPlan(probs, tol=1e-7, refine=4)
+    a1 = [a.clone() for a in plan.solve()[0]]
+    a2 = [a.clone() for a in plan.solve()[0]]
+    for x, y in zip(a1, a2):
+        assert torch.equal(x, y)
+    for p, w, a in zip(probs, ws, a1):
+        s_alpha, _ = krr.pcg_solve(p["X"], w.sigma, w.lam, p["Ut"], p["Y"], tol=1e-7, refine=4)
+        K = O.gaussian_kernel(w.X, w.X, w.sigma) + w.lam * np.eye(w.n)
+        kappa = np.linalg.cond(K)
+        diff = np.linalg.norm(a.cpu().numpy() - s_alpha.cpu().numpy())
+        assert diff <= 2 * kappa * 1e-7 * np.linalg.norm(s_alpha.cpu().numpy()), (w.n, kappa)
+    for p in probs:
+        p["Y"].mul_(-2.0)
+    a3, rep = plan.solve()
+    for x, y in zip(a1, a3):
+        torch.testing.assert_close(y, -2.0 * x, rtol=0, atol=1e-5 * float(x.abs().max()))
+
+
+def test_batch_unpreconditioned_and_breakdown(dev):
+    """use_precond = False runs plain CG on every member; a NaN right-hand side breaks down
+    that column only, while every other column still converges."""
+    ws = WL.batched_instances(count=4, n_lo=300, n_hi=800, salt=3)
+    for w in ws:
+        w.lam = max(w.lam, 0.05 * w.n)  # plain CG needs a moderate condition number
+    probs = _problems(ws, dev)
+    plan = krr.BatchPlan(probs, tol=1e-6, use_precond=False, refine=3)
+    alphas, rep = plan.solve()
+    _check_against_oracle(ws, alphas, rep, 1e-6)
+    plan.close()
+    probs[2]["Y"][3, 0] = float("nan")
+    plan = krr.BatchPlan(probs, tol=1e-6)
+    with pytest.raises(krr.KRRError) as e:
+        plan.solve()
+    rep = e.value.report
+    total = sum(w.m for w in ws)
+    assert e.value.status == krr.E_BREAKDOWN
+    assert rep.breakdown_cols == 1 and rep.converged_cols == total - 1
+
+
+def test_batch_full_recipe(dev):
+    """The full batched workload: 64 problems, n in [1024, 16384], s = n/8, to 1e-6. The
+    library's FP64 true residuals meet the tolerance; the oracle's residual on sampled rows
+    of three problems agrees."""
+    ws = WL.batched_instances()
+    probs = _problems(ws, dev)
+    plan = krr.BatchPlan(probs, tol=1e-6, refine=4)
+    alphas, rep = plan.solve()
+    assert max(max(r) for r in rep.relres_true) <= 1e-6
+    for i in (0, 31, 63):
+        w, a = ws[i], alphas[i].cpu().numpy()
+        rows = np.sort(np.random.default_rng(i).choice(w.n, min(w.n, 48), replace=False))
+        r = w.Y[rows] - O.kernel_matmat(w.X, w.X, w.sigma, a, shift=w.lam, rows=rows)
+        est = np.linalg.norm(r, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
+        assert est.max() <= 4e-6, (i, est)
