@@ -9,8 +9,11 @@ true residual at exit. Inputs are seeded synthetic data resident in HBM before t
 
 Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algorithmic
 kernel-product flops 2 n^2 (d + m) of all products in the timed steps divided by the
-timed wall time. `roofline` describes the dominant kernel (the fused kernel product),
-timed with HIP events inside the library on the stream it runs on. `fp64_path` is the
+timed wall time. `roofline` describes the dominant kernel (the fused kernel product) against
+the dense FP16 MFMA peak: algorithmic flops per launch over the average launch time, timed with
+HIP events inside the library on the stream it runs on; the executed MFMA work (three split
+products over padded widths) is reported beside it. `batched` is the solve of 64 uneven
+problems in one plan (persistent product, captured iteration graph). `fp64_path` is the
 same solve with the plain FP64 kernel product (time to tolerance), measured once after
 the timed steps. `cpu_baseline` times the CPU FP64 oracle's kernel product on a row
 sample on this host.
@@ -31,7 +34,7 @@ sys.path.insert(0, ROOT)
 PEAK_MFMA_F16 = 2.5e15          # dense FP16/BF16 MFMA flop/s
 PEAK_HBM = 8.0e12               # bytes/s
 CUS, CLOCK = 256, 2.4e9
-PEAK_EXP = CUS * 32 * CLOCK     # FP32 transcendental ops/s: half of the 64-lane VALU rate
+PEAK_EXP = CUS * 32 * CLOCK     # FP32 exp2 per second: 32 lanes per clock per CU
 
 
 def parse():
@@ -43,7 +46,73 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-problems solve")
+    ap.add_argument("--calib-bytes", type=int, default=0,
+                    help="run a plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
+
+
+def source_sha256(rel):
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def recorded_traffic(kernel_src):
+    """HBM bytes per launch of the kernel product from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_matmat_f16pv_mixture_n65536.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_sha256(kernel_src):
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batched_run(dev):
+    """The batched workload: 64 independent problems (n log-uniform in [1024, 16384], d in
+    {16, 32, 64, 128}, s = n/8, 1-4 right-hand sides) solved to 1e-6 together."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+    ws = WL.batched_instances()
+    t0 = time.perf_counter()
+    probs = []
+    for w in ws:
+        X = torch.from_numpy(w.X).to(dev)
+        Z = krr.features(X, torch.from_numpy(w.W).to(dev), torch.from_numpy(w.b).to(dev))
+        _, Ut = krr.precond_factor(Z, w.lam)
+        del Z
+        probs.append({"X": X, "sigma": w.sigma, "lam": w.lam, "Ut": Ut,
+                      "Y": torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)})
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan = krr.BatchPlan(probs, tol=1e-6, refine=4)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    _, rep = plan.solve(raise_on_error=False)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    flops = sum(2.0 * w.n * w.n * (w.d + w.m) for w in ws)
+    out = {"workload": "64 uneven problems, n in [1024, 16384], d in {16,32,64,128}, s = n/8",
+           "status": rep.status, "time_to_tol_s": t3 - t2, "setup_features_factor_s": t1 - t0,
+           "plan_create_s": t2 - t1, "iterations": rep.iters, "refine_steps": rep.refine_steps,
+           "relres_true_max": max(max(r) for r in rep.relres_true),
+           "product_ms": rep.product_ms, "iteration_ms": rep.iteration_ms,
+           "product_tflops_algorithmic": flops / (rep.product_ms * 1e-3) / 1e12,
+           "tiles_per_item": rep.tiles_per_item, "work_items": rep.work_items,
+           "sum_n": int(sum(w.n for w in ws))}
+    plan.close()
+    return out
 
 
 def cpu_baseline(w, seconds):
@@ -92,6 +161,15 @@ def main():
     W = torch.from_numpy(w.W).to(dev)
     b = torch.from_numpy(w.b).to(dev)
     torch.cuda.synchronize()
+    if args.calib_bytes > 0:
+        # a plain copy kernel of known size: what the byte counters read for it calibrates
+        # the counters of the kernels profiled in the same run
+        src = torch.ones(args.calib_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step(prec):
         Z = krr.features(X, W, b)
@@ -115,18 +193,23 @@ def main():
     mm_ms = sum(r.matmat_ms for r in reps)
     avg_launch_s = mm_ms / max(calls, 1) / 1e3
     pairs = float(n) * n
-    kp = int(math.ceil((d + 2) / 32.0) * 32)
-    exec_mfma = pairs * 3 * 2 * kp
-    t_mfma = flops_mm / PEAK_MFMA_F16
-    t_exp = pairs / PEAK_EXP
-    roof = {"bound": "alu", "achieved": pairs / avg_launch_s / 1e12, "peak": PEAK_EXP / 1e12,
-            "unit": "TFLOP/s", "frac": (pairs / avg_launch_s) / PEAK_EXP, "traffic": None,
-            "kernel": "matmat_mixed_kernel (FP16 hi/lo split MFMA distances + exp2 + V accumulate)",
-            "op_counted": "one FP32 exp per kernel entry (n^2 per launch)",
-            "avg_launch_ms": avg_launch_s * 1e3, "launches": calls,
-            "algorithmic_mfma_tflops": flops_mm / avg_launch_s / 1e12,
+    kp = int(math.ceil((d + 2) / 32.0) * 32)        # augmented, padded feature width
+    mp = int(math.ceil(m / 16.0) * 16)              # padded right-hand-side columns
+    exec_mfma = pairs * 3 * 2 * (kp + mp)           # split-3 distances + split-3 P V
+    roof = {"bound": "mfma", "achieved": flops_mm / avg_launch_s / 1e12,
+            "peak": PEAK_MFMA_F16 / 1e12, "unit": "TFLOP/s",
+            "frac": flops_mm / avg_launch_s / PEAK_MFMA_F16,
+            "traffic": recorded_traffic("paper_1611_03220_amd/csrc/matmat.hip"),
+            "kernel": "matmat_f16pv_kernel (FP16 hi/lo split MFMA distances, FP32 exp2, "
+                      "split MFMA accumulation of K V, FP64 partial sums)",
+            "algorithmic_flops_per_launch": flops_mm, "avg_launch_ms": avg_launch_s * 1e3,
+            "launches": calls,
+            "executed_mfma_flops_per_launch": exec_mfma,
             "executed_mfma_tflops": exec_mfma / avg_launch_s / 1e12,
-            "model_ms": {"mfma_algorithmic": t_mfma * 1e3, "exp": t_exp * 1e3}}
+            "executed_frac": exec_mfma / avg_launch_s / PEAK_MFMA_F16,
+            "exp_per_s": pairs / avg_launch_s, "exp_peak_per_s": PEAK_EXP,
+            "exp_frac": pairs / avg_launch_s / PEAK_EXP,
+            "timed_with": "HIP events on the library's stream around every product launch"}
     relres_true = max(max(r.relres_true) for r in reps)
     iters = [r.iters for r in reps]
     out = {
@@ -156,6 +239,12 @@ def main():
                             "kernel_matmat_tflops": flops_mm * r64.matmat_calls / max(r64.matmat_ms, 1e-9) * 1e-9,
                             "speedup_mixed_vs_fp64": t64 / (wall / args.steps)}
         print(f"[bench] fp64 path {t64:.3f} s", file=sys.stderr, flush=True)
+    if not args.no_batched:
+        del X, Y, W, b
+        torch.cuda.empty_cache()
+        out["batched"] = batched_run(dev)
+        print(f"[bench] batched solve {out['batched']['time_to_tol_s']:.3f} s", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
