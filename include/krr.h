@@ -63,7 +63,8 @@ typedef enum krr_op {
   KRR_OP_PRECOND_FACTOR = 1,
   KRR_OP_KERNEL_MATMAT = 2,
   KRR_OP_PCG_SOLVE = 3,
-  KRR_OP_GRAD = 4
+  KRR_OP_GRAD = 4,
+  KRR_OP_PRECOND_APPLY = 5
 } krr_op;
 
 /*
@@ -119,6 +120,20 @@ krr_status krr_features(const float* X, int64_t n, int64_t d, int64_t ldx, const
 krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
                               double* C, float* Ut, int64_t ldu, void* ws, size_t ws_bytes,
                               int64_t* info, void* stream);
+
+/*
+ * krr_precond_apply -- the preconditioner step of the PCG in Alg. 1, in the Woodbury form of
+ * Sec. 3.1:  Zout = (Z Z^T + lambda_p I)^{-1} R = (R - Ut (Ut^T R)) / lambda_p.
+ *   Ut : n x s FP32 from krr_precond_factor (ldu >= s), s < n.
+ *   R  : n x m FP64 (ldr >= m);  Zout: n x m FP64 (ldz >= m), must not alias R.
+ *   lambda_p : > 0, the value Ut was built with.
+ * Two streaming passes over Ut with FP64 accumulation (workspace: krr_workspace_bytes with
+ * KRR_OP_PRECOND_APPLY, n1 = n, s, m). Asynchronous on `stream`. Errors: KRR_E_ARG,
+ * KRR_E_WORKSPACE.
+ */
+krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu, double lambda_p,
+                             const double* R, int64_t m, int64_t ldr, double* Zout, int64_t ldz,
+                             void* ws, size_t ws_bytes, void* stream);
 
 /*
  * krr_kernel_matmat -- matrix-free kernel product (the per-iteration product of the PCG in
@@ -247,6 +262,7 @@ typedef struct krr_batch_report {
   double* relres_rec;      /* host[count * KRR_BATCH_MAX_M] or NULL: problem p column c at
                               p * KRR_BATCH_MAX_M + c (recursive residual) */
   double* relres_true;     /* same layout, FP64 true residual (opts->true_residual) or NULL */
+  int32_t* col_iters;      /* same layout or NULL: iterations of each column's first solve */
   double product_ms;       /* device time of one batched kernel product (autotuned) */
   double iteration_ms;     /* average device time of one replayed iteration graph */
   int32_t tiles_per_item;  /* autotuned work-item size, in 64-column tiles */

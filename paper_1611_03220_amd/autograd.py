@@ -11,7 +11,8 @@ KRRSolve:      alpha = (K(X; sigma) + lambda I)^{-1} Y by preconditioned CG (Eq.
                dL/dsigma is the difference of two terms that nearly cancel (here by two orders of
                magnitude), so its dK/dsigma products run in FP64 (`deriv_prec`) while both solves
                may run mixed.
-KernelMatmat:  OUT = K(X1, X2; sigma) V (e.g. validation predictions). Backward:
+KernelMatmat:  OUT = K(X1, X2; sigma) V (e.g. validation predictions; the loss below runs this
+               forward product in FP64 because the validation residual cancels). Backward:
                  dL/dV     = K(X2, X1) G,
                  dL/dsigma = <G, (dK/dsigma) V>.
 All arithmetic runs in libkrr; these classes only route tensors.
@@ -54,9 +55,9 @@ class KRRSolve(torch.autograd.Function):
 
 class KernelMatmat(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, sigma, X1, X2, V, prec, deriv_prec):
+    def forward(ctx, sigma, X1, X2, V, prec, deriv_prec, fwd_prec):
         s = _scalar(sigma)
-        out = krr.kernel_matmat(X1, X2, s, V, prec=prec)
+        out = krr.kernel_matmat(X1, X2, s, V, prec=fwd_prec or prec)
         ctx.save_for_backward(X1, X2, V)
         ctx.sig, ctx.prec, ctx.deriv_prec = s, prec, deriv_prec
         return out
@@ -68,7 +69,7 @@ class KernelMatmat(torch.autograd.Function):
         gV = krr.kernel_matmat(X2, X1, ctx.sig, G, prec=ctx.prec)
         dK = krr.kernel_matmat(X1, X2, ctx.sig, V, deriv=True, prec=ctx.deriv_prec)
         gs = (G * dK).sum()
-        return gs, None, None, gV, None, None
+        return gs, None, None, gV, None, None, None
 
 
 def krr_solve(X, Y, sigma, lam, Ut=None, **opts):
@@ -80,14 +81,19 @@ def krr_solve(X, Y, sigma, lam, Ut=None, **opts):
     return KRRSolve.apply(sigma, lam, X, Y, Ut, opts)
 
 
-def kernel_matmat(X1, X2, sigma, V, prec="f16x3", deriv_prec="fp64"):
-    """Differentiable K(X1, X2; sigma) V (dK/dsigma products in `deriv_prec`)."""
-    return KernelMatmat.apply(sigma, X1, X2, V, prec, deriv_prec)
+def kernel_matmat(X1, X2, sigma, V, prec="f16x3", deriv_prec="fp64", fwd_prec=None):
+    """Differentiable K(X1, X2; sigma) V: forward in `fwd_prec` (default `prec`), the
+    transposed product of the backward in `prec`, dK/dsigma products in `deriv_prec`."""
+    return KernelMatmat.apply(sigma, X1, X2, V, prec, deriv_prec, fwd_prec)
 
 
 def validation_loss(Xtr, Ytr, Xv, Yv, sigma, lam, Ut=None, prec="f16x3", deriv_prec="fp64",
                     **opts):
-    """L = 1/2 ||K(Xv, Xtr) alpha - Yv||_F^2 with alpha from the differentiable solve."""
+    """L = 1/2 ||K(Xv, Xtr) alpha - Yv||_F^2 with alpha from the differentiable solve.
+    The residual K(Xv, Xtr) alpha - Yv cancels most of the prediction when the model fits,
+    so the prediction product runs in `deriv_prec` (FP64 by default), like the dK/dsigma
+    products; the solves and the transposed product of the backward run in `prec`."""
     alpha = krr_solve(Xtr, Ytr, sigma, lam, Ut, prec=prec, deriv_prec=deriv_prec, **opts)
-    pred = kernel_matmat(Xv, Xtr, sigma, alpha, prec=prec, deriv_prec=deriv_prec)
+    pred = kernel_matmat(Xv, Xtr, sigma, alpha, prec=prec, deriv_prec=deriv_prec,
+                         fwd_prec=deriv_prec)
     return 0.5 * ((pred - Yv) ** 2).sum()

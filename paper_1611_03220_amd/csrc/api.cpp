@@ -315,6 +315,18 @@ struct GradLayout {
   double* w;
   double* part;
 };
+struct ApplyLayout {
+  double *part, *T, *r, *z;
+  int nchunk;
+};
+void layout_apply(Bump& b, ApplyLayout& L, int64_t n, int64_t s, int64_t m) {
+  L.nchunk = precond_nchunk(n, s);
+  L.part = b.take<double>((int64_t)L.nchunk * std::max<int64_t>(s, 1) * m);
+  L.T = b.take<double>(std::max<int64_t>(s, 1) * m);
+  L.r = b.take<double>(n * m);  // contiguous copies when the caller's are strided
+  L.z = b.take<double>(n * m);
+}
+
 void layout_grad(Bump& b, GradLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
   layout_matmat(b, L.mm, n, n, d, m, prec, true);
   L.af = b.take<float>(round_up(n, ROW_PAD) * m);
@@ -359,6 +371,7 @@ size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_
     }
     case KRR_OP_PCG_SOLVE: { PCGLayout L; layout_pcg(b, L, n1, d, s, m, prec); break; }
     case KRR_OP_GRAD: { GradLayout L; layout_grad(b, L, n1, d, m, prec); break; }
+    case KRR_OP_PRECOND_APPLY: { ApplyLayout L; layout_apply(b, L, n1, s, m); break; }
     default: return 0;
   }
   return b.off + 256;
@@ -440,6 +453,34 @@ krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz,
   CHECK_HIP(gemm_nt_f16x3(A, B, n, s, L.sk, 1, EPI_F32, 0, 1, 1.0, nullptr, 0, Ut, ldu, nullptr,
                           0.0f, st));
   CHECK_HIP(hipStreamSynchronize(st));
+  return KRR_OK;
+}
+
+// ---------------------------------------------------------------- precond apply
+krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu, double lambda_p,
+                             const double* R, int64_t m, int64_t ldr, double* Zout, int64_t ldz,
+                             void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!Ut || !R || !Zout) return fail(KRR_E_ARG, "krr_precond_apply: null pointer");
+  if (n < 2 || s < 1 || s >= n || ldu < s || m < 1 || ldr < m || ldz < m)
+    return fail(KRR_E_ARG, "krr_precond_apply: need 1 <= s < n, m >= 1 and ld >= width");
+  if (!(lambda_p > 0.0) || !std::isfinite(lambda_p))
+    return fail(KRR_E_ARG, "krr_precond_apply: lambda_p must be > 0");
+  if (static_cast<const void*>(R) == static_cast<const void*>(Zout))
+    return fail(KRR_E_ARG, "krr_precond_apply: Zout must not alias R");
+  CHECK_ST(check_ws(ws, ws_bytes, krr_workspace_bytes(KRR_OP_PRECOND_APPLY, n, n, 0, s, m, 0)));
+  Bump bb(ws);
+  ApplyLayout L;
+  layout_apply(bb, L, n, s, m);
+  hipStream_t st = (hipStream_t)stream;
+  const double* r = R;
+  if (ldr != m) {
+    CHECK_HIP(copy2d(R, ldr, L.r, m, n, m, st));
+    r = L.r;
+  }
+  double* z = ldz == m ? Zout : L.z;
+  CHECK_HIP(precond_apply(Ut, ldu, n, s, m, lambda_p, r, z, L.part, L.nchunk, L.T, st));
+  if (ldz != m) CHECK_HIP(copy2d(L.z, m, Zout, ldz, n, m, st));
   return KRR_OK;
 }
 
@@ -916,12 +957,12 @@ int64_t kpart_elems(krr_batch_plan* P, int g) {
 }
 
 hipError_t batch_product(krr_batch_plan* P, hipStream_t st) {
-  hipError_t e = batch_split_v(P->row_inst, P->meta, P->count, P->N, P->M, P->pf, P->red, P->nred,
-                               P->colmax, P->Vth, P->Vtl, P->vscale, st);
+  hipError_t e = batch_split_v(P->row_inst, P->meta, P->S.live, P->count, P->N, P->M, P->pf,
+                               P->red, P->nred, P->colmax, P->Vth, P->Vtl, P->vscale, st);
   if (e != hipSuccess) return e;
   e = matmat_batch(P->items, P->nitems, P->inst, P->S.live, P->counter, P->grid, st);
   if (e != hipSuccess) return e;
-  return batch_finalize(P->meta, P->row_inst, P->N, P->M, P->pf, P->q, st);
+  return batch_finalize(P->meta, P->row_inst, P->S.live, P->N, P->M, P->pf, P->q, st);
 }
 
 // One PCG iteration for every problem (the captured graph body).
@@ -929,15 +970,15 @@ hipError_t batch_iteration(krr_batch_plan* P, hipStream_t st) {
   const int M = P->M;
   hipError_t e;
   if ((e = batch_product(P, st))) return e;
-  if ((e = batch_dot<float, double>(P->pf, P->q, M, P->red, P->nred, P->part_pq, st))) return e;
+  if ((e = batch_dot<float, double>(P->pf, P->q, M, P->red, P->nred, P->S.live, P->part_pq, st))) return e;
   if ((e = batch_alpha(P->meta, P->count, M, P->part_pq, P->S, st))) return e;
   if ((e = batch_update_xr(P->row_inst, P->N, M, P->S.alpha, P->pf, P->q, P->x, P->r, st))) return e;
-  if ((e = batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->part_rr, st))) return e;
+  if ((e = batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->S.live, P->part_rr, st))) return e;
   if ((e = batch_conv(P->meta, P->count, M, P->part_rr, P->S, st))) return e;
   if ((e = batch_precond(P->meta, P->count, P->pitems, P->npitems, P->zitems, P->nzitems, P->smax,
-                         P->r, M, P->pc_part, P->T, P->z, st)))
+                         P->S.live, P->r, M, P->pc_part, P->T, P->z, st)))
     return e;
-  if ((e = batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->part_rz, st))) return e;
+  if ((e = batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->S.live, P->part_rz, st))) return e;
   if ((e = batch_beta(P->meta, P->count, M, P->part_rz, P->part_rr, P->S, st))) return e;
   return batch_update_p(P->row_inst, P->N, M, P->S.beta, P->S.active, 0, P->z, P->p, P->pf, st);
 }
@@ -1246,10 +1287,11 @@ void krr_batch_plan_destroy(krr_batch_plan* plan) { plan_free(plan); }
 static krr_status batch_pcg(krr_batch_plan* P, int* iters, double* ms, hipStream_t st) {
   const int M = P->M;
   CHECK_HIP(fill_f64(P->x, P->N * M, 0.0, st));
-  CHECK_HIP(batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->part_yy, st));
+  CHECK_HIP(fill_i32(P->S.live, P->count, 1, st));  // start-up reductions cover every problem
+  CHECK_HIP(batch_dot<double, double>(P->r, P->r, M, P->red, P->nred, P->S.live, P->part_yy, st));
   CHECK_HIP(batch_precond(P->meta, P->count, P->pitems, P->npitems, P->zitems, P->nzitems, P->smax,
-                          P->r, M, P->pc_part, P->T, P->z, st));
-  CHECK_HIP(batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->part_rz, st));
+                          P->S.live, P->r, M, P->pc_part, P->T, P->z, st));
+  CHECK_HIP(batch_dot<double, double>(P->r, P->z, M, P->red, P->nred, P->S.live, P->part_rz, st));
   CHECK_HIP(batch_init_scalars(P->meta, P->count, M, P->part_yy, P->part_rz, P->S, st));
   CHECK_HIP(batch_update_p(P->row_inst, P->N, M, P->S.beta, P->S.active, 1, P->z, P->p, P->pf, st));
   int h_count = 0;
@@ -1298,7 +1340,8 @@ krr_status krr_batch_solve(krr_batch_plan* P, krr_batch_report* rep, void* strea
   int total_iters = it;
   const double iter_ms = it > 0 ? ms / it : 0.0;
   std::vector<double> rn(cm), yn(cm);
-  std::vector<int> brk(cm);
+  std::vector<int> brk(cm), cit(cm);
+  CHECK_HIP(hipMemcpyAsync(cit.data(), P->S.col_iters, sizeof(int) * cm, hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipMemcpyAsync(rn.data(), P->S.rnorm, sizeof(double) * cm, hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipMemcpyAsync(yn.data(), P->S.ynorm, sizeof(double) * cm, hipMemcpyDeviceToHost, st));
   CHECK_HIP(hipMemcpyAsync(brk.data(), P->S.broken, sizeof(int) * cm, hipMemcpyDeviceToHost, st));
@@ -1311,6 +1354,7 @@ krr_status krr_batch_solve(krr_batch_plan* P, krr_batch_report* rep, void* strea
       if (brk[e]) ++nbrk;
       else if (rel <= tol) ++conv;
       if (rep && rep->relres_rec) rep->relres_rec[i * KRR_BATCH_MAX_M + c] = rel;
+      if (rep && rep->col_iters) rep->col_iters[i * KRR_BATCH_MAX_M + c] = cit[e];
     }
   // FP64 true residuals; refinement solves A delta = R for the columns above tol
   std::vector<double> rel_true(cm, 0.0);

@@ -5,6 +5,7 @@
 // deterministic: reduction items (problem, 1024-row chunk) write partials, scalar kernels sum
 // a problem's partials in item order.
 #include "batch.hpp"
+#include "woodbury.hpp"
 
 namespace krr {
 
@@ -17,8 +18,10 @@ template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void batch_dot_kernel(const TA* __restrict__ a,
                                                         const TB* __restrict__ b, int M,
                                                         const RedItem* __restrict__ items,
+                                                        const int* __restrict__ live,
                                                         double* __restrict__ part) {
   const RedItem it = items[blockIdx.x];
+  if (!live[it.inst]) return;
   __shared__ double sh[256];
   const int tid = threadIdx.x;
   const int rif = 256 / M;
@@ -38,15 +41,15 @@ __global__ __launch_bounds__(256) void batch_dot_kernel(const TA* __restrict__ a
 
 template <typename TA, typename TB>
 hipError_t batch_dot(const TA* a, const TB* b, int M, const RedItem* items, int nitems,
-                     double* part, hipStream_t st) {
-  batch_dot_kernel<TA, TB><<<nitems, 256, 0, st>>>(a, b, M, items, part);
+                     const int* live, double* part, hipStream_t st) {
+  batch_dot_kernel<TA, TB><<<nitems, 256, 0, st>>>(a, b, M, items, live, part);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 template hipError_t batch_dot<double, double>(const double*, const double*, int, const RedItem*,
-                                              int, double*, hipStream_t);
+                                              int, const int*, double*, hipStream_t);
 template hipError_t batch_dot<float, double>(const float*, const double*, int, const RedItem*,
-                                             int, double*, hipStream_t);
+                                             int, const int*, double*, hipStream_t);
 
 __device__ inline double inst_sum(const double* part, const BatchMeta& P, int M, int c) {
   double s = 0.0;
@@ -188,13 +191,15 @@ hipError_t batch_beta(const BatchMeta* meta, int count, int M, const double* par
 // ---------------------------------------------------------------- vectors
 // q[row][c] = sum_split part_p[split][lr][c] + lambda_p * pf[row][c] (zero on padding rows)
 __global__ void batch_finalize_kernel(const BatchMeta* __restrict__ meta,
-                                      const int* __restrict__ row_inst, int64_t nrows, int M,
+                                      const int* __restrict__ row_inst,
+                                      const int* __restrict__ live, int64_t nrows, int M,
                                       const float* __restrict__ pf, double* __restrict__ q) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nrows * M) return;
   const int64_t row = e / M;
   const int c = (int)(e % M);
   const int p = row_to_inst(row_inst, row);
+  if (!live[p]) return;
   const BatchMeta P = meta[p];
   const int64_t lr = row - P.off;
   double v = 0.0;
@@ -205,9 +210,10 @@ __global__ void batch_finalize_kernel(const BatchMeta* __restrict__ meta,
   q[e] = v;
 }
 
-hipError_t batch_finalize(const BatchMeta* meta, const int* row_inst, int64_t nrows, int M,
-                          const float* pf, double* q, hipStream_t st) {
-  batch_finalize_kernel<<<ceil_div(nrows * M, 256), 256, 0, st>>>(meta, row_inst, nrows, M, pf, q);
+hipError_t batch_finalize(const BatchMeta* meta, const int* row_inst, const int* live,
+                          int64_t nrows, int M, const float* pf, double* q, hipStream_t st) {
+  batch_finalize_kernel<<<ceil_div(nrows * M, 256), 256, 0, st>>>(meta, row_inst, live, nrows, M,
+                                                                  pf, q);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -265,8 +271,10 @@ hipError_t batch_update_p(const int* row_inst, int64_t nrows, int M, const doubl
 // colmax[p * 16 + c] = max |pf| over problem p's rows (reduction items), atomic max.
 __global__ __launch_bounds__(256) void batch_colmax_kernel(const float* __restrict__ pf, int M,
                                                            const RedItem* __restrict__ items,
+                                                           const int* __restrict__ live,
                                                            float* __restrict__ colmax) {
   const RedItem it = items[blockIdx.x];
+  if (!live[it.inst]) return;
   __shared__ float sh[256];
   const int tid = threadIdx.x;
   const int rif = 256 / M;
@@ -288,6 +296,7 @@ __global__ __launch_bounds__(256) void batch_colmax_kernel(const float* __restri
 // straddle problems (offsets are multiples of ROW_PAD).
 __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict__ row_inst,
                                                           const BatchMeta* __restrict__ meta,
+                                                          const int* __restrict__ live,
                                                           int64_t nrows, int M,
                                                           float* __restrict__ pf,
                                                           const float* __restrict__ colmax,
@@ -298,6 +307,7 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict_
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t r0 = (int64_t)blockIdx.x * 32;
   const int p = row_to_inst(row_inst, r0);
+  if (!live[p]) return;
   const BatchMeta P = meta[p];
   for (int e = threadIdx.x; e < 32 * 16; e += 256) {
     const int rr = e / 16, c = e % 16;
@@ -318,127 +328,94 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict_
   }
 }
 
-hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, int count, int64_t nrows,
-                         int M, float* pf, const RedItem* items, int nitems, float* colmax,
-                         _Float16* hi, _Float16* lo, float* vscale, hipStream_t st) {
+hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, const int* live, int count,
+                         int64_t nrows, int M, float* pf, const RedItem* items, int nitems,
+                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, hipStream_t st) {
   hipError_t e = fill_f32(colmax, (int64_t)count * 16, 0.0f, st);
   if (e != hipSuccess) return e;
-  batch_colmax_kernel<<<nitems, 256, 0, st>>>(pf, M, items, colmax);
+  batch_colmax_kernel<<<nitems, 256, 0, st>>>(pf, M, items, live, colmax);
   KRR_LAUNCH_CHECK();
-  batch_split_kernel<<<ceil_div(nrows, 32), 256, 0, st>>>(row_inst, meta, nrows, M, pf, colmax,
-                                                          hi, lo, vscale);
+  batch_split_kernel<<<ceil_div(nrows, 32), 256, 0, st>>>(row_inst, meta, live, nrows, M, pf,
+                                                          colmax, hi, lo, vscale);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 
 // --------------------------------------------------------- batched preconditioner
-// Pass 1: item (problem, 256 feature columns, row chunk): part[item][k][c] = sum_i Ut[i][k] r[i][c]
+// Pass 1: item (problem, 256 feature columns, row chunk): part[item chunk][k][c] for c < M.
+template <int MC>
 __global__ __launch_bounds__(256) void batch_t_partial_kernel(const PCItem* __restrict__ items,
                                                               const BatchMeta* __restrict__ meta,
-                                                              const double* __restrict__ r, int M,
+                                                              const int* __restrict__ live,
+                                                              const double* __restrict__ r,
                                                               double* __restrict__ part) {
   const PCItem it = items[blockIdx.x];
+  if (!live[it.inst]) return;
   const BatchMeta P = meta[it.inst];
-  __shared__ double sr[64][17];
-  const int64_t k = it.k0 + threadIdx.x;
-  double acc[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-  for (int64_t ib = it.i0; ib < it.i1; ib += 64) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      const int ii = e / 16, c = e % 16;
-      sr[ii][c] = (ib + ii < it.i1 && c < M) ? r[(P.off + ib + ii) * M + c] : 0.0;
-    }
-    __syncthreads();
-    const int64_t cnt = it.i1 - ib < 64 ? it.i1 - ib : 64;
-    if (k < P.s) {
-      for (int ii = 0; ii < cnt; ++ii) {
-        const double u = (double)P.Ut[(ib + ii) * P.ldu + k];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) acc[c] = fma(u, sr[ii][c], acc[c]);
-      }
-    }
-  }
-  if (k < P.s) {
-    double* out = part + it.part_off + (int64_t)it.chunk * P.s * 16 + k * 16;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) out[c] = acc[c];
-  }
+  woodbury_tpart<MC>(P.Ut, P.ldu, P.s, r + P.off * MC, MC, it.i0, it.i1, it.k0 + threadIdx.x,
+                     part + it.part_off + (int64_t)it.chunk * P.s * 16, 16);
 }
 
-// T_p[k][c] = sum over chunks; one thread per (problem, k, c) via a flat index list
-__global__ void batch_t_reduce_kernel(const BatchMeta* __restrict__ meta, int count,
+// T_p[k][c] = sum over chunks (c < M); blockIdx.y = problem
+__global__ void batch_t_reduce_kernel(const BatchMeta* __restrict__ meta,
+                                      const int* __restrict__ live, int M,
                                       const double* __restrict__ part, double* __restrict__ T) {
-  // blockIdx.y = problem
   const int p = blockIdx.y;
+  if (!live[p]) return;
   const BatchMeta P = meta[p];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (!P.has_u || e >= P.s * 16) return;
+  if (!P.has_u || e >= P.s * 16 || (int)(e % 16) >= M) return;
   double v = 0.0;
   for (int k = 0; k < P.pc_chunks; ++k) v += part[P.pc_part_off + (int64_t)k * P.s * 16 + e];
   T[P.t_off + e] = v;
 }
 
-// Pass 2: item (problem, 64-row block): z = (r - Ut T) / lambda_p (z = r without Ut)
+// Pass 2: item (problem, 64-row block): z = (r - Ut T) / lambda_p, or z = r without Ut
+template <int MC>
 __global__ __launch_bounds__(256) void batch_z_kernel(const ZItem* __restrict__ items,
                                                       const BatchMeta* __restrict__ meta,
+                                                      const int* __restrict__ live,
                                                       const double* __restrict__ T,
-                                                      const double* __restrict__ r, int M,
+                                                      const double* __restrict__ r,
                                                       double* __restrict__ z) {
+  __shared__ __attribute__((aligned(16))) float smem[woodbury_z_smem_floats(MC)];
   const ZItem it = items[blockIdx.x];
+  if (!live[it.inst]) return;
   const BatchMeta P = meta[it.inst];
-  __shared__ float su[64][65];
-  __shared__ double sT[64][17];
-  const int tid = threadIdx.x;
-  const int row = tid >> 2, sub = tid & 3;
-  const int64_t i0 = it.i0;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double* rp = r + P.off * MC;
+  double* zp = z + P.off * MC;
   if (P.has_u) {
-    for (int64_t k0 = 0; k0 < P.s; k0 += 64) {
-      __syncthreads();
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int rr = e >> 6, kk = e & 63;
-        su[rr][kk] = (i0 + rr < P.n && k0 + kk < P.s) ? P.Ut[(i0 + rr) * P.ldu + k0 + kk] : 0.0f;
-      }
-      for (int e = tid; e < 64 * 16; e += 256) {
-        const int kk = e / 16, c = e % 16;
-        sT[kk][c] = (k0 + kk < P.s) ? T[P.t_off + (k0 + kk) * 16 + c] : 0.0;
-      }
-      __syncthreads();
-      for (int kk = 0; kk < 64; ++kk) {
-        const double u = (double)su[row][kk];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = fma(u, sT[kk][sub + 4 * q], acc[q]);
-      }
-    }
-  }
-  const int64_t i = i0 + row;
-  if (i < P.n) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = sub + 4 * q;
-      if (c < M) {
-        const int64_t e = (P.off + i) * M + c;
-        z[e] = P.has_u ? (r[e] - acc[q]) * P.inv_lp : r[e];
-      }
+    woodbury_z<MC>(P.Ut, P.ldu, P.s, T + P.t_off, 16, rp, MC, P.inv_lp, zp, MC, it.i0, P.n, smem);
+  } else {
+    for (int e = threadIdx.x; e < 64 * MC; e += 256) {
+      const int64_t i = it.i0 + e / MC;
+      if (i < P.n) zp[i * MC + e % MC] = rp[i * MC + e % MC];
     }
   }
 }
 
 hipError_t batch_precond(const BatchMeta* meta, int count, const PCItem* pitems, int npitems,
-                         const ZItem* zitems, int nzitems, int64_t smax, const double* r, int M,
-                         double* part, double* T, double* z, hipStream_t st) {
-  if (npitems > 0) {
-    batch_t_partial_kernel<<<npitems, 256, 0, st>>>(pitems, meta, r, M, part);
-    KRR_LAUNCH_CHECK();
-    dim3 g(ceil_div(smax * 16, 256), count);
-    batch_t_reduce_kernel<<<g, 256, 0, st>>>(meta, count, part, T);
-    KRR_LAUNCH_CHECK();
+                         const ZItem* zitems, int nzitems, int64_t smax, const int* live,
+                         const double* r, int M, double* part, double* T, double* z,
+                         hipStream_t st) {
+  switch (M) {
+#define KRR_BP(N)                                                                            \
+  case N:                                                                                    \
+    if (npitems > 0) {                                                                       \
+      batch_t_partial_kernel<N><<<npitems, 256, 0, st>>>(pitems, meta, live, r, part);       \
+      KRR_LAUNCH_CHECK();                                                                    \
+      dim3 g(ceil_div(smax * 16, 256), count);                                               \
+      batch_t_reduce_kernel<<<g, 256, 0, st>>>(meta, live, M, part, T);                      \
+      KRR_LAUNCH_CHECK();                                                                    \
+    }                                                                                        \
+    batch_z_kernel<N><<<nzitems, 256, 0, st>>>(zitems, meta, live, T, r, z);                 \
+    KRR_LAUNCH_CHECK();                                                                      \
+    return hipSuccess;
+    KRR_BP(1) KRR_BP(2) KRR_BP(3) KRR_BP(4) KRR_BP(5) KRR_BP(6) KRR_BP(7) KRR_BP(8)
+    KRR_BP(9) KRR_BP(10) KRR_BP(11) KRR_BP(12) KRR_BP(13) KRR_BP(14) KRR_BP(15) KRR_BP(16)
+#undef KRR_BP
   }
-  batch_z_kernel<<<nzitems, 256, 0, st>>>(zitems, meta, T, r, M, z);
-  KRR_LAUNCH_CHECK();
-  return hipSuccess;
+  return hipErrorInvalidValue;
 }
 
 // packed <-> per-problem copies (rows < n_p, columns < m_p; padding zero on pack)

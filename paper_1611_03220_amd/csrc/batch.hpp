@@ -36,9 +36,11 @@ struct BatchScalars {
   double* tol;  // per (problem, column) relative tolerance; >= 1 leaves the column inactive
 };
 
+// Kernels below take `live` (per problem, 1 while any of its columns is active) and skip the
+// work of problems that have converged.
 template <typename TA, typename TB>
 hipError_t batch_dot(const TA* a, const TB* b, int M, const RedItem* items, int nitems,
-                     double* part, hipStream_t st);
+                     const int* live, double* part, hipStream_t st);
 hipError_t batch_init_scalars(const BatchMeta* meta, int count, int M, const double* part_yy,
                               const double* part_rz, BatchScalars& S, hipStream_t st);
 hipError_t batch_alpha(const BatchMeta* meta, int count, int M, const double* part_pq,
@@ -47,20 +49,21 @@ hipError_t batch_conv(const BatchMeta* meta, int count, int M, const double* par
                       BatchScalars& S, hipStream_t st);
 hipError_t batch_beta(const BatchMeta* meta, int count, int M, const double* part_rz,
                       const double* part_rr, BatchScalars& S, hipStream_t st);
-hipError_t batch_finalize(const BatchMeta* meta, const int* row_inst, int64_t nrows, int M,
-                          const float* pf, double* q, hipStream_t st);
+hipError_t batch_finalize(const BatchMeta* meta, const int* row_inst, const int* live,
+                          int64_t nrows, int M, const float* pf, double* q, hipStream_t st);
 hipError_t batch_update_xr(const int* row_inst, int64_t nrows, int M, const double* alpha,
                            const float* pf, const double* q, double* x, double* r,
                            hipStream_t st);
 hipError_t batch_update_p(const int* row_inst, int64_t nrows, int M, const double* beta,
                           const int* active, int init, const double* z, double* p, float* pf,
                           hipStream_t st);
-hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, int count, int64_t nrows,
-                         int M, float* pf, const RedItem* items, int nitems, float* colmax,
-                         _Float16* hi, _Float16* lo, float* vscale, hipStream_t st);
+hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, const int* live, int count,
+                         int64_t nrows, int M, float* pf, const RedItem* items, int nitems,
+                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, hipStream_t st);
 hipError_t batch_precond(const BatchMeta* meta, int count, const PCItem* pitems, int npitems,
-                         const ZItem* zitems, int nzitems, int64_t smax, const double* r, int M,
-                         double* part, double* T, double* z, hipStream_t st);
+                         const ZItem* zitems, int nzitems, int64_t smax, const int* live,
+                         const double* r, int M, double* part, double* T, double* z,
+                         hipStream_t st);
 // mode: BATCH_PACK_IN (caller's Y -> packed), BATCH_UNPACK_SET / BATCH_UNPACK_ADD
 // (packed -> caller's alpha, assigned or added)
 enum { BATCH_UNPACK_SET = 0, BATCH_PACK_IN = 1, BATCH_UNPACK_ADD = 2 };

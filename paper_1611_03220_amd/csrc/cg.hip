@@ -4,6 +4,7 @@
 // Reductions are two-pass and deterministic: each block writes one partial per column;
 // consumers sum the partials in block order.
 #include "kernels.hpp"
+#include "woodbury.hpp"
 
 namespace krr {
 
@@ -317,39 +318,17 @@ hipError_t add2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n
 
 // ---------------------------------------------------------- preconditioner apply
 // Pass 1: part[chunk][k][c] = sum_{i in chunk} Ut[i][k] r[i][c]. Block (kb, chunk): thread
-// t owns column k = 256 kb + t, all m columns of r in FP64 registers (m <= PC_M per pass).
+// Pass 1 (T partials over row chunks) and pass 2 (z) of the Woodbury apply; the device
+// bodies are shared with the batched solve. m columns run in passes of at most PC_M.
 constexpr int PC_M = 16;
 template <int MC>
 __global__ __launch_bounds__(256) void precond_t_partial_kernel(
     const float* __restrict__ Ut, int64_t ldu, const double* __restrict__ r, int64_t n, int64_t s,
     int64_t m, int c0, int64_t rows_per_chunk, double* __restrict__ part) {
-  __shared__ double sr[64][MC];
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
-  double acc[MC];
-#pragma unroll
-  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
-  for (int64_t ib = i0; ib < i1; ib += 64) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * MC; e += 256) {
-      const int ii = e / MC, c = e % MC;
-      sr[ii][c] = (ib + ii < i1) ? r[(ib + ii) * m + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    const int64_t cnt = i1 - ib < 64 ? i1 - ib : 64;
-    if (k < s) {
-      for (int ii = 0; ii < cnt; ++ii) {
-        const double u = (double)Ut[(ib + ii) * ldu + k];
-#pragma unroll
-        for (int c = 0; c < MC; ++c) acc[c] = fma(u, sr[ii][c], acc[c]);
-      }
-    }
-  }
-  if (k < s) {
-#pragma unroll
-    for (int c = 0; c < MC; ++c) part[((int64_t)blockIdx.y * s + k) * m + c0 + c] = acc[c];
-  }
+  woodbury_tpart<MC>(Ut, ldu, s, r + c0, m, i0, i1, k, part + (int64_t)blockIdx.y * s * m + c0, m);
 }
 
 // T[k][c] = sum_chunk part[chunk][k][c]
@@ -362,53 +341,16 @@ __global__ void precond_t_reduce_kernel(const double* __restrict__ part, int nch
   T[e] = v;
 }
 
-// Pass 2: z[i][c] = (r[i][c] - sum_k Ut[i][k] T[k][c]) / lambda_p, plus <r, z> partials.
-// Block: 64 rows; k in chunks of 64 staged through LDS (Ut tile 64 x 64, T chunk 64 x m).
-// Thread (row = t / 4, sub = t % 4) accumulates columns c = sub, sub + 4, ... for its row.
+// Pass 2: z[i][c] = (r[i][c] - sum_k Ut[i][k] T[k][c]) / lambda_p for 64-row blocks.
 template <int MC>
 __global__ __launch_bounds__(256) void precond_z_kernel(const float* __restrict__ Ut, int64_t ldu,
                                                         const double* __restrict__ T,
                                                         const double* __restrict__ r, int64_t n,
                                                         int64_t s, int64_t m, int c0,
                                                         double inv_lp, double* __restrict__ z) {
-  __shared__ float su[64][65];
-  __shared__ double sT[64][MC];
-  const int tid = threadIdx.x;
-  const int row = tid >> 2, sub = tid & 3;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  constexpr int CPT = (MC + 3) / 4;
-  double acc[CPT];
-#pragma unroll
-  for (int u = 0; u < CPT; ++u) acc[u] = 0.0;
-  for (int64_t k0 = 0; k0 < s; k0 += 64) {
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int rr = e >> 6, kk = e & 63;
-      su[rr][kk] = (i0 + rr < n && k0 + kk < s) ? Ut[(i0 + rr) * ldu + k0 + kk] : 0.0f;
-    }
-    for (int e = tid; e < 64 * MC; e += 256) {
-      const int kk = e / MC, c = e % MC;
-      sT[kk][c] = (k0 + kk < s) ? T[(k0 + kk) * m + c0 + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 64; ++kk) {
-      const double u = (double)su[row][kk];
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int c = sub + 4 * q;
-        if (c < MC) acc[q] = fma(u, sT[kk][c], acc[q]);
-      }
-    }
-  }
-  const int64_t i = i0 + row;
-  if (i < n) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int c = sub + 4 * q;
-      if (c < MC) z[i * m + c0 + c] = (r[i * m + c0 + c] - acc[q]) * inv_lp;
-    }
-  }
+  __shared__ __attribute__((aligned(16))) float smem[woodbury_z_smem_floats(MC)];
+  woodbury_z<MC>(Ut, ldu, s, T + c0, m, r + c0, m, inv_lp, z + c0, m, (int64_t)blockIdx.x * 64, n,
+                 smem);
 }
 
 hipError_t precond_apply(const float* Ut, int64_t ldu, int64_t n, int64_t s, int64_t m,

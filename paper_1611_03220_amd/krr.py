@@ -18,7 +18,7 @@ OK, E_ARG, E_NOT_SPD, E_NO_CONV, E_BREAKDOWN, E_HIP, E_WORKSPACE = range(7)
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_NOT_SPD", 3: "E_NO_CONV", 4: "E_BREAKDOWN",
                 5: "E_HIP", 6: "E_WORKSPACE"}
 PREC = {"fp64": 0, "f16x3": 1, "bf16x3": 2}
-OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD = range(5)
+OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD, OP_PRECOND_APPLY = range(6)
 
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -62,7 +62,7 @@ class BatchReport(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged_cols", _i32), ("breakdown_cols", _i32),
                 ("refine_steps", _i32),
                 ("relres_rec", ctypes.POINTER(_dbl)), ("relres_true", ctypes.POINTER(_dbl)),
-                ("product_ms", _dbl), ("iteration_ms", _dbl), ("tiles_per_item", _i32),
+                ("col_iters", ctypes.POINTER(_i32)), ("product_ms", _dbl), ("iteration_ms", _dbl), ("tiles_per_item", _i32),
                 ("work_items", _i32)]
 
 
@@ -88,6 +88,9 @@ def lib():
     L.krr_precond_factor.restype = _i32
     L.krr_precond_factor.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _vp, _sz,
                                      ctypes.POINTER(_i64), _vp]
+    L.krr_precond_apply.restype = _i32
+    L.krr_precond_apply.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _i64, _i64, _vp, _i64, _vp,
+                                    _sz, _vp]
     L.krr_kernel_matmat.restype = _i32
     L.krr_kernel_matmat.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _dbl, _vp, _i64,
                                     _i64, _vp, _i64, _i32, _i32, _vp, _sz, _vp]
@@ -110,7 +113,8 @@ def lib():
 
 
 EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_defaults",
-            "krr_features", "krr_precond_factor", "krr_kernel_matmat", "krr_pcg_solve",
+            "krr_features", "krr_precond_factor", "krr_precond_apply", "krr_kernel_matmat",
+            "krr_pcg_solve",
             "krr_grad", "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
 
 
@@ -191,6 +195,24 @@ def precond_factor(Z: torch.Tensor, lambda_p: float):
                                   _stream())
     _raise(st, info=info.value)
     return C, Ut
+
+
+def precond_apply(Ut: torch.Tensor, lambda_p: float, R: torch.Tensor) -> torch.Tensor:
+    """(Z Z^T + lambda_p I)^{-1} R = (R - Ut (Ut^T R)) / lambda_p (FP64 R and result)."""
+    _check(Ut, torch.float32, "Ut")
+    vec = R.dim() == 1
+    R2 = R[:, None] if vec else R
+    _check(R2, torch.float64, "R")
+    n, s = Ut.shape
+    m = R2.shape[1]
+    if R2.shape[0] != n:
+        raise ValueError("R rows must match Ut")
+    out = torch.empty((n, m), dtype=torch.float64, device=Ut.device)
+    ws = _ws(workspace_bytes(OP_PRECOND_APPLY, n, n, 0, s, m, 0), Ut.device)
+    st = lib().krr_precond_apply(Ut.data_ptr(), n, s, _ld(Ut), float(lambda_p), R2.data_ptr(), m,
+                                 _ld(R2), out.data_ptr(), m, ws.data_ptr(), ws.numel(), _stream())
+    _raise(st)
+    return out[:, 0] if vec else out
 
 
 def kernel_matmat(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Tensor,
@@ -318,6 +340,7 @@ class BatchSolveReport:
     refine_steps: int
     relres_rec: list       # per problem: list of its m columns
     relres_true: list
+    col_iters: list        # per problem: iterations of each column (first solve)
     product_ms: float
     iteration_ms: float
     tiles_per_item: int
@@ -382,15 +405,16 @@ class BatchPlan:
         if not self._handle:
             raise RuntimeError("plan destroyed")
         k = self.count * BATCH_MAX_M
-        rec, tru = (_dbl * k)(), (_dbl * k)()
+        rec, tru, cit = (_dbl * k)(), (_dbl * k)(), (_i32 * k)()
         rep = BatchReport()
         rep.relres_rec = ctypes.cast(rec, ctypes.POINTER(_dbl))
         rep.relres_true = ctypes.cast(tru, ctypes.POINTER(_dbl))
+        rep.col_iters = ctypes.cast(cit, ctypes.POINTER(_i32))
         st = lib().krr_batch_solve(self._handle, ctypes.byref(rep), _stream())
         per = lambda a: [[a[i * BATCH_MAX_M + c] for c in range(m)] for i, m in enumerate(self.ms)]
         report = BatchSolveReport(st, rep.iters, rep.converged_cols, rep.breakdown_cols,
                                   rep.refine_steps, per(rec),
-                                  per(tru), rep.product_ms, rep.iteration_ms, rep.tiles_per_item,
+                                  per(tru), per(cit), rep.product_ms, rep.iteration_ms, rep.tiles_per_item,
                                   rep.work_items)
         if raise_on_error and st != OK:
             raise KRRError(st, last_error(), report)

@@ -136,6 +136,23 @@ def test_binding_structs_match_header_layout(struct, cls):
     assert got[1:] == [getattr(cls, n).offset for n in names]
 
 
+def test_precond_apply_validation_before_device_work():
+    L = krr.lib()
+    fake = ctypes.c_void_p(256)
+    other = ctypes.c_void_p(512)
+    st = L.krr_precond_apply(fake, 10, 10, 10, 1.0, other, 1, 1, fake, 1, fake, 1 << 30, None)
+    assert st == krr.E_ARG and "s < n" in krr.last_error()
+    st = L.krr_precond_apply(fake, 10, 4, 4, 0.0, other, 1, 1, fake, 1, fake, 1 << 30, None)
+    assert st == krr.E_ARG and "lambda_p" in krr.last_error()
+    st = L.krr_precond_apply(fake, 10, 4, 4, 1.0, other, 2, 1, fake, 2, fake, 1 << 30, None)
+    assert st == krr.E_ARG
+    st = L.krr_precond_apply(fake, 10, 4, 4, 1.0, other, 1, 1, other, 1, fake, 1 << 30, None)
+    assert st == krr.E_ARG and "alias" in krr.last_error()
+    st = L.krr_precond_apply(fake, 10, 4, 4, 1.0, other, 1, 1, fake, 1, fake, 8, None)
+    assert st == krr.E_WORKSPACE
+    assert krr.workspace_bytes(krr.OP_PRECOND_APPLY, 65536, 65536, 0, 2048, 7, 0) > 2048 * 7 * 8
+
+
 def test_batch_plan_validation_before_device_work():
     L = krr.lib()
     fake = ctypes.c_void_p(256)

@@ -109,6 +109,22 @@ def test_batch_matches_single_solves_and_is_deterministic(dev):
         torch.testing.assert_close(y, -2.0 * x, rtol=0, atol=1e-5 * float(x.abs().max()))
 
 
+def test_batch_iteration_counts_match_single_solves(dev):
+    """Without refinement and above the mixed floor, every problem takes the iterations its
+    own single-problem solve takes (same Ut, same precision): the batched preconditioner,
+    scalars and masks reproduce the single path step for step."""
+    ws = WL.batched_instances(count=8, n_lo=400, n_hi=2500, salt=4)
+    for w in ws:
+        w.lam = max(w.lam, 1e-3 * w.n)
+    probs = _problems(ws, dev)
+    plan = krr.BatchPlan(probs, tol=1e-5, refine=0)
+    _, rep = plan.solve()
+    for i, (p, w) in enumerate(zip(probs, ws)):
+        _, r1 = krr.pcg_solve(p["X"], w.sigma, w.lam, p["Ut"], p["Y"], tol=1e-5, refine=0)
+        assert abs(max(rep.col_iters[i]) - r1.iters) <= 1, (i, rep.col_iters[i], r1.iters)
+    plan.close()
+
+
 def test_batch_unpreconditioned_and_breakdown(dev):
     """use_precond = False runs plain CG on every member; a NaN right-hand side breaks down
     that column only, while every other column still converges."""

@@ -191,6 +191,39 @@ def test_precond_factor_not_spd(dev):
 
 
 # ------------------------------------------------------------------ solves
+@pytest.mark.parametrize("n,s,m,ldr", [(3000, 256, 7, 7), (1000, 200, 1, 3), (777, 37, 20, 24),
+                                       (129, 64, 16, 16), (5000, 1000, 4, 4)])
+def test_precond_apply_parity(dev, n, s, m, ldr):
+    """Woodbury apply against the oracle on the same Ut: FP64 sums of exact FP32 products,
+    bounded by 4 (n + s) u64 (|Ut| (|Ut|^T |R|) + |R|) / lambda_p element-wise."""
+    rng = np.random.default_rng(n + s + m)
+    Ut = (rng.standard_normal((n, s)) / math.sqrt(n)).astype(np.float32)
+    Rfull = rng.standard_normal((n, ldr))
+    R = Rfull[:, :m]
+    lam_p = 0.37
+    got = krr.precond_apply(_t(Ut, dev), lam_p, _t(Rfull, dev)[:, :m])  # row stride ldr
+    ref = O.precond_apply(Ut.astype(np.float64).T, lam_p, R)
+    U = np.abs(Ut.astype(np.float64))
+    bound = 4 * (n + s) * 2.0 ** -53 * (U @ (U.T @ np.abs(R)) + np.abs(R)) / lam_p
+    assert np.all(np.abs(got.cpu().numpy() - ref) <= bound + 1e-300)
+
+
+def test_precond_apply_benchmark_size(dev):
+    """The benchmark's preconditioner (n = 65536, s = 2048, m = 7) applied to a random
+    residual, against the oracle's apply on the same Ut."""
+    w = WL.mixture_multi_rhs()
+    X = _t(w.X, dev)
+    Z = krr.features(X, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    R = np.random.default_rng(5).standard_normal((w.n, w.m))
+    got = krr.precond_apply(Ut, w.lam, _t(R, dev)).cpu().numpy()
+    Uh = Ut.cpu().numpy().astype(np.float64)
+    ref = O.precond_apply(Uh.T, w.lam, R)
+    U = np.abs(Uh)
+    bound = 4 * (w.n + w.s) * 2.0 ** -53 * (U @ (U.T @ np.abs(R)) + np.abs(R)) / w.lam
+    assert np.all(np.abs(got - ref) <= bound)
+
+
 def test_pcg_fp64_plain_workload(dev):
     """n = 2000, d = 8, s = 200, lambda = 2, FP64 to 1e-10 (the plain-method workload)."""
     w = WL.plain_fp64()
