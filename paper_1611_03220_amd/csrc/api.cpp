@@ -210,8 +210,8 @@ struct FeatLayout {
 };
 void layout_features(Bump& b, FeatLayout& L, int64_t n, int64_t d, int64_t s) {
   L.dk = round_up(d, 32);
-  L.np = round_up(n, 64);
-  L.sp = round_up(s, 64);
+  L.np = round_up(n, GEMM_TILE);
+  L.sp = round_up(s, GEMM_TILE);
   L.stats = b.take<float>(64);
   L.Xh = b.take<_Float16>(L.np * L.dk);
   L.Xl = b.take<_Float16>(L.np * L.dk);
@@ -226,7 +226,7 @@ int64_t pow2_pad(int64_t s) {
   return p;
 }
 int gram_nsplit(int64_t s, int64_t n) {
-  const int64_t t = ceil_div(s, 64);
+  const int64_t t = ceil_div(s, GEMM_TILE);
   const int64_t tiles = t * (t + 1) / 2;
   int64_t ns = ceil_div(2048, tiles);
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(n, 2048)));
@@ -244,8 +244,8 @@ struct FactorLayout {
 void layout_factor(Bump& b, FactorLayout& L, int64_t n, int64_t s) {
   L.nk = round_up(n, 32);
   L.sk = round_up(s, 32);
-  L.np = round_up(n, 64);
-  L.sp64 = round_up(s, 64);
+  L.np = round_up(n, GEMM_TILE);
+  L.sp64 = round_up(s, GEMM_TILE);
   L.s_pad = pow2_pad(s);
   L.nsplit = gram_nsplit(s, n);
   L.stats = b.take<float>(64);

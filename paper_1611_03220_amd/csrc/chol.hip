@@ -14,53 +14,77 @@ namespace krr {
 constexpr int NB = 64;
 
 // Factor the diagonal block at (k0, k0) of A (lda) in place (lower, strict upper zeroed)
-// and write its inverse into Ainv (same offsets, ld lda_inv). One wave: lane r owns row r.
+// and write its inverse into Ainv (same offsets, ld lda_inv). 256 threads.
+// Factor: right-looking in LDS; per column j one thread takes the pivot, the column below it
+// is scaled, and the trailing lower triangle takes the rank-1 update (4 threads per row).
+// Inverse: X = L^{-1} row by row, X[i][c] = (delta_ic - sum_{c<=k<i} L[i][k] X[k][c]) / L[i][i]
+// with the columns c in parallel and the k-sum split over 4 thread groups.
 // *info receives the 1-based global index of the first non-positive (or non-finite) pivot
 // if it is still 0.
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
-                                                        int64_t k0, double* __restrict__ Ainv,
-                                                        int64_t ldi, int* __restrict__ info) {
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
+                                                         int64_t k0, double* __restrict__ Ainv,
+                                                         int64_t ldi, int* __restrict__ info) {
   __shared__ double L[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
-  const int r = threadIdx.x;
-  for (int i = 0; i < NB; ++i) L[i][r] = (r <= i) ? A[(k0 + i) * lda + k0 + r] : 0.0;
+  __shared__ double part[4][NB];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int e = t; e < NB * NB; e += 256) {
+    const int i = e / NB, c = e % NB;
+    L[i][c] = (c <= i) ? A[(k0 + i) * lda + k0 + c] : 0.0;
+  }
   __syncthreads();
+  const int row = t >> 2, sub = t & 3;
   for (int j = 0; j < NB; ++j) {
-    const double dj = L[j][j];
-    if (r == 0 && (!(dj > 0.0) || !(dj < INFINITY)) && *info == 0) *info = (int)(k0 + j + 1);
-    const double ljj = sqrt(dj);
-    double lrj = 0.0;
-    if (r > j) {
-      lrj = L[r][j] / ljj;
-      L[r][j] = lrj;
+    if (t == 0) {
+      const double dj = L[j][j];
+      if (!(dj > 0.0) || !(dj < INFINITY)) {
+        if (!bad && *info == 0) *info = (int)(k0 + j + 1);
+        bad = 1;
+      }
+      L[j][j] = sqrt(dj);
     }
     __syncthreads();
-    if (r == j) L[j][j] = ljj;
-    if (r > j)
-      for (int c = j + 1; c <= r; ++c) L[r][c] -= lrj * L[c][j];
+    const double ljj = L[j][j];
+    if (t > j && t < NB) L[t][j] /= ljj;
+    __syncthreads();
+    // trailing update of rows r > j, columns j < c <= r
+    const int r = j + 1 + row;
+    if (r < NB) {
+      const double lrj = L[r][j];
+      for (int c = j + 1 + sub; c <= r; c += 4) L[r][c] -= lrj * L[c][j];
+    }
     __syncthreads();
   }
-  // inverse of the lower triangular block: lane c computes column c by forward substitution
-  {
-    const int c = r;
-    for (int i = 0; i < NB; ++i) {
-      if (i < c) { X[i][c] = 0.0; continue; }
-      double sacc = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) sacc -= L[i][k] * X[k][c];
-      X[i][c] = sacc / L[i][i];
-    }
-  }
-  __syncthreads();
+  // inverse of the lower triangular factor
+  const int c = t & 63, q = t >> 6;
   for (int i = 0; i < NB; ++i) {
-    A[(k0 + i) * lda + k0 + r] = L[i][r];
-    Ainv[(k0 + i) * ldi + k0 + r] = X[i][r];
+    double acc = 0.0;
+    if (c < i)
+      for (int k = c + q; k < i; k += 4) acc += L[i][k] * X[k][c];
+    part[q][c] = acc;
+    __syncthreads();
+    if (q == 0) {
+      double v;
+      if (c > i) v = 0.0;
+      else if (c == i) v = 1.0 / L[i][i];
+      else v = -(part[0][c] + part[1][c] + part[2][c] + part[3][c]) / L[i][i];
+      X[i][c] = v;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < NB * NB; e += 256) {
+    const int i = e / NB, cc = e % NB;
+    A[(k0 + i) * lda + k0 + cc] = cc <= i ? L[i][cc] : 0.0;
+    Ainv[(k0 + i) * ldi + k0 + cc] = X[i][cc];
   }
 }
 
 // G (s_pad x s_pad, lower part used) -> C in place; Cinv diagonal blocks filled.
 hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st) {
   for (int64_t k0 = 0; k0 < s_pad; k0 += NB) {
-    potrf_diag_kernel<<<1, 64, 0, st>>>(G, s_pad, k0, Cinv, s_pad, info);
+    potrf_diag_kernel<<<1, 256, 0, st>>>(G, s_pad, k0, Cinv, s_pad, info);
     KRR_LAUNCH_CHECK();
     const int64_t rest = s_pad - k0 - NB;
     if (rest <= 0) break;

@@ -9,6 +9,7 @@ namespace krr {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WAVE = 64;
 
@@ -16,6 +17,8 @@ constexpr int WAVE = 64;
 // (feature) dimension to a multiple of K_STEP (one 16x16x32 MFMA step).
 constexpr int ROW_PAD = 128;
 constexpr int K_STEP = 32;
+// Output tile of the split GEMMs; their operand rows are padded to a multiple of it.
+constexpr int GEMM_TILE = 128;
 
 __host__ __device__ inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -10,11 +10,16 @@
 
 namespace krr {
 
-constexpr int G_BM = 64, G_BN = 64, G_BK = 32;
-constexpr int G_LDS = G_BK + 8;
+constexpr int G_BM = GEMM_TILE, G_BN = GEMM_TILE, G_BK = 32;
 
+// Block: 128 x 128 output tile, 4 waves in 2 x 2, each wave 64 x 64 (4 x 4 MFMA blocks of
+// 16 x 16); k steps of 32 (one MFMA k). Operand tiles (hi and lo of A and B, 128 rows x 32
+// halves) are double-buffered in LDS; rows are 64 bytes whose four 16-byte pieces are XOR-
+// swizzled with (row >> 1) & 3, so the 16 rows x 4 pieces of a fragment read hit distinct
+// banks. Global loads for the next step are issued before the MFMAs of the current one.
+// Operand rows are padded to a multiple of 128 and k to a multiple of 32 (zero padding).
 template <int EPI>
-__global__ __launch_bounds__(256) void gemm_nt_f16x3_kernel(
+__global__ __launch_bounds__(256, 2) void gemm_nt_f16x3_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo, int64_t lda,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo, int64_t ldb, int64_t M,
     int64_t N, int64_t K, int64_t k_per_split, int lower_only, int tri_b,
@@ -23,40 +28,56 @@ __global__ __launch_bounds__(256) void gemm_nt_f16x3_kernel(
     const float* __restrict__ bias, float amp) {
   const int64_t bi = blockIdx.y, bj = blockIdx.x;
   if (lower_only && bj > bi) return;
-  __shared__ __attribute__((aligned(16))) _Float16 sAh[2][G_BM * G_LDS], sAl[2][G_BM * G_LDS];
-  __shared__ __attribute__((aligned(16))) _Float16 sBh[2][G_BN * G_LDS], sBl[2][G_BN * G_LDS];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int TILE = G_BM * G_BK;  // halves per operand tile
+  __shared__ __attribute__((aligned(16))) _Float16 smem[2][4][TILE];  // [buf][Ah, Al, Bh, Bl]
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lg = lane >> 4;
-  const int wr = w >> 1, wc = w & 1;  // wave owns a 32 x 32 quadrant
+  const int wr = w >> 1, wc = w & 1;
   const int64_t row0 = bi * G_BM, col0 = bj * G_BN;
-  int64_t k_begin = (int64_t)blockIdx.z * k_per_split;
+  const int64_t k_begin = (int64_t)blockIdx.z * k_per_split;
   int64_t k_end = k_begin + k_per_split < K ? k_begin + k_per_split : K;
   if (tri_b) {  // B lower triangular in (j, k): entries with k > j vanish
     const int64_t kmax = round_up(col0 + G_BN, G_BK);
     if (k_end > kmax) k_end = kmax;
   }
-  f32x4 acc[2][2];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  // each operand tile is 64 rows x 32 halves = 256 chunks of 16 bytes: one per thread
-  const int lrow = tid >> 2, lc8 = (tid & 3) * 8;
-  uint4 rah, ral, rbh, rbl;
-  auto gload = [&](int64_t k0) {
-    const int64_t oa = (row0 + lrow) * lda + k0 + lc8;
-    const int64_t ob = (col0 + lrow) * ldb + k0 + lc8;
-    rah = *reinterpret_cast<const uint4*>(Ahi + oa);
-    ral = *reinterpret_cast<const uint4*>(Alo + oa);
-    rbh = *reinterpret_cast<const uint4*>(Bhi + ob);
-    rbl = *reinterpret_cast<const uint4*>(Blo + ob);
+  // loader: 128 rows x 4 pieces = 512 pieces per operand; thread takes rows tid/4, tid/4 + 64
+  const int lr0 = tid >> 2, lp = tid & 3;
+  const int lr1 = lr0 + 64;
+  const int so0 = lr0 * G_BK + ((lp ^ ((lr0 >> 1) & 3)) * 8);
+  const int so1 = lr1 * G_BK + ((lp ^ ((lr1 >> 1) & 3)) * 8);
+  u32x4 ra[4], rb[4];  // [Ah0, Ah1, Al0, Al1], [Bh0, Bh1, Bl0, Bl1]
+  auto gload = [&](int64_t k0) __attribute__((always_inline)) {
+    const int64_t a0 = (row0 + lr0) * lda + k0 + lp * 8, a1 = (row0 + lr1) * lda + k0 + lp * 8;
+    const int64_t b0 = (col0 + lr0) * ldb + k0 + lp * 8, b1 = (col0 + lr1) * ldb + k0 + lp * 8;
+    ra[0] = *reinterpret_cast<const u32x4*>(Ahi + a0);
+    ra[1] = *reinterpret_cast<const u32x4*>(Ahi + a1);
+    ra[2] = *reinterpret_cast<const u32x4*>(Alo + a0);
+    ra[3] = *reinterpret_cast<const u32x4*>(Alo + a1);
+    rb[0] = *reinterpret_cast<const u32x4*>(Bhi + b0);
+    rb[1] = *reinterpret_cast<const u32x4*>(Bhi + b1);
+    rb[2] = *reinterpret_cast<const u32x4*>(Blo + b0);
+    rb[3] = *reinterpret_cast<const u32x4*>(Blo + b1);
   };
-  auto lstore = [&](int buf) {
-    *reinterpret_cast<uint4*>(&sAh[buf][lrow * G_LDS + lc8]) = rah;
-    *reinterpret_cast<uint4*>(&sAl[buf][lrow * G_LDS + lc8]) = ral;
-    *reinterpret_cast<uint4*>(&sBh[buf][lrow * G_LDS + lc8]) = rbh;
-    *reinterpret_cast<uint4*>(&sBl[buf][lrow * G_LDS + lc8]) = rbl;
+  auto lstore = [&](int buf) __attribute__((always_inline)) {
+    *reinterpret_cast<u32x4*>(&smem[buf][0][so0]) = ra[0];
+    *reinterpret_cast<u32x4*>(&smem[buf][0][so1]) = ra[1];
+    *reinterpret_cast<u32x4*>(&smem[buf][1][so0]) = ra[2];
+    *reinterpret_cast<u32x4*>(&smem[buf][1][so1]) = ra[3];
+    *reinterpret_cast<u32x4*>(&smem[buf][2][so0]) = rb[0];
+    *reinterpret_cast<u32x4*>(&smem[buf][2][so1]) = rb[1];
+    *reinterpret_cast<u32x4*>(&smem[buf][3][so0]) = rb[2];
+    *reinterpret_cast<u32x4*>(&smem[buf][3][so1]) = rb[3];
+  };
+  // fragment piece of row r (lane group lg reads k = 8 lg .. 8 lg + 7)
+  auto frag = [&](int buf, int op, int r) __attribute__((always_inline)) {
+    return *reinterpret_cast<const half8*>(&smem[buf][op][r * G_BK + ((lg ^ ((r >> 1) & 3)) * 8)]);
   };
   if (k_begin < k_end) {
     gload(k_begin);
@@ -65,39 +86,40 @@ __global__ __launch_bounds__(256) void gemm_nt_f16x3_kernel(
   __syncthreads();
   int buf = 0;
   for (int64_t k0 = k_begin; k0 < k_end; k0 += G_BK) {
-    if (k0 + G_BK < k_end) gload(k0 + G_BK);
-    half8 fah[2], fal[2], fbh[2], fbl[2];
+    const bool more = k0 + G_BK < k_end;
+    if (more) gload(k0 + G_BK);
+    half8 bh[4], bl[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int r = 32 * wr + 16 * a + li;
-      fah[a] = *reinterpret_cast<const half8*>(&sAh[buf][r * G_LDS + 8 * lg]);
-      fal[a] = *reinterpret_cast<const half8*>(&sAl[buf][r * G_LDS + 8 * lg]);
-      const int c = 32 * wc + 16 * a + li;
-      fbh[a] = *reinterpret_cast<const half8*>(&sBh[buf][c * G_LDS + 8 * lg]);
-      fbl[a] = *reinterpret_cast<const half8*>(&sBl[buf][c * G_LDS + 8 * lg]);
+    for (int b = 0; b < 4; ++b) {
+      const int c = 64 * wc + 16 * b + li;
+      bh[b] = frag(buf, 2, c);
+      bl[b] = frag(buf, 3, c);
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 4; ++a) {
+      const int r = 64 * wr + 16 * a + li;
+      const half8 ah = frag(buf, 0, r), al = frag(buf, 1, r);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fal[a], fbh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fah[a], fbl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fah[a], fbh[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < 4; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[b], acc[a][b], 0, 0, 0);
       }
-    if (k0 + G_BK < k_end) lstore(buf ^ 1);
+    }
+    if (more) lstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
   const float sa = split_scale(*qa), sb = split_scale(*qb);
   const double scale = alpha / ((double)sa * (double)sb);
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = row0 + 32 * wr + 16 * a + 4 * lg + r;
-        const int64_t j = col0 + 32 * wc + 16 * b + li;
+        const int64_t i = row0 + 64 * wr + 16 * a + 4 * lg + r;
+        const int64_t j = col0 + 64 * wc + 16 * b + li;
         if (i < M && j < N) {
           const double v = (double)acc[a][b][r] * scale;
           if (EPI == EPI_PART64) out64[(int64_t)blockIdx.z * out64_stride + i * ldc + j] = v;

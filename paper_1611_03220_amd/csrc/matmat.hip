@@ -253,7 +253,6 @@ constexpr int MM2_BM = 128;   // rows per block (4 waves x 32)
 constexpr int MM2_FLUSH = 2;  // tiles between FP32 -> FP64 flushes
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 // p - (float)h.x and p - (float)h.y in one mixed-precision FMA each
