@@ -66,69 +66,86 @@ template hipError_t dot_partial<double, double>(const double*, int64_t, const do
 template hipError_t dot_partial<float, double>(const float*, int64_t, const double*, int64_t,
                                                int64_t, int64_t, double*, int, hipStream_t);
 
+// Sum of the nblk block partials of column c by one wave (lane-strided, then a shuffle
+// tree): a fixed order, so the result is deterministic. Lane 0 holds the sum used.
 __device__ inline double sum_parts(const double* part, int nblk, int64_t m, int64_t c) {
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * m + c];
-  return s;
+  for (int b = lane; b < nblk; b += 64) s += part[(int64_t)b * m + c];
+  return wave_sum(s);
 }
 
 // ---------------------------------------------------------------- scalar kernels
+// One block of 256 threads; wave w handles columns w, w + 4, ...; lane 0 decides and writes.
 // Initial state: ynorm = ||y||, rnorm = ||r0||; active if finite and rnorm > tol * ynorm,
 // broken if non-finite; rho = <r0, z0> (from part_rz) for active columns.
-__global__ void cg_init_scalars_kernel(const double* part_yy, const double* part_rr,
-                                       const double* part_rz, int nblk, int64_t m, double tol,
-                                       double* ynorm, double* rnorm, double* rho, int* active,
-                                       int* broken, int* col_iters, int* count) {
+__global__ __launch_bounds__(256) void cg_init_scalars_kernel(
+    const double* part_yy, const double* part_rr, const double* part_rz, int nblk, int64_t m,
+    double tol, double* ynorm, double* rnorm, double* rho, int* active, int* broken,
+    int* col_iters, int* count) {
   __shared__ int cnt;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
-  for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c = w; c < m; c += 4) {
     const double yn = sqrt(sum_parts(part_yy, nblk, m, c));
     const double rn = sqrt(sum_parts(part_rr, nblk, m, c));
     const double rz = part_rz ? sum_parts(part_rz, nblk, m, c) : rn * rn;
-    const bool bad = !isfinite(yn) || !isfinite(rn) || !isfinite(rz);
-    const bool act = !bad && rn > tol * yn;
-    ynorm[c] = yn;
-    rnorm[c] = rn;
-    rho[c] = rz;
-    active[c] = act ? 1 : 0;
-    broken[c] = bad ? 1 : 0;
-    col_iters[c] = 0;
-    if (act) atomicAdd(&cnt, 1);
+    if (lane == 0) {
+      const bool bad = !isfinite(yn) || !isfinite(rn) || !isfinite(rz);
+      const bool act = !bad && rn > tol * yn;
+      ynorm[c] = yn;
+      rnorm[c] = rn;
+      rho[c] = rz;
+      active[c] = act ? 1 : 0;
+      broken[c] = bad ? 1 : 0;
+      col_iters[c] = 0;
+      if (act) atomicAdd(&cnt, 1);
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) *count = cnt;
 }
 
 // alpha_c = rho_c / <p, Ap>_c for active columns; curvature <= 0 or non-finite -> breakdown.
-__global__ void cg_alpha_kernel(const double* part_pq, int nblk, int64_t m, const double* rho,
-                                int* active, int* broken, double* alpha) {
-  for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
-    double a = 0.0;
-    if (active[c]) {
-      const double pq = sum_parts(part_pq, nblk, m, c);
+__global__ __launch_bounds__(256) void cg_alpha_kernel(const double* part_pq, int nblk, int64_t m,
+                                                       const double* rho, int* active,
+                                                       int* broken, double* alpha) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c = w; c < m; c += 4) {
+    if (!active[c]) {  // wave-uniform
+      if (lane == 0) alpha[c] = 0.0;
+      continue;
+    }
+    const double pq = sum_parts(part_pq, nblk, m, c);
+    if (lane == 0) {
+      double a = 0.0;
       if (!(pq > 0.0) || !isfinite(pq) || !isfinite(rho[c])) {
         active[c] = 0;
         broken[c] = 1;
       } else {
         a = rho[c] / pq;
       }
+      alpha[c] = a;
     }
-    alpha[c] = a;
   }
 }
 
 // ||r|| and convergence: active columns with ||r|| <= tol ||y|| are frozen.
-__global__ void cg_conv_kernel(const double* part_rr, int nblk, int64_t m, double tol,
-                               const double* ynorm, double* rnorm, int* active, int* broken,
-                               int* col_iters, int it, int* count, double* hist_slot) {
+__global__ __launch_bounds__(256) void cg_conv_kernel(const double* part_rr, int nblk, int64_t m,
+                                                      double tol, const double* ynorm,
+                                                      double* rnorm, int* active, int* broken,
+                                                      int* col_iters, int it, int* count,
+                                                      double* hist_slot) {
   __shared__ int cnt;
   __shared__ double worst;
   if (threadIdx.x == 0) { cnt = 0; worst = 0.0; }
   __syncthreads();
-  for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
-    if (active[c]) {
-      const double rn = sqrt(sum_parts(part_rr, nblk, m, c));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c = w; c < m; c += 4) {
+    if (!active[c]) continue;  // wave-uniform
+    const double rn = sqrt(sum_parts(part_rr, nblk, m, c));
+    if (lane == 0) {
       rnorm[c] = rn;
       col_iters[c] = it;
       if (!isfinite(rn)) {
@@ -152,12 +169,18 @@ __global__ void cg_conv_kernel(const double* part_rr, int nblk, int64_t m, doubl
 }
 
 // beta = rho_new / rho for active columns; rho <- rho_new. Non-finite -> breakdown.
-__global__ void cg_beta_kernel(const double* part_rz, const double* part_rr, int nblk, int64_t m,
-                               double* rho, int* active, int* broken, double* beta) {
-  for (int64_t c = threadIdx.x; c < m; c += blockDim.x) {
-    double bt = 0.0;
-    if (active[c]) {
-      const double rn = part_rz ? sum_parts(part_rz, nblk, m, c) : sum_parts(part_rr, nblk, m, c);
+__global__ __launch_bounds__(256) void cg_beta_kernel(const double* part_rz, const double* part_rr,
+                                                      int nblk, int64_t m, double* rho,
+                                                      int* active, int* broken, double* beta) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t c = w; c < m; c += 4) {
+    if (!active[c]) {  // wave-uniform
+      if (lane == 0) beta[c] = 0.0;
+      continue;
+    }
+    const double rn = part_rz ? sum_parts(part_rz, nblk, m, c) : sum_parts(part_rr, nblk, m, c);
+    if (lane == 0) {
+      double bt = 0.0;
       if (!isfinite(rn) || rho[c] == 0.0) {
         active[c] = 0;
         broken[c] = 1;
@@ -165,8 +188,8 @@ __global__ void cg_beta_kernel(const double* part_rz, const double* part_rr, int
         bt = rn / rho[c];
         rho[c] = rn;
       }
+      beta[c] = bt;
     }
-    beta[c] = bt;
   }
 }
 

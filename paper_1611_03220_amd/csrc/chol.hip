@@ -1,9 +1,10 @@
 // FP64 Cholesky of G = Z^T Z + lambda_p I and the inverse of its factor (step a3).
 //
 // Blocked right-looking factorisation with 64 x 64 diagonal blocks: one workgroup factors
-// the diagonal block in LDS and also inverts it; the panel below is multiplied by that
-// inverse (a GEMM instead of a triangular solve); the trailing lower triangle gets an
-// FP64 rank-64 update. The full inverse C^{-1} is then assembled by recursive doubling,
+// the diagonal block with its rows in registers; the panel below is solved against it (one
+// thread per panel row); the trailing lower triangle gets an FP64 rank-64 update. The
+// inverses of all diagonal blocks are then formed at once, one workgroup per block, and
+// the full inverse C^{-1} is assembled from them by recursive doubling,
 // inv([A 0; B D]) = [A^-1 0; -D^-1 B A^-1  D^-1], with batched FP64 GEMMs. The matrix
 // order is padded to 64 * 2^k with an identity block, which leaves the leading factor
 // and its inverse unchanged.
@@ -13,92 +14,129 @@ namespace krr {
 
 constexpr int NB = 64;
 
-// Factor the diagonal block at (k0, k0) of A (lda) in place (lower, strict upper zeroed)
-// and write its inverse into Ainv (same offsets, ld lda_inv). 256 threads.
-// Factor: right-looking in LDS; per column j one thread takes the pivot, the column below it
-// is scaled, and the trailing lower triangle takes the rank-1 update (4 threads per row).
-// Inverse: X = L^{-1} row by row, X[i][c] = (delta_ic - sum_{c<=k<i} L[i][k] X[k][c]) / L[i][i]
-// with the columns c in parallel and the k-sum split over 4 thread groups.
+// Factor the diagonal block at (k0, k0) of A (lda) in place (lower; strict upper zeroed).
+// 256 threads: thread (r, q) = (t / 4, t % 4) keeps W[r][c] for c = q, q + 4, ... in
+// registers. Column j: the owners of column j scale it (L[r][j] = W[r][j] / L[j][j]) and
+// publish it in LDS (zero for rows r <= j); after one barrier every row updates
+// W[r][c] -= L[r][j] L[c][j] for all its c (zeros make this a no-op for c <= j, and the
+// entries above the diagonal are never read); the owner of the next diagonal entry
+// publishes it before the second barrier. The column loop is unrolled so that register
+// indices are constants.
 // *info receives the 1-based global index of the first non-positive (or non-finite) pivot
 // if it is still 0.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
-                                                         int64_t k0, double* __restrict__ Ainv,
-                                                         int64_t ldi, int* __restrict__ info) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ double part[4][NB];
-  __shared__ int bad;
-  const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, c = e % NB;
-    L[i][c] = (c <= i) ? A[(k0 + i) * lda + k0 + c] : 0.0;
+                                                         int64_t k0, int* __restrict__ info) {
+  __shared__ double col[NB];
+  __shared__ double piv;
+  const int t = threadIdx.x, r = t >> 2, q = t & 3;
+  double w[NB / 4];
+#pragma unroll
+  for (int u = 0; u < NB / 4; ++u) {
+    const int c = q + 4 * u;
+    w[u] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
   }
+  if (t == 0) piv = w[0];
   __syncthreads();
-  const int row = t >> 2, sub = t & 3;
+  int first_bad = 0;
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    if (t == 0) {
-      const double dj = L[j][j];
-      if (!(dj > 0.0) || !(dj < INFINITY)) {
-        if (!bad && *info == 0) *info = (int)(k0 + j + 1);
-        bad = 1;
-      }
-      L[j][j] = sqrt(dj);
+    const double dj = piv;
+    if (first_bad == 0 && (!(dj > 0.0) || !(dj < INFINITY))) first_bad = j + 1;
+    const double ljj = sqrt(dj);
+    if (q == (j & 3)) {
+      const double lrj = r == j ? ljj : (r > j ? w[j >> 2] / ljj : 0.0);
+      w[j >> 2] = lrj;
+      col[r] = r > j ? lrj : 0.0;  // zero at and above the pivot: those rows take no update
     }
     __syncthreads();
-    const double ljj = L[j][j];
-    if (t > j && t < NB) L[t][j] /= ljj;
-    __syncthreads();
-    // trailing update of rows r > j, columns j < c <= r
-    const int r = j + 1 + row;
-    if (r < NB) {
-      const double lrj = L[r][j];
-      for (int c = j + 1 + sub; c <= r; c += 4) L[r][c] -= lrj * L[c][j];
-    }
+    // branch-free: col[c] = 0 for c <= j leaves finished columns alone; entries above the
+    // diagonal (c > r) take updates but are never read
+    const double lr = col[r];
+#pragma unroll
+    for (int u = 0; u < NB / 4; ++u) w[u] = fma(-lr, col[q + 4 * u], w[u]);
+    if (j + 1 < NB && r == j + 1 && q == ((j + 1) & 3)) piv = w[(j + 1) >> 2];
     __syncthreads();
   }
-  // inverse of the lower triangular factor
-  const int c = t & 63, q = t >> 6;
-  for (int i = 0; i < NB; ++i) {
-    double acc = 0.0;
-    if (c < i)
-      for (int k = c + q; k < i; k += 4) acc += L[i][k] * X[k][c];
-    part[q][c] = acc;
-    __syncthreads();
-    if (q == 0) {
-      double v;
-      if (c > i) v = 0.0;
-      else if (c == i) v = 1.0 / L[i][i];
-      else v = -(part[0][c] + part[1][c] + part[2][c] + part[3][c]) / L[i][i];
-      X[i][c] = v;
-    }
-    __syncthreads();
+  if (t == 0 && first_bad != 0 && *info == 0) *info = (int)(k0 + first_bad);
+#pragma unroll
+  for (int u = 0; u < NB / 4; ++u) {
+    const int c = q + 4 * u;
+    A[(k0 + r) * lda + k0 + c] = c <= r ? w[u] : 0.0;
   }
-  for (int e = t; e < NB * NB; e += 256) {
-    const int i = e / NB, cc = e % NB;
-    A[(k0 + i) * lda + k0 + cc] = cc <= i ? L[i][cc] : 0.0;
-    Ainv[(k0 + i) * ldi + k0 + cc] = X[i][cc];
+}
+
+// Forward substitution against the 64 x 64 lower factor held in LDS (Ls, reciprocal
+// diagonal in dinv): x[j] = (b[j] - sum_{k<j} Ls[j][k] x[k]) dinv[j]. Every thread reads the
+// same Ls entries (broadcasts); the loops are unrolled so x stays in registers.
+__device__ __forceinline__ void lower_solve64(const double (*Ls)[NB + 1], const double* dinv,
+                                              double (&x)[NB]) {
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double acc = x[j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) acc = fma(-Ls[j][k], x[k], acc);
+    x[j] = acc * dinv[j];
   }
+}
+
+// Panel below the diagonal block k0: P <- P L^{-T} (row i of P solves x L^T = p_i), one
+// thread per row, L staged in LDS.
+__global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ G, int64_t ld,
+                                                         int64_t k0, int64_t rows) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
+  for (int e = threadIdx.x; e < NB * NB; e += 256) Ls[e / NB][e % NB] = G[(k0 + e / NB) * ld + k0 + e % NB];
+  __syncthreads();
+  if (threadIdx.x < NB) dinv[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  double* p = G + (k0 + NB + i) * ld + k0;
+  double x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) x[j] = p[j];
+  lower_solve64(Ls, dinv, x);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) p[j] = x[j];
+}
+
+// Inverses of all diagonal 64 x 64 blocks of the factor (block b = blockIdx.x), written to
+// the same positions of Cinv: thread c solves L x = e_c for column c of the inverse.
+__global__ __launch_bounds__(64) void diag_inverse_kernel(const double* __restrict__ G,
+                                                          int64_t ld, double* __restrict__ Cinv) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
+  const int64_t k0 = (int64_t)blockIdx.x * NB;
+  for (int e = threadIdx.x; e < NB * NB; e += 64) Ls[e / NB][e % NB] = G[(k0 + e / NB) * ld + k0 + e % NB];
+  __syncthreads();
+  dinv[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
+  __syncthreads();
+  const int c = threadIdx.x;
+  double x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) x[j] = j == c ? 1.0 : 0.0;
+  lower_solve64(Ls, dinv, x);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) Cinv[(k0 + j) * ld + k0 + c] = x[j];
 }
 
 // G (s_pad x s_pad, lower part used) -> C in place; Cinv diagonal blocks filled.
 hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st) {
   for (int64_t k0 = 0; k0 < s_pad; k0 += NB) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(G, s_pad, k0, Cinv, s_pad, info);
+    potrf_diag_kernel<<<1, 256, 0, st>>>(G, s_pad, k0, info);
     KRR_LAUNCH_CHECK();
     const int64_t rest = s_pad - k0 - NB;
     if (rest <= 0) break;
+    trsm_panel_kernel<<<ceil_div(rest, 256), 256, 0, st>>>(G, s_pad, k0, rest);
+    KRR_LAUNCH_CHECK();
     double* panel = G + (k0 + NB) * s_pad + k0;
-    const double* linv = Cinv + k0 * s_pad + k0;
-    // panel <- panel * Linv^T   (B(k, j) = Linv[j][k])
-    hipError_t e = dgemm(rest, NB, NB, 1.0, panel, s_pad, 1, 0, linv, 1, s_pad, 0, 0.0, panel,
-                         s_pad, 0, 1, 0, st);
-    if (e != hipSuccess) return e;
     // trailing lower triangle <- trailing - panel * panel^T
-    e = dgemm(rest, rest, NB, -1.0, panel, s_pad, 1, 0, panel, 1, s_pad, 0, 1.0,
-              G + (k0 + NB) * s_pad + k0 + NB, s_pad, 0, 1, 1, st);
+    hipError_t e = dgemm(rest, rest, NB, -1.0, panel, s_pad, 1, 0, panel, 1, s_pad, 0, 1.0,
+                         G + (k0 + NB) * s_pad + k0 + NB, s_pad, 0, 1, 1, st);
     if (e != hipSuccess) return e;
   }
+  diag_inverse_kernel<<<s_pad / NB, 64, 0, st>>>(G, s_pad, Cinv);
+  KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 

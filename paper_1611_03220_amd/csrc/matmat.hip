@@ -255,16 +255,31 @@ typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// p - (float)h.x and p - (float)h.y in one mixed-precision FMA each
-__device__ inline float sub_half_lo(half2v h, float p) {
-  float r;
-  asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(p));
+// Low parts of a split pair: (rn16(pa - h.x), rn16(pb - h.y)), each one mixed-precision FMA
+// rounding straight to FP16 into its half of the result (pa - h.x is exact in FP32, so this
+// equals rounding the FP32 difference).
+__device__ inline half2v split_lo2(half2v h, float pa, float pb) {
+  half2v r;
+  asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+      "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+      : "=&v"(r)
+      : "v"(h), "v"(pa), "v"(pb));
   return r;
 }
-__device__ inline float sub_half_hi(half2v h, float p) {
-  float r;
-  asm("v_fma_mix_f32 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h), "v"(p));
-  return r;
+
+// LDS position (halves) of V^T[c][j] in a 64-column tile, j a multiple of 4. Within each
+// 32-column group, j = 16 b + 4 g + r sits at 8 g + 4 b + r: the eight values lane group g
+// feeds to the P V MFMA (the k order of the P fragment) form one 16-byte piece. The eight
+// pieces of row c are XOR-swizzled with (c >> 1) & 7, so the 16 rows of a fragment read
+// spread over all banks.
+__device__ inline int vpos(int c, int j) {
+  const int J = j & 31;
+  const int p = (j & ~31) + 8 * ((J & 15) >> 2) + 4 * (J >> 4);
+  return c * MM_BN + (((p >> 3) ^ ((c >> 1) & 7)) << 3) + (p & 7);
+}
+// the piece lane group g reads for 32-column group jp of row c
+__device__ inline int vfrag(int c, int jp, int g) {
+  return c * MM_BN + (((4 * jp + g) ^ ((c >> 1) & 7)) << 3);
 }
 
 template <int KS, int NCT>
@@ -345,8 +360,8 @@ __device__ __forceinline__ void f16pv_body(
   const _Float16* gvh = Vth + (int64_t)vc * ldvt + t_begin * MM_BN + vj8 * 8;
   const _Float16* gvl = Vtl + (int64_t)vc * ldvt + t_begin * MM_BN + vj8 * 8;
   // 8-byte units of a V^T row are swizzled by the row index (16 units per row)
-  const int svo0 = vc * MM_BN + (((2 * vj8) ^ (vc & 15)) * 4);
-  const int svo1 = vc * MM_BN + (((2 * vj8 + 1) ^ (vc & 15)) * 4);
+  const int svo0 = vpos(vc, 8 * vj8);
+  const int svo1 = vpos(vc, 8 * vj8 + 4);
   // prefetch registers as native vectors in named variables (an array of HIP's uint4
   // struct is left in scratch memory by the compiler)
   u32x4 rbh0 = {}, rbh1 = {}, rbh2 = {}, rbh3 = {}, rbl0 = {}, rbl1 = {}, rbl2 = {}, rbl3 = {};
@@ -398,14 +413,9 @@ __device__ __forceinline__ void f16pv_body(
     half8 vh[NCT], vl[NCT];
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
-      const int c = 16 * ct + li;
-      const int u0 = ((8 * jp + lg) ^ (c & 15)) * 4, u1 = ((8 * jp + 4 + lg) ^ (c & 15)) * 4;
-      const half4 h0 = *reinterpret_cast<const half4*>(&sm.Vh[buf][c * MM_BN + u0]);
-      const half4 h1 = *reinterpret_cast<const half4*>(&sm.Vh[buf][c * MM_BN + u1]);
-      const half4 l0 = *reinterpret_cast<const half4*>(&sm.Vl[buf][c * MM_BN + u0]);
-      const half4 l1 = *reinterpret_cast<const half4*>(&sm.Vl[buf][c * MM_BN + u1]);
-      vh[ct] = half8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
-      vl[ct] = half8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+      const int u = vfrag(16 * ct + li, jp, lg);
+      vh[ct] = *reinterpret_cast<const half8*>(&sm.Vh[buf][u]);
+      vl[ct] = *reinterpret_cast<const half8*>(&sm.Vl[buf][u]);
     }
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib) {
@@ -424,7 +434,7 @@ __device__ __forceinline__ void f16pv_body(
           // round-to-nearest split: |(hi + lo) - p| <= 2^-22 |p| (2^-25 absolute below the
           // FP16 normal range), unbiased
           const half2v h = half2v{(_Float16)pa, (_Float16)pb};
-          const half2v l = half2v{(_Float16)sub_half_lo(h, pa), (_Float16)sub_half_hi(h, pb)};
+          const half2v l = split_lo2(h, pa, pb);
           ph[4 * jb + r] = h[0];
           ph[4 * jb + r + 1] = h[1];
           pl[4 * jb + r] = l[0];
@@ -596,8 +606,8 @@ __device__ __forceinline__ void f16pv_bigd_body(
   const int sb0 = brow * 32 + ((bcol ^ ((brow >> 1) & 3)) * 8);
   const bool vload = tid < VCH;
   const int vc = vload ? tid / (MM_BN / 8) : 0, vj8 = vload ? tid % (MM_BN / 8) : 0;
-  const int svo0 = vc * MM_BN + (((2 * vj8) ^ (vc & 15)) * 4);
-  const int svo1 = vc * MM_BN + (((2 * vj8 + 1) ^ (vc & 15)) * 4);
+  const int svo0 = vpos(vc, 8 * vj8);
+  const int svo1 = vpos(vc, 8 * vj8 + 4);
   u32x4 ra0h = {}, ra0l = {}, ra1h = {}, ra1l = {}, rbh = {}, rbl = {}, rvh = {}, rvl = {};
   auto gload = [&](int64_t q) __attribute__((always_inline)) {
     const int64_t t = t_begin + q / KC;
@@ -672,14 +682,9 @@ __device__ __forceinline__ void f16pv_bigd_body(
         half8 vh[NCT], vl[NCT];
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
-          const int c = 16 * ct + li;
-          const int u0 = ((8 * jp + lg) ^ (c & 15)) * 4, u1 = ((8 * jp + 4 + lg) ^ (c & 15)) * 4;
-          const half4 h0 = *reinterpret_cast<const half4*>(V_at(vb, 0) + c * MM_BN + u0);
-          const half4 h1 = *reinterpret_cast<const half4*>(V_at(vb, 0) + c * MM_BN + u1);
-          const half4 l0 = *reinterpret_cast<const half4*>(V_at(vb, 1) + c * MM_BN + u0);
-          const half4 l1 = *reinterpret_cast<const half4*>(V_at(vb, 1) + c * MM_BN + u1);
-          vh[ct] = half8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
-          vl[ct] = half8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+          const int u = vfrag(16 * ct + li, jp, lg);
+          vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
+          vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
         }
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
@@ -696,7 +701,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
                 pb *= -l2b * dscale;
               }
               const half2v h = half2v{(_Float16)pa, (_Float16)pb};
-              const half2v l = half2v{(_Float16)sub_half_lo(h, pa), (_Float16)sub_half_hi(h, pb)};
+              const half2v l = split_lo2(h, pa, pb);
               ph[4 * jj + r] = h[0];
               ph[4 * jj + r + 1] = h[1];
               pl[4 * jj + r] = l[0];
