@@ -965,6 +965,24 @@ __global__ __launch_bounds__(256) void matmat_f64_kernel(
 constexpr int F64M_TJ = 32;  // columns per LDS tile
 typedef double d4v __attribute__((ext_vector_type(4)));
 
+// e^{-x} for x >= 0 in FP64 with a 64-entry table T[j] = 2^{-j/64}: with y = x log2(e)
+// (clamped at 1100, far below the smallest double), k = rint(64 y) and r = y - k/64 in
+// [-1/128, 1/128], e^{-x} = 2^{-(k >> 6)} T[k & 63] e^{-r ln 2}; the last factor is a
+// degree-6 Taylor polynomial (truncation below 1e-19 on that interval).
+__device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
+  const double y = fmin(x * 1.4426950408889634, 1100.0);
+  const double kf = rint(y * 64.0);
+  const int k = (int)kf;
+  const double u = fma(kf, 0.015625, -y) * 0.6931471805599453;  // = -r ln 2
+  double q = fma(u, 1.0 / 720.0, 1.0 / 120.0);
+  q = fma(u, q, 1.0 / 24.0);
+  q = fma(u, q, 1.0 / 6.0);
+  q = fma(u, q, 0.5);
+  q = fma(u, q, 1.0);
+  q = fma(u, q, 1.0);
+  return ldexp(T[k & 63] * q, -(k >> 6));
+}
+
 template <int KD, int NCT>
 __global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
     const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
@@ -978,9 +996,11 @@ __global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
   __shared__ double sX[2][F64M_TJ * LX];
   __shared__ double sV[2][F64M_TJ * LV];
   __shared__ double sN[2][F64M_TJ];
+  __shared__ double sE[64];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t i0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);  // read after the first barrier
   const int64_t ntiles = ceil_div(n2, F64M_TJ);
   const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
@@ -1014,18 +1034,22 @@ __global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
     if (t + 1 < t_end) load_tile(t + 1, buf ^ 1);
 #pragma unroll
     for (int jb = 0; jb < F64M_TJ / 16; ++jb) {
-      d4v g = {0.0, 0.0, 0.0, 0.0};
+      // two interleaved accumulation chains over the k steps
+      d4v g0 = {0.0, 0.0, 0.0, 0.0}, g1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int sk = 0; sk < KD; ++sk) {
-        const double a = sX[buf][(16 * jb + li) * LX + 4 * sk + lg];
-        g = __builtin_amdgcn_mfma_f64_16x16x4f64(a, xi[sk], g, 0, 0, 0);
+      for (int sk = 0; sk < KD; sk += 2) {
+        const double a0 = sX[buf][(16 * jb + li) * LX + 4 * sk + lg];
+        const double a1 = sX[buf][(16 * jb + li) * LX + 4 * (sk + 1) + lg];
+        g0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xi[sk], g0, 0, 0, 0);
+        g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xi[sk + 1], g1, 0, 0, 0);
       }
+      const d4v g = g0 + g1;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jj = 16 * jb + lg + 4 * r;
         double D = nui + sN[buf][jj] - 2.0 * g[r];
         D = D > 0.0 ? D : 0.0;
-        double p = exp(-D * c);
+        double p = exp_neg_tab(D * c, sE);
         if (deriv) p *= D * dscale;
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct)
