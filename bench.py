@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-problems solve")
+    ap.add_argument("--extra", action="append", default=[], choices=["pixels", "differentiation"],
+                    help="also run a full-size leg of another workload (repeatable)")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="run a plain device copy of this many bytes (counter calibration)")
     return ap.parse_args()
@@ -113,6 +115,70 @@ def batched_run(dev):
            "sum_n": int(sum(w.n for w in ws))}
     plan.close()
     return out
+
+
+def _sync_time():
+    import torch
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def pixels_run(dev):
+    """Large dense-feature workload: n = 262144 pixel-like points (d = 784, 80 % zeros),
+    10 one-vs-all right-hand sides, s = 8192 features, lambda = 1e-5 n, solved to 1e-6 with
+    the mixed product and FP64-residual refinement."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+    w = WL.pixels()
+    X = torch.from_numpy(w.X).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+    W = torch.from_numpy(w.W).to(dev)
+    b = torch.from_numpy(w.b).to(dev)
+    t0 = _sync_time()
+    Z = krr.features(X, W, b)
+    t1 = _sync_time()
+    _, Ut = krr.precond_factor(Z, w.lam)
+    del Z
+    t2 = _sync_time()
+    _, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, refine=3, raise_on_error=False)
+    t3 = _sync_time()
+    flops = 2.0 * w.n * w.n * (w.d + w.m)
+    return {"workload": f"pixels n={w.n} d={w.d} m={w.m} s={w.s}", "status": rep.status,
+            "time_to_tol_s": t3 - t0, "features_s": t1 - t0, "factor_s": t2 - t1,
+            "solve_s": t3 - t2, "iterations": rep.iters, "refine_steps": rep.refine_steps,
+            "relres_true_max": max(rep.relres_true), "matmat_calls": rep.matmat_calls,
+            "matmat_tflops_algorithmic": flops * rep.matmat_calls / max(rep.matmat_ms, 1e-9) * 1e-9}
+
+
+def differentiation_run(dev):
+    """Differentiation workload: n = 131072 training + 16384 validation points, d = 440,
+    147 one-vs-all columns, s = 4096; validation loss and its sigma / lambda gradients
+    through the adjoint solve (mixed solves, FP64 derivative products)."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import autograd as KA
+    from paper_1611_03220_amd import workloads as WL
+    w = WL.correlated_differentiation()
+    Xtr, Xv = torch.from_numpy(w.X).to(dev), torch.from_numpy(w.Xv).to(dev)
+    Ytr = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+    Yv = torch.from_numpy(np.ascontiguousarray(w.Yv)).to(dev)
+    t0 = _sync_time()
+    Z = krr.features(Xtr, torch.from_numpy(w.W).to(dev), torch.from_numpy(w.b).to(dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    del Z
+    t1 = _sync_time()
+    sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(w.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    L = KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, tol=1e-6, refine=3)
+    t2 = _sync_time()
+    L.backward()
+    t3 = _sync_time()
+    return {"workload": f"differentiation n={w.n}+{w.Xv.shape[0]} d={w.d} m={w.m} s={w.s}",
+            "setup_s": t1 - t0, "forward_s": t2 - t1, "backward_s": t3 - t2,
+            "loss": float(L.detach()), "dL_dsigma": float(sig.grad), "dL_dlambda": float(lam.grad)}
 
 
 def cpu_baseline(w, seconds):
@@ -245,6 +311,10 @@ def main():
         out["batched"] = batched_run(dev)
         print(f"[bench] batched solve {out['batched']['time_to_tol_s']:.3f} s", file=sys.stderr,
               flush=True)
+    for extra in args.extra:
+        torch.cuda.empty_cache()
+        out[extra] = pixels_run(dev) if extra == "pixels" else differentiation_run(dev)
+        print(f"[bench] {extra}: {out[extra]}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

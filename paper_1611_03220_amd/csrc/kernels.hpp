@@ -14,10 +14,11 @@ template <typename T> struct MixedPoints {
 };
 
 struct F64Points {
-  const double* X;   // round_up(n, 64) x dp
-  const double* nu;  // round_up(n, 64)
+  const double* X;   // rows_pad x dp (dp <= 128), or nullptr when Xf is used
+  const double* nu;  // rows_pad, FP64 squared norms
   int64_t n;
-  int64_t dp;        // multiple of 32
+  int64_t dp;        // multiple of 8 (<= 128) or of 32
+  const float* Xf = nullptr;  // rows_pad x dp FP32 coordinates (dp > 128)
 };
 
 struct SplitOperand {
@@ -49,6 +50,8 @@ hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows
                        hipStream_t st);
 hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                            int64_t dp, double* X64, double* nu, hipStream_t st);
+hipError_t prep_points_f64x(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                            int64_t dp, float* X32, double* nu, hipStream_t st);
 hipError_t vec_to_f32(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,
                       int64_t ldo, float* out, hipStream_t st);
 hipError_t vec_pad_f64(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,

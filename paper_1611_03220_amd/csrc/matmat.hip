@@ -272,14 +272,21 @@ __device__ inline half2v split_lo2(half2v h, float pa, float pb) {
 // feeds to the P V MFMA (the k order of the P fragment) form one 16-byte piece. The eight
 // pieces of row c are XOR-swizzled with (c >> 1) & 7, so the 16 rows of a fragment read
 // spread over all banks.
+// Rows of TN = 128 columns have 16 pieces, swizzled with c & 15 instead.
+template <int TN = MM_BN>
+__device__ inline int vswz(int c) {
+  return TN == 64 ? ((c >> 1) & 7) : (c & 15);
+}
+template <int TN = MM_BN>
 __device__ inline int vpos(int c, int j) {
   const int J = j & 31;
   const int p = (j & ~31) + 8 * ((J & 15) >> 2) + 4 * (J >> 4);
-  return c * MM_BN + (((p >> 3) ^ ((c >> 1) & 7)) << 3) + (p & 7);
+  return c * TN + (((p >> 3) ^ vswz<TN>(c)) << 3) + (p & 7);
 }
 // the piece lane group g reads for 32-column group jp of row c
+template <int TN = MM_BN>
 __device__ inline int vfrag(int c, int jp, int g) {
-  return c * MM_BN + (((4 * jp + g) ^ ((c >> 1) & 7)) << 3);
+  return c * TN + (((4 * jp + g) ^ vswz<TN>(c)) << 3);
 }
 
 template <int KS, int NCT>
@@ -549,13 +556,18 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16
 }
 
 // Large-d variant: the row operands no longer fit in registers, so both operands stream
-// through LDS in 32-wide k chunks. Block: 128 rows (4 waves x 32) against 64-column tiles;
-// per tile, KC = Kp/32 chunk steps accumulate S^T for the wave's 2 x 4 blocks of 16 x 16,
-// then the same epilogue as above (exp2, FP16 hi/lo split, MFMA accumulation against V^T).
-// Chunk rows are 64 bytes; their 16-byte pieces are XOR-swizzled with (row >> 1) & 3 so
-// fragment reads are conflict-free.
+// through LDS in 32-wide k chunks. Block: 128 rows (4 waves x 32) against column tiles of
+// TN = 16 NJB columns; per tile, KC = Kp/32 chunk steps accumulate S^T for the wave's
+// NJB x 2 blocks of 16 x 16, then the same epilogue as above (exp2, FP16 hi/lo split, MFMA
+// accumulation against V^T). Wider tiles re-stream the row operand less often: its chunks
+// are read once per column tile. Chunk rows are 64 bytes whose 16-byte pieces are
+// XOR-swizzled with (row >> 1) & 3 so fragment reads are conflict-free.
 constexpr int BD_BM = 128;
-template <int NCT, bool UNIT, bool DERIV>
+template <int NCT, int NJB>
+constexpr int bigd_smem_halves() {
+  return 2 * 2 * BD_BM * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB);
+}
+template <int NCT, bool UNIT, bool DERIV, int NJB>
 __device__ __forceinline__ void f16pv_bigd_body(
     _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -563,24 +575,26 @@ __device__ __forceinline__ void f16pv_bigd_body(
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
     int tiles_per_split, int64_t rb, int64_t split) {
-  constexpr int ACH = BD_BM * 4;            // 16-byte chunks in an A chunk-tile (per array)
-  constexpr int BCH = MM_BN * 4;
+  constexpr int TN = 16 * NJB;
+  constexpr int BPT = TN * 4 / 256;          // B chunk pieces per thread
   constexpr int VR = NCT * 16;
-  constexpr int VCH = VR * MM_BN / 8;
-  static_assert(ACH == 512 && BCH == 256 && VCH <= 256, "tile shape");
-  // LDS layout (halves): A[2][2][128*32], B[2][2][64*32], V[2][2][VR*64]
+  constexpr int VCH = VR * TN / 8;           // V^T pieces per tile
+  constexpr int VPT = (VCH + 255) / 256;
+  constexpr int FLUSH = TN >= 128 ? 1 : MM2_FLUSH;  // flush every 128 columns
+  static_assert(BPT >= 1 && BPT <= 2 && VPT <= 2, "tile shape");
+  // LDS layout (halves): A[2][2][128*32], B[2][2][TN*32], V[2][2][VR*TN]
   _Float16* sA = smem;
   _Float16* sB = sA + 2 * 2 * BD_BM * 32;
-  _Float16* sV = sB + 2 * 2 * MM_BN * 32;
+  _Float16* sV = sB + 2 * 2 * TN * 32;
   auto A_at = [&](int buf, int hl) { return sA + (buf * 2 + hl) * BD_BM * 32; };
-  auto B_at = [&](int buf, int hl) { return sB + (buf * 2 + hl) * MM_BN * 32; };
-  auto V_at = [&](int buf, int hl) { return sV + (buf * 2 + hl) * VR * MM_BN; };
+  auto B_at = [&](int buf, int hl) { return sB + (buf * 2 + hl) * TN * 32; };
+  auto V_at = [&](int buf, int hl) { return sV + (buf * 2 + hl) * VR * TN; };
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t blk_i0 = rb * BD_BM;
   const int64_t i0 = blk_i0 + 32 * w;
-  const int64_t ntiles = ceil_div(n2, MM_BN);
+  const int64_t ntiles = ceil_div(n2, TN);
   const int64_t t_begin = split * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = KP / 32;
@@ -596,32 +610,46 @@ __device__ __forceinline__ void f16pv_bigd_body(
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc64[ib][ct][r] = 0.0;
     }
-  f32x4 S[4][2];
+  f32x4 S[NJB][2];
 
-  // chunk loaders: A rows blk_i0 + ch/4 (two chunks per thread), B rows j0 + ch/4 (one)
-  const int arow0 = tid >> 2, arow1 = (tid + 256) >> 2, acol = tid & 3;
-  const int brow = tid >> 2, bcol = tid & 3;
+  // chunk loaders: A rows blk_i0 + tid/4 and + 64; B rows j0 + tid/4 (+ 64 when TN = 128)
+  const int arow0 = tid >> 2, arow1 = arow0 + 64, acol = tid & 3;
   const int sa0 = arow0 * 32 + ((acol ^ ((arow0 >> 1) & 3)) * 8);
   const int sa1 = arow1 * 32 + ((acol ^ ((arow1 >> 1) & 3)) * 8);
-  const int sb0 = brow * 32 + ((bcol ^ ((brow >> 1) & 3)) * 8);
-  const bool vload = tid < VCH;
-  const int vc = vload ? tid / (MM_BN / 8) : 0, vj8 = vload ? tid % (MM_BN / 8) : 0;
-  const int svo0 = vpos(vc, 8 * vj8);
-  const int svo1 = vpos(vc, 8 * vj8 + 4);
-  u32x4 ra0h = {}, ra0l = {}, ra1h = {}, ra1l = {}, rbh = {}, rbl = {}, rvh = {}, rvl = {};
+  const int brow1 = arow0 + 64;
+  const int sb1 = brow1 * 32 + ((acol ^ ((brow1 >> 1) & 3)) * 8);
+  // V^T pieces: piece e = tid + 256 u covers row e / (TN / 8), columns 8 (e % (TN / 8)) ..
+  const bool vld0 = tid < VCH, vld1 = VPT > 1 && tid + 256 < VCH;
+  const int ve0 = vld0 ? tid : 0, ve1 = vld1 ? tid + 256 : 0;
+  const int vc0 = ve0 / (TN / 8), vj0 = ve0 % (TN / 8);
+  const int vc1 = ve1 / (TN / 8), vj1 = ve1 % (TN / 8);
+  const int svo00 = vpos<TN>(vc0, 8 * vj0), svo01 = vpos<TN>(vc0, 8 * vj0 + 4);
+  const int svo10 = vpos<TN>(vc1, 8 * vj1), svo11 = vpos<TN>(vc1, 8 * vj1 + 4);
+  u32x4 ra0h = {}, ra0l = {}, ra1h = {}, ra1l = {}, rb0h = {}, rb0l = {}, rb1h = {}, rb1l = {};
+  u32x4 rv0h = {}, rv0l = {}, rv1h = {}, rv1l = {};
   auto gload = [&](int64_t q) __attribute__((always_inline)) {
     const int64_t t = t_begin + q / KC;
     const int kc = (int)(q % KC);
-    const int64_t ko = (int64_t)kc * 32;
-    ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko + acol * 8);
-    ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko + acol * 8);
-    ra1h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow1) * KP + ko + acol * 8);
-    ra1l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow1) * KP + ko + acol * 8);
-    rbh = *reinterpret_cast<const u32x4*>(Bhi + (t * MM_BN + brow) * KP + ko + bcol * 8);
-    rbl = *reinterpret_cast<const u32x4*>(Blo + (t * MM_BN + brow) * KP + ko + bcol * 8);
-    if (kc == 0 && vload) {
-      rvh = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc * ldvt + t * MM_BN + vj8 * 8);
-      rvl = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc * ldvt + t * MM_BN + vj8 * 8);
+    const int64_t ko = (int64_t)kc * 32 + acol * 8;
+    ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
+    ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko);
+    ra1h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow1) * KP + ko);
+    ra1l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow1) * KP + ko);
+    rb0h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + arow0) * KP + ko);
+    rb0l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + arow0) * KP + ko);
+    if (BPT > 1) {
+      rb1h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + brow1) * KP + ko);
+      rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
+    }
+    if (kc == 0) {
+      if (vld0) {
+        rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+        rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+      }
+      if (vld1) {
+        rv1h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
+        rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
+      }
     }
   };
   auto lstore = [&](int64_t q) __attribute__((always_inline)) {
@@ -631,14 +659,26 @@ __device__ __forceinline__ void f16pv_bigd_body(
     *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa0) = ra0l;
     *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa1) = ra1h;
     *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa1) = ra1l;
-    *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb0) = rbh;
-    *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb0) = rbl;
-    if (kc == 0 && vload) {
+    *reinterpret_cast<u32x4*>(B_at(buf, 0) + sa0) = rb0h;
+    *reinterpret_cast<u32x4*>(B_at(buf, 1) + sa0) = rb0l;
+    if (BPT > 1) {
+      *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb1) = rb1h;
+      *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb1) = rb1l;
+    }
+    if (kc == 0) {
       const int vb = (int)((q / KC) & 1);
-      *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo0) = u32x2{rvh.x, rvh.y};
-      *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo1) = u32x2{rvh.z, rvh.w};
-      *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo0) = u32x2{rvl.x, rvl.y};
-      *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo1) = u32x2{rvl.z, rvl.w};
+      if (vld0) {
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{rv0h.x, rv0h.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo01) = u32x2{rv0h.z, rv0h.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo00) = u32x2{rv0l.x, rv0l.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo01) = u32x2{rv0l.z, rv0l.w};
+      }
+      if (vld1) {
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo10) = u32x2{rv1h.x, rv1h.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo11) = u32x2{rv1h.z, rv1h.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo10) = u32x2{rv1l.x, rv1l.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo11) = u32x2{rv1l.z, rv1l.w};
+      }
     }
   };
 
@@ -662,7 +702,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
       al[ib] = *reinterpret_cast<const half8*>(A_at(buf, 1) + o);
     }
 #pragma unroll
-    for (int jb = 0; jb < 4; ++jb) {
+    for (int jb = 0; jb < NJB; ++jb) {
       const int row = 16 * jb + li;
       const int o = row * 32 + ((lg ^ ((row >> 1) & 3)) * 8);
       const half8 bh = *reinterpret_cast<const half8*>(B_at(buf, 0) + o);
@@ -678,11 +718,11 @@ __device__ __forceinline__ void f16pv_bigd_body(
     if (kc == KC - 1) {
       const int vb = (int)((q / KC) & 1);
 #pragma unroll
-      for (int jp = 0; jp < 2; ++jp) {
+      for (int jp = 0; jp < NJB / 2; ++jp) {
         half8 vh[NCT], vl[NCT];
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) {
-          const int u = vfrag(16 * ct + li, jp, lg);
+          const int u = vfrag<TN>(16 * ct + li, jp, lg);
           vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
           vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
         }
@@ -715,7 +755,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
           }
         }
       }
-      if (++since_flush == MM2_FLUSH || q + 1 == nsteps) {
+      if (++since_flush == FLUSH || q + 1 == nsteps) {
         since_flush = 0;
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib)
@@ -747,6 +787,10 @@ __device__ __forceinline__ void f16pv_bigd_body(
   }
 }
 
+// column tiles of the large-d single-problem product (the batched product keeps 64)
+constexpr int BD_NJB = 8;
+constexpr int BD_TN = 16 * BD_NJB;
+
 template <int NCT, bool DERIV>
 __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
@@ -755,17 +799,18 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
     int64_t part_stride, int tiles_per_split) {
-  __shared__ __attribute__((aligned(16)))
-  _Float16 smem[2 * 2 * BD_BM * 32 + 2 * 2 * MM_BN * 32 + 2 * 2 * NCT * 16 * MM_BN];
+  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, BD_NJB>()];
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                      KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split,
-                                      blockIdx.x, blockIdx.y);
+    f16pv_bigd_body<NCT, true, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+                                              n1, n2, m, KP, qinv2, dscale, part, ldp,
+                                              part_stride, tiles_per_split, blockIdx.x,
+                                              blockIdx.y);
   else
-    f16pv_bigd_body<NCT, false, DERIV>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                       KP, qinv2, dscale, part, ldp, part_stride, tiles_per_split,
-                                       blockIdx.x, blockIdx.y);
+    f16pv_bigd_body<NCT, false, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+                                               n1, n2, m, KP, qinv2, dscale, part, ldp,
+                                               part_stride, tiles_per_split, blockIdx.x,
+                                               blockIdx.y);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
@@ -779,6 +824,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   const int nct = (int)(V.mpad / 16);
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
+    const int tps = (int)ceil_div(ceil_div(B.n, BD_TN), nsplit);
     if (nct == 1) {
       if (deriv)
         matmat_f16pv_bigd_kernel<1, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
@@ -822,8 +868,7 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
                                                               const BatchInst* __restrict__ inst,
                                                               const int* __restrict__ live,
                                                               int* __restrict__ counter) {
-  __shared__ __attribute__((aligned(16)))
-  _Float16 smem[2 * 2 * BD_BM * 32 + 2 * 2 * MM_BN * 32 + 2 * 2 * 16 * MM_BN];
+  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<1, 4>()];
   __shared__ int cur;
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
@@ -836,11 +881,11 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
     const BatchInst I = inst[wi.inst];
     const float qinv2 = *I.qinv2;
     if (qinv2 == 1.0f)
-      f16pv_bigd_body<1, true, false>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
+      f16pv_bigd_body<1, true, false, 4>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
                                       I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
                                       I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
     else
-      f16pv_bigd_body<1, false, false>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
+      f16pv_bigd_body<1, false, false, 4>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
                                        I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
                                        I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
     __syncthreads();
@@ -857,104 +902,6 @@ hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* ins
 }
 
 // ------------------------------------------------------------------- FP64 path
-// Block: 64 rows x 64-column tiles; thread (ty, tx) = (t/16, t%16) owns rows 4ty..4ty+3 and
-// columns tx, tx+16, tx+32, tx+48 of each tile. Distances from FP64 norms and an FP64 dot
-// product staged through LDS in 32-wide k chunks, FP64 exp, FP64 accumulation.
-constexpr int F64_BK = 32;
-
-template <int MC>
-__global__ __launch_bounds__(256) void matmat_f64_kernel(
-    const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
-    const double* __restrict__ nub, int64_t dp, const double* __restrict__ V, int64_t ldv,
-    int64_t n1, int64_t n2, int c0, double c, int deriv, double dscale, double* __restrict__ part,
-    int64_t ldp, int64_t part_stride, int tiles_per_split) {
-  __shared__ double sA[64][F64_BK + 1];
-  __shared__ double sB[64][F64_BK + 1];
-  __shared__ double sV[64][MC];
-  __shared__ double snb[64];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  const int64_t ntiles = ceil_div(n2, 64);
-  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
-  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
-  double acc[4][MC];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < MC; ++q) acc[r][q] = 0.0;
-  double na[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) na[r] = nua[i0 + 4 * ty + r];
-
-  for (int64_t t = t_begin; t < t_end; ++t) {
-    const int64_t j0 = t * 64;
-    double g[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) g[r][q] = 0.0;
-    for (int64_t k0 = 0; k0 < dp; k0 += F64_BK) {
-      __syncthreads();
-      for (int e = tid; e < 64 * F64_BK; e += 256) {
-        const int rr = e / F64_BK, kk = e % F64_BK;
-        sA[rr][kk] = Xa[(i0 + rr) * dp + k0 + kk];
-        sB[rr][kk] = Xb[(j0 + rr) * dp + k0 + kk];
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int kk = 0; kk < F64_BK; ++kk) {
-        double a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = sA[4 * ty + r][kk];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = sB[tx + 16 * q][kk];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) g[r][q] = fma(a[r], b[q], g[r][q]);
-      }
-    }
-    for (int e = tid; e < 64 * MC; e += 256) {
-      const int rr = e / MC, q = e % MC;
-      sV[rr][q] = (j0 + rr < n2) ? V[(j0 + rr) * ldv + c0 + q] : 0.0;
-    }
-    if (tid < 64) snb[tid] = nub[j0 + tid];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int jj = tx + 16 * q;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        double D = na[r] + snb[jj] - 2.0 * g[r][q];
-        D = D > 0.0 ? D : 0.0;
-        double p = exp(-D * c);
-        if (deriv) p *= D * dscale;
-#pragma unroll
-        for (int u = 0; u < MC; ++u) acc[r][u] = fma(p, sV[jj][u], acc[r][u]);
-      }
-    }
-  }
-  // reduce over the 16 threads (tx) sharing rows: consecutive lanes of one wave
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int u = 0; u < MC; ++u) {
-      double s = acc[r][u];
-      for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
-      acc[r][u] = s;
-    }
-  double* pout = part + (int64_t)blockIdx.y * part_stride;
-#pragma unroll
-  for (int u = 0; u < MC; ++u)
-    if (tx == u) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + 4 * ty + r;
-        if (i < n1) pout[i * ldp + c0 + u] = acc[r][u];
-      }
-    }
-}
-
 // FP64 kernel product on FP64 MFMA (16x16x4). Lane layout (gfx950): A operand lane l holds
 // A[l%16][l/16], B operand B[l/16][l%16], result register r holds C[l/16 + 4r][l%16].
 // Each wave owns 16 rows i whose coordinates stay in registers as the B operand; the
@@ -1088,12 +1035,167 @@ static void launch_f64mfma(dim3 grid, hipStream_t st, const F64Points& A, const 
                                                        part_stride, tps);
 }
 
+// Large-d FP64 product (dp > 128, multiple of 32): both point sets stream through LDS in
+// 32-wide k chunks as FP32 coordinates (exact copies of X), converted to FP64 for the 16x16x4
+// FP64 MFMA, so every product x_ik x_jk is exact and the sums are FP64. Block: 128 rows (4
+// waves x 32) against 64-column tiles; per tile the wave accumulates G^T for its 4 x 2 blocks
+// of 16 x 16, then D = nu_i + nu_j - 2 G, k = exp(-D c) (FP64, table-driven) and
+// OUT[i][:] += sum_j k V[j][:] on FP64 MFMA. The V tile of a column tile is written to LDS at
+// the tile's first chunk and read at its last (at least one barrier in between; the previous
+// tile's readers have passed a barrier), so it needs one buffer.
+constexpr int F64B_TJ = 64;
+constexpr int F64B_LK = 33;  // padded LDS row of a chunk (floats)
+template <int NCT>
+__global__ __launch_bounds__(256, 2) void matmat_f64big_kernel(
+    const float* __restrict__ Xa, const double* __restrict__ nua, const float* __restrict__ Xb,
+    const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
+    int64_t n2, int64_t m, int c0, int dp, double c, int deriv, double dscale,
+    double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split) {
+  constexpr int VC = 16 * NCT;
+  constexpr int LV = VC + 1;
+  __shared__ float sR[2][128 * F64B_LK];
+  __shared__ float sC[2][F64B_TJ * F64B_LK];
+  __shared__ double sV[F64B_TJ * LV];
+  __shared__ double sN[F64B_TJ];
+  __shared__ double sE[64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t blk_i0 = (int64_t)blockIdx.x * 128;
+  const int64_t ntiles = ceil_div(n2, F64B_TJ);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+  const int KC = dp / 32;
+  const int64_t nsteps = (t_end - t_begin) * KC;
+  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);
+
+  double nui[2];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib) nui[ib] = nua[blk_i0 + 32 * w + 16 * ib + li];
+  d4v g[4][2], acc[2][NCT];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[ib][ct] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  // loaders: row chunk 128 x 32 floats (4 float4 per thread), column chunk 64 x 32 (2),
+  // V tile 64 x VC doubles and nu of the tile's columns at each tile's first chunk
+  const int lrow = tid >> 3, lc4 = (tid & 7) * 4;
+  float4 rr[4], rc[2];
+  double rv[F64B_TJ * VC / 256];
+  double rn = 0.0;
+  auto gload = [&](int64_t q) __attribute__((always_inline)) {
+    const int64_t t = t_begin + q / KC;
+    const int kc = (int)(q % KC);
+    const int64_t ko = (int64_t)kc * 32 + lc4;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      rr[u] = *reinterpret_cast<const float4*>(Xa + (blk_i0 + lrow + 32 * u) * dp + ko);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      rc[u] = *reinterpret_cast<const float4*>(Xb + (t * F64B_TJ + lrow + 32 * u) * dp + ko);
+    if (kc == 0) {
+#pragma unroll
+      for (int u = 0; u < F64B_TJ * VC / 256; ++u) {
+        const int e = tid + 256 * u, r = e / VC, cc = e % VC;
+        const int64_t j = t * F64B_TJ + r;
+        rv[u] = (j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
+      }
+      if (tid < F64B_TJ) rn = nub[t * F64B_TJ + tid];
+    }
+  };
+  auto lstore = [&](int64_t q) __attribute__((always_inline)) {
+    const int buf = (int)(q & 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      float* d = &sR[buf][(lrow + 32 * u) * F64B_LK + lc4];
+      d[0] = rr[u].x; d[1] = rr[u].y; d[2] = rr[u].z; d[3] = rr[u].w;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      float* d = &sC[buf][(lrow + 32 * u) * F64B_LK + lc4];
+      d[0] = rc[u].x; d[1] = rc[u].y; d[2] = rc[u].z; d[3] = rc[u].w;
+    }
+  };
+  auto vstore = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < F64B_TJ * VC / 256; ++u) {
+      const int e = tid + 256 * u;
+      sV[(e / VC) * LV + e % VC] = rv[u];
+    }
+    if (tid < F64B_TJ) sN[tid] = rn;
+  };
+
+  if (nsteps > 0) {
+    gload(0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t q = 0; q < nsteps; ++q) {
+    const int buf = (int)(q & 1);
+    const int kc = (int)(q % KC);
+    if (kc == 0) {
+      vstore();  // this tile's V and nu (read at its last chunk, after a barrier)
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) g[jb][ib] = d4v{0.0, 0.0, 0.0, 0.0};
+    }
+    if (q + 1 < nsteps) gload(q + 1);
+#pragma unroll
+    for (int sk = 0; sk < 8; ++sk) {
+      double a[4], b[2];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb) a[jb] = (double)sC[buf][(16 * jb + li) * F64B_LK + 4 * sk + lg];
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+        b[ib] = (double)sR[buf][(32 * w + 16 * ib + li) * F64B_LK + 4 * sk + lg];
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+          g[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[jb], b[ib], g[jb][ib], 0, 0, 0);
+    }
+    if (kc == KC - 1) {
+#pragma unroll
+      for (int jb = 0; jb < 4; ++jb)
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int jj = 16 * jb + lg + 4 * r;
+            double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];
+            D = D > 0.0 ? D : 0.0;
+            double p = exp_neg_tab(D * c, sE);
+            if (deriv) p *= D * dscale;
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+              acc[ib][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[jj * LV + 16 * ct + li],
+                                                                 acc[ib][ct], 0, 0, 0);
+          }
+    }
+    if (q + 1 < nsteps) lstore(q + 1);
+    __syncthreads();
+  }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t cc = c0 + 16 * ct + li;
+    if (cc < m) {
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = blk_i0 + 32 * w + 16 * ib + lg + 4 * r;
+          if (i < n1) pout[i * ldp + cc] = acc[ib][ct][r];
+        }
+    }
+  }
+}
+
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
                       int64_t part_stride, int nsplit, hipStream_t st) {
   if (A.dp != B.dp) return hipErrorInvalidValue;
-  const int64_t ntiles = ceil_div(B.n, 64);
-  const int tps = (int)ceil_div(ntiles, nsplit);
   dim3 grid(ceil_div(A.n, 64), nsplit);
   if (A.dp <= 128 && A.dp % 8 == 0) {
     // FP64 MFMA kernel: 32-point column tiles, up to 32 right-hand sides per pass
@@ -1116,18 +1218,18 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
     }
     return hipSuccess;
   }
-  for (int64_t c0 = 0; c0 < m; c0 += 8) {
-    const int mc = (int)std::min<int64_t>(8, m - c0);
-    switch (mc) {
-#define KRR_MC(N)                                                                              \
-  case N:                                                                                      \
-    matmat_f64_kernel<N><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, A.dp, V, ldv, A.n, B.n,   \
-                                               (int)c0, c, deriv ? 1 : 0, dscale, part, ldp,   \
-                                               part_stride, tps);                              \
-    break;
-      KRR_MC(1) KRR_MC(2) KRR_MC(3) KRR_MC(4) KRR_MC(5) KRR_MC(6) KRR_MC(7) KRR_MC(8)
-#undef KRR_MC
-    }
+  if (!A.Xf || !B.Xf || A.dp % 32) return hipErrorInvalidValue;
+  const int tpsb = (int)ceil_div(ceil_div(B.n, F64B_TJ), nsplit);
+  dim3 gridb(ceil_div(A.n, 128), nsplit);
+  for (int64_t c0 = 0; c0 < m; c0 += 32) {
+    if (m - c0 > 16)
+      matmat_f64big_kernel<2><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m,
+                                                     (int)c0, (int)A.dp, c, deriv ? 1 : 0, dscale,
+                                                     part, ldp, part_stride, tpsb);
+    else
+      matmat_f64big_kernel<1><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m,
+                                                     (int)c0, (int)A.dp, c, deriv ? 1 : 0, dscale,
+                                                     part, ldp, part_stride, tpsb);
     KRR_LAUNCH_CHECK();
   }
   return hipSuccess;

@@ -219,10 +219,11 @@ hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows
 }
 
 // FP64 points for the plain FP64 path: X64 (rows_pad x dp, zero padded) and nu (rows_pad).
+template <typename T>
 __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __restrict__ X,
                                                               int64_t n, int64_t d, int64_t ldx,
                                                               int64_t rows_pad, int64_t dp,
-                                                              double* __restrict__ X64,
+                                                              T* __restrict__ X64,
                                                               double* __restrict__ nu) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __res
   double s = 0.0;
   for (int64_t k = lane; k < dp; k += 64) {
     double v = (row < n && k < d) ? (double)X[row * ldx + k] : 0.0;
-    X64[row * dp + k] = v;
+    X64[row * dp + k] = (T)v;  // exact for both types: v is an FP32 value
     s += v * v;
   }
   s = wave_sum(s);
@@ -239,8 +240,18 @@ __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __res
 
 hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                            int64_t dp, double* X64, double* nu, hipStream_t st) {
-  prep_points_f64_kernel<<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, dp, X64,
-                                                                nu);
+  prep_points_f64_kernel<double><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad,
+                                                                        dp, X64, nu);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// Same with the coordinates kept in FP32 (an exact copy, zero padded) for the large-d FP64
+// product, which converts them on the fly; nu is still formed in FP64.
+hipError_t prep_points_f64x(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                            int64_t dp, float* X32, double* nu, hipStream_t st) {
+  prep_points_f64_kernel<float><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad,
+                                                                       dp, X32, nu);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -365,6 +365,29 @@ def test_matmat_large_d_and_many_columns(dev, case):
     """d beyond the register-resident kernel (both operands through LDS) and m > 32
     (several column passes)."""
     n1, n2, d, m = case
+    _large_d_case(dev, n1, n2, d, m)
+
+
+@pytest.mark.parametrize("case", [(150, 333, 300, 5), (200, 257, 440, 40), (64, 300, 784, 10),
+                                  (129, 65, 136, 17)])
+def test_matmat_fp64_large_d(dev, case):
+    """FP64 product with d > 128 (FP32 coordinates through LDS, FP64 MFMA): 1e-12 relative to
+    (|K| |V|)_i, value and sigma-derivative, ragged row and column counts."""
+    n1, n2, d, m = case
+    rng = np.random.default_rng(d + m + 1)
+    X1 = rng.standard_normal((n1, d)).astype(np.float32)
+    X2 = rng.standard_normal((n2, d)).astype(np.float32)
+    V = rng.standard_normal((n2, m))
+    sigma = 0.8 * math.sqrt(d)
+    for deriv in (False, True):
+        got = krr.kernel_matmat(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), deriv=deriv,
+                                prec="fp64").cpu().numpy()
+        ref = O.kernel_matmat(X1, X2, sigma, V, deriv=deriv)
+        bound = 1e-12 * _abs_bound(X1, X2, sigma, V, deriv)
+        assert np.all(np.abs(got - ref) <= bound), (deriv, np.max(np.abs(got - ref) / bound))
+
+
+def _large_d_case(dev, n1, n2, d, m):
     rng = np.random.default_rng(d + m)
     X1 = rng.standard_normal((n1, d)).astype(np.float32)
     X2 = rng.standard_normal((n2, d)).astype(np.float32)
