@@ -455,3 +455,56 @@ def test_validation_gradient_central_differences(dev):
     fd_l = (loss(w.sigma, w.lam * math.exp(h), "fp64") - loss(w.sigma, w.lam * math.exp(-h), "fp64")) / (2 * h) / w.lam
     assert float(sig.grad) == pytest.approx(fd_s, rel=1e-4)
     assert float(lam.grad) == pytest.approx(fd_l, rel=1e-4)
+
+
+# ------------------------------------------------------------ full-size workloads
+def test_pixels_full_size_sampled(dev):
+    """The large dense-feature workload (n = 262144, d = 784, 10 right-hand sides,
+    s = 8192) at full size: the kernel product on sampled rows against the oracle (same
+    bound as the small cases) and the solve to 1e-6, whose FP64 true residual the oracle's
+    residual on sampled rows confirms."""
+    w = WL.pixels()
+    X, Y = _t(w.X, dev), _t(w.Y, dev)
+    rows = np.sort(np.random.default_rng(11).choice(w.n, 24, replace=False))
+    V = np.random.default_rng(12).standard_normal((w.n, w.m))
+    got = krr.kernel_matmat(X, X, w.sigma, _t(V, dev)).cpu().numpy()[rows]
+    Kr = O.gaussian_kernel(w.X[rows], w.X, w.sigma)
+    ref = Kr @ V
+    tau = _tau("f16x3", w.X[rows], w.X, w.sigma, w.d)
+    assert np.all(np.abs(got - ref) <= tau * (np.abs(Kr) @ np.abs(V)))
+    Z = krr.features(X, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    del Z
+    alpha, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=1e-6, refine=3)
+    assert max(rep.relres_true) <= 1e-6
+    a = alpha.cpu().numpy()
+    r = w.Y[rows] - (Kr @ a + w.lam * a[rows])
+    est = np.linalg.norm(r, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
+    assert est.max() <= 4e-6, est
+
+
+def test_differentiation_full_size_central_differences(dev):
+    """The differentiation workload at full size (n = 131072 + 16384, d = 440, 147 columns,
+    s = 4096): the adjoint gradients of the mixed path against central differences (log
+    sigma, log lambda, h = 1e-4) of the loss evaluated with refined solves to 1e-10 and the
+    FP64 validation product; 1e-4 relative."""
+    from paper_1611_03220_amd import autograd as KA
+    w = WL.correlated_differentiation()
+    Xtr, Xv = _t(w.X, dev), _t(w.Xv, dev)
+    Ytr, Yv = _t(w.Y, dev), _t(w.Yv, dev)
+    Z = krr.features(Xtr, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    del Z
+    sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev, requires_grad=True)
+    lam = torch.tensor(w.lam, dtype=torch.float64, device=dev, requires_grad=True)
+    KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, tol=1e-9, refine=4).backward()
+
+    def loss(s_, l_):
+        with torch.no_grad():
+            return float(KA.validation_loss(Xtr, Ytr, Xv, Yv, s_, l_, Ut, tol=1e-10, refine=6))
+
+    h = 1e-4
+    fd_s = (loss(w.sigma * math.exp(h), w.lam) - loss(w.sigma * math.exp(-h), w.lam)) / (2 * h) / w.sigma
+    fd_l = (loss(w.sigma, w.lam * math.exp(h)) - loss(w.sigma, w.lam * math.exp(-h))) / (2 * h) / w.lam
+    assert float(sig.grad) == pytest.approx(fd_s, rel=1e-4)
+    assert float(lam.grad) == pytest.approx(fd_l, rel=1e-4)
