@@ -1,4 +1,4 @@
-// Batched PCG vector work (hot-path step a9): many independent problems packed row-wise.
+// Batched PCG vector work: many independent problems packed row-wise.
 // Problem p owns packed rows [off_p, off_p + n_p) (offsets are multiples of ROW_PAD) and M
 // columns (p's own m_p <= M; extra columns carry zero right-hand sides and stay inactive).
 // Per-(problem, column) scalars live at index p * M + c. Reductions are two-pass and

@@ -1,4 +1,4 @@
-// PCG vector work (hot-path steps a5, a6): per-column FP64 inner products, step lengths,
+// PCG vector work: per-column FP64 inner products, step lengths,
 // iterate updates, convergence masks, and the Woodbury preconditioner apply
 //   z = (r - Ut (Ut^T r)) / lambda_p     (Sec. 3.1).
 // Reductions are two-pass and deterministic: each block writes one partial per column;

@@ -1,4 +1,4 @@
-// FP64 Cholesky of G = Z^T Z + lambda_p I and the inverse of its factor (step a3).
+// FP64 Cholesky of G = Z^T Z + lambda_p I and the inverse of its factor (Sec. 3.1).
 //
 // Blocked right-looking factorisation with 64 x 64 diagonal blocks: one workgroup factors
 // the diagonal block with its rows in registers; the panel below is solved against it (one

@@ -1,4 +1,4 @@
-// Dense products of the set-up steps (a2, a3):
+// Dense products of the set-up (random features and preconditioner factor):
 //   * gemm_nt_f16x3: C[M x N] = s * sum_k A[i, k] B[j, k] on MFMA from FP16 hi/lo splits
 //     (three products), FP32 accumulate within a k split, with epilogues
 //       EPI_PART64 : FP64 partial per k split (Gram Z^T Z; summed in fixed order later)

@@ -1,4 +1,4 @@
-// Matrix-free Gaussian kernel products (hot-path step a4): OUT = K(X1, X2) V.
+// Matrix-free Gaussian kernel products: OUT = K(X1, X2) V.
 //
 // Mixed kernel (F16X3 / BF16X3): each 64-thread wave owns 16 output rows i; the block
 // (4 waves, 64 rows) sweeps a range of 64-column tiles j. Per 16x16 (i, j) block, three

@@ -1,4 +1,4 @@
-// Point preparation (hot-path step a1) and operand splitting for the MFMA products.
+// Point preparation and operand splitting for the MFMA products.
 //
 // The Gaussian kernel (Sec. 5) is evaluated through the norm expansion
 //   -||x_i - x_j||^2 c = 2c <x_i, x_j> - c nu_i - c nu_j,   nu = ||x||^2, c = log2(e)/(2 sigma^2),

@@ -4,7 +4,7 @@ This module generates the inputs that both the HIP path and the CPU oracle consu
 points X, right-hand sides Y, the kernel bandwidth sigma and ridge lambda, and the
 random draws of the feature map (W, b). It holds none of the method's arithmetic.
 
-Every array is generated in FP64 with ``numpy.random.default_rng(161103220 + 1000*cfg
+Every array is generated in FP64 with ``numpy.random.default_rng(161103220 + 1000*family
 + stream)`` and rounded once to FP32 where it is a data input (X, W, b); those FP32
 values are the canonical inputs for both sides. Streams: 0 points, 1 labels / teacher,
 2 feature-map draws (W, b), 3 bandwidth pairs, 4 noise.
@@ -23,8 +23,8 @@ import numpy as np
 SEED_BASE = 161103220
 
 
-def rng_for(cfg: int, stream: int, salt: int = 0) -> np.random.Generator:
-    return np.random.default_rng(SEED_BASE + 1000 * cfg + stream + 100000 * salt)
+def rng_for(family: int, stream: int, salt: int = 0) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + 1000 * family + stream + 100000 * salt)
 
 
 @dataclasses.dataclass
@@ -87,13 +87,13 @@ def plain_fp64(n: int = 2000, d: int = 8, s: int = 200, lam_per_n: float = 1e-3,
                tol: float = 1e-10, salt: int = 0) -> Workload:
     """Single-RHS regression: X ~ N(0,1), sigma = sqrt(d), lambda = 1e-3 n,
     y = sin(X u) + 0.1 eps with u ~ N(0, I/d)."""
-    cfg = 0
-    X = rng_for(cfg, 0, salt).standard_normal((n, d)).astype(np.float32)
-    u = rng_for(cfg, 1, salt).standard_normal(d) / math.sqrt(d)
-    eps = rng_for(cfg, 4, salt).standard_normal(n)
+    family = 0
+    X = rng_for(family, 0, salt).standard_normal((n, d)).astype(np.float32)
+    u = rng_for(family, 1, salt).standard_normal(d) / math.sqrt(d)
+    eps = rng_for(family, 4, salt).standard_normal(n)
     Y = np.ascontiguousarray((np.sin(X.astype(np.float64) @ u) + 0.1 * eps)[:, None])
     sigma = math.sqrt(d)
-    W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt))
+    W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt))
     return Workload("plain_fp64", X, Y, sigma, lam_per_n * n, s, W, b, tol)
 
 
@@ -102,15 +102,15 @@ def mixture_multi_rhs(n: int = 65536, d: int = 54, k: int = 7, s: int = 2048,
     """k-component Gaussian mixture (means ~ N(0, 4 I), unit covariance, uniform weights),
     standardised per column; k one-vs-all +-1 columns; sigma = median pairwise distance
     (the same kernel as scaling X to unit median distance with sigma = 1)."""
-    cfg = 1
-    r0 = rng_for(cfg, 0, salt)
+    family = 1
+    r0 = rng_for(family, 0, salt)
     means = 2.0 * r0.standard_normal((k, d))
-    lab = rng_for(cfg, 1, salt).integers(0, k, n)
+    lab = rng_for(family, 1, salt).integers(0, k, n)
     X = means[lab] + r0.standard_normal((n, d))
     X = (X - X.mean(0)) / X.std(0)
     X = X.astype(np.float32)
-    sigma = median_distance(X, rng_for(cfg, 3, salt))
-    W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt))
+    sigma = median_distance(X, rng_for(family, 3, salt))
+    W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt))
     return Workload("mixture_multi_rhs", X, one_vs_all(lab, k), sigma, lam_per_n * n, s, W, b, tol)
 
 
@@ -118,20 +118,20 @@ def pixels(n: int = 262144, d: int = 784, k: int = 10, s: int = 8192,
            lam_per_n: float = 1e-5, tol: float = 1e-6, salt: int = 0) -> Workload:
     """Pixel-like points in [0, 1]: 80% zeros, nonzeros ~ U(0, 1); k one-vs-all columns
     from the argmax of a random linear teacher applied to the centred points."""
-    cfg = 2
-    r0 = rng_for(cfg, 0, salt)
+    family = 2
+    r0 = rng_for(family, 0, salt)
     X = np.zeros((n, d), np.float32)
     for a in range(0, n, 8192):
         blk = r0.uniform(0.0, 1.0, (min(8192, n - a), d))
         blk[r0.random(blk.shape) < 0.8] = 0.0
         X[a:a + blk.shape[0]] = blk
-    T = rng_for(cfg, 1, salt).standard_normal((d, k))
+    T = rng_for(family, 1, salt).standard_normal((d, k))
     mu = X.astype(np.float64).mean(0)
     lab = np.empty(n, np.int64)
     for a in range(0, n, 8192):
         lab[a:a + 8192] = np.argmax((X[a:a + 8192].astype(np.float64) - mu) @ T, axis=1)
-    sigma = median_distance(X, rng_for(cfg, 3, salt))
-    W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt))
+    sigma = median_distance(X, rng_for(family, 3, salt))
+    W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt))
     return Workload("pixels", X, one_vs_all(lab, k), sigma, lam_per_n * n, s, W, b, tol)
 
 
@@ -141,22 +141,22 @@ def correlated_differentiation(n: int = 131072, n_val: int = 16384, d: int = 440
     """X = G A^T / sqrt(d) with G, A ~ N(0,1) (covariance A A^T / d); k one-vs-all columns
     from the argmax of a random linear teacher; n training plus n_val validation points;
     sigma = median training distance, lambda = 1e-4 n."""
-    cfg = 4
-    r0 = rng_for(cfg, 0, salt)
+    family = 4
+    r0 = rng_for(family, 0, salt)
     A = r0.standard_normal((d, d))
     tot = n + n_val
     X = np.empty((tot, d), np.float32)
     for a in range(0, tot, 8192):
         m_ = min(8192, tot - a)
         X[a:a + m_] = (r0.standard_normal((m_, d)) @ A.T / math.sqrt(d)).astype(np.float32)
-    T = rng_for(cfg, 1, salt).standard_normal((d, k))
+    T = rng_for(family, 1, salt).standard_normal((d, k))
     lab = np.empty(tot, np.int64)
     for a in range(0, tot, 8192):
         lab[a:a + 8192] = np.argmax(X[a:a + 8192].astype(np.float64) @ T, axis=1)
     Yall = one_vs_all(lab, k)
     Xtr, Xv = X[:n], X[n:]
-    sigma = median_distance(Xtr, rng_for(cfg, 3, salt))
-    W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt))
+    sigma = median_distance(Xtr, rng_for(family, 3, salt))
+    W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt))
     return Workload("correlated_differentiation", Xtr, Yall[:n], sigma, lam_per_n * n, s, W, b,
                     tol, Xv=Xv, Yv=Yall[n:])
 
@@ -166,20 +166,20 @@ def batched_instances(count: int = 64, n_lo: int = 1024, n_hi: int = 16384,
     """``count`` independent problems: n log-uniform in [n_lo, n_hi], d uniform over
     ``dims``, X ~ N(0,1), s = n/8, 1..4 right-hand sides y = sin(X u) + 0.1 eps,
     lambda log-uniform in [1e-6, 1e-2] n, sigma = sqrt(d)."""
-    cfg = 3
-    meta = rng_for(cfg, 1, salt)
+    family = 3
+    meta = rng_for(family, 1, salt)
     out = []
     for t in range(count):
         n = int(round(math.exp(meta.uniform(math.log(n_lo), math.log(n_hi)))))
         d = int(meta.choice(dims))
         m = int(meta.integers(1, 5))
         lam = math.exp(meta.uniform(math.log(1e-6), math.log(1e-2))) * n
-        X = rng_for(cfg, 0, salt * 1000 + t + 1).standard_normal((n, d)).astype(np.float32)
-        u = rng_for(cfg, 1, salt * 1000 + t + 1).standard_normal((d, m)) / math.sqrt(d)
-        eps = rng_for(cfg, 4, salt * 1000 + t + 1).standard_normal((n, m))
+        X = rng_for(family, 0, salt * 1000 + t + 1).standard_normal((n, d)).astype(np.float32)
+        u = rng_for(family, 1, salt * 1000 + t + 1).standard_normal((d, m)) / math.sqrt(d)
+        eps = rng_for(family, 4, salt * 1000 + t + 1).standard_normal((n, m))
         Y = np.sin(X.astype(np.float64) @ u) + 0.1 * eps
         sigma = math.sqrt(d)
         s = max(1, n // 8)
-        W, b = rff_draw(d, s, sigma, rng_for(cfg, 2, salt * 1000 + t + 1))
+        W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt * 1000 + t + 1))
         out.append(Workload(f"batched_{t}", X, Y, sigma, lam, s, W, b, tol))
     return out

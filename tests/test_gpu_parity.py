@@ -416,7 +416,7 @@ def _diff_workload():
 def test_validation_gradient_matches_oracle(dev, prec):
     """The differentiation workload's recipe (d = 440, 147 classes) at n = 3072 + 384:
     validation loss and its sigma / lambda gradients through the adjoint PCG against the
-    oracle's dense FP64 adjoint gradients (spec bound: 1e-4 relative)."""
+    oracle's dense FP64 adjoint gradients (bound: 1e-4 relative)."""
     from paper_1611_03220_amd import autograd as KA
     w = _diff_workload()
     Xtr, Xv = _t(w.X, dev), _t(w.Xv, dev)
