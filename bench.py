@@ -55,9 +55,16 @@ def parse():
 
 
 def source_sha256(rel):
+    """Digest of a source file's code: comments and white space removed, so that editing a
+    comment does not invalidate counters taken on the same kernels."""
     import hashlib
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    import re
+    with open(os.path.join(ROOT, rel)) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    src = " ".join(src.split())
+    return hashlib.sha256(src.encode()).hexdigest()
 
 
 def recorded_traffic(kernel_src):
