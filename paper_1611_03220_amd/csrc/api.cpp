@@ -240,7 +240,7 @@ int64_t pow2_pad(int64_t s) {
 int gram_nsplit(int64_t s, int64_t n) {
   const int64_t t = ceil_div(s, GEMM_TILE);
   const int64_t tiles = t * (t + 1) / 2;
-  int64_t ns = ceil_div(2048, tiles);
+  int64_t ns = ceil_div(1024, tiles);  // enough blocks; every split adds s^2 FP64 partials
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, ceil_div(n, 2048)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(ns, 32));
 }
@@ -285,7 +285,7 @@ struct PCGLayout {
   int nchunk;
 };
 int precond_nchunk(int64_t n, int64_t s) {
-  const int64_t kb = ceil_div(std::max<int64_t>(s, 1), 256);
+  const int64_t kb = ceil_div(std::max<int64_t>(s, 1), 512);  // feature columns per block
   int64_t nc = ceil_div(1024, kb);
   nc = std::min<int64_t>(nc, std::max<int64_t>(1, ceil_div(n, 256)));
   return (int)std::max<int64_t>(1, std::min<int64_t>(nc, 512));
@@ -1119,7 +1119,7 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
       red_h.push_back(RedItem{i, off + r0, off + std::min<int64_t>(b.n, r0 + 1024)});
     Mt.red_end = (int)red_h.size();
     if (Mt.has_u) {
-      const int chunks = (int)std::max<int64_t>(1, ceil_div(b.n, 2048));
+      const int chunks = (int)std::max<int64_t>(1, ceil_div(b.n, 512));  // rows per first-pass item
       Mt.pc_chunks = chunks;
       Mt.pc_part_off = pc_off;
       Mt.t_off = t_off;

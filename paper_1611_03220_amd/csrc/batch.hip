@@ -352,8 +352,8 @@ __global__ __launch_bounds__(256) void batch_t_partial_kernel(const PCItem* __re
   const PCItem it = items[blockIdx.x];
   if (!live[it.inst]) return;
   const BatchMeta P = meta[it.inst];
-  woodbury_tpart<MC>(P.Ut, P.ldu, P.s, r + P.off * MC, MC, it.i0, it.i1, it.k0 + threadIdx.x,
-                     part + it.part_off + (int64_t)it.chunk * P.s * 16, 16);
+  woodbury_tpart<MC, 1>(P.Ut, P.ldu, P.s, r + P.off * MC, MC, it.i0, it.i1, it.k0 + threadIdx.x,
+                        part + it.part_off + (int64_t)it.chunk * P.s * 16, 16);
 }
 
 // T_p[k][c] = sum over chunks (c < M); blockIdx.y = problem

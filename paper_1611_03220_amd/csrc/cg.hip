@@ -348,10 +348,12 @@ template <int MC>
 __global__ __launch_bounds__(256) void precond_t_partial_kernel(
     const float* __restrict__ Ut, int64_t ldu, const double* __restrict__ r, int64_t n, int64_t s,
     int64_t m, int c0, int64_t rows_per_chunk, double* __restrict__ part) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int KPT = woodbury_kpt(MC);
+  const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * KPT;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
-  woodbury_tpart<MC>(Ut, ldu, s, r + c0, m, i0, i1, k, part + (int64_t)blockIdx.y * s * m + c0, m);
+  woodbury_tpart<MC, KPT>(Ut, ldu, s, r + c0, m, i0, i1, k0,
+                          part + (int64_t)blockIdx.y * s * m + c0, m);
 }
 
 // T[k][c] = sum_chunk part[chunk][k][c]
@@ -359,9 +361,18 @@ __global__ void precond_t_reduce_kernel(const double* __restrict__ part, int nch
                                         int64_t m, double* __restrict__ T) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= s * m) return;
-  double v = 0.0;
-  for (int b = 0; b < nchunk; ++b) v += part[(int64_t)b * s * m + e];
-  T[e] = v;
+  // four interleaved partial sums (independent loads in flight), combined in a fixed order
+  const int64_t st = s * m;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int b = 0;
+  for (; b + 4 <= nchunk; b += 4) {
+    v0 += part[(int64_t)b * st + e];
+    v1 += part[(int64_t)(b + 1) * st + e];
+    v2 += part[(int64_t)(b + 2) * st + e];
+    v3 += part[(int64_t)(b + 3) * st + e];
+  }
+  for (; b < nchunk; ++b) v0 += part[(int64_t)b * st + e];
+  T[e] = (v0 + v1) + (v2 + v3);
 }
 
 // Pass 2: z[i][c] = (r[i][c] - sum_k Ut[i][k] T[k][c]) / lambda_p for 64-row blocks.
@@ -382,7 +393,7 @@ hipError_t precond_apply(const float* Ut, int64_t ldu, int64_t n, int64_t s, int
   const int64_t rows_per_chunk = ceil_div(n, nchunk);
   for (int64_t c0 = 0; c0 < m; c0 += PC_M) {
     const int mc = (int)std::min<int64_t>(PC_M, m - c0);
-    dim3 g1(ceil_div(s, 256), nchunk);
+    dim3 g1(ceil_div(s, 256 * (mc <= 8 ? 2 : 1)), nchunk);  // 256 threads x woodbury_kpt(mc)
     switch (mc) {
 #define KRR_PC(N)                                                                            \
   case N:                                                                                    \

@@ -491,8 +491,12 @@ __device__ __forceinline__ void f16pv_body(
     gvl += MM_BN;
     }
     f32x4 S0[2][2], S1[2][2];
+    // raised wave priority while issuing the distance MFMAs lets the waves of a SIMD
+    // alternate between MFMA-heavy and VALU-heavy phases (measured: 4 % faster)
+    __builtin_amdgcn_s_setprio(1);
     dist(buf, 0, S0);
     dist(buf, 1, S1);
+    __builtin_amdgcn_s_setprio(0);
     epi(buf, 0, S0);
     epi(buf, 1, S1);
     if (++since_flush == MM2_FLUSH || t + 1 == t_end) {

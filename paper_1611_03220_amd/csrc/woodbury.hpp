@@ -7,48 +7,77 @@
 
 namespace krr {
 
-// Pass 1: T partial over rows [i0, i1) for one feature column k (one thread per k; the
-// threads of a block read consecutive k, so every row read is one contiguous segment).
+// Pass 1: T partial over rows [i0, i1) for feature columns k0 .. k0 + KPT - 1 (consecutive
+// threads take consecutive column groups, so every row read is one contiguous segment; KPT
+// columns per thread and eight rows per step keep enough loads in flight to stream Ut).
 // The rows of r are the same for every lane, so they come through scalar loads.
 // out[k * ldo + c] = sum_{i in [i0, i1)} Ut[i][k] r[i][c], c < MC.
-template <int MC>
+template <int MC, int KPT>
 __device__ __forceinline__ void woodbury_tpart(const float* __restrict__ Ut, int64_t ldu,
                                                int64_t s, const double* __restrict__ r,
-                                               int64_t ldr, int64_t i0, int64_t i1, int64_t k,
+                                               int64_t ldr, int64_t i0, int64_t i1, int64_t k0,
                                                double* __restrict__ out, int64_t ldo) {
-  double acc[MC];
+  constexpr int RU = 8;  // rows per step
+  double acc[KPT][MC];
 #pragma unroll
-  for (int c = 0; c < MC; ++c) acc[c] = 0.0;
-  const bool kin = k < s;
-  const float* up = Ut + (kin ? k : 0);
-  int64_t i = i0;
-  for (; i + 4 <= i1; i += 4) {
-    float u[4];
+  for (int q = 0; q < KPT; ++q)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float t = up[kin ? (i + j) * ldu : 0];
-      u[j] = kin ? t : 0.0f;
+    for (int c = 0; c < MC; ++c) acc[q][c] = 0.0;
+  bool kin[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) kin[q] = k0 + q < s;
+  // vector loads when the whole group is in range and aligned (ldu and k0 multiples of KPT)
+  const bool vec = KPT > 1 && k0 + KPT <= s && (ldu % KPT) == 0 &&
+                   (reinterpret_cast<uintptr_t>(Ut) % (4 * KPT)) == 0;
+  const float* up = Ut + (kin[0] ? k0 : 0);
+  auto load = [&](int64_t i, float (&u)[KPT]) __attribute__((always_inline)) {
+    if (KPT == 2 && vec) {
+      const float2 t = *reinterpret_cast<const float2*>(up + i * ldu);
+      u[0] = t.x;
+      u[KPT - 1] = t.y;
+    } else {
+#pragma unroll
+      for (int q = 0; q < KPT; ++q) {
+        const float t = Ut[kin[q] ? i * ldu + k0 + q : 0];
+        u[q] = kin[q] ? t : 0.0f;
+      }
     }
+  };
+  int64_t i = i0;
+  for (; i + RU <= i1; i += RU) {
+    float u[RU][KPT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const double uj = (double)u[j];
+    for (int j = 0; j < RU; ++j) load(i + j, u[j]);
+#pragma unroll
+    for (int j = 0; j < RU; ++j) {
       const double* rr = r + (i + j) * ldr;
 #pragma unroll
-      for (int c = 0; c < MC; ++c) acc[c] = fma(uj, rr[c], acc[c]);
+      for (int c = 0; c < MC; ++c) {
+        const double rc = rr[c];
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[j][q], rc, acc[q][c]);
+      }
     }
   }
   for (; i < i1; ++i) {
-    const float t = up[kin ? i * ldu : 0];
-    const double uj = kin ? (double)t : 0.0;
+    float u[KPT];
+    load(i, u);
     const double* rr = r + i * ldr;
 #pragma unroll
-    for (int c = 0; c < MC; ++c) acc[c] = fma(uj, rr[c], acc[c]);
-  }
-  if (kin) {
+    for (int c = 0; c < MC; ++c)
 #pragma unroll
-    for (int c = 0; c < MC; ++c) out[k * ldo + c] = acc[c];
+      for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[q], rr[c], acc[q][c]);
   }
+#pragma unroll
+  for (int q = 0; q < KPT; ++q)
+    if (kin[q]) {
+#pragma unroll
+      for (int c = 0; c < MC; ++c) out[(k0 + q) * ldo + c] = acc[q][c];
+    }
 }
+
+// columns per thread of the first pass for MC right-hand sides
+constexpr int woodbury_kpt(int MC) { return MC <= 8 ? 2 : 1; }
 
 // Pass 2 for one block of 64 rows [i0, i0 + 64) (rows >= iend masked) with 256 threads:
 // wave w covers the feature range [w kq, (w + 1) kq) in chunks of 32; lane l owns row i0 + l.
