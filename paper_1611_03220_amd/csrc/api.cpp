@@ -116,6 +116,8 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
   } else {
     c.pv = use_pv(prec, d);
     c.Kp = kp_for(prec, d);
+    // large-d MFMA product on many row blocks: 8 column splits, launched in XCD groups
+    if (c.pv && c.Kp > 128 && ceil_div(n1, 128) >= 64) c.nsplit = 8;
     if (c.pv) {
       c.mpad = round_up(std::min<int64_t>(m, 32), 16);
       c.Vth = b.take<_Float16>(c.mpad * c.rp2);

@@ -629,73 +629,77 @@ __device__ __forceinline__ void f16pv_bigd_body(
   const int vc1 = ve1 / (TN / 8), vj1 = ve1 % (TN / 8);
   const int svo00 = vpos<TN>(vc0, 8 * vj0), svo01 = vpos<TN>(vc0, 8 * vj0 + 4);
   const int svo10 = vpos<TN>(vc1, 8 * vj1), svo11 = vpos<TN>(vc1, 8 * vj1 + 4);
-  u32x4 ra0h = {}, ra0l = {}, ra1h = {}, ra1l = {}, rb0h = {}, rb0l = {}, rb1h = {}, rb1l = {};
-  u32x4 rv0h = {}, rv0l = {}, rv1h = {}, rv1l = {};
-  auto gload = [&](int64_t q) __attribute__((always_inline)) {
+  // two register sets: the chunk two steps ahead is loaded while the next one waits to be
+  // stored, so global loads have about one and a half steps to arrive
+  struct Regs {
+    u32x4 ra0h, ra0l, ra1h, ra1l, rb0h, rb0l, rb1h, rb1l, rv0h, rv0l, rv1h, rv1l;
+  };
+  Regs R0 = {}, R1 = {};
+  auto gload = [&](int64_t q, Regs& R) __attribute__((always_inline)) {
     const int64_t t = t_begin + q / KC;
     const int kc = (int)(q % KC);
     const int64_t ko = (int64_t)kc * 32 + acol * 8;
-    ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
-    ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko);
-    ra1h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow1) * KP + ko);
-    ra1l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow1) * KP + ko);
-    rb0h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + arow0) * KP + ko);
-    rb0l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + arow0) * KP + ko);
+    R.ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
+    R.ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko);
+    R.ra1h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow1) * KP + ko);
+    R.ra1l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow1) * KP + ko);
+    R.rb0h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + arow0) * KP + ko);
+    R.rb0l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + arow0) * KP + ko);
     if (BPT > 1) {
-      rb1h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + brow1) * KP + ko);
-      rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
+      R.rb1h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + brow1) * KP + ko);
+      R.rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
     }
     if (kc == 0) {
       if (vld0) {
-        rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
-        rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+        R.rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+        R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
       }
       if (vld1) {
-        rv1h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
-        rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
+        R.rv1h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
+        R.rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
       }
     }
   };
-  auto lstore = [&](int64_t q) __attribute__((always_inline)) {
+  auto lstore = [&](int64_t q, const Regs& R) __attribute__((always_inline)) {
     const int buf = (int)(q & 1);
     const int kc = (int)(q % KC);
-    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa0) = ra0h;
-    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa0) = ra0l;
-    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa1) = ra1h;
-    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa1) = ra1l;
-    *reinterpret_cast<u32x4*>(B_at(buf, 0) + sa0) = rb0h;
-    *reinterpret_cast<u32x4*>(B_at(buf, 1) + sa0) = rb0l;
+    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa0) = R.ra0h;
+    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa0) = R.ra0l;
+    *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa1) = R.ra1h;
+    *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa1) = R.ra1l;
+    *reinterpret_cast<u32x4*>(B_at(buf, 0) + sa0) = R.rb0h;
+    *reinterpret_cast<u32x4*>(B_at(buf, 1) + sa0) = R.rb0l;
     if (BPT > 1) {
-      *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb1) = rb1h;
-      *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb1) = rb1l;
+      *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb1) = R.rb1h;
+      *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb1) = R.rb1l;
     }
     if (kc == 0) {
       const int vb = (int)((q / KC) & 1);
       if (vld0) {
-        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{rv0h.x, rv0h.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo01) = u32x2{rv0h.z, rv0h.w};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo00) = u32x2{rv0l.x, rv0l.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo01) = u32x2{rv0l.z, rv0l.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{R.rv0h.x, R.rv0h.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo01) = u32x2{R.rv0h.z, R.rv0h.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo00) = u32x2{R.rv0l.x, R.rv0l.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo01) = u32x2{R.rv0l.z, R.rv0l.w};
       }
       if (vld1) {
-        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo10) = u32x2{rv1h.x, rv1h.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo11) = u32x2{rv1h.z, rv1h.w};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo10) = u32x2{rv1l.x, rv1l.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo11) = u32x2{rv1l.z, rv1l.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo10) = u32x2{R.rv1h.x, R.rv1h.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo11) = u32x2{R.rv1h.z, R.rv1h.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo10) = u32x2{R.rv1l.x, R.rv1l.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo11) = u32x2{R.rv1l.z, R.rv1l.w};
       }
     }
   };
 
   if (nsteps > 0) {
-    gload(0);
-    lstore(0);
+    gload(0, R0);
+    lstore(0, R0);
   }
+  if (nsteps > 1) gload(1, R0);
   __syncthreads();
   int since_flush = 0;
-  for (int64_t q = 0; q < nsteps; ++q) {
+  auto compute = [&](int64_t q) __attribute__((always_inline)) {
     const int buf = (int)(q & 1);
     const int kc = (int)(q % KC);
-    if (q + 1 < nsteps) gload(q + 1);
     // fragments of this chunk: rows of the wave (B operand) and the tile's columns (A operand)
     half8 ah[2], al[2];
 #pragma unroll
@@ -771,8 +775,16 @@ __device__ __forceinline__ void f16pv_bigd_body(
           }
       }
     }
-    if (q + 1 < nsteps) lstore(q + 1);
+  };
+  auto step = [&](int64_t q, const Regs& hold, Regs& spare) __attribute__((always_inline)) {
+    if (q + 2 < nsteps) gload(q + 2, spare);
+    compute(q);
+    if (q + 1 < nsteps) lstore(q + 1, hold);
     __syncthreads();
+  };
+  for (int64_t q = 0; q < nsteps; q += 2) {
+    step(q, R0, R1);
+    if (q + 1 < nsteps) step(q + 1, R1, R0);
   }
   double* pout = part + split * part_stride;
 #pragma unroll
@@ -794,6 +806,8 @@ __device__ __forceinline__ void f16pv_bigd_body(
 // column tiles of the large-d single-problem product (the batched product keeps 64)
 constexpr int BD_NJB = 8;
 constexpr int BD_TN = 16 * BD_NJB;
+// grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
+constexpr int BD_GROUP = 8;
 
 template <int NCT, bool DERIV>
 __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
@@ -802,19 +816,29 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split) {
+    int64_t part_stride, int tiles_per_split, int grouped) {
   __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, BD_NJB>()];
+  int64_t rb = blockIdx.x, sp = blockIdx.y;
+  if (grouped) {
+    // 1-D grid of (row block, split) pairs with BD_GROUP splits, ordered so that the blocks
+    // one XCD runs together (workgroups go round-robin to the 8 XCDs) form groups of
+    // BD_GROUP row blocks x BD_GROUP splits: each group shares its row operand chunks and its
+    // column tiles in that XCD's L2 instead of streaming them per block.
+    const int64_t b = blockIdx.x, x = b % 8, t = b / 8;
+    const int64_t gid = (t / (BD_GROUP * BD_GROUP)) * 8 + x, u = t % (BD_GROUP * BD_GROUP);
+    rb = gid * BD_GROUP + u / BD_GROUP;
+    sp = u % BD_GROUP;
+    if (rb * BD_BM >= n1) return;  // padding block
+  }
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
     f16pv_bigd_body<NCT, true, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                               n1, n2, m, KP, qinv2, dscale, part, ldp,
-                                              part_stride, tiles_per_split, blockIdx.x,
-                                              blockIdx.y);
+                                              part_stride, tiles_per_split, rb, sp);
   else
     f16pv_bigd_body<NCT, false, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                                n1, n2, m, KP, qinv2, dscale, part, ldp,
-                                               part_stride, tiles_per_split, blockIdx.x,
-                                               blockIdx.y);
+                                               part_stride, tiles_per_split, rb, sp);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
@@ -829,16 +853,19 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
     const int tps = (int)ceil_div(ceil_div(B.n, BD_TN), nsplit);
+    const int64_t nrb = ceil_div(A.n, BD_BM);
+    const int grouped = nsplit == BD_GROUP && nrb >= 8 * BD_GROUP ? 1 : 0;
+    if (grouped) grid = dim3((unsigned)(round_up(nrb, 8 * BD_GROUP) * BD_GROUP), 1);
     if (nct == 1) {
       if (deriv)
-        matmat_f16pv_bigd_kernel<1, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+        matmat_f16pv_bigd_kernel<1, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
       else
-        matmat_f16pv_bigd_kernel<1, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+        matmat_f16pv_bigd_kernel<1, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
     } else {
       if (deriv)
-        matmat_f16pv_bigd_kernel<2, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+        matmat_f16pv_bigd_kernel<2, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
       else
-        matmat_f16pv_bigd_kernel<2, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps);
+        matmat_f16pv_bigd_kernel<2, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
     }
     KRR_LAUNCH_CHECK();
     return hipSuccess;
