@@ -11,7 +11,7 @@ Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algori
 kernel-product flops 2 n^2 (d + m) of all products in the timed steps divided by the
 timed wall time. `roofline` describes the dominant kernel (the fused kernel product) against
 the dense FP16 MFMA peak: algorithmic flops per launch over the average launch time, timed with
-HIP events inside the library on the stream it runs on; the executed MFMA work (three split
+HIP events inside the library on the stream it runs on; the executed MFMA work (split
 products over padded widths) is reported beside it. `batched` is the solve of 64 uneven
 problems in one plan (persistent product, captured iteration graph). `fp64_path` is the
 same solve with the plain FP64 kernel product (time to tolerance), measured once after
@@ -268,7 +268,9 @@ def main():
     pairs = float(n) * n
     kp = int(math.ceil((d + 2) / 32.0) * 32)        # augmented, padded feature width
     mp = int(math.ceil(m / 16.0) * 16)              # padded right-hand-side columns
-    exec_mfma = pairs * 3 * 2 * (kp + mp)           # split-3 distances + split-3 P V
+    # split-3 distances; P V takes three split products, or two when m <= 8 (the hi and lo
+    # parts of V share one 16-column operand)
+    exec_mfma = pairs * 2 * (3 * kp + (2 if m <= 8 else 3) * mp)
     roof = {"bound": "mfma", "achieved": flops_mm / avg_launch_s / 1e12,
             "peak": PEAK_MFMA_F16 / 1e12, "unit": "TFLOP/s",
             "frac": flops_mm / avg_launch_s / PEAK_MFMA_F16,

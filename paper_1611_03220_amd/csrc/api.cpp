@@ -189,10 +189,11 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
       for (int64_t c0 = 0; c0 < c.m; c0 += 32) {
         const int64_t mc = std::min<int64_t>(32, c.m - c0);
         const int64_t mp = round_up(mc, 16);
-        hipError_t e = vec_split_t(Vf + c0, c.n2, mc, ldv, c.rp2, mp, c.colmax, PSHIFT, c.Vth,
-                                   c.Vtl, c.vscale, st);
+        const bool packed = mc <= 8;  // hi and lo parts share one 16-row operand
+        hipError_t e = vec_split_t(Vf + c0, c.n2, mc, ldv, c.rp2, mp, c.colmax, PSHIFT, packed,
+                                   c.Vth, c.Vtl, c.vscale, st);
         if (e != hipSuccess) return e;
-        SplitRhs V{c.Vth, c.Vtl, c.vscale, c.rp2, mp};
+        SplitRhs V{c.Vth, c.Vtl, c.vscale, c.rp2, mp, packed};
         e = matmat_f16pv(A, B, V, mc, deriv, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st);
         if (e != hipSuccess) return e;
       }
@@ -972,9 +973,10 @@ int64_t kpart_elems(krr_batch_plan* P, int g) {
 
 hipError_t batch_product(krr_batch_plan* P, hipStream_t st) {
   hipError_t e = batch_split_v(P->row_inst, P->meta, P->S.live, P->count, P->N, P->M, P->pf,
-                               P->red, P->nred, P->colmax, P->Vth, P->Vtl, P->vscale, st);
+                               P->red, P->nred, P->colmax, P->Vth, P->Vtl, P->vscale,
+                               P->M <= 8, st);
   if (e != hipSuccess) return e;
-  e = matmat_batch(P->items, P->nitems, P->inst, P->S.live, P->counter, P->grid, st);
+  e = matmat_batch(P->items, P->nitems, P->inst, P->S.live, P->counter, P->M <= 8, P->grid, st);
   if (e != hipSuccess) return e;
   return batch_finalize(P->meta, P->row_inst, P->S.live, P->N, P->M, P->pf, P->q, st);
 }

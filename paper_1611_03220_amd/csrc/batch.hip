@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256) void batch_colmax_kernel(const float* __restri
 
 // Vt[c][row] = split(q_pc pf[row][c]) for c < 16 (zero beyond M and on padding rows);
 // pf <- the value the split represents; vscale[p * 16 + c] = 1 / q_pc. 32-row tiles never
-// straddle problems (offsets are multiples of ROW_PAD).
+// straddle problems (offsets are multiples of ROW_PAD). Packed (M <= 8): row c < 8 of hi
+// holds the high part of column c, row c + 8 its low part, and lo is not written.
 __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict__ row_inst,
                                                           const BatchMeta* __restrict__ meta,
                                                           const int* __restrict__ live,
@@ -302,7 +303,8 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict_
                                                           const float* __restrict__ colmax,
                                                           _Float16* __restrict__ hi,
                                                           _Float16* __restrict__ lo,
-                                                          float* __restrict__ vscale) {
+                                                          float* __restrict__ vscale,
+                                                          int packed) {
   __shared__ float tile[32][17];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const int64_t r0 = (int64_t)blockIdx.x * 32;
@@ -316,13 +318,23 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict_
   }
   __syncthreads();
   for (int c = ty; c < 16; c += 8) {
-    const float qv = c < M ? split_scale(colmax[p * 16 + c]) : 1.0f;
+    const int cv = packed ? (c & 7) : c;  // source column
+    const bool low_row = packed && c >= 8;
+    const float qv = cv < M ? split_scale(colmax[p * 16 + cv]) : 1.0f;
     const int64_t row = r0 + tx;
-    const float v = tile[tx][c] * qv;
+    const float v = tile[tx][cv] * qv;
     _Float16 h, l;
     Elem<_Float16>::split(v, h, l);
-    hi[(int64_t)c * nrows + row] = h;
-    lo[(int64_t)c * nrows + row] = l;
+    if (packed) {
+      hi[(int64_t)c * nrows + row] = low_row ? l : h;
+    } else {
+      hi[(int64_t)c * nrows + row] = h;
+      lo[(int64_t)c * nrows + row] = l;
+    }
+    if (low_row) {
+      if (row == P.off) vscale[p * 16 + c] = 0.0f;
+      continue;
+    }
     if (c < M && row - P.off < P.n) pf[row * M + c] = ((float)h + (float)l) / qv;
     if (row == P.off) vscale[p * 16 + c] = c < M ? 1.0f / qv : 0.0f;
   }
@@ -330,13 +342,15 @@ __global__ __launch_bounds__(256) void batch_split_kernel(const int* __restrict_
 
 hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, const int* live, int count,
                          int64_t nrows, int M, float* pf, const RedItem* items, int nitems,
-                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, hipStream_t st) {
+                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, bool packed,
+                         hipStream_t st) {
+  if (packed && M > 8) return hipErrorInvalidValue;
   hipError_t e = fill_f32(colmax, (int64_t)count * 16, 0.0f, st);
   if (e != hipSuccess) return e;
   batch_colmax_kernel<<<nitems, 256, 0, st>>>(pf, M, items, live, colmax);
   KRR_LAUNCH_CHECK();
   batch_split_kernel<<<ceil_div(nrows, 32), 256, 0, st>>>(row_inst, meta, live, nrows, M, pf,
-                                                          colmax, hi, lo, vscale);
+                                                          colmax, hi, lo, vscale, packed ? 1 : 0);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -59,7 +59,8 @@ hipError_t batch_update_p(const int* row_inst, int64_t nrows, int M, const doubl
                           hipStream_t st);
 hipError_t batch_split_v(const int* row_inst, const BatchMeta* meta, const int* live, int count,
                          int64_t nrows, int M, float* pf, const RedItem* items, int nitems,
-                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, hipStream_t st);
+                         float* colmax, _Float16* hi, _Float16* lo, float* vscale, bool packed,
+                         hipStream_t st);
 hipError_t batch_precond(const BatchMeta* meta, int count, const PCItem* pitems, int npitems,
                          const ZItem* zitems, int nzitems, int64_t smax, const int* live,
                          const double* r, int M, double* part, double* T, double* z,

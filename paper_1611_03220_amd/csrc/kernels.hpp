@@ -46,8 +46,8 @@ hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_
                        int64_t Kp, double c2, const float* stats, int side, int pshift, T* hi,
                        T* lo, float* qinv2, hipStream_t st);
 hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
-                       float* colmax, int pshift, _Float16* hi, _Float16* lo, float* vscale,
-                       hipStream_t st);
+                       float* colmax, int pshift, bool packed, _Float16* hi, _Float16* lo,
+                       float* vscale, hipStream_t st);
 hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                            int64_t dp, double* X64, double* nu, hipStream_t st);
 hipError_t prep_points_f64x(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
@@ -70,6 +70,7 @@ struct SplitRhs {          // right-hand sides prepared for the MFMA accumulatio
   const _Float16* lo;
   const float* vscale;     // [mpad] 1 / (column scale * 2^pshift)
   int64_t rows_pad, mpad;
+  bool packed = false;     // m <= 8: rows 0..7 of hi hold the high parts, rows 8..15 the low
 };
 // Exponent shift of the MFMA-accumulate products. Folding a shift into the augmented
 // contraction makes the FP32 accumulator carry log2 k + shift, whose rounding is relative
@@ -107,7 +108,7 @@ struct BatchItem {          // a 128-row block of one problem against one column
   int64_t rb, split;
 };
 hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
-                        const int* live, int* counter, int grid, hipStream_t st);
+                        const int* live, int* counter, bool packed, int grid, hipStream_t st);
 
 // gemm.hip
 hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M, int64_t N,

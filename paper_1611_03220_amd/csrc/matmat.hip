@@ -242,7 +242,8 @@ template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const Mixed
 //   and four consecutive j -- the A-operand layout of the next product once two 16-column
 //   blocks are concatenated along k;
 //   P = exp2(S / q^2) = k, split into FP16 hi + lo (both rounded to nearest: the error is
-//   unbiased), multiplied on MFMA with the FP16 hi/lo split of V^T (three products), FP32
+//   unbiased), multiplied on MFMA with the FP16 hi/lo split of V^T (three products; two
+//   when m <= 8 and both halves of V^T share one operand), FP32
 //   accumulate, FP64 sums every MM2_FLUSH tiles.
 // The distance products of the second j-pair are issued before the first j-pair's
 // epilogue so one wave's MFMA and VALU work overlap. LDS tiles are XOR-swizzled (no
@@ -289,6 +290,18 @@ __device__ inline int vfrag(int c, int jp, int g) {
   return c * TN + (((4 * jp + g) ^ vswz<TN>(c)) << 3);
 }
 
+// Packed right-hand sides (m <= 8): the 16 columns of the P V product hold P V_hi in
+// columns 0..7 and P V_lo in columns 8..15 (P's hi and lo parts both multiply the one
+// operand: two MFMAs instead of three, and the lo x lo term is included); lane li < 8 adds
+// lane li + 8 of its 16-lane row to finish column li.
+template <int NCT>
+__device__ inline void pack_combine(double (&acc64)[2][NCT][4]) {
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc64[ib][0][r] += __shfl_down(acc64[ib][0][r], 8, 16);
+}
+
 template <int KS, int NCT>
 struct PVSmem {
   static constexpr int KP = KS * 32;
@@ -298,7 +311,7 @@ struct PVSmem {
   _Float16 Vl[2][NCT * 16 * MM_BN];
 };
 
-template <int KS, int NCT, bool UNIT, bool DERIV>
+template <int KS, int NCT, bool UNIT, bool DERIV, bool PACK>
 __device__ __forceinline__ void f16pv_body(
     PVSmem<KS, NCT>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -361,6 +374,7 @@ __device__ __forceinline__ void f16pv_body(
   }
   KRR_PV_INIT(0) KRR_PV_INIT(1) KRR_PV_INIT(2) KRR_PV_INIT(3)
 #undef KRR_PV_INIT
+  static_assert(!PACK || NCT == 1, "packed right-hand sides use one 16-row operand");
   const bool vload = tid < VCH;
   const int vch = vload ? tid : 0;
   const int vc = vch / (MM_BN / 8), vj8 = vch % (MM_BN / 8);
@@ -422,7 +436,7 @@ __device__ __forceinline__ void f16pv_body(
     for (int ct = 0; ct < NCT; ++ct) {
       const int u = vfrag(16 * ct + li, jp, lg);
       vh[ct] = *reinterpret_cast<const half8*>(&sm.Vh[buf][u]);
-      vl[ct] = *reinterpret_cast<const half8*>(&sm.Vl[buf][u]);
+      if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(&sm.Vl[buf][u]);
     }
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib) {
@@ -450,7 +464,8 @@ __device__ __forceinline__ void f16pv_body(
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) {
         acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl, vh[ct], acc[ib][ct], 0, 0, 0);
-        acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
+        if (!PACK)
+          acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
         acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vh[ct], acc[ib][ct], 0, 0, 0);
       }
     }
@@ -462,7 +477,7 @@ __device__ __forceinline__ void f16pv_body(
     gbl += MM_BN * KP;
     if (vload) {
       rvh = *reinterpret_cast<const u32x4*>(gvh);
-      rvl = *reinterpret_cast<const u32x4*>(gvl);
+      if (!PACK) rvl = *reinterpret_cast<const u32x4*>(gvl);
     }
     gvh += MM_BN;
     gvl += MM_BN;
@@ -470,8 +485,10 @@ __device__ __forceinline__ void f16pv_body(
     if (vload) {
       *reinterpret_cast<u32x2*>(&sm.Vh[0][svo0]) = u32x2{rvh.x, rvh.y};
       *reinterpret_cast<u32x2*>(&sm.Vh[0][svo1]) = u32x2{rvh.z, rvh.w};
-      *reinterpret_cast<u32x2*>(&sm.Vl[0][svo0]) = u32x2{rvl.x, rvl.y};
-      *reinterpret_cast<u32x2*>(&sm.Vl[0][svo1]) = u32x2{rvl.z, rvl.w};
+      if (!PACK) {
+        *reinterpret_cast<u32x2*>(&sm.Vl[0][svo0]) = u32x2{rvl.x, rvl.y};
+        *reinterpret_cast<u32x2*>(&sm.Vl[0][svo1]) = u32x2{rvl.z, rvl.w};
+      }
     }
   }
   __syncthreads();
@@ -485,7 +502,7 @@ __device__ __forceinline__ void f16pv_body(
     gbl += MM_BN * KP;
     if (vload) {
       rvh = *reinterpret_cast<const u32x4*>(gvh);
-      rvl = *reinterpret_cast<const u32x4*>(gvl);
+      if (!PACK) rvl = *reinterpret_cast<const u32x4*>(gvl);
     }
     gvh += MM_BN;
     gvl += MM_BN;
@@ -515,8 +532,10 @@ __device__ __forceinline__ void f16pv_body(
     if (vload) {
       *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo0]) = u32x2{rvh.x, rvh.y};
       *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo1]) = u32x2{rvh.z, rvh.w};
-      *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo0]) = u32x2{rvl.x, rvl.y};
-      *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo1]) = u32x2{rvl.z, rvl.w};
+      if (!PACK) {
+        *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo0]) = u32x2{rvl.x, rvl.y};
+        *reinterpret_cast<u32x2*>(&sm.Vl[buf ^ 1][svo1]) = u32x2{rvl.z, rvl.w};
+      }
     }
     }
     __syncthreads();
@@ -524,11 +543,12 @@ __device__ __forceinline__ void f16pv_body(
 #undef KRR_PV_LD
 #undef KRR_PV_ST
   // lane holds OUT[i0 + 16 ib + 4 lg + r][16 ct + li]
+  if (PACK) pack_combine<NCT>(acc64);
   double* pout = part + (int64_t)blockIdx.y * part_stride;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
-    if (c < m) {
+    if (c < m && (!PACK || li < 8)) {
       const double vs = (double)vscale[c];
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
@@ -541,7 +561,7 @@ __device__ __forceinline__ void f16pv_body(
   }
 }
 
-template <int KS, int NCT, bool DERIV>
+template <int KS, int NCT, bool DERIV, bool PACK>
 __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16pv_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -552,10 +572,10 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16
   __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT> sm;
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
-    f16pv_body<KS, NCT, true, DERIV>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+    f16pv_body<KS, NCT, true, DERIV, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
                                      qinv2, dscale, part, ldp, part_stride, tiles_per_split);
   else
-    f16pv_body<KS, NCT, false, DERIV>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+    f16pv_body<KS, NCT, false, DERIV, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
                                       qinv2, dscale, part, ldp, part_stride, tiles_per_split);
 }
 
@@ -571,7 +591,7 @@ template <int NCT, int NJB>
 constexpr int bigd_smem_halves() {
   return 2 * 2 * BD_BM * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB);
 }
-template <int NCT, bool UNIT, bool DERIV, int NJB>
+template <int NCT, bool UNIT, bool DERIV, int NJB, bool PACK>
 __device__ __forceinline__ void f16pv_bigd_body(
     _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -586,6 +606,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   constexpr int VPT = (VCH + 255) / 256;
   constexpr int FLUSH = TN >= 128 ? 1 : MM2_FLUSH;  // flush every 128 columns
   static_assert(BPT >= 1 && BPT <= 2 && VPT <= 2, "tile shape");
+  static_assert(!PACK || NCT == 1, "packed right-hand sides use one 16-row operand");
   // LDS layout (halves): A[2][2][128*32], B[2][2][TN*32], V[2][2][VR*TN]
   _Float16* sA = smem;
   _Float16* sB = sA + 2 * 2 * BD_BM * 32;
@@ -652,11 +673,13 @@ __device__ __forceinline__ void f16pv_bigd_body(
     if (kc == 0) {
       if (vld0) {
         R.rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
-        R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+        if (!PACK)
+          R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
       }
       if (vld1) {
         R.rv1h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
-        R.rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
+        if (!PACK)
+          R.rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
       }
     }
   };
@@ -678,14 +701,18 @@ __device__ __forceinline__ void f16pv_bigd_body(
       if (vld0) {
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{R.rv0h.x, R.rv0h.y};
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo01) = u32x2{R.rv0h.z, R.rv0h.w};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo00) = u32x2{R.rv0l.x, R.rv0l.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo01) = u32x2{R.rv0l.z, R.rv0l.w};
+        if (!PACK) {
+          *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo00) = u32x2{R.rv0l.x, R.rv0l.y};
+          *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo01) = u32x2{R.rv0l.z, R.rv0l.w};
+        }
       }
       if (vld1) {
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo10) = u32x2{R.rv1h.x, R.rv1h.y};
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo11) = u32x2{R.rv1h.z, R.rv1h.w};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo10) = u32x2{R.rv1l.x, R.rv1l.y};
-        *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo11) = u32x2{R.rv1l.z, R.rv1l.w};
+        if (!PACK) {
+          *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo10) = u32x2{R.rv1l.x, R.rv1l.y};
+          *reinterpret_cast<u32x2*>(V_at(vb, 1) + svo11) = u32x2{R.rv1l.z, R.rv1l.w};
+        }
       }
     }
   };
@@ -732,7 +759,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
         for (int ct = 0; ct < NCT; ++ct) {
           const int u = vfrag<TN>(16 * ct + li, jp, lg);
           vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
-          vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
+          if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
         }
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
@@ -758,7 +785,9 @@ __device__ __forceinline__ void f16pv_bigd_body(
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
             acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl, vh[ct], acc[ib][ct], 0, 0, 0);
-            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
+            if (!PACK)
+              acc[ib][ct] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
             acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vh[ct], acc[ib][ct], 0, 0, 0);
           }
         }
@@ -786,11 +815,12 @@ __device__ __forceinline__ void f16pv_bigd_body(
     step(q, R0, R1);
     if (q + 1 < nsteps) step(q + 1, R1, R0);
   }
+  if (PACK) pack_combine<NCT>(acc64);
   double* pout = part + split * part_stride;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
-    if (c < m) {
+    if (c < m && (!PACK || li < 8)) {
       const double vs = (double)vscale[c];
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
@@ -809,7 +839,7 @@ constexpr int BD_TN = 16 * BD_NJB;
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
-template <int NCT, bool DERIV>
+template <int NCT, bool DERIV, bool PACK>
 __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -832,11 +862,11 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
   }
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+    f16pv_bigd_body<NCT, true, DERIV, BD_NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                               n1, n2, m, KP, qinv2, dscale, part, ldp,
                                               part_stride, tiles_per_split, rb, sp);
   else
-    f16pv_bigd_body<NCT, false, DERIV, BD_NJB>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+    f16pv_bigd_body<NCT, false, DERIV, BD_NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                                n1, n2, m, KP, qinv2, dscale, part, ldp,
                                                part_stride, tiles_per_split, rb, sp);
 }
@@ -845,6 +875,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
                         const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
   if (A.Kp != B.Kp || V.mpad < round_up(m, 16) || V.mpad > 32) return hipErrorInvalidValue;
+  if (V.packed && (m > 8 || V.mpad != 16)) return hipErrorInvalidValue;
   if (part_stride < round_up(A.n, MM2_BM) * ldp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, MM_BN);
   const int tps = (int)ceil_div(ntiles, nsplit);
@@ -856,35 +887,40 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
     const int64_t nrb = ceil_div(A.n, BD_BM);
     const int grouped = nsplit == BD_GROUP && nrb >= 8 * BD_GROUP ? 1 : 0;
     if (grouped) grid = dim3((unsigned)(round_up(nrb, 8 * BD_GROUP) * BD_GROUP), 1);
-    if (nct == 1) {
-      if (deriv)
-        matmat_f16pv_bigd_kernel<1, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
-      else
-        matmat_f16pv_bigd_kernel<1, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
+#define KRR_BD(NCT_, D_, P_)                                                                  \
+  matmat_f16pv_bigd_kernel<NCT_, D_, P_><<<grid, 256, 0, st>>>(                               \
+      A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, \
+      part, ldp, part_stride, tps, grouped)
+    if (nct == 1 && V.packed) {
+      if (deriv) KRR_BD(1, true, true);
+      else KRR_BD(1, false, true);
+    } else if (nct == 1) {
+      if (deriv) KRR_BD(1, true, false);
+      else KRR_BD(1, false, false);
     } else {
-      if (deriv)
-        matmat_f16pv_bigd_kernel<2, true><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
-      else
-        matmat_f16pv_bigd_kernel<2, false><<<grid, 256, 0, st>>>(A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, part, ldp, part_stride, tps, grouped);
+      if (deriv) KRR_BD(2, true, false);
+      else KRR_BD(2, false, false);
     }
+#undef KRR_BD
     KRR_LAUNCH_CHECK();
     return hipSuccess;
   }
-#define KRR_PV(KS_, NCT_)                                                                     \
-  if (A.Kp == KS_ * 32 && nct == NCT_) {                                                      \
+#define KRR_PV(KS_, NCT_, PK_)                                                                \
+  if (A.Kp == KS_ * 32 && nct == NCT_ && V.packed == PK_) {                                   \
     if (deriv)                                                                                \
-      matmat_f16pv_kernel<KS_, NCT_, true><<<grid, 256, 0, st>>>(                             \
+      matmat_f16pv_kernel<KS_, NCT_, true, PK_><<<grid, 256, 0, st>>>(                        \
           A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
           dscale, part, ldp, part_stride, tps);                                               \
     else                                                                                      \
-      matmat_f16pv_kernel<KS_, NCT_, false><<<grid, 256, 0, st>>>(                            \
+      matmat_f16pv_kernel<KS_, NCT_, false, PK_><<<grid, 256, 0, st>>>(                       \
           A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
           dscale, part, ldp, part_stride, tps);                                               \
     KRR_LAUNCH_CHECK();                                                                       \
     return hipSuccess;                                                                        \
   }
-  KRR_PV(1, 1) KRR_PV(2, 1) KRR_PV(3, 1) KRR_PV(4, 1)
-  KRR_PV(1, 2) KRR_PV(2, 2) KRR_PV(3, 2) KRR_PV(4, 2)
+  KRR_PV(1, 1, true) KRR_PV(2, 1, true) KRR_PV(3, 1, true) KRR_PV(4, 1, true)
+  KRR_PV(1, 1, false) KRR_PV(2, 1, false) KRR_PV(3, 1, false) KRR_PV(4, 1, false)
+  KRR_PV(1, 2, false) KRR_PV(2, 2, false) KRR_PV(3, 2, false) KRR_PV(4, 2, false)
 #undef KRR_PV
   return hipErrorInvalidValue;
 }
@@ -898,7 +934,8 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
                                                               int nitems,
                                                               const BatchInst* __restrict__ inst,
                                                               const int* __restrict__ live,
-                                                              int* __restrict__ counter) {
+                                                              int* __restrict__ counter,
+                                                              int packed) {
   __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<1, 4>()];
   __shared__ int cur;
   for (;;) {
@@ -911,23 +948,27 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
     if (!live[wi.inst]) continue;  // uniform per block
     const BatchInst I = inst[wi.inst];
     const float qinv2 = *I.qinv2;
-    if (qinv2 == 1.0f)
-      f16pv_bigd_body<1, true, false, 4>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
-                                      I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
-                                      I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
-    else
-      f16pv_bigd_body<1, false, false, 4>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,
-                                       I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,
-                                       I.part_stride, wi.tiles_per_split, wi.rb, wi.split);
+#define KRR_BATCH_BODY(U, PK)                                                                    \
+  f16pv_bigd_body<1, U, false, 4, PK>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,   \
+                                      I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,     \
+                                      I.part_stride, wi.tiles_per_split, wi.rb, wi.split)
+    if (packed) {
+      if (qinv2 == 1.0f) KRR_BATCH_BODY(true, true);
+      else KRR_BATCH_BODY(false, true);
+    } else {
+      if (qinv2 == 1.0f) KRR_BATCH_BODY(true, false);
+      else KRR_BATCH_BODY(false, false);
+    }
+#undef KRR_BATCH_BODY
     __syncthreads();
   }
 }
 
 hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
-                        const int* live, int* counter, int grid, hipStream_t st) {
+                        const int* live, int* counter, bool packed, int grid, hipStream_t st) {
   hipError_t e = fill_i32(counter, 1, 0, st);
   if (e != hipSuccess) return e;
-  matmat_batch_kernel<<<grid, 256, 0, st>>>(items, nitems, inst, live, counter);
+  matmat_batch_kernel<<<grid, 256, 0, st>>>(items, nitems, inst, live, counter, packed ? 1 : 0);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -171,11 +171,14 @@ __global__ __launch_bounds__(256) void vec_colmax_kernel(const float* __restrict
 // qv_c = split_scale(colmax[c]); V[j, c] is overwritten by the value the split represents
 // exactly, (hi + lo) / qv_c, so later updates use the vector the products saw.
 // vscale[c] = 1 / (qv_c 2^pshift) undoes both the V scale and the 2^pshift of the kernel.
+// Packed (m <= 8, mpad = 16): row c < 8 of hi holds the high part of column c and row c + 8
+// its low part; lo is not written. One 16-row operand then carries both halves.
 __global__ __launch_bounds__(256) void vec_split_t_kernel(float* __restrict__ V, int64_t n,
                                                           int64_t m, int64_t ldv, int64_t rows_pad,
                                                           int64_t mpad,
                                                           const float* __restrict__ colmax,
-                                                          int pshift, _Float16* __restrict__ hi,
+                                                          int pshift, int packed,
+                                                          _Float16* __restrict__ hi,
                                                           _Float16* __restrict__ lo,
                                                           float* __restrict__ vscale) {
   __shared__ float tile[32][33];
@@ -191,29 +194,40 @@ __global__ __launch_bounds__(256) void vec_split_t_kernel(float* __restrict__ V,
   for (int yy = ty; yy < 32; yy += 8) {
     const int64_t c = c0 + yy, j = j0 + tx;
     if (c < mpad && j < rows_pad) {
-      const float qv = c < m ? split_scale(colmax[c]) : 1.0f;
-      const float v = tile[tx][yy] * qv;
+      const int64_t cv = packed ? (c & 7) : c;  // source column
+      const bool low_row = packed && c >= 8;
+      const float qv = cv < m ? split_scale(colmax[cv]) : 1.0f;
+      const float v = tile[tx][cv - c0] * qv;
       _Float16 h, l;
       Elem<_Float16>::split(v, h, l);
-      hi[c * rows_pad + j] = h;
-      lo[c * rows_pad + j] = l;
-      if (j < n && c < m) V[j * ldv + c] = ((float)h + (float)l) / qv;
-      if (j == 0) vscale[c] = c < m ? 1.0f / (qv * ldexpf(1.0f, pshift)) : 0.0f;
+      if (packed) {
+        hi[c * rows_pad + j] = low_row ? l : h;
+      } else {
+        hi[c * rows_pad + j] = h;
+        lo[c * rows_pad + j] = l;
+      }
+      if (!low_row) {
+        if (j < n && c < m) V[j * ldv + c] = ((float)h + (float)l) / qv;
+        if (j == 0) vscale[c] = c < m ? 1.0f / (qv * ldexpf(1.0f, pshift)) : 0.0f;
+      } else if (j == 0) {
+        vscale[c] = 0.0f;
+      }
     }
   }
 }
 
 hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
-                       float* colmax, int pshift, _Float16* hi, _Float16* lo, float* vscale,
-                       hipStream_t st) {
+                       float* colmax, int pshift, bool packed, _Float16* hi, _Float16* lo,
+                       float* vscale, hipStream_t st) {
+  if (packed && (m > 8 || mpad != 16)) return hipErrorInvalidValue;
   hipError_t e = fill_f32(colmax, m, 0.0f, st);
   if (e != hipSuccess) return e;
   const int64_t blocks = std::min<int64_t>(512, std::max<int64_t>(1, ceil_div(n, 256)));
   vec_colmax_kernel<<<blocks, 256, 0, st>>>(V, n, m, ldv, colmax);
   KRR_LAUNCH_CHECK();
   dim3 grid(ceil_div(rows_pad, 32), ceil_div(mpad, 32));
-  vec_split_t_kernel<<<grid, 256, 0, st>>>(V, n, m, ldv, rows_pad, mpad, colmax, pshift, hi, lo,
-                                           vscale);
+  vec_split_t_kernel<<<grid, 256, 0, st>>>(V, n, m, ldv, rows_pad, mpad, colmax, pshift,
+                                           packed ? 1 : 0, hi, lo, vscale);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

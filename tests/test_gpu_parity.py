@@ -59,7 +59,8 @@ MATMAT_CASES = [
     (300, 517, 54, 7, False),
     (64, 64, 8, 1, True),
     (1, 130, 3, 2, False),
-    (257, 257, 30, 9, True),     # two column passes (8 + 1)
+    (257, 257, 30, 9, True),     # nine columns: hi and lo parts in separate operands
+    (190, 333, 20, 8, False),    # eight columns: hi and lo parts packed in one operand
     (100, 2000, 126, 3, False),  # Kp = 128
     (70, 90, 254, 1, False),     # largest d of the register-resident mixed kernel
     (129, 65, 1, 5, False),
