@@ -290,6 +290,10 @@ __device__ inline int vfrag(int c, int jp, int g) {
   return c * TN + (((4 * jp + g) ^ vswz<TN>(c)) << 3);
 }
 
+// s_waitcnt vmcnt(0): wait for all outstanding vector memory loads (gfx9 encoding, expcnt
+// and lgkmcnt left at their maxima).
+__device__ inline void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Packed right-hand sides (m <= 8): the 16 columns of the P V product hold P V_hi in
 // columns 0..7 and P V_lo in columns 8..15 (P's hi and lo parts both multiply the one
 // operand: two MFMAs instead of three, and the lo x lo term is included); lane li < 8 adds
@@ -491,6 +495,11 @@ __device__ __forceinline__ void f16pv_body(
       }
     }
   }
+  // Every global load issued so far (the row operand above all) completes here, on every
+  // path: otherwise the loop inherits them as pending, and the compiler's wait counts
+  // inside the loop become conservative enough to stall the distance MFMAs on the next
+  // tile's prefetch.
+  wait_vmem_all();
   __syncthreads();
   int since_flush = 0;
   for (int64_t t = t_begin; t < t_end; ++t) {
@@ -1003,7 +1012,7 @@ __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
 }
 
 template <int KD, int NCT>
-__global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
+__global__ __launch_bounds__(256, 3) void matmat_f64mfma_kernel(
     const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
     const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
     int64_t n2, int64_t m, int c0, double c, int deriv, double dscale, double* __restrict__ part,
@@ -1032,25 +1041,51 @@ __global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
 
-  auto load_tile = [&](int64_t t, int buf) __attribute__((always_inline)) {
+  // The next column tile is loaded into registers while the current one is used, then
+  // stored to the other LDS buffer (global load latency overlaps the MFMA work).
+  constexpr int XPT = (F64M_TJ * DP + 255) / 256;  // point coordinates per thread
+  constexpr int VPT = (F64M_TJ * VC + 255) / 256;  // right-hand-side values per thread
+  double rx[XPT], rv[VPT], rn = 0.0;
+  auto gload = [&](int64_t t) __attribute__((always_inline)) {
     const int64_t j0 = t * F64M_TJ;
-    for (int e = tid; e < F64M_TJ * DP; e += 256) {
-      const int r = e / DP, k = e % DP;
-      sX[buf][r * LX + k] = Xb[(j0 + r) * DP + k];
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < F64M_TJ * DP) rx[u] = Xb[j0 * DP + e];  // rows padded past n2: in bounds
     }
-    for (int e = tid; e < F64M_TJ * VC; e += 256) {
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
       const int r = e / VC, cc = e % VC;
       const int64_t j = j0 + r;
-      sV[buf][r * LV + cc] = (j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
+      rv[u] = (e < F64M_TJ * VC && j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
     }
-    if (tid < F64M_TJ) sN[buf][tid] = nub[j0 + tid];
+    if (tid < F64M_TJ) rn = nub[j0 + tid];
+  };
+  auto lstore = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int u = 0; u < XPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < F64M_TJ * DP) sX[buf][(e / DP) * LX + e % DP] = rx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < F64M_TJ * VC) sV[buf][(e / VC) * LV + e % VC] = rv[u];
+    }
+    if (tid < F64M_TJ) sN[buf][tid] = rn;
   };
 
-  if (t_begin < t_end) load_tile(t_begin, 0);
+  if (t_begin < t_end) {
+    gload(t_begin);
+    lstore(0);
+  }
+  wait_vmem_all();  // the row coordinates above included, on every path
   __syncthreads();
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int buf = (int)((t - t_begin) & 1);
-    if (t + 1 < t_end) load_tile(t + 1, buf ^ 1);
+    const bool more = t + 1 < t_end;
+    if (more) gload(t + 1);
 #pragma unroll
     for (int jb = 0; jb < F64M_TJ / 16; ++jb) {
       // two interleaved accumulation chains over the k steps
@@ -1076,6 +1111,7 @@ __global__ __launch_bounds__(256) void matmat_f64mfma_kernel(
                                                          0, 0, 0);
       }
     }
+    if (more) lstore(buf ^ 1);
     __syncthreads();
   }
   double* pout = part + (int64_t)blockIdx.y * part_stride;
