@@ -632,7 +632,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   const int64_t t_begin = split * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = KP / 32;
-  const int64_t nsteps = (t_end - t_begin) * KC;
+  const int nsteps = (int)((t_end - t_begin) * KC);
 
   f32x4 acc[2][NCT];
   double acc64[2][NCT][4];
@@ -653,21 +653,39 @@ __device__ __forceinline__ void f16pv_bigd_body(
   const int brow1 = arow0 + 64;
   const int sb1 = brow1 * 32 + ((acol ^ ((brow1 >> 1) & 3)) * 8);
   // V^T pieces: piece e = tid + 256 u covers row e / (TN / 8), columns 8 (e % (TN / 8)) ..
+  // Threads past the last piece load a duplicate and do not store it.
   const bool vld0 = tid < VCH, vld1 = VPT > 1 && tid + 256 < VCH;
-  const int ve0 = vld0 ? tid : 0, ve1 = vld1 ? tid + 256 : 0;
+  const int ve0 = tid % VCH, ve1 = (tid + 256) % VCH;
   const int vc0 = ve0 / (TN / 8), vj0 = ve0 % (TN / 8);
   const int vc1 = ve1 / (TN / 8), vj1 = ve1 % (TN / 8);
   const int svo00 = vpos<TN>(vc0, 8 * vj0), svo01 = vpos<TN>(vc0, 8 * vj0 + 4);
   const int svo10 = vpos<TN>(vc1, 8 * vj1), svo11 = vpos<TN>(vc1, 8 * vj1 + 4);
   // two register sets: the chunk two steps ahead is loaded while the next one waits to be
-  // stored, so global loads have about one and a half steps to arrive
+  // stored, so global loads have about one and a half steps to arrive. With UNIFORM every
+  // step issues the chunk loads (past the last step the last chunk again; the V^T tile
+  // only with the first chunk of a tile): the compiler's wait counts then let the newer
+  // set stay in flight while the older one is stored. Measured: faster for two column
+  // tiles of V (NCT = 2), slower for one, which keeps the loads of the final steps
+  // conditional.
+  constexpr bool UNIFORM = NCT > 1;
   struct Regs {
     u32x4 ra0h, ra0l, ra1h, ra1l, rb0h, rb0l, rb1h, rb1l, rv0h, rv0l, rv1h, rv1l;
   };
   Regs R0 = {}, R1 = {};
-  auto gload = [&](int64_t q, Regs& R) __attribute__((always_inline)) {
-    const int64_t t = t_begin + q / KC;
-    const int kc = (int)(q % KC);
+  // position of a step: column tile (relative to t_begin) and k chunk, advanced one step at
+  // a time (no division in the loop)
+  struct Pos {
+    int t, kc;
+  };
+  auto advance = [&](Pos& p) __attribute__((always_inline)) {
+    if (++p.kc == KC) {
+      p.kc = 0;
+      ++p.t;
+    }
+  };
+  auto gload = [&](const Pos& p, Regs& R) __attribute__((always_inline)) {
+    const int64_t t = t_begin + p.t;
+    const int kc = p.kc;
     const int64_t ko = (int64_t)kc * 32 + acol * 8;
     R.ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
     R.ra0l = *reinterpret_cast<const u32x4*>(Alo + (blk_i0 + arow0) * KP + ko);
@@ -680,21 +698,19 @@ __device__ __forceinline__ void f16pv_bigd_body(
       R.rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
     }
     if (kc == 0) {
-      if (vld0) {
-        R.rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
-        if (!PACK)
-          R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
-      }
-      if (vld1) {
+      R.rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+      if (!PACK)
+        R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
+      if (VPT > 1) {
         R.rv1h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
         if (!PACK)
           R.rv1l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc1 * ldvt + t * TN + vj1 * 8);
       }
     }
   };
-  auto lstore = [&](int64_t q, const Regs& R) __attribute__((always_inline)) {
-    const int buf = (int)(q & 1);
-    const int kc = (int)(q % KC);
+  auto lstore = [&](int q, const Pos& p, const Regs& R) __attribute__((always_inline)) {
+    const int buf = q & 1;
+    const int kc = p.kc;
     *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa0) = R.ra0h;
     *reinterpret_cast<u32x4*>(A_at(buf, 1) + sa0) = R.ra0l;
     *reinterpret_cast<u32x4*>(A_at(buf, 0) + sa1) = R.ra1h;
@@ -706,7 +722,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
       *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb1) = R.rb1l;
     }
     if (kc == 0) {
-      const int vb = (int)((q / KC) & 1);
+      const int vb = p.t & 1;
       if (vld0) {
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{R.rv0h.x, R.rv0h.y};
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo01) = u32x2{R.rv0h.z, R.rv0h.w};
@@ -726,16 +742,24 @@ __device__ __forceinline__ void f16pv_bigd_body(
     }
   };
 
+  // pc, pn, pg: positions of steps q, q + 1 and min(q + 2, nsteps - 1)
+  Pos pc{0, 0}, pn{0, 0}, pg{0, 0};
   if (nsteps > 0) {
-    gload(0, R0);
-    lstore(0, R0);
+    gload(pc, R0);
+    lstore(0, pc, R0);
+    if (nsteps > 1) advance(pn);
+    gload(pn, R0);
+    pg = pn;
+    if (nsteps > 2) advance(pg);
   }
-  if (nsteps > 1) gload(1, R0);
+  // complete the prologue's loads once here, so the loop does not inherit them as pending
+  // (that makes the compiler wait for every outstanding load at the top of each step)
+  wait_vmem_all();
   __syncthreads();
   int since_flush = 0;
-  auto compute = [&](int64_t q) __attribute__((always_inline)) {
-    const int buf = (int)(q & 1);
-    const int kc = (int)(q % KC);
+  auto compute = [&](int q, const Pos& p) __attribute__((always_inline)) {
+    const int buf = q & 1;
+    const int kc = p.kc;
     // fragments of this chunk: rows of the wave (B operand) and the tile's columns (A operand)
     half8 ah[2], al[2];
 #pragma unroll
@@ -760,7 +784,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
       }
     }
     if (kc == KC - 1) {
-      const int vb = (int)((q / KC) & 1);
+      const int vb = p.t & 1;
 #pragma unroll
       for (int jp = 0; jp < NJB / 2; ++jp) {
         half8 vh[NCT], vl[NCT];
@@ -814,13 +838,16 @@ __device__ __forceinline__ void f16pv_bigd_body(
       }
     }
   };
-  auto step = [&](int64_t q, const Regs& hold, Regs& spare) __attribute__((always_inline)) {
-    if (q + 2 < nsteps) gload(q + 2, spare);
-    compute(q);
-    if (q + 1 < nsteps) lstore(q + 1, hold);
+  auto step = [&](int q, const Regs& hold, Regs& spare) __attribute__((always_inline)) {
+    if (UNIFORM || q + 2 < nsteps) gload(pg, spare);
+    compute(q, pc);
+    if (q + 1 < nsteps) lstore(q + 1, pn, hold);
     __syncthreads();
+    advance(pc);
+    advance(pn);
+    if (q + 3 < nsteps) advance(pg);
   };
-  for (int64_t q = 0; q < nsteps; q += 2) {
+  for (int q = 0; q < nsteps; q += 2) {
     step(q, R0, R1);
     if (q + 1 < nsteps) step(q + 1, R1, R0);
   }
