@@ -667,7 +667,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   // set stay in flight while the older one is stored. Measured: faster for two column
   // tiles of V (NCT = 2), slower for one, which keeps the loads of the final steps
   // conditional.
-  constexpr bool UNIFORM = NCT > 1;
+  constexpr bool UNIFORM = NCT > 1 || NJB < 8;
   struct Regs {
     u32x4 ra0h, ra0l, ra1h, ra1l, rb0h, rb0l, rb1h, rb1l, rv0h, rv0l, rv1h, rv1l;
   };
