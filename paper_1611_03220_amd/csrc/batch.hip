@@ -363,11 +363,12 @@ __global__ __launch_bounds__(256) void batch_t_partial_kernel(const PCItem* __re
                                                               const int* __restrict__ live,
                                                               const double* __restrict__ r,
                                                               double* __restrict__ part) {
+  __shared__ double sr[WB_RB * MC];
   const PCItem it = items[blockIdx.x];
-  if (!live[it.inst]) return;
+  if (!live[it.inst]) return;  // uniform per block
   const BatchMeta P = meta[it.inst];
   woodbury_tpart<MC, 1>(P.Ut, P.ldu, P.s, r + P.off * MC, MC, it.i0, it.i1, it.k0 + threadIdx.x,
-                        part + it.part_off + (int64_t)it.chunk * P.s * 16, 16);
+                        part + it.part_off + (int64_t)it.chunk * P.s * 16, 16, sr);
 }
 
 // T_p[k][c] = sum over chunks (c < M); blockIdx.y = problem

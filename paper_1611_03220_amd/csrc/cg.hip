@@ -340,7 +340,6 @@ hipError_t add2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n
 }
 
 // ---------------------------------------------------------- preconditioner apply
-// Pass 1: part[chunk][k][c] = sum_{i in chunk} Ut[i][k] r[i][c]. Block (kb, chunk): thread
 // Pass 1 (T partials over row chunks) and pass 2 (z) of the Woodbury apply; the device
 // bodies are shared with the batched solve. m columns run in passes of at most PC_M.
 constexpr int PC_M = 16;
@@ -349,11 +348,12 @@ __global__ __launch_bounds__(256) void precond_t_partial_kernel(
     const float* __restrict__ Ut, int64_t ldu, const double* __restrict__ r, int64_t n, int64_t s,
     int64_t m, int c0, int64_t rows_per_chunk, double* __restrict__ part) {
   constexpr int KPT = woodbury_kpt(MC);
+  __shared__ double sr[WB_RB * MC];
   const int64_t k0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * KPT;
   const int64_t i0 = (int64_t)blockIdx.y * rows_per_chunk;
   const int64_t i1 = i0 + rows_per_chunk < n ? i0 + rows_per_chunk : n;
   woodbury_tpart<MC, KPT>(Ut, ldu, s, r + c0, m, i0, i1, k0,
-                          part + (int64_t)blockIdx.y * s * m + c0, m);
+                          part + (int64_t)blockIdx.y * s * m + c0, m, sr);
 }
 
 // T[k][c] = sum_chunk part[chunk][k][c]

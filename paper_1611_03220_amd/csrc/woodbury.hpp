@@ -3,21 +3,26 @@
 // Two streaming passes over Ut, each reading it once from HBM; FP64 accumulation.
 // Device bodies shared by the single-problem and the batched launches.
 #pragma once
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace krr {
 
 // Pass 1: T partial over rows [i0, i1) for feature columns k0 .. k0 + KPT - 1 (consecutive
 // threads take consecutive column groups, so every row read is one contiguous segment; KPT
-// columns per thread and eight rows per step keep enough loads in flight to stream Ut).
-// The rows of r are the same for every lane, so they come through scalar loads.
+// columns per thread and sixteen rows per step keep enough loads in flight to stream Ut).
+// All threads of the block call it with the same rows: the rows of r are staged in LDS
+// (sr: at least WB_RB * MC doubles) in rounds of WB_RB and read back as broadcasts.
 // out[k * ldo + c] = sum_{i in [i0, i1)} Ut[i][k] r[i][c], c < MC.
+constexpr int WB_RB = 128;  // rows of r staged per round
 template <int MC, int KPT>
 __device__ __forceinline__ void woodbury_tpart(const float* __restrict__ Ut, int64_t ldu,
                                                int64_t s, const double* __restrict__ r,
                                                int64_t ldr, int64_t i0, int64_t i1, int64_t k0,
-                                               double* __restrict__ out, int64_t ldo) {
-  constexpr int RU = 8;  // rows per step
+                                               double* __restrict__ out, int64_t ldo,
+                                               double* __restrict__ sr) {
+  constexpr int RU = 16;  // rows per step
   double acc[KPT][MC];
 #pragma unroll
   for (int q = 0; q < KPT; ++q)
@@ -30,43 +35,55 @@ __device__ __forceinline__ void woodbury_tpart(const float* __restrict__ Ut, int
   const bool vec = KPT > 1 && k0 + KPT <= s && (ldu % KPT) == 0 &&
                    (reinterpret_cast<uintptr_t>(Ut) % (4 * KPT)) == 0;
   const float* up = Ut + (kin[0] ? k0 : 0);
-  auto load = [&](int64_t i, float (&u)[KPT]) __attribute__((always_inline)) {
-    if (KPT == 2 && vec) {
-      const float2 t = *reinterpret_cast<const float2*>(up + i * ldu);
-      u[0] = t.x;
-      u[KPT - 1] = t.y;
-    } else {
+  // rows [ib, ib + nr) of one round; VEC selects float2 loads (uniform per thread)
+  auto rows = [&](auto vec_tag, int64_t ib, int nr) __attribute__((always_inline)) {
+    constexpr bool VEC = decltype(vec_tag)::value;
+    auto load = [&](int64_t i, float (&u)[KPT]) __attribute__((always_inline)) {
+      if (VEC) {
+        const float2 t = *reinterpret_cast<const float2*>(up + i * ldu);
+        u[0] = t.x;
+        u[KPT - 1] = t.y;
+      } else {
 #pragma unroll
-      for (int q = 0; q < KPT; ++q) {
-        const float t = Ut[kin[q] ? i * ldu + k0 + q : 0];
-        u[q] = kin[q] ? t : 0.0f;
+        for (int q = 0; q < KPT; ++q) {
+          const float t = Ut[kin[q] ? i * ldu + k0 + q : 0];
+          u[q] = kin[q] ? t : 0.0f;
+        }
       }
+    };
+    int j0 = 0;
+    for (; j0 + RU <= nr; j0 += RU) {
+      float u[RU][KPT];
+#pragma unroll
+      for (int j = 0; j < RU; ++j) load(ib + j0 + j, u[j]);
+#pragma unroll
+      for (int j = 0; j < RU; ++j) {
+        const double* rr = sr + (j0 + j) * MC;
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+          const double rc = rr[c];
+#pragma unroll
+          for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[j][q], rc, acc[q][c]);
+        }
+      }
+    }
+    for (; j0 < nr; ++j0) {
+      float u[KPT];
+      load(ib + j0, u);
+      const double* rr = sr + j0 * MC;
+#pragma unroll
+      for (int c = 0; c < MC; ++c)
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[q], rr[c], acc[q][c]);
     }
   };
-  int64_t i = i0;
-  for (; i + RU <= i1; i += RU) {
-    float u[RU][KPT];
-#pragma unroll
-    for (int j = 0; j < RU; ++j) load(i + j, u[j]);
-#pragma unroll
-    for (int j = 0; j < RU; ++j) {
-      const double* rr = r + (i + j) * ldr;
-#pragma unroll
-      for (int c = 0; c < MC; ++c) {
-        const double rc = rr[c];
-#pragma unroll
-        for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[j][q], rc, acc[q][c]);
-      }
-    }
-  }
-  for (; i < i1; ++i) {
-    float u[KPT];
-    load(i, u);
-    const double* rr = r + i * ldr;
-#pragma unroll
-    for (int c = 0; c < MC; ++c)
-#pragma unroll
-      for (int q = 0; q < KPT; ++q) acc[q][c] = fma((double)u[q], rr[c], acc[q][c]);
+  for (int64_t ib = i0; ib < i1; ib += WB_RB) {
+    const int nr = (int)(i1 - ib < WB_RB ? i1 - ib : WB_RB);
+    __syncthreads();  // the previous round's reads of sr are done
+    for (int e = threadIdx.x; e < nr * MC; e += blockDim.x) sr[e] = r[(ib + e / MC) * ldr + e % MC];
+    __syncthreads();
+    if (KPT > 1 && vec) rows(std::true_type{}, ib, nr);
+    else rows(std::false_type{}, ib, nr);
   }
 #pragma unroll
   for (int q = 0; q < KPT; ++q)
