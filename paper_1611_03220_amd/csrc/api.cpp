@@ -85,8 +85,10 @@ struct MatmatCtx {
   int nsplit = 1;
   float* stats = nullptr;   // [0] max|x|, [1] max nu, [2] 1/q^2
   void *Ahi = nullptr, *Alo = nullptr, *Bhi = nullptr, *Blo = nullptr;
-  double *XA = nullptr, *nuA = nullptr, *XB = nullptr, *nuB = nullptr;
+  double *nuA = nullptr, *nuB = nullptr;
   float *XAf = nullptr, *XBf = nullptr;  // FP32 coordinates of the large-d FP64 product
+  int8_t *SA = nullptr, *SB = nullptr;    // int8 slices of the FP64 product (d <= 128)
+  double *scA = nullptr, *scB = nullptr;  // their row scales
   double* part = nullptr;   // nsplit x rp1 x m
   int64_t part_stride = 0;
   double c2 = 0;            // log2(e) / (2 sigma^2)
@@ -104,14 +106,18 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
   if (prec == KRR_PREC_FP64) {
     c.dp = dp_for(d);
     if (c.dp <= 128) {
-      c.XA = b.take<double>(c.rp1 * c.dp);
-      if (!square) c.XB = b.take<double>(c.rp2 * c.dp);
+      c.SA = b.take<int8_t>(c.rp1 * OZ_SLICES * oz_kp(d));
+      c.scA = b.take<double>(c.rp1);
+      if (!square) {
+        c.SB = b.take<int8_t>(c.rp2 * OZ_SLICES * oz_kp(d));
+        c.scB = b.take<double>(c.rp2);
+      }
     } else {
       c.XAf = b.take<float>(c.rp1 * c.dp);
       if (!square) c.XBf = b.take<float>(c.rp2 * c.dp);
     }
     c.nuA = b.take<double>(c.rp1);
-    if (square) { c.XB = c.XA; c.XBf = c.XAf; c.nuB = c.nuA; }
+    if (square) { c.XBf = c.XAf; c.SB = c.SA; c.scB = c.scA; c.nuB = c.nuA; }
     else c.nuB = b.take<double>(c.rp2);
   } else {
     c.pv = use_pv(prec, d);
@@ -146,8 +152,8 @@ hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const flo
       if (X2 && (e = prep_points_f64x(X2, c.n2, c.d, ldx2, c.rp2, c.dp, c.XBf, c.nuB, st))) return e;
       return hipSuccess;
     }
-    if ((e = prep_points_f64(X1, c.n1, c.d, ldx1, c.rp1, c.dp, c.XA, c.nuA, st))) return e;
-    if (X2 && (e = prep_points_f64(X2, c.n2, c.d, ldx2, c.rp2, c.dp, c.XB, c.nuB, st))) return e;
+    if ((e = prep_points_i8(X1, c.n1, c.d, ldx1, c.rp1, c.SA, c.scA, c.nuA, st))) return e;
+    if (X2 && (e = prep_points_i8(X2, c.n2, c.d, ldx2, c.rp2, c.SB, c.scB, c.nuB, st))) return e;
     return hipSuccess;
   }
   if ((e = fill_f32(c.stats, 4, 0.0f, st))) return e;
@@ -177,7 +183,8 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
                       hipStream_t st) {
   const double sig3 = c.sigma * c.sigma * c.sigma;
   if (c.prec == KRR_PREC_FP64) {
-    F64Points A{c.XA, c.nuA, c.n1, c.dp, c.XAf}, B{c.XB, c.nuB, c.n2, c.dp, c.XBf};
+    F64Points A{c.nuA, c.n1, c.dp, c.XAf, c.SA, c.scA, c.d};
+    F64Points B{c.nuB, c.n2, c.dp, c.XBf, c.SB, c.scB, c.d};
     return matmat_f64(A, B, V64, ldv, c.m, deriv, 1.0 / (2.0 * c.sigma * c.sigma), 1.0 / sig3,
                       c.part, c.m, c.part_stride, c.nsplit, st);
   }

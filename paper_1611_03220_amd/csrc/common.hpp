@@ -78,6 +78,20 @@ template <typename T> __device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
+template <typename T> __device__ inline T wave_max(T v) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+
+// Exact int8 slices of the points for the FP64 product on int8 MFMA: OZ_SLICES balanced
+// base-256 digits of a 46-bit fixed-point form of each row, OZ_KC(d) chunks of 64 bytes
+// per slice.
+constexpr int OZ_SLICES = 6;
+constexpr int OZ_BITS = 46;
+__host__ __device__ inline int64_t oz_kp(int64_t d) { return round_up(d, 64); }
 
 }  // namespace krr
 

@@ -14,11 +14,13 @@ template <typename T> struct MixedPoints {
 };
 
 struct F64Points {
-  const double* X;   // rows_pad x dp (dp <= 128), or nullptr when Xf is used
   const double* nu;  // rows_pad, FP64 squared norms
   int64_t n;
   int64_t dp;        // multiple of 8 (<= 128) or of 32
   const float* Xf = nullptr;  // rows_pad x dp FP32 coordinates (dp > 128)
+  const int8_t* S = nullptr;  // int8 slices (d <= 128): rows_pad x OZ_SLICES x oz_kp(d)
+  const double* scale = nullptr;  // rows_pad: 2^(e_i - 46) of the slices
+  int64_t d = 0;
 };
 
 struct SplitOperand {
@@ -48,8 +50,8 @@ hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_
 hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
                        float* colmax, int pshift, bool packed, _Float16* hi, _Float16* lo,
                        float* vscale, hipStream_t st);
-hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                           int64_t dp, double* X64, double* nu, hipStream_t st);
+hipError_t prep_points_i8(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                          int8_t* S, double* scale, double* nu, hipStream_t st);
 hipError_t prep_points_f64x(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                             int64_t dp, float* X32, double* nu, hipStream_t st);
 hipError_t vec_to_f32(const double* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad,

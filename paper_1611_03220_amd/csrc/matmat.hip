@@ -1010,24 +1010,20 @@ hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* ins
 }
 
 // ------------------------------------------------------------------- FP64 path
-// FP64 kernel product on FP64 MFMA (16x16x4). Lane layout (gfx950): A operand lane l holds
-// A[l%16][l/16], B operand B[l/16][l%16], result register r holds C[l/16 + 4r][l%16].
-// Each wave owns 16 rows i whose coordinates stay in registers as the B operand; the
-// column points x_j stream through LDS in 32-point tiles. Per 16-column block:
-//   G^T[j][i] = <x_j, x_i> (KD MFMAs), D = nu_i + nu_j - 2 G, k = exp(-D c) (FP64, VALU),
-//   OUT[i][:] += sum_j k V[j][:] on MFMA with k as the A operand (contraction over 4 j per
-//   MFMA: register r of G^T supplies j = l/16 + 4r), FP64 accumulation throughout.
-constexpr int F64M_TJ = 32;  // columns per LDS tile
+// FP64 MFMA (16x16x4) lane layout (gfx950): A operand lane l holds A[l%16][l/16], B operand
+// B[l/16][l%16], result register r holds C[l/16 + 4r][l%16].
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 // e^{-x} for x >= 0 in FP64 with a 64-entry table T[j] = 2^{-j/64}: with y = x log2(e)
-// (clamped at 1100, far below the smallest double), k = rint(64 y) and r = y - k/64 in
+// (clamped at 1100, far below the smallest double; a NaN passes through to the result),
+// k = rint(64 y) and r = y - k/64 in
 // [-1/128, 1/128], e^{-x} = 2^{-(k >> 6)} T[k & 63] e^{-r ln 2}; the last factor is a
 // degree-6 Taylor polynomial (truncation below 1e-19 on that interval).
 __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
-  const double y = fmin(x * 1.4426950408889634, 1100.0);
+  const double y0 = x * 1.4426950408889634;
+  const double y = y0 > 1100.0 ? 1100.0 : y0;
   const double kf = rint(y * 64.0);
-  const int k = (int)kf;
+  const int k = __double2int_rn(kf);  // hardware conversion: a NaN gives 0 (any k is in range)
   const double u = fma(kf, 0.015625, -y) * 0.6931471805599453;  // = -r ln 2
   double q = fma(u, 1.0 / 720.0, 1.0 / 120.0);
   q = fma(u, q, 1.0 / 24.0);
@@ -1036,138 +1032,6 @@ __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
   q = fma(u, q, 1.0);
   q = fma(u, q, 1.0);
   return ldexp(T[k & 63] * q, -(k >> 6));
-}
-
-template <int KD, int NCT>
-__global__ __launch_bounds__(256, 3) void matmat_f64mfma_kernel(
-    const double* __restrict__ Xa, const double* __restrict__ nua, const double* __restrict__ Xb,
-    const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
-    int64_t n2, int64_t m, int c0, double c, int deriv, double dscale, double* __restrict__ part,
-    int64_t ldp, int64_t part_stride, int tiles_per_split) {
-  constexpr int DP = 4 * KD;
-  constexpr int LX = DP + 1;           // padded row of the column tile (doubles)
-  constexpr int VC = 16 * NCT;
-  constexpr int LV = VC + 1;
-  __shared__ double sX[2][F64M_TJ * LX];
-  __shared__ double sV[2][F64M_TJ * LV];
-  __shared__ double sN[2][F64M_TJ];
-  __shared__ double sE[64];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int li = lane & 15, lg = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * 64 + 16 * w;
-  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);  // read after the first barrier
-  const int64_t ntiles = ceil_div(n2, F64M_TJ);
-  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
-  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
-
-  double xi[KD];
-#pragma unroll
-  for (int sk = 0; sk < KD; ++sk) xi[sk] = Xa[(i0 + li) * DP + 4 * sk + lg];
-  const double nui = nua[i0 + li];
-  d4v acc[NCT];
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
-
-  // The next column tile is loaded into registers while the current one is used, then
-  // stored to the other LDS buffer (global load latency overlaps the MFMA work).
-  constexpr int XPT = (F64M_TJ * DP + 255) / 256;  // point coordinates per thread
-  constexpr int VPT = (F64M_TJ * VC + 255) / 256;  // right-hand-side values per thread
-  double rx[XPT], rv[VPT], rn = 0.0;
-  auto gload = [&](int64_t t) __attribute__((always_inline)) {
-    const int64_t j0 = t * F64M_TJ;
-#pragma unroll
-    for (int u = 0; u < XPT; ++u) {
-      const int e = tid + 256 * u;
-      if (e < F64M_TJ * DP) rx[u] = Xb[j0 * DP + e];  // rows padded past n2: in bounds
-    }
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int e = tid + 256 * u;
-      const int r = e / VC, cc = e % VC;
-      const int64_t j = j0 + r;
-      rv[u] = (e < F64M_TJ * VC && j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
-    }
-    if (tid < F64M_TJ) rn = nub[j0 + tid];
-  };
-  auto lstore = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-    for (int u = 0; u < XPT; ++u) {
-      const int e = tid + 256 * u;
-      if (e < F64M_TJ * DP) sX[buf][(e / DP) * LX + e % DP] = rx[u];
-    }
-#pragma unroll
-    for (int u = 0; u < VPT; ++u) {
-      const int e = tid + 256 * u;
-      if (e < F64M_TJ * VC) sV[buf][(e / VC) * LV + e % VC] = rv[u];
-    }
-    if (tid < F64M_TJ) sN[buf][tid] = rn;
-  };
-
-  if (t_begin < t_end) {
-    gload(t_begin);
-    lstore(0);
-  }
-  wait_vmem_all();  // the row coordinates above included, on every path
-  __syncthreads();
-  for (int64_t t = t_begin; t < t_end; ++t) {
-    const int buf = (int)((t - t_begin) & 1);
-    const bool more = t + 1 < t_end;
-    if (more) gload(t + 1);
-#pragma unroll
-    for (int jb = 0; jb < F64M_TJ / 16; ++jb) {
-      // two interleaved accumulation chains over the k steps
-      d4v g0 = {0.0, 0.0, 0.0, 0.0}, g1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int sk = 0; sk < KD; sk += 2) {
-        const double a0 = sX[buf][(16 * jb + li) * LX + 4 * sk + lg];
-        const double a1 = sX[buf][(16 * jb + li) * LX + 4 * (sk + 1) + lg];
-        g0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xi[sk], g0, 0, 0, 0);
-        g1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xi[sk + 1], g1, 0, 0, 0);
-      }
-      const d4v g = g0 + g1;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int jj = 16 * jb + lg + 4 * r;
-        double D = nui + sN[buf][jj] - 2.0 * g[r];
-        D = D > 0.0 ? D : 0.0;
-        double p = exp_neg_tab(D * c, sE);
-        if (deriv) p *= D * dscale;
-#pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
-          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li], acc[ct],
-                                                         0, 0, 0);
-      }
-    }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-  }
-  double* pout = part + (int64_t)blockIdx.y * part_stride;
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    const int64_t cc = c0 + 16 * ct + li;
-    if (cc < m) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + lg + 4 * r;
-        if (i < n1) pout[i * ldp + cc] = acc[ct][r];
-      }
-    }
-  }
-}
-
-template <int KD>
-static void launch_f64mfma(dim3 grid, hipStream_t st, const F64Points& A, const F64Points& B,
-                           const double* V, int64_t ldv, int64_t m, int c0, int nct, double c,
-                           int deriv, double dscale, double* part, int64_t ldp,
-                           int64_t part_stride, int tps) {
-  if (nct == 1)
-    matmat_f64mfma_kernel<KD, 1><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, V, ldv, A.n, B.n, m,
-                                                       c0, c, deriv, dscale, part, ldp,
-                                                       part_stride, tps);
-  else
-    matmat_f64mfma_kernel<KD, 2><<<grid, 256, 0, st>>>(A.X, A.nu, B.X, B.nu, V, ldv, A.n, B.n, m,
-                                                       c0, c, deriv, dscale, part, ldp,
-                                                       part_stride, tps);
 }
 
 // Large-d FP64 product (dp > 128, multiple of 32): both point sets stream through LDS in
@@ -1299,7 +1163,7 @@ __global__ __launch_bounds__(256, 2) void matmat_f64big_kernel(
           for (int r = 0; r < 4; ++r) {
             const int jj = 16 * jb + lg + 4 * r;
             double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];
-            D = D > 0.0 ? D : 0.0;
+            D = D < 0.0 ? 0.0 : D;  // a NaN stays NaN
             double p = exp_neg_tab(D * c, sE);
             if (deriv) p *= D * dscale;
 #pragma unroll
@@ -1327,28 +1191,193 @@ __global__ __launch_bounds__(256, 2) void matmat_f64big_kernel(
   }
 }
 
+// FP64 kernel product with the inner products on int8 MFMA (16x16x64, exact int32 sums).
+// With the slices of prep_points_i8, <x_i, x_j> = s_i s_j sum_{a,b} 256^(10 - a - b)
+// <D_ia, D_jb>. The digit products of one diagonal s = a + b share a weight, so they
+// accumulate in one int32 sum E_s (exact: |E_s| < 2^24 per 64-wide chunk); diagonals
+// s <= 6 are kept (26 of the 36 products; the dropped ones weigh below 2^-50 of the
+// largest), then combined in FP64:
+//   G_int = 2^72 (256 E_0 + E_1) + 2^56 (256 E_2 + E_3) + 2^40 (256 E_4 + E_5) + 2^32 E_6,
+// the two first brackets formed exactly in int32. D = nu_i + nu_j - 2 s_i s_j G_int,
+// k = exp(-c D) in FP64 (table exp), OUT[i][:] += sum_j k V[j][:] on FP64 MFMA.
+// Block: 4 waves x 16 rows; the row slices stay in registers as the B operand, the column
+// points stream through LDS in 32-point tiles (register prefetch) as the A operand, so lane
+// l holds S^T[j = 4 (l/16) + r][i = l % 16], r < 4, the A-operand layout of the FP64
+// product's contraction over four j per MFMA.
+constexpr int F64I_TJ = 32;
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+template <int KC, int NCT>
+__global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
+    const int8_t* __restrict__ Sa, const double* __restrict__ sca, const double* __restrict__ nua,
+    const int8_t* __restrict__ Sb, const double* __restrict__ scb, const double* __restrict__ nub,
+    const double* __restrict__ V, int64_t ldv, int64_t n1, int64_t n2, int64_t m, int c0, double c,
+    int deriv, double dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
+    int tiles_per_split) {
+  constexpr int KP = 64 * KC;              // bytes per slice row
+  constexpr int RB = OZ_SLICES * KP;       // bytes per point
+  constexpr int RS = RB + 16;              // LDS row stride: fragment reads conflict-free
+  constexpr int VC = 16 * NCT;
+  constexpr int LV = VC + 1;
+  constexpr int SCH = F64I_TJ * RB / 16;   // 16-byte pieces per column tile
+  constexpr int SPT = (SCH + 255) / 256;
+  constexpr int VPT = (F64I_TJ * VC + 255) / 256;
+  __shared__ __attribute__((aligned(16))) int8_t sS[2][F64I_TJ * RS];
+  __shared__ double sV[2][F64I_TJ * LV];
+  __shared__ double sN[2][F64I_TJ];
+  __shared__ double sC[2][F64I_TJ];
+  __shared__ double sE[64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);  // read after the first barrier
+  const int64_t ntiles = ceil_div(n2, F64I_TJ);
+  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+
+  i32x4 xr[OZ_SLICES][KC];
+#pragma unroll
+  for (int a = 0; a < OZ_SLICES; ++a)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+      xr[a][kc] = *reinterpret_cast<const i32x4*>(Sa + ((i0 + li) * OZ_SLICES + a) * KP +
+                                                  kc * 64 + 16 * lg);
+  const double nui = nua[i0 + li];
+  const double ai = -2.0 * 4294967296.0 * sca[i0 + li];  // -2 * 2^32 * s_i
+  d4v acc[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
+
+  i32x4 rs[SPT];
+  double rv[VPT], rn = 0.0;
+  auto gload = [&](int64_t t) __attribute__((always_inline)) {
+    const int64_t j0 = t * F64I_TJ;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < SCH) rs[u] = *reinterpret_cast<const i32x4*>(Sb + j0 * RB + 16 * (int64_t)e);
+    }
+    // right-hand sides: out-of-range entries load a valid element and are zeroed at the
+    // store (a select right after the load would wait for it)
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / VC, cc = e % VC;
+      const int64_t j = j0 + r;
+      const bool ok = e < F64I_TJ * VC && j < n2 && c0 + cc < m;
+      rv[u] = V[ok ? j * ldv + c0 + cc : 0];
+    }
+    if (tid < F64I_TJ) rn = nub[j0 + tid];
+    else if (tid < 2 * F64I_TJ) rn = scb[j0 + tid - F64I_TJ];
+  };
+  auto lstore = [&](int64_t t, int buf) __attribute__((always_inline)) {
+    const int64_t j0 = t * F64I_TJ;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int e = tid + 256 * u;
+      if (e < SCH) {
+        const int row = (16 * e) / RB, off = (16 * e) % RB;
+        *reinterpret_cast<i32x4*>(&sS[buf][row * RS + off]) = rs[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < VPT; ++u) {
+      const int e = tid + 256 * u;
+      const int r = e / VC, cc = e % VC;
+      if (e < F64I_TJ * VC) sV[buf][r * LV + cc] = (j0 + r < n2 && c0 + cc < m) ? rv[u] : 0.0;
+    }
+    if (tid < F64I_TJ) sN[buf][tid] = rn;
+    else if (tid < 2 * F64I_TJ) sC[buf][tid - F64I_TJ] = rn;
+  };
+
+  if (t_begin < t_end) {
+    gload(t_begin);
+    lstore(t_begin, 0);
+  }
+  wait_vmem_all();  // the row slices above included, on every path
+  __syncthreads();
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int buf = (int)((t - t_begin) & 1);
+    const bool more = t + 1 < t_end;
+    if (more) gload(t + 1);
+#pragma unroll 1
+    for (int jb = 0; jb < F64I_TJ / 16; ++jb) {
+      i32x4 E[7];
+#pragma unroll
+      for (int q = 0; q < 7; ++q) E[q] = i32x4{0, 0, 0, 0};
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        i32x4 cf[OZ_SLICES];
+#pragma unroll
+        for (int b = 0; b < OZ_SLICES; ++b)
+          cf[b] = *reinterpret_cast<const i32x4*>(&sS[buf][(16 * jb + li) * RS + b * KP +
+                                                           kc * 64 + 16 * lg]);
+#pragma unroll
+        for (int b = 0; b < OZ_SLICES; ++b)
+#pragma unroll
+          for (int a = 0; a < OZ_SLICES; ++a)
+            if (a + b <= 6)
+              E[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cf[b], xr[a][kc], E[a + b], 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = 16 * jb + 4 * lg + r;
+        const int H = E[0][r] * 256 + E[1][r];  // |H| < 2^28, |L| < 2^31 (int32, exact)
+        const int L = E[2][r] * 256 + E[3][r];
+        double g = fma((double)H, 65536.0, (double)L);
+        if (KC == 1)  // |256 E_4 + E_5| < 2^31 for one 64-wide chunk
+          g = fma(g, 65536.0, (double)(E[4][r] * 256 + E[5][r]));
+        else
+          g = fma(g, 65536.0, fma((double)E[4][r], 256.0, (double)E[5][r]));
+        g = fma(g, 256.0, (double)E[6][r]);  // = G_int / 2^32
+        double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
+        D = D < 0.0 ? 0.0 : D;  // a NaN stays NaN
+        double p = exp_neg_tab(D * c, sE);
+        if (deriv) p *= D * dscale;
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li], acc[ct],
+                                                         0, 0, 0);
+      }
+    }
+    if (more) lstore(t + 1, buf ^ 1);
+    __syncthreads();
+  }
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int64_t cc = c0 + 16 * ct + li;
+    if (cc < m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + lg + 4 * r;
+        if (i < n1) pout[i * ldp + cc] = acc[ct][r];
+      }
+    }
+  }
+}
+
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
                       int64_t part_stride, int nsplit, hipStream_t st) {
   if (A.dp != B.dp) return hipErrorInvalidValue;
   dim3 grid(ceil_div(A.n, 64), nsplit);
-  if (A.dp <= 128 && A.dp % 8 == 0) {
-    // FP64 MFMA kernel: 32-point column tiles, up to 32 right-hand sides per pass
-    const int64_t ntj = ceil_div(B.n, F64M_TJ);
-    const int tpsm = (int)ceil_div(ntj, nsplit);
+  if (A.S && B.S) {
+    // int8-slice kernel (d <= 128): 32-point column tiles, up to 32 right-hand sides per pass
+    if (A.d != B.d || A.d > 128 || A.d < 1) return hipErrorInvalidValue;
+    const int kc = (int)(oz_kp(A.d) / 64);
+    const int tps = (int)ceil_div(ceil_div(B.n, F64I_TJ), nsplit);
     for (int64_t c0 = 0; c0 < m; c0 += 32) {
       const int nct = m - c0 > 16 ? 2 : 1;
-      switch (A.dp / 4) {
-#define KRR_KD(K)                                                                            \
-  case K:                                                                                    \
-    launch_f64mfma<K>(grid, st, A, B, V, ldv, m, (int)c0, nct, c, deriv ? 1 : 0, dscale, part, \
-                      ldp, part_stride, tpsm);                                               \
-    break;
-        KRR_KD(2) KRR_KD(4) KRR_KD(6) KRR_KD(8) KRR_KD(10) KRR_KD(12) KRR_KD(14) KRR_KD(16)
-        KRR_KD(18) KRR_KD(20) KRR_KD(22) KRR_KD(24) KRR_KD(26) KRR_KD(28) KRR_KD(30) KRR_KD(32)
-#undef KRR_KD
-        default: return hipErrorInvalidValue;
-      }
+#define KRR_I8(KC_, NCT_)                                                                      \
+  matmat_f64i8_kernel<KC_, NCT_><<<grid, 256, 0, st>>>(A.S, A.scale, A.nu, B.S, B.scale, B.nu, \
+                                                       V, ldv, A.n, B.n, m, (int)c0, c,        \
+                                                       deriv ? 1 : 0, dscale, part, ldp,       \
+                                                       part_stride, tps)
+      if (kc == 1 && nct == 1) KRR_I8(1, 1);
+      else if (kc == 1) KRR_I8(1, 2);
+      else if (nct == 1) KRR_I8(2, 1);
+      else KRR_I8(2, 2);
+#undef KRR_I8
       KRR_LAUNCH_CHECK();
     }
     return hipSuccess;

@@ -232,7 +232,65 @@ hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows
   return hipSuccess;
 }
 
-// FP64 points for the plain FP64 path: X64 (rows_pad x dp, zero padded) and nu (rows_pad).
+// Integer slices of the points for the FP64 product on int8 MFMA. This is the error-free
+// splitting of a matrix product into products of short-integer matrices (Ozaki, Ogita,
+// Oishi and Rump, 2012) in its fixed-point form: row i is scaled by 2^(46 - e_i), e_i the
+// exponent with max_k |x_ik| < 2^e_i, and rounded to integers X_ik (exact for every element
+// within 22 binades of the row maximum, since an FP32 value carries 24 bits); then
+// X_ik = sum_a D_iak 256^(5 - a) with balanced digits D_iak in [-128, 127] (|D_i0k| <= 65).
+// S[(row * 6 + a) * kp + k] = D_iak (int8, zero padded to kp and rows_pad),
+// scale[row] = 2^(e_i - 46), nu[row] = sum_k x_ik^2 in FP64 (NaN if the row holds a
+// non-finite value, so that it propagates as in the plain FP64 product).
+__global__ __launch_bounds__(256) void prep_points_i8_kernel(const float* __restrict__ X,
+                                                             int64_t n, int64_t d, int64_t ldx,
+                                                             int64_t rows_pad, int64_t kp,
+                                                             int8_t* __restrict__ S,
+                                                             double* __restrict__ scale,
+                                                             double* __restrict__ nu) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows_pad) return;
+  float mx = 0.0f;
+  double ss = 0.0;
+  int bad = 0;
+  for (int64_t k = lane; k < d; k += 64) {
+    const float v = row < n ? X[row * ldx + k] : 0.0f;
+    if (!isfinite(v)) bad = 1;
+    mx = fmaxf(mx, fabsf(v));
+    ss += (double)v * (double)v;
+  }
+  mx = wave_max(mx);
+  ss = wave_sum(ss);
+  bad = wave_max(bad);
+  int e = 0;
+  if (!bad && mx > 0.0f) frexpf(mx, &e);  // mx = f 2^e, f in [0.5, 1): every |x| < 2^e
+  const double up = ldexp(1.0, OZ_BITS - e);
+  for (int64_t k = lane; k < kp; k += 64) {
+    const double v = (row < n && k < d && !bad) ? (double)X[row * ldx + k] : 0.0;
+    long long q = (long long)rint(v * up);  // |q| < 2^46
+    for (int a = OZ_SLICES - 1; a > 0; --a) {
+      const long long dg = ((q + 128) & 255) - 128;  // q = dg (mod 256), dg in [-128, 127]
+      S[(row * OZ_SLICES + a) * kp + k] = (int8_t)dg;
+      q = (q - dg) >> 8;  // exact: q - dg is a multiple of 256
+    }
+    S[(row * OZ_SLICES) * kp + k] = (int8_t)q;
+  }
+  if (lane == 0) {
+    scale[row] = ldexp(1.0, e - OZ_BITS);
+    nu[row] = bad ? __builtin_nan("") : ss;
+  }
+}
+
+hipError_t prep_points_i8(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
+                          int8_t* S, double* scale, double* nu, hipStream_t st) {
+  prep_points_i8_kernel<<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, oz_kp(d),
+                                                              S, scale, nu);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+// Point copies for the large-d FP64 product: X64 (rows_pad x dp, zero padded; an FP32 copy
+// holds the FP32 values exactly) and nu (rows_pad) formed in FP64.
 template <typename T>
 __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __restrict__ X,
                                                               int64_t n, int64_t d, int64_t ldx,
@@ -250,14 +308,6 @@ __global__ __launch_bounds__(256) void prep_points_f64_kernel(const float* __res
   }
   s = wave_sum(s);
   if (lane == 0) nu[row] = s;
-}
-
-hipError_t prep_points_f64(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                           int64_t dp, double* X64, double* nu, hipStream_t st) {
-  prep_points_f64_kernel<double><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad,
-                                                                        dp, X64, nu);
-  KRR_LAUNCH_CHECK();
-  return hipSuccess;
 }
 
 // Same with the coordinates kept in FP32 (an exact copy, zero padded) for the large-d FP64

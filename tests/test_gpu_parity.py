@@ -388,6 +388,44 @@ def test_matmat_fp64_large_d(dev, case):
         assert np.all(np.abs(got - ref) <= bound), (deriv, np.max(np.abs(got - ref) / bound))
 
 
+def test_matmat_fp64_wide_dynamic_range(dev):
+    """FP64 product (integer-slice inner products for d <= 128) on rows whose entries span
+    30 binades, so the fixed-point slices round the smallest ones, with d over one 64-wide
+    chunk, a zero row and duplicate points: 1e-12 relative to (|K| |V|)_i, value and
+    sigma-derivative."""
+    rng = np.random.default_rng(11)
+    for n1, n2, d, m in [(150, 211, 40, 3), (97, 130, 100, 18)]:
+        scales = 2.0 ** rng.integers(-20, 10, size=d)
+        X1 = (rng.standard_normal((n1, d)) * scales).astype(np.float32)
+        X2 = (rng.standard_normal((n2, d)) * scales).astype(np.float32)
+        X1[3] = 0.0
+        X2[5] = X2[7]
+        X1[9] = X2[7]
+        V = rng.standard_normal((n2, m))
+        sigma = 0.8 * float(np.sqrt((scales ** 2).sum()))
+        for deriv in (False, True):
+            got = krr.kernel_matmat(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), deriv=deriv,
+                                    prec="fp64").cpu().numpy()
+            ref = O.kernel_matmat(X1, X2, sigma, V, deriv=deriv)
+            bound = 1e-12 * _abs_bound(X1, X2, sigma, V, deriv) + 1e-300
+            assert np.all(np.abs(got - ref) <= bound), (d, deriv, np.max(np.abs(got - ref) / bound))
+
+
+def test_matmat_fp64_nan_point_propagates(dev):
+    """A NaN coordinate makes every output of the FP64 product NaN, as in the oracle (every
+    row meets the NaN point); the other rows of a product without it stay finite."""
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((70, 9)).astype(np.float32)
+    V = rng.standard_normal((70, 2))
+    X[13, 4] = np.nan
+    got = krr.kernel_matmat(_t(X, dev), _t(X, dev), 3.0, _t(V, dev), prec="fp64").cpu().numpy()
+    ref = O.kernel_matmat(X, X, 3.0, V)
+    assert np.isnan(ref).all() and np.isnan(got).all()
+    got2 = krr.kernel_matmat(_t(X[:13], dev), _t(X[14:], dev), 3.0, _t(V[14:], dev),
+                             prec="fp64").cpu().numpy()
+    assert np.isfinite(got2).all()
+
+
 def _large_d_case(dev, n1, n2, d, m):
     rng = np.random.default_rng(d + m)
     X1 = rng.standard_normal((n1, d)).astype(np.float32)
