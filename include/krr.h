@@ -50,7 +50,11 @@ typedef enum krr_status {
 
 /* Arithmetic of the kernel product K V (Sec. 3.1: the dominant per-iteration cost). */
 typedef enum krr_prec {
-  KRR_PREC_FP64 = 0,   /* FP64 distances, FP64 exp, FP64 sums ("plain FP64 path") */
+  KRR_PREC_FP64 = 0,   /* FP64-class distances, FP64 exp, FP64 sums ("plain FP64 path"):
+                          for d <= 128 the inner products are exact integer sums of the rows
+                          in 46-bit fixed point (relative to each row's largest coordinate),
+                          computed on int8 MFMA; for larger d FP64 products of the FP32
+                          coordinates */
   KRR_PREC_F16X3 = 1,  /* distances on MFMA from FP16 hi+lo splits of the (power-of-two
                           scaled) points, 3 products hi*hi + hi*lo + lo*hi, FP32 accumulate;
                           FP32 exp2; FP32 products with V, FP64 sums across tiles (default) */
