@@ -370,10 +370,11 @@ def test_matmat_large_d_and_many_columns(dev, case):
 
 
 @pytest.mark.parametrize("case", [(150, 333, 300, 5), (200, 257, 440, 40), (64, 300, 784, 10),
-                                  (129, 65, 136, 17)])
+                                  (129, 65, 136, 17), (40, 50, 16500, 2)])
 def test_matmat_fp64_large_d(dev, case):
     """FP64 product with d > 128 (FP32 coordinates through LDS, FP64 MFMA): 1e-12 relative to
-    (|K| |V|)_i, value and sigma-derivative, ragged row and column counts."""
+    (|K| |V|)_i, value and sigma-derivative, ragged row and column counts, two column passes
+    (m = 40) and a long k loop (d = 16500)."""
     n1, n2, d, m = case
     rng = np.random.default_rng(d + m + 1)
     X1 = rng.standard_normal((n1, d)).astype(np.float32)
