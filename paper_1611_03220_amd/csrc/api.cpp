@@ -62,6 +62,11 @@ int64_t kp_for(int prec, int64_t d) {
   return use_pv(prec, d) ? round_up(d + 2 + (PSHIFT > 0), K_STEP) : kp_for(d);
 }
 // FP64 point width: multiples of 8 up to 128 (FP64 MFMA kernel), else of 32 (VALU kernel)
+// right-hand-side columns per pass of the MFMA-accumulate product: 32, or 64 for large d
+// (where the distance work of a pass dominates its P V work)
+int64_t pv_pass_width(int64_t Kp) { return Kp > 128 ? 64 : 32; }
+// rows of the split V^T operand for a pass of mc columns: 16, 32 or 64 (NCT = 1, 2, 4)
+int64_t pv_pass_rows(int64_t mc) { return mc > 32 ? 64 : round_up(mc, 16); }
 int64_t dp_for(int64_t d) { return round_up(d, 8) <= 128 ? round_up(d, 8) : round_up(d, 32); }
 
 // Split of the column sweep over blockIdx.y so that small row counts still fill the chip.
@@ -125,7 +130,7 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     // large-d MFMA product on many row blocks: 8 column splits, launched in XCD groups
     if (c.pv && c.Kp > 128 && ceil_div(n1, 128) >= 64) c.nsplit = 8;
     if (c.pv) {
-      c.mpad = round_up(std::min<int64_t>(m, 32), 16);
+      c.mpad = pv_pass_rows(std::min<int64_t>(m, pv_pass_width(c.Kp)));
       c.Vth = b.take<_Float16>(c.mpad * c.rp2);
       c.Vtl = b.take<_Float16>(c.mpad * c.rp2);
       c.colmax = b.take<float>(m);
@@ -193,9 +198,11 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
     MixedPoints<_Float16> A{(const _Float16*)c.Ahi, (const _Float16*)c.Alo, c.n1, c.Kp, c.stats + 2};
     MixedPoints<_Float16> B{(const _Float16*)c.Bhi, (const _Float16*)c.Blo, c.n2, c.Kp, c.stats + 2};
     if (c.pv) {
-      for (int64_t c0 = 0; c0 < c.m; c0 += 32) {
-        const int64_t mc = std::min<int64_t>(32, c.m - c0);
-        const int64_t mp = round_up(mc, 16);
+      const int64_t W = pv_pass_width(c.Kp);
+      for (int64_t c0 = 0; c0 < c.m; c0 += W) {
+        const int64_t mc = std::min<int64_t>(W, c.m - c0);
+        const int64_t mp = pv_pass_rows(mc);
+        if (mp > c.mpad) return hipErrorInvalidValue;  // V^T buffers hold c.mpad rows
         const bool packed = mc <= 8;  // hi and lo parts share one 16-row operand
         hipError_t e = vec_split_t(Vf + c0, c.n2, mc, ldv, c.rp2, mp, c.colmax, PSHIFT, packed,
                                    c.Vth, c.Vtl, c.vscale, st);

@@ -74,6 +74,12 @@ __device__ inline void atomic_max_pos(float* addr, float v) {
   if (v > 0.0f) atomicMax(reinterpret_cast<unsigned int*>(addr), __float_as_uint(v));
 }
 
+// s_waitcnt vmcnt(0): wait for all outstanding vector memory loads (gfx9 encoding, expcnt
+// and lgkmcnt left at their maxima). Issued before a loop, it keeps loads of the prologue
+// from reaching the loop as pending, which would make the compiler's wait counts inside
+// the loop stall on the loop's own prefetch.
+__device__ inline void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 template <typename T> __device__ inline T wave_sum(T v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f16x3_kernel(
     gload(k_begin);
     lstore(0);
   }
+  wait_vmem_all();  // no load pending at the loop's entry on any path (precise waits inside)
   __syncthreads();
   int buf = 0;
   for (int64_t k0 = k_begin; k0 < k_end; k0 += G_BK) {

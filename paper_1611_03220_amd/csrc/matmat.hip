@@ -290,10 +290,6 @@ __device__ inline int vfrag(int c, int jp, int g) {
   return c * TN + (((4 * jp + g) ^ vswz<TN>(c)) << 3);
 }
 
-// s_waitcnt vmcnt(0): wait for all outstanding vector memory loads (gfx9 encoding, expcnt
-// and lgkmcnt left at their maxima).
-__device__ inline void wait_vmem_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
-
 // Packed right-hand sides (m <= 8): the 16 columns of the P V product hold P V_hi in
 // columns 0..7 and P V_lo in columns 8..15 (P's hi and lo parts both multiply the one
 // operand: two MFMAs instead of three, and the lo x lo term is included); lane li < 8 adds
@@ -869,21 +865,24 @@ __device__ __forceinline__ void f16pv_bigd_body(
   }
 }
 
-// column tiles of the large-d single-problem product (the batched product keeps 64)
+// column tiles of the large-d single-problem product (the batched product keeps 64, and so
+// does the 64-column pass, NCT = 4, whose accumulators leave no registers for wider tiles)
 constexpr int BD_NJB = 8;
 constexpr int BD_TN = 16 * BD_NJB;
+constexpr int bd_njb(int nct) { return nct == 4 ? 4 : BD_NJB; }
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
 template <int NCT, bool DERIV, bool PACK>
-__global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
+__global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
     int64_t part_stride, int tiles_per_split, int grouped) {
-  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, BD_NJB>()];
+  constexpr int NJB = bd_njb(NCT);
+  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, NJB>()];
   int64_t rb = blockIdx.x, sp = blockIdx.y;
   if (grouped) {
     // 1-D grid of (row block, split) pairs with BD_GROUP splits, ordered so that the blocks
@@ -898,11 +897,11 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
   }
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, DERIV, BD_NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+    f16pv_bigd_body<NCT, true, DERIV, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                               n1, n2, m, KP, qinv2, dscale, part, ldp,
                                               part_stride, tiles_per_split, rb, sp);
   else
-    f16pv_bigd_body<NCT, false, DERIV, BD_NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+    f16pv_bigd_body<NCT, false, DERIV, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
                                                n1, n2, m, KP, qinv2, dscale, part, ldp,
                                                part_stride, tiles_per_split, rb, sp);
 }
@@ -910,7 +909,9 @@ __global__ __launch_bounds__(256, 2) void matmat_f16pv_bigd_kernel(
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
                         const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
-  if (A.Kp != B.Kp || V.mpad < round_up(m, 16) || V.mpad > 32) return hipErrorInvalidValue;
+  if (A.Kp != B.Kp || V.mpad < round_up(m, 16)) return hipErrorInvalidValue;
+  // passes of up to 32 columns (64 for large d, NCT = 4)
+  if (A.Kp > 128 ? !(V.mpad <= 32 || V.mpad == 64) : V.mpad > 32) return hipErrorInvalidValue;
   if (V.packed && (m > 8 || V.mpad != 16)) return hipErrorInvalidValue;
   if (part_stride < round_up(A.n, MM2_BM) * ldp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, MM_BN);
@@ -919,7 +920,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   const int nct = (int)(V.mpad / 16);
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
-    const int tps = (int)ceil_div(ceil_div(B.n, BD_TN), nsplit);
+    const int tps = (int)ceil_div(ceil_div(B.n, 16 * (nct == 4 ? bd_njb(4) : BD_NJB)), nsplit);
     const int64_t nrb = ceil_div(A.n, BD_BM);
     const int grouped = nsplit == BD_GROUP && nrb >= 8 * BD_GROUP ? 1 : 0;
     if (grouped) grid = dim3((unsigned)(round_up(nrb, 8 * BD_GROUP) * BD_GROUP), 1);
@@ -933,9 +934,12 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
     } else if (nct == 1) {
       if (deriv) KRR_BD(1, true, false);
       else KRR_BD(1, false, false);
-    } else {
+    } else if (nct == 2) {
       if (deriv) KRR_BD(2, true, false);
       else KRR_BD(2, false, false);
+    } else {
+      if (deriv) KRR_BD(4, true, false);
+      else KRR_BD(4, false, false);
     }
 #undef KRR_BD
     KRR_LAUNCH_CHECK();
