@@ -1049,7 +1049,7 @@ __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
 constexpr int F64B_TJ = 64;
 constexpr int F64B_LK = 33;  // padded LDS row of a chunk (floats)
 template <int NCT>
-__global__ __launch_bounds__(256, 2) void matmat_f64big_kernel(
+__global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
     const float* __restrict__ Xa, const double* __restrict__ nua, const float* __restrict__ Xb,
     const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
     int64_t n2, int64_t m, int c0, int dp, double c, int deriv, double dscale,
@@ -1389,15 +1389,16 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
   if (!A.Xf || !B.Xf || A.dp % 32) return hipErrorInvalidValue;
   const int tpsb = (int)ceil_div(ceil_div(B.n, F64B_TJ), nsplit);
   dim3 gridb(ceil_div(A.n, 128), nsplit);
-  for (int64_t c0 = 0; c0 < m; c0 += 32) {
-    if (m - c0 > 16)
-      matmat_f64big_kernel<2><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m,
-                                                     (int)c0, (int)A.dp, c, deriv ? 1 : 0, dscale,
-                                                     part, ldp, part_stride, tpsb);
-    else
-      matmat_f64big_kernel<1><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m,
-                                                     (int)c0, (int)A.dp, c, deriv ? 1 : 0, dscale,
-                                                     part, ldp, part_stride, tpsb);
+  // passes of up to 64 right-hand sides: the inner products dominate a pass's work
+  for (int64_t c0 = 0; c0 < m; c0 += 64) {
+#define KRR_F64B(NCT_)                                                                        \
+  matmat_f64big_kernel<NCT_><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m, \
+                                                    (int)c0, (int)A.dp, c, deriv ? 1 : 0,      \
+                                                    dscale, part, ldp, part_stride, tpsb)
+    if (m - c0 > 32) KRR_F64B(4);
+    else if (m - c0 > 16) KRR_F64B(2);
+    else KRR_F64B(1);
+#undef KRR_F64B
     KRR_LAUNCH_CHECK();
   }
   return hipSuccess;
