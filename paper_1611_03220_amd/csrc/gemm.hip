@@ -152,9 +152,10 @@ hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M
 // ------------------------------------------------------------------- FP64 GEMM
 // C[i, j] = beta C[i, j] + alpha sum_k A(i, k) B(k, j), A(i, k) = A[i*sai + k*sak],
 // B(k, j) = B[k*sbk + j*sbj]; batched over blockIdx.z with element strides bA, bB, bC.
-// 64 x 64 tile, k chunks of 16, each thread 4 x 4 outputs. lower_only skips tiles that lie
-// strictly above the block diagonal and entries with j > i.
-constexpr int D_BK = 16;
+// 64 x 64 tile, k chunks of 64 (one load round trip for the rank-64 Cholesky updates: all
+// loads of a chunk are issued before any is used), each thread 4 x 4 outputs. lower_only
+// skips tiles that lie strictly above the block diagonal and entries with j > i.
+constexpr int D_BK = 64;
 __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K,
                                                     double alpha, const double* __restrict__ A,
                                                     int64_t sai, int64_t sak, int64_t bA,
@@ -176,17 +177,34 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+  constexpr int EPT = 64 * D_BK / 256;  // elements of each operand tile per thread
+  // element e of a tile: consecutive threads along the unit-stride index
+  auto a_pos = [&](int e, int& rr, int& kk) __attribute__((always_inline)) {
+    if (sak == 1) { rr = e / D_BK; kk = e % D_BK; } else { kk = e / 64; rr = e % 64; }
+  };
+  auto b_pos = [&](int e, int& cc, int& kk) __attribute__((always_inline)) {
+    if (sbk == 1) { cc = e / D_BK; kk = e % D_BK; } else { kk = e / 64; cc = e % 64; }
+  };
   for (int64_t k0 = 0; k0 < K; k0 += D_BK) {
-    for (int e = tid; e < 64 * D_BK; e += 256) {
-      // A tile: prefer consecutive threads along the unit-stride index
-      int rr, kk;
-      if (sak == 1) { rr = e / D_BK; kk = e % D_BK; } else { kk = e / 64; rr = e % 64; }
-      const int64_t gi = row0 + rr, gk = k0 + kk;
-      sA[kk][rr] = (gi < M && gk < K) ? A[gi * sai + gk * sak] : 0.0;
-      int cc, k2;
-      if (sbk == 1) { cc = e / D_BK; k2 = e % D_BK; } else { k2 = e / 64; cc = e % 64; }
-      const int64_t gj = col0 + cc, gk2 = k0 + k2;
-      sB[k2][cc] = (gj < N && gk2 < K) ? B[gk2 * sbk + gj * sbj] : 0.0;
+    // out-of-range elements load a valid element and are zeroed at the LDS store (a select
+    // right after each load would wait for it)
+    double va[EPT], vb[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      int rr, kk, cc, k2;
+      a_pos(tid + 256 * u, rr, kk);
+      b_pos(tid + 256 * u, cc, k2);
+      const int64_t gi = row0 + rr, gk = k0 + kk, gj = col0 + cc, gk2 = k0 + k2;
+      va[u] = A[(gi < M && gk < K) ? gi * sai + gk * sak : 0];
+      vb[u] = B[(gj < N && gk2 < K) ? gk2 * sbk + gj * sbj : 0];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      int rr, kk, cc, k2;
+      a_pos(tid + 256 * u, rr, kk);
+      b_pos(tid + 256 * u, cc, k2);
+      sA[kk][rr] = (row0 + rr < M && k0 + kk < K) ? va[u] : 0.0;
+      sB[k2][cc] = (col0 + cc < N && k0 + k2 < K) ? vb[u] : 0.0;
     }
     __syncthreads();
 #pragma unroll
