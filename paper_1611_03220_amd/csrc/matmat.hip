@@ -1018,24 +1018,23 @@ hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* ins
 // B[l/16][l%16], result register r holds C[l/16 + 4r][l%16].
 typedef double d4v __attribute__((ext_vector_type(4)));
 
-// e^{-x} for x >= 0 in FP64 with a 64-entry table T[j] = 2^{-j/64}: with y = x log2(e)
-// (clamped at 1100, far below the smallest double; a NaN passes through to the result),
-// k = rint(64 y) and r = y - k/64 in
-// [-1/128, 1/128], e^{-x} = 2^{-(k >> 6)} T[k & 63] e^{-r ln 2}; the last factor is a
-// degree-6 Taylor polynomial (truncation below 1e-19 on that interval).
+// e^{-x} for x >= 0 in FP64 with a 256-entry table T[j] = 2^{-j/256} (EXP_TAB entries in
+// LDS): with y = x log2(e) (clamped at 1100, far below the smallest double; a NaN passes
+// through to the result), k = rint(256 y) and r = y - k/256 in [-1/512, 1/512],
+// e^{-x} = 2^{-(k >> 8)} T[k & 255] e^{-r ln 2}; the last factor is a degree-4 Taylor
+// polynomial (truncation below 4e-17 on that interval).
+constexpr int EXP_TAB = 256;
 __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
   const double y0 = x * 1.4426950408889634;
   const double y = y0 > 1100.0 ? 1100.0 : y0;
-  const double kf = rint(y * 64.0);
+  const double kf = rint(y * 256.0);
   const int k = __double2int_rn(kf);  // hardware conversion: a NaN gives 0 (any k is in range)
-  const double u = fma(kf, 0.015625, -y) * 0.6931471805599453;  // = -r ln 2
-  double q = fma(u, 1.0 / 720.0, 1.0 / 120.0);
-  q = fma(u, q, 1.0 / 24.0);
-  q = fma(u, q, 1.0 / 6.0);
+  const double u = fma(kf, 0.00390625, -y) * 0.6931471805599453;  // = -r ln 2
+  double q = fma(u, 1.0 / 24.0, 1.0 / 6.0);
   q = fma(u, q, 0.5);
   q = fma(u, q, 1.0);
   q = fma(u, q, 1.0);
-  return ldexp(T[k & 63] * q, -(k >> 6));
+  return ldexp(T[k & (EXP_TAB - 1)] * q, -(k >> 8));
 }
 
 // Large-d FP64 product (dp > 128, multiple of 32): both point sets stream through LDS in
@@ -1060,7 +1059,7 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
   __shared__ float sC[2][F64B_TJ * F64B_LK];
   __shared__ double sV[F64B_TJ * LV];
   __shared__ double sN[F64B_TJ];
-  __shared__ double sE[64];
+  __shared__ double sE[EXP_TAB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t blk_i0 = (int64_t)blockIdx.x * 128;
@@ -1069,7 +1068,7 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = dp / 32;
   const int64_t nsteps = (t_end - t_begin) * KC;
-  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);
+  for (int e = tid; e < EXP_TAB; e += 256) sE[e] = exp2(-(double)e / EXP_TAB);
 
   double nui[2];
 #pragma unroll
@@ -1229,11 +1228,11 @@ __global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
   __shared__ double sV[2][F64I_TJ * LV];
   __shared__ double sN[2][F64I_TJ];
   __shared__ double sC[2][F64I_TJ];
-  __shared__ double sE[64];
+  __shared__ double sE[EXP_TAB];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t i0 = (int64_t)blockIdx.x * 64 + 16 * w;
-  if (tid < 64) sE[tid] = exp2(-(double)tid / 64.0);  // read after the first barrier
+  for (int e = tid; e < EXP_TAB; e += 256) sE[e] = exp2(-(double)e / EXP_TAB);  // read after the first barrier
   const int64_t ntiles = ceil_div(n2, F64I_TJ);
   const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
