@@ -1022,7 +1022,8 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 // LDS): with y = x log2(e) (clamped at 1100, far below the smallest double; a NaN passes
 // through to the result), k = rint(256 y) and r = y - k/256 in [-1/512, 1/512],
 // e^{-x} = 2^{-(k >> 8)} T[k & 255] e^{-r ln 2}; the last factor is a degree-4 Taylor
-// polynomial (truncation below 4e-17 on that interval).
+// polynomial (truncation below 4e-17 on that interval). A slightly negative x (rounding of
+// a zero distance) takes the same steps with k <= 0 and is as accurate.
 constexpr int EXP_TAB = 256;
 __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
   const double y0 = x * 1.4426950408889634;
@@ -1165,8 +1166,7 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int jj = 16 * jb + lg + 4 * r;
-            double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];
-            D = D < 0.0 ? 0.0 : D;  // a NaN stays NaN
+            const double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];  // >= 0 up to rounding
             double p = exp_neg_tab(D * c, sE);
             if (deriv) p *= D * dscale;
 #pragma unroll
@@ -1332,8 +1332,9 @@ __global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
         else
           g = fma(g, 65536.0, fma((double)E[4][r], 256.0, (double)E[5][r]));
         g = fma(g, 256.0, (double)E[6][r]);  // = G_int / 2^32
-        double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
-        D = D < 0.0 ? 0.0 : D;  // a NaN stays NaN
+        // D >= 0 up to rounding (|D| ~ 1e-15 nu for duplicate points): no clamp needed, the
+        // exp below is exact in form for small negative arguments, and a NaN stays NaN
+        const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
         double p = exp_neg_tab(D * c, sE);
         if (deriv) p *= D * dscale;
 #pragma unroll
