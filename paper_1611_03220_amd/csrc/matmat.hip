@@ -1206,11 +1206,14 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 // Block: 4 waves x 16 rows; the row slices stay in registers as the B operand, the column
 // points stream through LDS in 32-point tiles (register prefetch) as the A operand, so lane
 // l holds S^T[j = 4 (l/16) + r][i = l % 16], r < 4, the A-operand layout of the FP64
-// product's contraction over four j per MFMA.
+// product's contraction over four j per MFMA. With VPV (at most 8 right-hand sides) the
+// P V step runs on the VALU instead: lane l accumulates its row's 8 columns over its four
+// j (V rows read as LDS broadcasts) and the four lane groups are summed at the end in a
+// fixed order (4 m FMAs per lane and block instead of four FP64 MFMAs padded to 16 columns).
 constexpr int F64I_TJ = 32;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-template <int KC, int NCT>
-__global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
+template <int KC, int NCT, bool VPV>
+__global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8_kernel(
     const int8_t* __restrict__ Sa, const double* __restrict__ sca, const double* __restrict__ nua,
     const int8_t* __restrict__ Sb, const double* __restrict__ scb, const double* __restrict__ nub,
     const double* __restrict__ V, int64_t ldv, int64_t n1, int64_t n2, int64_t m, int c0, double c,
@@ -1219,8 +1222,10 @@ __global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
   constexpr int KP = 64 * KC;              // bytes per slice row
   constexpr int RB = OZ_SLICES * KP;       // bytes per point
   constexpr int RS = RB + 16;              // LDS row stride: fragment reads conflict-free
-  constexpr int VC = 16 * NCT;
-  constexpr int LV = VC + 1;
+  static_assert(!VPV || NCT == 1, "VALU P V covers one pass of at most 8 columns");
+  constexpr int VC = VPV ? 8 : 16 * NCT;
+  constexpr int LV = VPV ? 10 : VC + 1;    // VPV: 80-byte rows, 16-byte aligned, and rows
+                                           // four apart fall on distinct banks
   constexpr int SCH = F64I_TJ * RB / 16;   // 16-byte pieces per column tile
   constexpr int SPT = (SCH + 255) / 256;
   constexpr int VPT = (F64I_TJ * VC + 255) / 256;
@@ -1249,6 +1254,9 @@ __global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
   d4v acc[NCT];
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4v{0.0, 0.0, 0.0, 0.0};
+  double accv[VPV ? 8 : 1];
+#pragma unroll
+  for (int cc = 0; cc < (VPV ? 8 : 1); ++cc) accv[cc] = 0.0;
 
   i32x4 rs[SPT];
   double rv[VPT], rn = 0.0;
@@ -1337,16 +1345,37 @@ __global__ __launch_bounds__(256, KC == 1 ? 3 : 1) void matmat_f64i8_kernel(
         const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
         double p = exp_neg_tab(D * c, sE);
         if (deriv) p *= D * dscale;
+        if (VPV) {
+          const double* vr = &sV[buf][jj * LV];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
-          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li], acc[ct],
-                                                         0, 0, 0);
+          for (int cc = 0; cc < 8; ++cc) accv[cc] = fma(p, vr[cc], accv[cc]);
+        } else {
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li],
+                                                           acc[ct], 0, 0, 0);
+        }
       }
     }
     if (more) lstore(t + 1, buf ^ 1);
     __syncthreads();
   }
   double* pout = part + (int64_t)blockIdx.y * part_stride;
+  if (VPV) {
+    // lane (li, lg) holds row i0 + li summed over its lane group's j: add the four groups
+#pragma unroll
+    for (int cc = 0; cc < 8; ++cc) {
+      accv[cc] += __shfl_xor(accv[cc], 16, 64);
+      accv[cc] += __shfl_xor(accv[cc], 32, 64);
+    }
+    const int64_t i = i0 + li;
+    if (lg == 0 && i < n1) {
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+        if (c0 + cc < m) pout[i * ldp + c0 + cc] = accv[cc];
+    }
+    return;
+  }
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t cc = c0 + 16 * ct + li;
@@ -1372,15 +1401,17 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
     const int tps = (int)ceil_div(ceil_div(B.n, F64I_TJ), nsplit);
     for (int64_t c0 = 0; c0 < m; c0 += 32) {
       const int nct = m - c0 > 16 ? 2 : 1;
-#define KRR_I8(KC_, NCT_)                                                                      \
-  matmat_f64i8_kernel<KC_, NCT_><<<grid, 256, 0, st>>>(A.S, A.scale, A.nu, B.S, B.scale, B.nu, \
-                                                       V, ldv, A.n, B.n, m, (int)c0, c,        \
-                                                       deriv ? 1 : 0, dscale, part, ldp,       \
-                                                       part_stride, tps)
-      if (kc == 1 && nct == 1) KRR_I8(1, 1);
-      else if (kc == 1) KRR_I8(1, 2);
-      else if (nct == 1) KRR_I8(2, 1);
-      else KRR_I8(2, 2);
+#define KRR_I8(KC_, NCT_, VPV_)                                                                \
+  matmat_f64i8_kernel<KC_, NCT_, VPV_><<<grid, 256, 0, st>>>(                                  \
+      A.S, A.scale, A.nu, B.S, B.scale, B.nu, V, ldv, A.n, B.n, m, (int)c0, c, deriv ? 1 : 0,   \
+      dscale, part, ldp, part_stride, tps)
+      const bool vpv = m - c0 <= 8;  // P V on the VALU
+      if (kc == 1 && vpv) KRR_I8(1, 1, true);
+      else if (kc == 1 && nct == 1) KRR_I8(1, 1, false);
+      else if (kc == 1) KRR_I8(1, 2, false);
+      else if (vpv) KRR_I8(2, 1, true);
+      else if (nct == 1) KRR_I8(2, 1, false);
+      else KRR_I8(2, 2, false);
 #undef KRR_I8
       KRR_LAUNCH_CHECK();
     }
