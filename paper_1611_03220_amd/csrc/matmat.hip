@@ -302,18 +302,18 @@ __device__ inline void pack_combine(double (&acc64)[2][NCT][4]) {
     for (int r = 0; r < 4; ++r) acc64[ib][0][r] += __shfl_down(acc64[ib][0][r], 8, 16);
 }
 
-template <int KS, int NCT>
+template <int KS, int NCT, bool PACK>
 struct PVSmem {
   static constexpr int KP = KS * 32;
   _Float16 Bh[2][MM_BN * KP];
   _Float16 Bl[2][MM_BN * KP];
   _Float16 Vh[2][NCT * 16 * MM_BN];
-  _Float16 Vl[2][NCT * 16 * MM_BN];
+  _Float16 Vl[2][PACK ? 8 : NCT * 16 * MM_BN];  // unused with packed V^T
 };
 
 template <int KS, int NCT, bool UNIT, bool DERIV, bool PACK>
 __device__ __forceinline__ void f16pv_body(
-    PVSmem<KS, NCT>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
+    PVSmem<KS, NCT, PACK>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
@@ -512,15 +512,16 @@ __device__ __forceinline__ void f16pv_body(
     gvh += MM_BN;
     gvl += MM_BN;
     }
-    f32x4 S0[2][2], S1[2][2];
+    f32x4 S0[2][2];
     // raised wave priority while issuing the distance MFMAs lets the waves of a SIMD
-    // alternate between MFMA-heavy and VALU-heavy phases (measured: 4 % faster)
-    __builtin_amdgcn_s_setprio(1);
-    dist(buf, 0, S0);
-    dist(buf, 1, S1);
-    __builtin_amdgcn_s_setprio(0);
-    epi(buf, 0, S0);
-    epi(buf, 1, S1);
+    // alternate between MFMA-heavy and VALU-heavy phases
+#pragma unroll
+    for (int jp = 0; jp < 2; ++jp) {
+      __builtin_amdgcn_s_setprio(1);
+      dist(buf, jp, S0);
+      __builtin_amdgcn_s_setprio(0);
+      epi(buf, jp, S0);
+    }
     if (++since_flush == MM2_FLUSH || t + 1 == t_end) {
       since_flush = 0;
 #pragma unroll
@@ -567,14 +568,14 @@ __device__ __forceinline__ void f16pv_body(
 }
 
 template <int KS, int NCT, bool DERIV, bool PACK>
-__global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 3 : 2) void matmat_f16pv_kernel(
+__global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16pv_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
     int64_t part_stride, int tiles_per_split) {
-  __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT> sm;
+  __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT, PACK> sm;
   const float qinv2 = *qinv2_ptr;
   if (qinv2 == 1.0f)
     f16pv_body<KS, NCT, true, DERIV, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
