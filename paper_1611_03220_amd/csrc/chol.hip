@@ -1,6 +1,6 @@
 // FP64 Cholesky of G = Z^T Z + lambda_p I and the inverse of its factor (Sec. 3.1).
 //
-// Blocked right-looking factorisation with 64 x 64 diagonal blocks: one workgroup factors
+// Blocked right-looking factorisation with 64 x 64 diagonal blocks: one wave factors
 // the diagonal block with its rows in registers; the panel below is solved against it (one
 // thread per panel row); the trailing lower triangle gets an FP64 rank-64 update. The
 // inverses of all diagonal blocks are then formed at once, one workgroup per block, and
@@ -15,54 +15,55 @@ namespace krr {
 constexpr int NB = 64;
 
 // Factor the diagonal block at (k0, k0) of A (lda) in place (lower; strict upper zeroed).
-// 256 threads: thread (r, q) = (t / 4, t % 4) keeps W[r][c] for c = q, q + 4, ... in
-// registers. Column j: the owners of column j scale it (L[r][j] = W[r][j] / L[j][j]) and
-// publish it in LDS (zero for rows r <= j); after one barrier every row updates
-// W[r][c] -= L[r][j] L[c][j] for all its c (zeros make this a no-op for c <= j, and the
-// entries above the diagonal are never read); the owner of the next diagonal entry
-// publishes it before the second barrier. The column loop is unrolled so that register
-// indices are constants.
+// One wave: lane r keeps row r of the block in registers. Column j: the pivot W[j][j] is
+// read from lane j (readlane); every lane scales its entry W[r][j] by 1 / sqrt(W[j][j])
+// (below the diagonal this is L[r][j], on it L[j][j] to within an ulp) and publishes it
+// in LDS; every row then subtracts L[r][j] L[c][j] from its entries c > j. Values
+// above the diagonal of a row are never used for its lower part, and col[c] is read only
+// for c > j, so the steps need no lane-dependent selects. Within one wave the LDS write
+// is seen by the reads that follow it, so no barrier is needed; the column steps are
+// unrolled at compile time, so register indices are constants.
 // *info receives the 1-based global index of the first non-positive (or non-finite) pivot
 // if it is still 0.
-__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
-                                                         int64_t k0, int* __restrict__ info) {
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Column steps J, J + 1, ... of the diagonal factorisation (compile-time J, so register
+// indices are constants and the update touches only the columns after J).
+template <int J>
+__device__ __forceinline__ void potrf_steps(double (&w)[NB], double* col, int r,
+                                            int& first_bad) {
+  if constexpr (J < NB) {
+    const double dj = lane_value(w[J], J);
+    if (first_bad == 0 && (!(dj > 0.0) || !(dj < INFINITY))) first_bad = J + 1;
+    const double inv = 1.0 / sqrt(dj);
+    const double lrj = w[J] * inv;
+    w[J] = lrj;
+    col[r] = lrj;
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = J + 1; c < NB; ++c) w[c] = fma(-lrj, col[c], w[c]);
+    __builtin_amdgcn_wave_barrier();
+    potrf_steps<J + 1>(w, col, r, first_bad);
+  }
+}
+
+__global__ __launch_bounds__(64, 2) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
+                                                        int64_t k0, int* __restrict__ info) {
   __shared__ double col[NB];
-  __shared__ double piv;
-  const int t = threadIdx.x, r = t >> 2, q = t & 3;
-  double w[NB / 4];
+  const int r = threadIdx.x;
+  double w[NB];  // the whole row; entries above the diagonal (stale) are never used, and
+                 // loading them keeps lane-dependent masks out of the steps
 #pragma unroll
-  for (int u = 0; u < NB / 4; ++u) {
-    const int c = q + 4 * u;
-    w[u] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
-  }
-  if (t == 0) piv = w[0];
-  __syncthreads();
+  for (int c = 0; c < NB; ++c) w[c] = A[(k0 + r) * lda + k0 + c];
   int first_bad = 0;
+  potrf_steps<0>(w, col, r, first_bad);
+  if (r == 0 && first_bad != 0 && *info == 0) *info = (int)(k0 + first_bad);
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const double dj = piv;
-    if (first_bad == 0 && (!(dj > 0.0) || !(dj < INFINITY))) first_bad = j + 1;
-    const double ljj = sqrt(dj);
-    if (q == (j & 3)) {
-      const double lrj = r == j ? ljj : (r > j ? w[j >> 2] / ljj : 0.0);
-      w[j >> 2] = lrj;
-      col[r] = r > j ? lrj : 0.0;  // zero at and above the pivot: those rows take no update
-    }
-    __syncthreads();
-    // branch-free: col[c] = 0 for c <= j leaves finished columns alone; entries above the
-    // diagonal (c > r) take updates but are never read
-    const double lr = col[r];
-#pragma unroll
-    for (int u = 0; u < NB / 4; ++u) w[u] = fma(-lr, col[q + 4 * u], w[u]);
-    if (j + 1 < NB && r == j + 1 && q == ((j + 1) & 3)) piv = w[(j + 1) >> 2];
-    __syncthreads();
-  }
-  if (t == 0 && first_bad != 0 && *info == 0) *info = (int)(k0 + first_bad);
-#pragma unroll
-  for (int u = 0; u < NB / 4; ++u) {
-    const int c = q + 4 * u;
-    A[(k0 + r) * lda + k0 + c] = c <= r ? w[u] : 0.0;
-  }
+  for (int c = 0; c < NB; ++c) A[(k0 + r) * lda + k0 + c] = c <= r ? w[c] : 0.0;
 }
 
 // Forward substitution against the 64 x 64 lower factor held in LDS (Ls, reciprocal
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(64) void diag_inverse_kernel(const double* __restri
 // G (s_pad x s_pad, lower part used) -> C in place; Cinv diagonal blocks filled.
 hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st) {
   for (int64_t k0 = 0; k0 < s_pad; k0 += NB) {
-    potrf_diag_kernel<<<1, 256, 0, st>>>(G, s_pad, k0, info);
+    potrf_diag_kernel<<<1, NB, 0, st>>>(G, s_pad, k0, info);
     KRR_LAUNCH_CHECK();
     const int64_t rest = s_pad - k0 - NB;
     if (rest <= 0) break;

@@ -26,7 +26,13 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f16x3_kernel(
     const float* __restrict__ qa, const float* __restrict__ qb, double alpha,
     double* __restrict__ out64, int64_t out64_stride, float* __restrict__ out32, int64_t ldc,
     const float* __restrict__ bias, float amp) {
-  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  // XCD-aware order: workgroups go round-robin to the 8 XCDs (linear id mod 8), so the
+  // linear ids are remapped to give each XCD one contiguous run of tiles (row-major, the
+  // k split outermost); its L2 then serves the operand rows that neighbouring tiles share.
+  const int64_t gx = gridDim.x, gy = gridDim.y, total = gx * gy * (int64_t)gridDim.z;
+  int64_t lin = blockIdx.x + gx * (blockIdx.y + gy * (int64_t)blockIdx.z);
+  if (total % 8 == 0) lin = (lin % 8) * (total / 8) + lin / 8;
+  const int64_t bj = lin % gx, bi = (lin / gx) % gy, bz = lin / (gx * gy);
   if (lower_only && bj > bi) return;
   constexpr int TILE = G_BM * G_BK;  // halves per operand tile
   __shared__ __attribute__((aligned(16))) _Float16 smem[2][4][TILE];  // [buf][Ah, Al, Bh, Bl]
@@ -35,7 +41,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f16x3_kernel(
   const int li = lane & 15, lg = lane >> 4;
   const int wr = w >> 1, wc = w & 1;
   const int64_t row0 = bi * G_BM, col0 = bj * G_BN;
-  const int64_t k_begin = (int64_t)blockIdx.z * k_per_split;
+  const int64_t k_begin = bz * k_per_split;
   int64_t k_end = k_begin + k_per_split < K ? k_begin + k_per_split : K;
   if (tri_b) {  // B lower triangular in (j, k): entries with k > j vanish
     const int64_t kmax = round_up(col0 + G_BN, G_BK);
@@ -123,7 +129,7 @@ __global__ __launch_bounds__(256, 2) void gemm_nt_f16x3_kernel(
         const int64_t j = col0 + 64 * wc + 16 * b + li;
         if (i < M && j < N) {
           const double v = (double)acc[a][b][r] * scale;
-          if (EPI == EPI_PART64) out64[(int64_t)blockIdx.z * out64_stride + i * ldc + j] = v;
+          if (EPI == EPI_PART64) out64[bz * out64_stride + i * ldc + j] = v;
           else if (EPI == EPI_F32) out32[i * ldc + j] = (float)v;
           else out32[i * ldc + j] = amp * cosf((float)v + bias[j]);
         }
