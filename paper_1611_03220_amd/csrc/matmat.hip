@@ -1020,18 +1020,20 @@ hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* ins
 typedef double d4v __attribute__((ext_vector_type(4)));
 
 // e^{-x} for x >= 0 in FP64 with a 256-entry table T[j] = 2^{-j/256} (EXP_TAB entries in
-// LDS): with y = x log2(e) (clamped at 1100, far below the smallest double; a NaN passes
-// through to the result), k = rint(256 y) and r = y - k/256 in [-1/512, 1/512],
-// e^{-x} = 2^{-(k >> 8)} T[k & 255] e^{-r ln 2}; the last factor is a degree-4 Taylor
-// polynomial (truncation below 4e-17 on that interval). A slightly negative x (rounding of
-// a zero distance) takes the same steps with k <= 0 and is as accurate.
+// LDS): with y = 256 x log2(e), k = rint(y) and r = k/256 - x log2(e) in [-1/512, 1/512],
+// e^{-x} = 2^{-(k >> 8)} T[k & 255] e^{r ln 2}. k is rounded by adding 1.5 * 2^52 (its low
+// word is then k in two's complement, |k| < 2^31) and u = r ln 2 = k (ln 2 / 256) - x is
+// formed with ln 2 / 256 split in two (the high part has 34 bits, so k times it is exact
+// for k < 2^19); the last factor is a degree-4 Taylor polynomial (truncation below 4e-17).
+// x is clamped at 745.2, where e^{-x} is below half the smallest subnormal; a NaN passes
+// through. A slightly negative x (rounding of a zero distance) takes the same steps.
 constexpr int EXP_TAB = 256;
 __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
-  const double y0 = x * 1.4426950408889634;
-  const double y = y0 > 1100.0 ? 1100.0 : y0;
-  const double kf = rint(y * 256.0);
-  const int k = __double2int_rn(kf);  // hardware conversion: a NaN gives 0 (any k is in range)
-  const double u = fma(kf, 0.00390625, -y) * 0.6931471805599453;  // = -r ln 2
+  const double xc = x > 745.2 ? 745.2 : x;
+  const double sh = fma(xc, 369.3299304675746, 6755399441055744.0);  // 1.5 * 2^52
+  const int k = __double2loint(sh);
+  const double kf = sh - 6755399441055744.0;
+  const double u = fma(kf, 6.327543041662719e-14, fma(kf, 0.002707606173999011, -xc));
   double q = fma(u, 1.0 / 24.0, 1.0 / 6.0);
   q = fma(u, q, 0.5);
   q = fma(u, q, 1.0);
@@ -1213,12 +1215,12 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 // fixed order (4 m FMAs per lane and block instead of four FP64 MFMAs padded to 16 columns).
 constexpr int F64I_TJ = 32;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-template <int KC, int NCT, bool VPV>
+template <int KC, int NCT, bool VPV, bool DERIV>
 __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8_kernel(
     const int8_t* __restrict__ Sa, const double* __restrict__ sca, const double* __restrict__ nua,
     const int8_t* __restrict__ Sb, const double* __restrict__ scb, const double* __restrict__ nub,
     const double* __restrict__ V, int64_t ldv, int64_t n1, int64_t n2, int64_t m, int c0, double c,
-    int deriv, double dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
+    double dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
     int tiles_per_split) {
   constexpr int KP = 64 * KC;              // bytes per slice row
   constexpr int RB = OZ_SLICES * KP;       // bytes per point
@@ -1345,7 +1347,7 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
         // exp below is exact in form for small negative arguments, and a NaN stays NaN
         const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
         double p = exp_neg_tab(D * c, sE);
-        if (deriv) p *= D * dscale;
+        if (DERIV) p *= D * dscale;
         if (VPV) {
           const double* vr = &sV[buf][jj * LV];
 #pragma unroll
@@ -1402,17 +1404,23 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
     const int tps = (int)ceil_div(ceil_div(B.n, F64I_TJ), nsplit);
     for (int64_t c0 = 0; c0 < m; c0 += 32) {
       const int nct = m - c0 > 16 ? 2 : 1;
-#define KRR_I8(KC_, NCT_, VPV_)                                                                \
-  matmat_f64i8_kernel<KC_, NCT_, VPV_><<<grid, 256, 0, st>>>(                                  \
-      A.S, A.scale, A.nu, B.S, B.scale, B.nu, V, ldv, A.n, B.n, m, (int)c0, c, deriv ? 1 : 0,   \
-      dscale, part, ldp, part_stride, tps)
+#define KRR_I8(KC_, NCT_, VPV_, DV_)                                                           \
+  matmat_f64i8_kernel<KC_, NCT_, VPV_, DV_><<<grid, 256, 0, st>>>(                             \
+      A.S, A.scale, A.nu, B.S, B.scale, B.nu, V, ldv, A.n, B.n, m, (int)c0, c, dscale, part,    \
+      ldp, part_stride, tps)
+#define KRR_I8D(KC_, NCT_, VPV_)                                                               \
+  do {                                                                                         \
+    if (deriv) KRR_I8(KC_, NCT_, VPV_, true);                                                  \
+    else KRR_I8(KC_, NCT_, VPV_, false);                                                       \
+  } while (0)
       const bool vpv = m - c0 <= 8;  // P V on the VALU
-      if (kc == 1 && vpv) KRR_I8(1, 1, true);
-      else if (kc == 1 && nct == 1) KRR_I8(1, 1, false);
-      else if (kc == 1) KRR_I8(1, 2, false);
-      else if (vpv) KRR_I8(2, 1, true);
-      else if (nct == 1) KRR_I8(2, 1, false);
-      else KRR_I8(2, 2, false);
+      if (kc == 1 && vpv) KRR_I8D(1, 1, true);
+      else if (kc == 1 && nct == 1) KRR_I8D(1, 1, false);
+      else if (kc == 1) KRR_I8D(1, 2, false);
+      else if (vpv) KRR_I8D(2, 1, true);
+      else if (nct == 1) KRR_I8D(2, 1, false);
+      else KRR_I8D(2, 2, false);
+#undef KRR_I8D
 #undef KRR_I8
       KRR_LAUNCH_CHECK();
     }
