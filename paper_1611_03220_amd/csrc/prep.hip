@@ -386,44 +386,43 @@ template hipError_t absmax<double>(const double*, int64_t, int64_t, int64_t, flo
 
 // dst (rows_pad x cols_pad, k contiguous) = split(q * src), q = split_scale(*amax).
 // transpose = 0: dst[r][c] = src[r][c]; transpose = 1: dst[c][r] = src[r][c] (dst is
-// cols_pad x rows_pad). Padding is zero. LDS-tiled 32 x 32 so both sides coalesce.
+// cols_pad x rows_pad). Padding is zero. Block: 32 output rows x 64 output columns; each
+// thread writes two adjacent columns (4-byte stores of the hi and lo pairs), so a wave's
+// stores cover 128-byte row segments; the transposed case goes through a 64 x 32 LDS tile
+// (rows of 33 floats: the column-pair reads hit distinct banks). cols_pad must be even.
 template <typename S, typename T>
 __global__ __launch_bounds__(256) void split_kernel(const S* __restrict__ src, int64_t rows,
                                                     int64_t cols, int64_t ld,
                                                     const float* __restrict__ amax, int transpose,
                                                     int64_t out_rows, int64_t out_cols,
                                                     T* __restrict__ hi, T* __restrict__ lo) {
-  __shared__ float tile[32][33];
+  __shared__ float tile[64][33];
   const float q = split_scale(*amax);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  // block covers output tile (orow0.., ocol0..)
-  const int64_t orow0 = (int64_t)blockIdx.y * 32, ocol0 = (int64_t)blockIdx.x * 32;
+  const int64_t orow0 = (int64_t)blockIdx.y * 32, ocol0 = (int64_t)blockIdx.x * 64;
+  auto put = [&](int64_t r, int64_t c, float v0, float v1) __attribute__((always_inline)) {
+    T h0, l0, h1, l1;
+    Elem<T>::split(v0, h0, l0);
+    Elem<T>::split(v1, h1, l1);
+    typedef T pair_t __attribute__((ext_vector_type(2)));
+    *reinterpret_cast<pair_t*>(&hi[r * out_cols + c]) = pair_t{h0, h1};
+    *reinterpret_cast<pair_t*>(&lo[r * out_cols + c]) = pair_t{l0, l1};
+  };
+  auto val = [&](int64_t sr, int64_t sc) __attribute__((always_inline)) {
+    return (sr < rows && sc < cols) ? (float)((double)q * (double)src[sr * ld + sc]) : 0.0f;
+  };
   if (!transpose) {
     for (int yy = ty; yy < 32; yy += 8) {
-      int64_t r = orow0 + yy, c = ocol0 + tx;
-      if (r < out_rows && c < out_cols) {
-        float v = (r < rows && c < cols) ? (float)((double)q * (double)src[r * ld + c]) : 0.0f;
-        T a, b;
-        Elem<T>::split(v, a, b);
-        hi[r * out_cols + c] = a;
-        lo[r * out_cols + c] = b;
-      }
+      const int64_t r = orow0 + yy, c = ocol0 + 2 * tx;
+      if (r < out_rows && c < out_cols) put(r, c, val(r, c), val(r, c + 1));
     }
   } else {
-    // output row = source column, output col = source row
-    for (int yy = ty; yy < 32; yy += 8) {
-      int64_t sr = ocol0 + yy, sc = orow0 + tx;  // source tile, coalesced along sc
-      tile[yy][tx] = (sr < rows && sc < cols) ? (float)((double)q * (double)src[sr * ld + sc]) : 0.0f;
-    }
+    // source rows ocol0 .. ocol0 + 63 (output columns), source columns orow0 .. + 31
+    for (int yy = ty; yy < 64; yy += 8) tile[yy][tx] = val(ocol0 + yy, orow0 + tx);
     __syncthreads();
     for (int yy = ty; yy < 32; yy += 8) {
-      int64_t r = orow0 + yy, c = ocol0 + tx;
-      if (r < out_rows && c < out_cols) {
-        T a, b;
-        Elem<T>::split(tile[tx][yy], a, b);
-        hi[r * out_cols + c] = a;
-        lo[r * out_cols + c] = b;
-      }
+      const int64_t r = orow0 + yy, c = ocol0 + 2 * tx;
+      if (r < out_rows && c < out_cols) put(r, c, tile[2 * tx][yy], tile[2 * tx + 1][yy]);
     }
   }
 }
@@ -432,7 +431,8 @@ template <typename S, typename T>
 hipError_t split_operand(const S* src, int64_t rows, int64_t cols, int64_t ld, const float* amax,
                          int transpose, int64_t out_rows, int64_t out_cols, T* hi, T* lo,
                          hipStream_t st) {
-  dim3 grid(ceil_div(out_cols, 32), ceil_div(out_rows, 32));
+  if (out_cols % 2) return hipErrorInvalidValue;
+  dim3 grid(ceil_div(out_cols, 64), ceil_div(out_rows, 32));
   split_kernel<S, T><<<grid, 256, 0, st>>>(src, rows, cols, ld, amax, transpose, out_rows,
                                            out_cols, hi, lo);
   KRR_LAUNCH_CHECK();
