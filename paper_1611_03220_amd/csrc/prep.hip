@@ -356,19 +356,20 @@ hipError_t vec_pad_f64(const double* V, int64_t n, int64_t m, int64_t ldv, int64
 
 // ------------------------------------------------- generic operand splitting (GEMMs)
 // max |src| over a rows x cols FP32 or FP64 matrix -> atomic max into *amax (starts at 0).
+// Each wave takes whole rows (lanes along the row, so reads coalesce and no index division
+// is needed); the waves' maxima meet in LDS and one atomic per block.
 template <typename S>
 __global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, int64_t rows,
                                                      int64_t cols, int64_t ld, float* amax) {
   float m = 0.0f;
-  const int64_t total = rows * cols;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * 256) {
-    int64_t r = e / cols, c = e % cols;
-    m = fmaxf(m, (float)fabs((double)src[r * ld + c]));
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + w; r < rows; r += (int64_t)gridDim.x * 4) {
+    const S* row = src + r * ld;
+    for (int64_t c = lane; c < cols; c += 64) m = fmaxf(m, (float)fabs((double)row[c]));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   __shared__ float red[4];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  if (lane == 0) red[w] = m;
   __syncthreads();
   if (threadIdx.x == 0) atomic_max_pos(amax, fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
 }
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, 
 template <typename S>
 hipError_t absmax(const S* src, int64_t rows, int64_t cols, int64_t ld, float* amax,
                   hipStream_t st) {
-  int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(rows * cols, 256)));
+  int64_t blocks = std::min<int64_t>(2048, std::max<int64_t>(1, ceil_div(rows, 4)));
   absmax_kernel<S><<<blocks, 256, 0, st>>>(src, rows, cols, ld, amax);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
