@@ -162,27 +162,49 @@ hipError_t tri_inverse_doubling(const double* C, int64_t s_pad, double* Cinv, do
 
 // Gram reduction: G[i][j] = sum_s part[s][i][j] for the lower triangle (i >= j, i, j < s),
 // mirrored; + lambda_p on the diagonal; identity on the padded diagonal; zero elsewhere.
-__global__ void gram_finalize_kernel(const double* __restrict__ part, int nsplit, int64_t s,
-                                     int64_t ldp, int64_t pstride, double lambda_p, int64_t s_pad,
-                                     double* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= s_pad * s_pad) return;
-  const int64_t i = e / s_pad, j = e % s_pad;
-  double v = 0.0;
-  if (i < s && j < s) {
-    const int64_t a = i >= j ? i : j, b = i >= j ? j : i;  // lower triangle entry
-    for (int k = 0; k < nsplit; ++k) v += part[k * pstride + a * ldp + b];
-    if (i == j) v += lambda_p;
-  } else if (i == j) {
-    v = 1.0;
+// 32 x 32 tiles: the block of a tile on or below the diagonal reads that lower source
+// tile of every split once (coalesced rows), sums the splits in order, and writes the tile
+// and, through LDS, its mirror above the diagonal; in a diagonal tile the entries above
+// the diagonal take their lower mirror. Blocks of tiles above the diagonal return.
+constexpr int GF_T = 32;
+__global__ __launch_bounds__(256) void gram_finalize_kernel(const double* __restrict__ part,
+                                                            int nsplit, int64_t s, int64_t ldp,
+                                                            int64_t pstride, double lambda_p,
+                                                            int64_t s_pad,
+                                                            double* __restrict__ G) {
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bj > bi) return;
+  __shared__ double t[GF_T][GF_T + 1];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const int64_t i0 = bi * GF_T, j0 = bj * GF_T;
+  for (int yy = ty; yy < GF_T; yy += 8) {
+    const int64_t i = i0 + yy, j = j0 + tx;
+    double v = 0.0;
+    if (i < s && j < s)
+      for (int k = 0; k < nsplit; ++k) v += part[k * pstride + i * ldp + j];
+    t[yy][tx] = v;
   }
-  G[e] = v;
+  __syncthreads();
+  for (int yy = ty; yy < GF_T; yy += 8) {
+    const int64_t i = i0 + yy, j = j0 + tx;
+    double v = (bi == bj && tx > yy) ? t[tx][yy] : t[yy][tx];
+    if (i >= s || j >= s) v = i == j ? 1.0 : 0.0;
+    else if (i == j) v += lambda_p;
+    G[i * s_pad + j] = v;
+  }
+  if (bi != bj) {
+    for (int yy = ty; yy < GF_T; yy += 8) {
+      const int64_t r = j0 + yy, c = i0 + tx;  // mirror entry (r, c) = source (c, r)
+      G[r * s_pad + c] = (r < s && c < s) ? t[tx][yy] : 0.0;
+    }
+  }
 }
 
 hipError_t gram_finalize(const double* part, int nsplit, int64_t s, int64_t ldp, int64_t pstride,
                          double lambda_p, int64_t s_pad, double* G, hipStream_t st) {
-  gram_finalize_kernel<<<ceil_div(s_pad * s_pad, 256), 256, 0, st>>>(part, nsplit, s, ldp,
-                                                                      pstride, lambda_p, s_pad, G);
+  if (s_pad % GF_T) return hipErrorInvalidValue;
+  dim3 grid(s_pad / GF_T, s_pad / GF_T);
+  gram_finalize_kernel<<<grid, 256, 0, st>>>(part, nsplit, s, ldp, pstride, lambda_p, s_pad, G);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

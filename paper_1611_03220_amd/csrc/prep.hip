@@ -357,7 +357,8 @@ hipError_t vec_pad_f64(const double* V, int64_t n, int64_t m, int64_t ldv, int64
 // ------------------------------------------------- generic operand splitting (GEMMs)
 // max |src| over a rows x cols FP32 or FP64 matrix -> atomic max into *amax (starts at 0).
 // Each wave takes whole rows (lanes along the row, so reads coalesce and no index division
-// is needed); the waves' maxima meet in LDS and one atomic per block.
+// is needed; four loads per lane in flight); the waves' maxima meet in LDS and one atomic
+// per block.
 template <typename S>
 __global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, int64_t rows,
                                                      int64_t cols, int64_t ld, float* amax) {
@@ -365,7 +366,13 @@ __global__ __launch_bounds__(256) void absmax_kernel(const S* __restrict__ src, 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int64_t r = (int64_t)blockIdx.x * 4 + w; r < rows; r += (int64_t)gridDim.x * 4) {
     const S* row = src + r * ld;
-    for (int64_t c = lane; c < cols; c += 64) m = fmaxf(m, (float)fabs((double)row[c]));
+    int64_t c = lane;
+    for (; c + 192 < cols; c += 256) {  // four independent loads in flight per lane
+      const S a = row[c], b = row[c + 64], d = row[c + 128], e = row[c + 192];
+      m = fmaxf(fmaxf(m, (float)fabs((double)a)), (float)fabs((double)b));
+      m = fmaxf(fmaxf(m, (float)fabs((double)d)), (float)fabs((double)e));
+    }
+    for (; c < cols; c += 64) m = fmaxf(m, (float)fabs((double)row[c]));
   }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
   __shared__ float red[4];
