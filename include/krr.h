@@ -4,7 +4,7 @@
  *
  * Method: Avron, Clarkson, Woodruff, "Faster Kernel Ridge Regression Using Sketching
  * and Preconditioning" (arXiv 1611.03220). The library solves Eq. 1,
- *     (K + lambda I_n) c = y,   K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))   (Sec. 5),
+ *     (K + lambda I_n) c = y,   K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2))   (Sec. 6),
  * by PCG (Alg. 1) with the preconditioner Z Z^T + lambda_p I_n built from random
  * Fourier features Z = sqrt(2/s) cos(X W + b) (Sec. 2.2) and applied through its
  * Woodbury form lambda_p^{-1} (I - U^T U), U = C^{-1} Z^T, C C^T = Z^T Z + lambda_p I_s
@@ -143,7 +143,7 @@ krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu,
  * krr_kernel_matmat -- matrix-free kernel product (the per-iteration product of the PCG in
  * Alg. 1; Sec. 3.1 cost discussion):
  *     OUT[i, :] = sum_j k(x1_i, x2_j) V[j, :] + shift * V[i, :],
- * with k the Gaussian kernel of Sec. 5, or, with deriv = 1, its sigma-derivative
+ * with k the Gaussian kernel of Sec. 6, or, with deriv = 1, its sigma-derivative
  * dk/dsigma = k * ||x1_i - x2_j||^2 / sigma^3.
  *   X1 : n1 x d FP32 (ldx1 >= d);  X2 : n2 x d FP32 (ldx2 >= d).
  *   V  : n2 x m FP64 (ldv >= m);   OUT: n1 x m FP64 (ldo >= m), must not alias V.
@@ -158,7 +158,7 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
 
 /* Options of krr_pcg_solve (zero-initialise, then set what you need; see krr_pcg_defaults). */
 typedef struct krr_pcg_opts {
-  double tol;            /* stop when ||y_j - A c_j|| <= tol ||y_j|| for every column j (Sec. 5),
+  double tol;            /* stop when ||y_j - A c_j|| <= tol ||y_j|| for every column j (Sec. 6),
                             tracked on the recursive residual */
   int32_t max_iter;      /* iteration cap (the paper's ablation uses 1000) */
   int32_t prec;          /* krr_prec of the kernel products */
@@ -195,7 +195,7 @@ void krr_pcg_defaults(krr_pcg_opts* o);
 /*
  * krr_pcg_solve -- the solve of Alg. 1: (K + lambda I_n) alpha = Y by PCG with the
  * preconditioner (Z Z^T + lambda_p I)^{-1} = (I - Ut Ut^T) / lambda_p, one independent
- * PCG recurrence per right-hand side (columns freeze once converged; Sec. 5).
+ * PCG recurrence per right-hand side (columns freeze once converged; Sec. 6).
  *   X     : n x d FP32 (ldx >= d).   sigma > 0, lambda > 0.
  *   Ut, s, ldu : output of krr_precond_factor (ignored when opts->use_precond == 0).
  *   Y     : n x m FP64 right-hand sides (ldy >= m).

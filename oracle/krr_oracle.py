@@ -20,10 +20,10 @@ Readings of the paper taken here (each is also listed in the design notes):
     varies it).
   * PCG: the standard method (Shewchuk's form, which the paper cites for its bound),
     started from zero (Thm. 1), stopped on the recursive residual
-    ||r_j|| <= tol ||y_j|| for every right-hand side (Sec. 5), columns independent and
+    ||r_j|| <= tol ||y_j|| for every right-hand side (Sec. 6), columns independent and
     frozen once converged.
-  * Squared distances are clamped at zero (they are exact here, so the clamp never
-    fires in the oracle).
+  * Squared distances are formed as sums of squared coordinate differences, which are
+    never negative, so no clamp at zero is needed or applied.
 """
 from __future__ import annotations
 
@@ -50,7 +50,7 @@ STATUS_BREAKDOWN = 4
 def sq_dists(X1: np.ndarray, X2: np.ndarray, block: int = 256) -> np.ndarray:
     """Squared Euclidean distances D_ij = sum_k (x1_ik - x2_jk)^2 in FP64.
 
-    Difference form, evaluated block by block (Sec. 5 defines the Gaussian kernel on
+    Difference form, evaluated block by block (Sec. 6 defines the Gaussian kernel on
     ||x - z||^2). The block of rows is capped so the difference array stays near 2^24
     elements.
     """
@@ -65,12 +65,12 @@ def sq_dists(X1: np.ndarray, X2: np.ndarray, block: int = 256) -> np.ndarray:
 
 
 def gaussian_kernel(X1, X2, sigma: float) -> np.ndarray:
-    """K_ij = exp(-||x_i - z_j||^2 / (2 sigma^2)): the Gaussian kernel of Sec. 5."""
+    """K_ij = exp(-||x_i - z_j||^2 / (2 sigma^2)): the Gaussian kernel of Sec. 6."""
     return np.exp(-sq_dists(X1, X2) / (2.0 * sigma * sigma))
 
 
 def gaussian_kernel_dsigma(X1, X2, sigma: float) -> np.ndarray:
-    """dK/dsigma = K * ||x - z||^2 / sigma^3 (derivative of the Sec. 5 kernel)."""
+    """dK/dsigma = K * ||x - z||^2 / sigma^3 (derivative of the Sec. 6 kernel)."""
     D = sq_dists(X1, X2)
     return np.exp(-D / (2.0 * sigma * sigma)) * D / sigma ** 3
 
@@ -184,7 +184,7 @@ def pcg(apply_A, Y, apply_M=None, tol: float = 1e-6, max_iter: int = 1000, x0=No
 
     The solve of Alg. 1: (K + lambda I) c = y by PCG with a fixed SPD preconditioner,
     starting from zero (Thm. 1), stopping when ||y_j - A x_j|| <= tol ||y_j|| (tracked on
-    the recursive residual) for every column (Sec. 5). Standard PCG: alpha = rho/<p, Ap>,
+    the recursive residual) for every column (Sec. 6). Standard PCG: alpha = rho/<p, Ap>,
     beta = rho_new/rho. A column whose curvature <p, Ap> is not positive or not finite is
     frozen and reported as a breakdown.
     """
@@ -257,7 +257,7 @@ def krr_pcg(X, sigma: float, lam: float, Y, U=None, lambda_p=None, tol=1e-6, max
 
 
 def relres_true(X, sigma: float, lam: float, alpha, Y, rows=None) -> np.ndarray:
-    """Per-column ||y - (K + lambda I) c|| / ||y|| in FP64 (the Sec. 5 stopping quantity).
+    """Per-column ||y - (K + lambda I) c|| / ||y|| in FP64 (the Sec. 6 stopping quantity).
 
     With ``rows`` given, both norms are taken over those rows only (a sampled check).
     """

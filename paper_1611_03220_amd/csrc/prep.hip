@@ -1,6 +1,6 @@
 // Point preparation and operand splitting for the MFMA products.
 //
-// The Gaussian kernel (Sec. 5) is evaluated through the norm expansion
+// The Gaussian kernel (Sec. 6) is evaluated through the norm expansion
 //   -||x_i - x_j||^2 c = 2c <x_i, x_j> - c nu_i - c nu_j,   nu = ||x||^2, c = log2(e)/(2 sigma^2),
 // which becomes ONE inner product of augmented rows
 //   a_i = q [sqrt(2c) x_i, -c nu_i, 1],   b_j = q [sqrt(2c) x_j, 1, -c nu_j],

@@ -9,7 +9,7 @@ Every array is generated in FP64 with ``numpy.random.default_rng(161103220 + 100
 values are the canonical inputs for both sides. Streams: 0 points, 1 labels / teacher,
 2 feature-map draws (W, b), 3 bandwidth pairs, 4 noise.
 
-Shapes follow the workloads the paper measures on (Sec. 5: one-vs-all classification
+Shapes follow the workloads the paper measures on (Sec. 6: one-vs-all classification
 label matrices, Gaussian kernel, sigma and lambda as hyper-parameters); no dataset
 from the paper is reproduced, synthetic stand-ins of the same shape are generated.
 """

@@ -26,7 +26,7 @@ def _golden(golden_dir):
     return vals
 
 
-# ----------------------------------------------------------------- kernel (Sec. 5)
+# ----------------------------------------------------------------- kernel (Sec. 6)
 def test_kernel_hand_values(golden_dir):
     g = _golden(golden_dir)
     K = O.gaussian_kernel(np.array([[0.0, 0.0]]), np.array([[3.0, 4.0]]), 5.0)
@@ -289,6 +289,36 @@ def test_spectrum_clusters_as_s_grows():
     assert all(a > b for a, b in zip(spread, spread[1:])), spread
 
 
+def test_spectrum_equals_generalized_eigenproblem():
+    """The preconditioned spectrum (Sec. 3.1 preconditioner; the eigenvalue argument in the
+    proof of Thm. 1) is the spectrum of the pencil (K + lambda I, Z Z^T + lambda_p I), which
+    LAPACK's generalized symmetric eigensolver computes by another route. lambda != lambda_p
+    so that swapping them or dropping either shows."""
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((90, 3))
+    K = O.gaussian_kernel(X, X, 1.1)
+    Z = O.rff_features(X, rng.standard_normal((3, 40)) / 1.1, rng.uniform(0, 2 * np.pi, 40))
+    lam, lam_p = 0.03, 0.2
+    ref = sla.eigh(K + lam * np.eye(90), Z @ Z.T + lam_p * np.eye(90), eigvals_only=True)
+    np.testing.assert_allclose(O.preconditioned_spectrum(K, lam, Z, lam_p), ref, rtol=1e-10)
+
+
+def test_spectrum_special_cases():
+    """Z = 0: the preconditioner is lambda_p I, so the spectrum is (eig(K) + lambda) /
+    lambda_p. Z Z^T = K exactly with lambda_p = lambda: the preconditioner is the matrix
+    itself and every eigenvalue is 1."""
+    rng = np.random.default_rng(32)
+    X = rng.standard_normal((70, 2))
+    K = O.gaussian_kernel(X, X, 0.9)
+    lam, lam_p = 0.07, 0.5
+    ev = O.preconditioned_spectrum(K, lam, np.zeros((70, 5)), lam_p)
+    np.testing.assert_allclose(ev, (np.linalg.eigvalsh(K) + lam) / lam_p, rtol=1e-10, atol=1e-13)
+    w, V = np.linalg.eigh(K)
+    Zfull = V * np.sqrt(np.clip(w, 0.0, None))  # Z Z^T = K up to rounding
+    ev = O.preconditioned_spectrum(K, lam, Zfull, lam)
+    np.testing.assert_allclose(ev, 1.0, atol=1e-10)
+
+
 def test_pcg_status_codes():
     X, Y, sig, lam, Z = _problem(n=80, seed=18)
     res = O.krr_pcg(X, sig, lam, Y, tol=1e-14, max_iter=1)
@@ -301,7 +331,7 @@ def test_pcg_status_codes():
 
 
 def test_pcg_columns_independent():
-    """Multi-RHS PCG runs independent columns (Sec. 5): a joint solve equals per-column
+    """Multi-RHS PCG runs independent columns (Sec. 6): a joint solve equals per-column
     solves when the products are formed column by column (same rounding)."""
     X, Y, sig, lam, Z = _problem(n=150, seed=19, m=3)
     _, U = O.precond_factor(Z, lam)
