@@ -1,22 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the random-features-preconditioned KRR solve on one MI355X.
 
-One step is the whole hot path on the multi-RHS workload (n = 65536 points, d = 54,
-7 one-vs-all right-hand sides, s = 2048 random Fourier features, lambda = 1e-4 n, sigma
-= median pairwise distance, tolerance 1e-6): random features, preconditioner
-factorisation and mixed-precision PCG to 1e-6 (the three phases of Alg. 1), and the FP64
-true residual at exit. Inputs are seeded synthetic data resident in HBM before timing.
+Headline step: the whole hot path on the largest single-GPU workload (pixels: n = 262144
+points, d = 784, 10 one-vs-all right-hand sides, s = 8192 random Fourier features, lambda =
+1e-5 n, sigma = median pairwise distance): random features, preconditioner factorisation and
+mixed-precision PCG (the three phases of Alg. 1), with the FP64 true residual at exit and
+FP64-residual refinement until every column meets 1e-6. Inputs are seeded synthetic data
+resident in HBM before timing.
 
 Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algorithmic
-kernel-product flops 2 n^2 (d + m) of all products in the timed steps divided by the
-timed wall time. `roofline` describes the dominant kernel (the fused kernel product) against
-the dense FP16 MFMA peak: algorithmic flops per launch over the average launch time, timed with
-HIP events inside the library on the stream it runs on; the executed MFMA work (split
-products over padded widths) is reported beside it. `batched` is the solve of 64 uneven
-problems in one plan (persistent product, captured iteration graph). `fp64_path` is the
-same solve with the plain FP64 kernel product (time to tolerance), measured once after
-the timed steps. `cpu_baseline` times the CPU FP64 oracle's kernel product on a row
-sample on this host.
+kernel-product flops 2 n^2 (d + m) of all mixed products in the timed steps divided by the
+timed wall time. `roofline` describes the dominant kernel (the fused large-d kernel product)
+against the dense FP16 MFMA peak: algorithmic flops per launch over the average launch time,
+timed with HIP events inside the library on the stream the product runs on. `fp64_path` is the
+same solve with the plain FP64 kernel product. Secondary legs: the multi-RHS mixture workload
+(n = 65536, d = 54) with its own FP64 path and roofline, the plain FP64 workload, the
+preconditioner ablation (lambda_p = lambda, 10 lambda, none; Table 2 and Table 4 of the paper),
+the batched uneven problems and the differentiation workload. Every solve reports `tol_met`;
+the script exits with status 1 after printing when any solve misses its tolerance.
+`cpu_baseline` times the CPU FP64 oracle's kernel product on a row sample on this host's cores
+(one process per core) and extrapolates its time to tolerance.
 """
 from __future__ import annotations
 
@@ -36,21 +39,25 @@ PEAK_HBM = 8.0e12               # bytes/s
 CUS, CLOCK = 256, 2.4e9
 PEAK_EXP = CUS * 32 * CLOCK     # FP32 exp2 per second: 32 lanes per clock per CU
 
+METRIC = "kernel matmat TFLOP/s + time-to-1e-6 residual PCG solve, mixed vs FP64 path"
+LEGS = ["mixture", "plain", "ablation", "batched", "differentiation"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=65536, help="points (65536 is the benchmark workload)")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path solve")
+    ap.add_argument("--headline", choices=["pixels", "mixture"], default="pixels",
+                    help="workload of the timed steps (pixels is the largest single-GPU one)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-path solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-problems solve")
-    ap.add_argument("--extra", action="append", default=[], choices=["pixels", "differentiation"],
-                    help="also run a full-size leg of another workload (repeatable)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="comma-separated secondary legs to run (empty for none)")
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="run a plain device copy of this many bytes (counter calibration)")
+    ap.add_argument("--refine", type=int, default=2)
     return ap.parse_args()
 
 
@@ -67,10 +74,10 @@ def source_sha256(rel):
     return hashlib.sha256(src.encode()).hexdigest()
 
 
-def recorded_traffic(kernel_src):
-    """HBM bytes per launch of the kernel product from the committed counter summary, or
-    None when the kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_matmat_f16pv_mixture_n65536.md")
+def recorded_traffic(summary, kernel_src):
+    """HBM bytes per launch of a kernel from a committed counter summary, or None when the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -86,7 +93,161 @@ def recorded_traffic(kernel_src):
         return None
 
 
-def batched_run(dev):
+def _sync_time():
+    import torch
+    torch.cuda.synchronize()
+    return time.perf_counter()
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def tol_met(rep, tol):
+    """A solve meets its tolerance when it returned OK and every column's FP64 true
+    residual is at most tol."""
+    from paper_1611_03220_amd import krr
+    vals = [v for v in rep.relres_true]
+    return rep.status == krr.OK and bool(vals) and all(v <= tol for v in vals)
+
+
+def kernel_shapes(d, m):
+    """(Kp, executed MFMA flops per pair) of the F16X3 product for d and m."""
+    kp = int(math.ceil((d + 2) / 32.0) * 32)         # augmented, padded feature width
+    W = 64 if kp > 128 else 32                        # right-hand-side columns per pass
+    per_pair = 0
+    for c0 in range(0, m, W):
+        mc = min(W, m - c0)
+        mp = 64 if mc > 32 else int(math.ceil(mc / 16.0) * 16)
+        # three split products for the distances per pass; P V takes three split products,
+        # or two when mc <= 8 (the hi and lo parts of V share one 16-column operand)
+        per_pair += 2 * (3 * kp + (2 if mc <= 8 else 3) * mp)
+    return kp, per_pair
+
+
+class Problem:
+    """A workload's device tensors."""
+
+    def __init__(self, w, dev):
+        import numpy as np
+        import torch
+        self.w = w
+        self.X = torch.from_numpy(w.X).to(dev)
+        self.Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+        self.W = torch.from_numpy(w.W).to(dev)
+        self.b = torch.from_numpy(w.b).to(dev)
+
+    def solve(self, prec, refine, lambda_p=None, use_precond=True, max_iter=1000):
+        """Features, factor and PCG to the workload's tolerance (one step of Alg. 1)."""
+        from paper_1611_03220_amd import krr
+        w = self.w
+        Ut = None
+        if use_precond:
+            Z = krr.features(self.X, self.W, self.b)
+            _, Ut = krr.precond_factor(Z, lambda_p or w.lam)
+            del Z
+        return krr.pcg_solve(self.X, w.sigma, w.lam, Ut, self.Y, tol=w.tol, prec=prec,
+                             use_precond=use_precond, lambda_p=lambda_p, refine=refine,
+                             max_iter=max_iter, raise_on_error=False)
+
+
+def timed_steps(P, steps, warmup, refine):
+    for _ in range(warmup):
+        P.solve("f16x3", refine)
+    t0 = _sync_time()
+    reps = [P.solve("f16x3", refine)[1] for _ in range(steps)]
+    wall = _sync_time() - t0
+    return reps, wall
+
+
+def roofline_of(w, reps, kernel, summary, src="paper_1611_03220_amd/csrc/matmat.hip"):
+    n, d, m = w.n, w.d, w.m
+    flops = 2.0 * n * n * (d + m)
+    calls = sum(r.matmat_calls for r in reps)
+    avg_s = sum(r.matmat_ms for r in reps) / max(calls, 1) / 1e3
+    pairs = float(n) * n
+    kp, exec_pp = kernel_shapes(d, m)
+    return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_MFMA_F16 / 1e12,
+            "unit": "TFLOP/s", "frac": flops / avg_s / PEAK_MFMA_F16,
+            "traffic": recorded_traffic(summary, src), "kernel": kernel,
+            "algorithmic_flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3,
+            "launches": calls, "executed_mfma_flops_per_launch": pairs * exec_pp,
+            "executed_mfma_tflops": pairs * exec_pp / avg_s / 1e12,
+            "executed_frac": pairs * exec_pp / avg_s / PEAK_MFMA_F16,
+            "exp_per_s": pairs / avg_s, "exp_peak_per_s": PEAK_EXP,
+            "exp_frac": pairs / avg_s / PEAK_EXP,
+            "timed_with": "HIP events on the library's stream around every product launch"}
+
+
+def solve_summary(rep, wall, tol, w):
+    flops = 2.0 * w.n * w.n * (w.d + w.m)
+    return {"time_to_tol_s": wall, "iterations": rep.iters, "refine_steps": rep.refine_steps,
+            "relres_true_max": max(rep.relres_true), "status": rep.status,
+            "tol_met": tol_met(rep, tol), "matmat_calls": rep.matmat_calls,
+            "matmat_tflops_algorithmic": flops * rep.matmat_calls / max(rep.matmat_ms, 1e-9) * 1e-9}
+
+
+def fp64_leg(P, refine):
+    t0 = _sync_time()
+    _, r64 = P.solve("fp64", refine)
+    t64 = _sync_time() - t0
+    out = solve_summary(r64, t64, P.w.tol, P.w)
+    out["fp64_products"] = r64.matmat_calls + 1 + r64.refine_steps
+    return out
+
+
+def mixture_run(dev, args):
+    """The multi-RHS mixture workload (n = 65536, d = 54, m = 7, s = 2048) to 1e-6: three
+    timed steps, the roofline of its kernel product and its FP64 path."""
+    from paper_1611_03220_amd import workloads as WL
+    P = Problem(WL.mixture_multi_rhs(), dev)
+    reps, wall = timed_steps(P, 3, 1, args.refine)
+    w = P.w
+    out = {"workload": f"Gaussian mixture n={w.n} d={w.d} m={w.m} s={w.s}",
+           "ms_per_step": wall / 3 * 1e3, "time_to_tol_mixed_s": wall / 3,
+           "iterations": [r.iters for r in reps],
+           "relres_true_max": max(max(r.relres_true) for r in reps),
+           "tol_met": all(tol_met(r, w.tol) for r in reps),
+           "value_tflops": sum(r.matmat_calls for r in reps) * 2.0 * w.n * w.n * (w.d + w.m) / wall / 1e12,
+           "roofline": roofline_of(w, reps, "matmat_f16pv_kernel (d + 2 <= 128: register-resident "
+                                   "row operand)", "traffic_matmat_f16pv_mixture_n65536.md")}
+    if not args.no_fp64:
+        out["fp64_path"] = fp64_leg(P, args.refine)
+        out["fp64_path"]["speedup_mixed_vs_fp64"] = out["fp64_path"]["time_to_tol_s"] / (wall / 3)
+    return out
+
+
+def plain_run(dev, args):
+    """The plain FP64 method (n = 2000, d = 8, s = 200, one right-hand side) to 1e-10."""
+    from paper_1611_03220_amd import workloads as WL
+    P = Problem(WL.plain_fp64(), dev)
+    P.solve("fp64", 0)
+    t0 = _sync_time()
+    _, rep = P.solve("fp64", 0)
+    return {"workload": "plain n=2000 d=8 s=200 fp64 tol=1e-10",
+            **solve_summary(rep, _sync_time() - t0, P.w.tol, P.w)}
+
+
+def ablation_run(dev, args):
+    """Preconditioner ablation on the mixture workload: lambda_p = lambda (Alg. 1), lambda_p =
+    10 lambda (Table 2's larger preconditioner regulariser) and plain CG (Table 4), each to
+    1e-6 with a 1000-iteration cap."""
+    from paper_1611_03220_amd import workloads as WL
+    P = Problem(WL.mixture_multi_rhs(), dev)
+    w = P.w
+    out = {"workload": f"Gaussian mixture n={w.n} d={w.d} m={w.m} s={w.s}"}
+    for name, kw in (("lambda_p=lambda", {}), ("lambda_p=10lambda", {"lambda_p": 10 * w.lam}),
+                     ("no_preconditioner", {"use_precond": False})):
+        P.solve("f16x3", args.refine, **kw)
+        t0 = _sync_time()
+        _, rep = P.solve("f16x3", args.refine, **kw)
+        out[name] = solve_summary(rep, _sync_time() - t0, w.tol, w)
+        if name == "no_preconditioner":
+            out[name]["tol_met_expected"] = False  # plain CG may stop at the cap (Table 4)
+    return out
+
+
+def batched_run(dev, args):
     """The batched workload: 64 independent problems (n log-uniform in [1024, 16384], d in
     {16, 32, 64, 128}, s = n/8, 1-4 right-hand sides) solved to 1e-6 together."""
     import numpy as np
@@ -94,7 +255,7 @@ def batched_run(dev):
     from paper_1611_03220_amd import krr
     from paper_1611_03220_amd import workloads as WL
     ws = WL.batched_instances()
-    t0 = time.perf_counter()
+    t0 = _sync_time()
     probs = []
     for w in ws:
         X = torch.from_numpy(w.X).to(dev)
@@ -103,19 +264,18 @@ def batched_run(dev):
         del Z
         probs.append({"X": X, "sigma": w.sigma, "lam": w.lam, "Ut": Ut,
                       "Y": torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)})
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    t1 = _sync_time()
     plan = krr.BatchPlan(probs, tol=1e-6, refine=4)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    t2 = _sync_time()
     _, rep = plan.solve(raise_on_error=False)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    t3 = _sync_time()
     flops = sum(2.0 * w.n * w.n * (w.d + w.m) for w in ws)
+    worst = max(max(r) for r in rep.relres_true)
     out = {"workload": "64 uneven problems, n in [1024, 16384], d in {16,32,64,128}, s = n/8",
            "status": rep.status, "time_to_tol_s": t3 - t2, "setup_features_factor_s": t1 - t0,
            "plan_create_s": t2 - t1, "iterations": rep.iters, "refine_steps": rep.refine_steps,
-           "relres_true_max": max(max(r) for r in rep.relres_true),
+           "first_solve_col_iters_max": max(max(c) for c in rep.col_iters),
+           "relres_true_max": worst, "tol_met": rep.status == krr.OK and worst <= 1e-6,
            "product_ms": rep.product_ms, "iteration_ms": rep.iteration_ms,
            "product_tflops_algorithmic": flops / (rep.product_ms * 1e-3) / 1e12,
            "tiles_per_item": rep.tiles_per_item, "work_items": rep.work_items,
@@ -124,42 +284,7 @@ def batched_run(dev):
     return out
 
 
-def _sync_time():
-    import torch
-    torch.cuda.synchronize()
-    return time.perf_counter()
-
-
-def pixels_run(dev):
-    """Large dense-feature workload: n = 262144 pixel-like points (d = 784, 80 % zeros),
-    10 one-vs-all right-hand sides, s = 8192 features, lambda = 1e-5 n, solved to 1e-6 with
-    the mixed product and FP64-residual refinement."""
-    import numpy as np
-    import torch
-    from paper_1611_03220_amd import krr
-    from paper_1611_03220_amd import workloads as WL
-    w = WL.pixels()
-    X = torch.from_numpy(w.X).to(dev)
-    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
-    W = torch.from_numpy(w.W).to(dev)
-    b = torch.from_numpy(w.b).to(dev)
-    t0 = _sync_time()
-    Z = krr.features(X, W, b)
-    t1 = _sync_time()
-    _, Ut = krr.precond_factor(Z, w.lam)
-    del Z
-    t2 = _sync_time()
-    _, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, refine=3, raise_on_error=False)
-    t3 = _sync_time()
-    flops = 2.0 * w.n * w.n * (w.d + w.m)
-    return {"workload": f"pixels n={w.n} d={w.d} m={w.m} s={w.s}", "status": rep.status,
-            "time_to_tol_s": t3 - t0, "features_s": t1 - t0, "factor_s": t2 - t1,
-            "solve_s": t3 - t2, "iterations": rep.iters, "refine_steps": rep.refine_steps,
-            "relres_true_max": max(rep.relres_true), "matmat_calls": rep.matmat_calls,
-            "matmat_tflops_algorithmic": flops * rep.matmat_calls / max(rep.matmat_ms, 1e-9) * 1e-9}
-
-
-def differentiation_run(dev):
+def differentiation_run(dev, args):
     """Differentiation workload: n = 131072 training + 16384 validation points, d = 440,
     147 one-vs-all columns, s = 4096; validation loss and its sigma / lambda gradients
     through the adjoint solve (mixed solves, FP64 derivative products)."""
@@ -188,32 +313,66 @@ def differentiation_run(dev):
             "loss": float(L.detach()), "dL_dsigma": float(sig.grad), "dL_dlambda": float(lam.grad)}
 
 
-def cpu_baseline(w, seconds):
-    """Time the oracle's FP64 kernel product on a growing row sample for ~`seconds`."""
+# ------------------------------------------------------------------ CPU baseline
+_CPU = {}
+
+
+def _oracle_rows(bounds):
+    """Worker: the oracle's FP64 product on rows [a, b) (one BLAS thread per process)."""
     import numpy as np
     import oracle as O
     try:
         from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(limits=1)
     except ImportError:  # pragma: no cover
-        threadpool_limits = None
-    V = np.random.default_rng(0).standard_normal((w.n, w.m))
-    rows_done, t_used, rows = 0, 0.0, 8
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+        ctx = None
+    w, V = _CPU["w"], _CPU["V"]
+    t0 = time.perf_counter()
+    O.kernel_matmat(w.X, w.X, w.sigma, V, rows=np.arange(bounds[0], bounds[1]))
+    dt = time.perf_counter() - t0
+    if ctx is not None:
+        ctx.__exit__(None, None, None)
+    return bounds[1] - bounds[0], dt
+
+
+def cpu_baseline(w, seconds):
+    """The oracle's FP64 kernel product K[rows, :] V on a row sample, one process per host
+    core (forked before the GPU is touched), for about `seconds` of wall time."""
+    import multiprocessing as mp
+    import numpy as np
     try:
-        while t_used < seconds:
-            idx = np.arange(rows_done, rows_done + rows) % w.n
-            t0 = time.perf_counter()
-            O.kernel_matmat(w.X, w.X, w.sigma, V, rows=idx)
-            t_used += time.perf_counter() - t0
-            rows_done += rows
-            rows = min(rows * 2, 256)
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
-    flops = 2.0 * rows_done * w.n * (w.d + w.m)
-    return {"value": flops / t_used / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 difference-form kernel product K[rows, :] V for {rows_done} of "
-                      f"{w.n} rows (d={w.d}, m={w.m}), {t_used:.1f} s, one thread"}
+        from threadpoolctl import threadpool_info
+        blas = [(i.get("internal_api"), i.get("num_threads")) for i in threadpool_info()]
+    except ImportError:  # pragma: no cover
+        blas = []
+    cores = os.cpu_count() or 1
+    workers = max(1, min(16, cores))
+    _CPU["w"] = w
+    _CPU["V"] = np.random.default_rng(0).standard_normal((w.n, w.m))
+    # probe the per-row cost on one worker, then size the sample to the time budget
+    _, dt = _oracle_rows((0, 2))
+    per_row = dt / 2
+    rows_per_worker = max(1, int(seconds / max(per_row, 1e-9)))
+    chunk = max(1, min(64, rows_per_worker))
+    jobs = []
+    start = 2
+    for _ in range(workers * max(1, rows_per_worker // chunk)):
+        jobs.append((start % w.n, min(w.n, start % w.n + chunk)))
+        start += chunk
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_rows, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    rows = sum(r for r, _ in res)
+    flops = 2.0 * rows * w.n * (w.d + w.m)
+    full_product_s = wall * w.n / rows
+    return {"value": flops / wall / 1e12, "unit": "TFLOP/s", "cores": workers, "kind": "oracle",
+            "sample": f"FP64 difference-form kernel product K[rows, :] V for {rows} of {w.n} rows "
+                      f"(d={w.d}, m={w.m}) in {wall:.1f} s on {workers} processes of one BLAS "
+                      f"thread each",
+            "host_cpu_count": cores, "blas_threads_per_process": 1, "blas_default": blas,
+            "full_product_s_extrapolated": full_product_s}
 
 
 def main():
@@ -222,18 +381,17 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU "
               "by design; the design notes describe how it would shard", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    from paper_1611_03220_amd import workloads as WL
+    w = WL.pixels() if args.headline == "pixels" else WL.mixture_multi_rhs()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_seconds)  # host processes forked before any GPU use
+        _log(f"cpu baseline {cpu['value']:.2e} TFLOP/s on {cpu['cores']} processes")
     import torch
     from paper_1611_03220_amd import krr
-    from paper_1611_03220_amd import workloads as WL
 
+    krr.lib()
     dev = torch.device("cuda:0")
-    w = WL.mixture_multi_rhs(n=args.n)
-    X = torch.from_numpy(w.X).to(dev)
-    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
-    W = torch.from_numpy(w.W).to(dev)
-    b = torch.from_numpy(w.b).to(dev)
-    torch.cuda.synchronize()
     if args.calib_bytes > 0:
         # a plain copy kernel of known size: what the byte counters read for it calibrates
         # the counters of the kernels profiled in the same run
@@ -243,90 +401,79 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
-
-    def step(prec):
-        Z = krr.features(X, W, b)
-        _, Ut = krr.precond_factor(Z, w.lam)
-        alpha, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, prec=prec,
-                                   true_residual=True, raise_on_error=False)
-        return alpha, rep
-
-    for _ in range(args.warmup):
-        step("f16x3")
+    P = Problem(w, dev)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = [step("f16x3")[1] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {wall:.3f} s", file=sys.stderr, flush=True)
-
+    reps, wall = timed_steps(P, args.steps, args.warmup, args.refine)
+    _log(f"timed {args.steps} {args.headline} steps in {wall:.3f} s")
     n, d, m = w.n, w.d, w.m
     flops_mm = 2.0 * n * n * (d + m)
     calls = sum(r.matmat_calls for r in reps)
-    mm_ms = sum(r.matmat_ms for r in reps)
-    avg_launch_s = mm_ms / max(calls, 1) / 1e3
-    pairs = float(n) * n
-    kp = int(math.ceil((d + 2) / 32.0) * 32)        # augmented, padded feature width
-    mp = int(math.ceil(m / 16.0) * 16)              # padded right-hand-side columns
-    # split-3 distances; P V takes three split products, or two when m <= 8 (the hi and lo
-    # parts of V share one 16-column operand)
-    exec_mfma = pairs * 2 * (3 * kp + (2 if m <= 8 else 3) * mp)
-    roof = {"bound": "mfma", "achieved": flops_mm / avg_launch_s / 1e12,
-            "peak": PEAK_MFMA_F16 / 1e12, "unit": "TFLOP/s",
-            "frac": flops_mm / avg_launch_s / PEAK_MFMA_F16,
-            "traffic": recorded_traffic("paper_1611_03220_amd/csrc/matmat.hip"),
-            "kernel": "matmat_f16pv_kernel (FP16 hi/lo split MFMA distances, FP32 exp2, "
-                      "split MFMA accumulation of K V, FP64 partial sums)",
-            "algorithmic_flops_per_launch": flops_mm, "avg_launch_ms": avg_launch_s * 1e3,
-            "launches": calls,
-            "executed_mfma_flops_per_launch": exec_mfma,
-            "executed_mfma_tflops": exec_mfma / avg_launch_s / 1e12,
-            "executed_frac": exec_mfma / avg_launch_s / PEAK_MFMA_F16,
-            "exp_per_s": pairs / avg_launch_s, "exp_peak_per_s": PEAK_EXP,
-            "exp_frac": pairs / avg_launch_s / PEAK_EXP,
-            "timed_with": "HIP events on the library's stream around every product launch"}
-    relres_true = max(max(r.relres_true) for r in reps)
-    iters = [r.iters for r in reps]
+    if args.headline == "pixels":
+        kname = ("matmat_f16pv_bigd_kernel (large d: FP16 hi/lo split MFMA distances with both "
+                 "operands through LDS, FP32 exp2, split MFMA accumulation of K V, FP64 partials)")
+        summary = "traffic_matmat_f16pv_bigd_pixels_n262144.md"
+    else:
+        kname = "matmat_f16pv_kernel (d + 2 <= 128: register-resident row operand)"
+        summary = "traffic_matmat_f16pv_mixture_n65536.md"
+    met = all(tol_met(r, w.tol) for r in reps)
     out = {
-        "metric": "kernel matmat TFLOP/s + time-to-1e-6 residual PCG solve, mixed vs FP64 path",
+        "metric": METRIC,
         "value": calls * flops_mm / wall / 1e12,
         "unit": "TFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f16x3-split MFMA + f32 exp, f64 CG scalars", "data": "synthetic",
-        "config": {"workload": "multi-RHS Gaussian mixture", "n": n, "d": d, "m": m, "s": w.s,
-                   "lambda": w.lam, "sigma": w.sigma, "tol": w.tol, "parallelism": "single GPU"},
+        "config": {"workload": f"{w.name}: n={n} d={d} m={m} s={w.s}", "n": n, "d": d, "m": m,
+                   "s": w.s, "lambda": w.lam, "sigma": w.sigma, "tol": w.tol,
+                   "parallelism": "single GPU"},
         "time_to_tol_mixed_s": wall / args.steps,
-        "iterations": iters,
-        "relres_true_max": relres_true,
-        "kernel_matmat_tflops": flops_mm / avg_launch_s / 1e12,
-        "roofline": roof,
+        "iterations": [r.iters for r in reps],
+        "refine_steps": [r.refine_steps for r in reps],
+        "relres_true_max": max(max(r.relres_true) for r in reps),
+        "tol_met": met,
+        "kernel_matmat_tflops": roofline_of(w, reps, kname, summary)["achieved"],
+        "roofline": roofline_of(w, reps, kname, summary),
     }
     if not args.no_fp64:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        _, r64 = step("fp64")
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t1
-        out["fp64_path"] = {"time_to_tol_s": t64, "iterations": r64.iters,
-                            "relres_true_max": max(r64.relres_true),
-                            "kernel_matmat_tflops": flops_mm * r64.matmat_calls / max(r64.matmat_ms, 1e-9) * 1e-9,
-                            "speedup_mixed_vs_fp64": t64 / (wall / args.steps)}
-        print(f"[bench] fp64 path {t64:.3f} s", file=sys.stderr, flush=True)
-    if not args.no_batched:
-        del X, Y, W, b
+        out["fp64_path"] = fp64_leg(P, args.refine)
+        out["fp64_path"]["speedup_mixed_vs_fp64"] = out["fp64_path"]["time_to_tol_s"] / (wall / args.steps)
+        _log(f"fp64 path {out['fp64_path']['time_to_tol_s']:.3f} s")
+    del P
+    torch.cuda.empty_cache()
+    misses = [] if met else ["headline"]
+    if "fp64_path" in out and not out["fp64_path"]["tol_met"]:
+        misses.append("fp64_path")
+    runners = {"mixture": mixture_run, "plain": plain_run, "ablation": ablation_run,
+               "batched": batched_run, "differentiation": differentiation_run}
+    for leg in [x for x in args.legs.split(",") if x]:
+        if leg == args.headline:
+            continue
+        out[leg] = runners[leg](dev, args)
         torch.cuda.empty_cache()
-        out["batched"] = batched_run(dev)
-        print(f"[bench] batched solve {out['batched']['time_to_tol_s']:.3f} s", file=sys.stderr,
-              flush=True)
-    for extra in args.extra:
-        torch.cuda.empty_cache()
-        out[extra] = pixels_run(dev) if extra == "pixels" else differentiation_run(dev)
-        print(f"[bench] {extra}: {out[extra]}", file=sys.stderr, flush=True)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        _log(f"{leg}: done")
+        res = out[leg]
+        if leg == "ablation":
+            for k in ("lambda_p=lambda", "lambda_p=10lambda"):
+                if not res[k]["tol_met"]:
+                    misses.append(f"ablation.{k}")
+        elif "tol_met" in res and not res["tol_met"]:
+            misses.append(leg)
+        elif leg == "mixture" and "fp64_path" in res and not res["fp64_path"]["tol_met"]:
+            misses.append("mixture.fp64_path")
+    if cpu is not None:
+        fp64 = out.get("fp64_path")
+        prods = fp64["fp64_products"] if fp64 else None
+        cpu["time_to_tol_s_extrapolated"] = (cpu["full_product_s_extrapolated"] * prods
+                                             if prods else None)
+        cpu["time_to_tol_note"] = ("extrapolated: one full oracle product (row-sample rate) "
+                                   "times the products of the FP64-path solve")
+        out["cpu_baseline"] = cpu
+    out["tolerance_misses"] = misses
     print(json.dumps(out), flush=True)
+    if misses:
+        _log(f"tolerance missed: {misses}")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

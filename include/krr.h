@@ -68,7 +68,8 @@ typedef enum krr_op {
   KRR_OP_KERNEL_MATMAT = 2,
   KRR_OP_PCG_SOLVE = 3,
   KRR_OP_GRAD = 4,
-  KRR_OP_PRECOND_APPLY = 5
+  KRR_OP_PRECOND_APPLY = 5,
+  KRR_OP_DSIGMA_INNER = 6
 } krr_op;
 
 /*
@@ -148,7 +149,9 @@ krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu,
  *   X1 : n1 x d FP32 (ldx1 >= d);  X2 : n2 x d FP32 (ldx2 >= d).
  *   V  : n2 x m FP64 (ldv >= m);   OUT: n1 x m FP64 (ldo >= m), must not alias V.
  *   shift : requires n1 == n2 when non-zero (square case: shift = lambda gives (K + lambda I) V).
- *   prec  : a krr_prec. Squared distances are clamped at zero.
+ *   prec  : a krr_prec. Squared distances are not clamped at zero: where rounding leaves one
+ *           slightly negative (coincident points), k comes out slightly above 1, within the
+ *           product's error bound; a NaN coordinate propagates to every output it meets.
  * Asynchronous on `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE.
  */
 krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const float* X2, int64_t n2,
@@ -227,6 +230,29 @@ krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double si
                     const double* alpha, const double* abar, int64_t m, int64_t ld,
                     double* dL_dsigma, double* dL_dlambda, int32_t prec, void* ws, size_t ws_bytes,
                     void* stream);
+
+/*
+ * krr_kernel_dsigma_inner -- the direct sigma-term of a loss that reads a kernel product
+ * (the validation prediction of a differentiated solve):
+ *     out = <G, (dK(X1, X2)/dsigma) V> = sum_ij dk(x1_i, x2_j)/dsigma <G[i, :], V[j, :]>,
+ * with dk/dsigma = k * ||x1_i - x2_j||^2 / sigma^3 (the Sec. 6 Gaussian kernel differentiated
+ * in sigma). It is the term of dL/dsigma that does not pass through the solve; krr_grad
+ * gives the term that does.
+ *   X1 : n1 x d FP32 (ldx1 >= d);  X2 : n2 x d FP32 (ldx2 >= d).
+ *   V  : n2 x m FP64 (ldv >= m);   G  : n1 x m FP64 (ldg >= m).
+ *   out : HOST pointer, receives the FP64 sum.
+ *   prec : a krr_prec for the dK/dsigma product (FP64 recommended: the two sigma-terms of a
+ *          validation loss nearly cancel).
+ * One matrix-free dK/dsigma product (as krr_kernel_matmat with deriv = 1) and an FP64 inner
+ * product with G summed in a fixed order (deterministic). Workspace: krr_workspace_bytes with
+ * KRR_OP_DSIGMA_INNER (n1, n2, d, 0, m, prec). Synchronises `stream`. Errors: KRR_E_ARG,
+ * KRR_E_WORKSPACE.
+ */
+krr_status krr_kernel_dsigma_inner(const float* X1, int64_t n1, int64_t ldx1, const float* X2,
+                                   int64_t n2, int64_t ldx2, int64_t d, double sigma,
+                                   const double* V, int64_t m, int64_t ldv, const double* G,
+                                   int64_t ldg, double* out, int32_t prec, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
  * Batched solves: many independent problems in one plan. Every iteration runs ONE persistent

@@ -14,7 +14,7 @@ KRRSolve:      alpha = (K(X; sigma) + lambda I)^{-1} Y by preconditioned CG (Eq.
 KernelMatmat:  OUT = K(X1, X2; sigma) V (e.g. validation predictions; the loss below runs this
                forward product in FP64 because the validation residual cancels). Backward:
                  dL/dV     = K(X2, X1) G,
-                 dL/dsigma = <G, (dK/dsigma) V>.
+                 dL/dsigma = <G, (dK/dsigma) V>   (krr_kernel_dsigma_inner, FP64 sum).
 All arithmetic runs in libkrr; these classes only route tensors.
 """
 from __future__ import annotations
@@ -67,8 +67,8 @@ class KernelMatmat(torch.autograd.Function):
         X1, X2, V = ctx.saved_tensors
         G = G.contiguous()
         gV = krr.kernel_matmat(X2, X1, ctx.sig, G, prec=ctx.prec)
-        dK = krr.kernel_matmat(X1, X2, ctx.sig, V, deriv=True, prec=ctx.deriv_prec)
-        gs = (G * dK).sum()
+        ds = krr.kernel_dsigma_inner(X1, X2, ctx.sig, V, G, prec=ctx.deriv_prec)
+        gs = torch.tensor(ds, dtype=torch.float64, device=V.device)
         return gs, None, None, gV, None, None, None
 
 

@@ -356,6 +356,20 @@ void layout_apply(Bump& b, ApplyLayout& L, int64_t n, int64_t s, int64_t m) {
   L.z = b.take<double>(n * m);
 }
 
+// <G, (dK(X1, X2)/dsigma) V>: cross product partials, FP32 V copy, the product, partial dots
+struct InnerLayout {
+  MatmatCtx mm;
+  float* vf;
+  double* w;
+  double* part;
+};
+void layout_inner(Bump& b, InnerLayout& L, int64_t n1, int64_t n2, int64_t d, int64_t m, int prec) {
+  layout_matmat(b, L.mm, n1, n2, d, m, prec, false);
+  L.vf = prec != KRR_PREC_FP64 ? b.take<float>(round_up(n2, ROW_PAD) * m) : nullptr;
+  L.w = b.take<double>(n1 * m);
+  L.part = b.take<double>(NBLK * m);
+}
+
 void layout_grad(Bump& b, GradLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
   layout_matmat(b, L.mm, n, n, d, m, prec, true);
   L.af = b.take<float>(round_up(n, ROW_PAD) * m);
@@ -401,6 +415,12 @@ size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_
     case KRR_OP_PCG_SOLVE: { PCGLayout L; layout_pcg(b, L, n1, d, s, m, prec); break; }
     case KRR_OP_GRAD: { GradLayout L; layout_grad(b, L, n1, d, m, prec); break; }
     case KRR_OP_PRECOND_APPLY: { ApplyLayout L; layout_apply(b, L, n1, s, m); break; }
+    case KRR_OP_DSIGMA_INNER: {
+      if (n2 < 1) return 0;
+      InnerLayout L;
+      layout_inner(b, L, n1, n2, d, m, prec);
+      break;
+    }
     default: return 0;
   }
   return b.off + 256;
@@ -882,6 +902,47 @@ krr_status krr_grad(const float* X, int64_t n, int64_t d, int64_t ldx, double si
   for (int64_t e = 0; e < NBLK * m; ++e) { s1 += h[e]; s2 += h[NBLK * m + e]; }
   *dL_dsigma = -s1;
   *dL_dlambda = -s2;
+  return KRR_OK;
+}
+
+// --------------------------------------------------- direct sigma-term of a loss
+krr_status krr_kernel_dsigma_inner(const float* X1, int64_t n1, int64_t ldx1, const float* X2,
+                                   int64_t n2, int64_t ldx2, int64_t d, double sigma,
+                                   const double* V, int64_t m, int64_t ldv, const double* G,
+                                   int64_t ldg, double* out, int32_t prec, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X1 || !X2 || !V || !G || !out) return fail(KRR_E_ARG, "krr_kernel_dsigma_inner: null pointer");
+  if (n1 < 1 || n2 < 1 || d < 1 || m < 1 || ldx1 < d || ldx2 < d || ldv < m || ldg < m)
+    return fail(KRR_E_ARG, "krr_kernel_dsigma_inner: bad sizes or strides");
+  if (!(sigma > 0.0) || !std::isfinite(sigma))
+    return fail(KRR_E_ARG, "krr_kernel_dsigma_inner: sigma must be > 0");
+  if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_kernel_dsigma_inner: unknown precision %d", prec);
+  if (prec == KRR_PREC_BF16X3 && kp_for(d) > 256)
+    return fail(KRR_E_ARG, "krr_kernel_dsigma_inner: BF16X3 supports d <= 254 (d=%lld)", (long long)d);
+  const size_t need = krr_workspace_bytes(KRR_OP_DSIGMA_INNER, n1, n2, d, 0, m, prec);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  Bump bb(ws);
+  InnerLayout L;
+  layout_inner(bb, L, n1, n2, d, m, prec);
+  hipStream_t st = (hipStream_t)stream;
+  CHECK_HIP(prepare_points(L.mm, X1, ldx1, X2, ldx2, sigma, st));
+  // W = (dK/dsigma) V, then <G, W> in FP64
+  if (prec == KRR_PREC_FP64) {
+    CHECK_HIP(run_matmat(L.mm, nullptr, V, ldv, true, st));
+  } else {
+    CHECK_HIP(vec_to_f32(V, n2, m, ldv, round_up(n2, ROW_PAD), m, L.vf, st));
+    CHECK_HIP(run_matmat(L.mm, L.vf, nullptr, m, true, st));
+  }
+  CHECK_HIP(matmat_finalize<double>(L.mm.part, L.mm.part_stride, L.mm.nsplit, n1, m, m, 0.0, V,
+                                    ldv, L.w, m, st));
+  CHECK_HIP(dot_partial<double, double>(G, ldg, L.w, m, n1, m, L.part, NBLK, st));
+  std::vector<double> h(NBLK * m);
+  CHECK_HIP(hipMemcpyAsync(h.data(), L.part, sizeof(double) * NBLK * m, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  double acc = 0.0;
+  for (int64_t e = 0; e < NBLK * m; ++e) acc += h[e];
+  *out = acc;
   return KRR_OK;
 }
 

@@ -6,7 +6,6 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-import math
 import os
 
 import torch
@@ -18,7 +17,8 @@ OK, E_ARG, E_NOT_SPD, E_NO_CONV, E_BREAKDOWN, E_HIP, E_WORKSPACE = range(7)
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_NOT_SPD", 3: "E_NO_CONV", 4: "E_BREAKDOWN",
                 5: "E_HIP", 6: "E_WORKSPACE"}
 PREC = {"fp64": 0, "f16x3": 1, "bf16x3": 2}
-OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD, OP_PRECOND_APPLY = range(6)
+(OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD, OP_PRECOND_APPLY,
+ OP_DSIGMA_INNER) = range(7)
 
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -101,6 +101,10 @@ def lib():
     L.krr_grad.restype = _i32
     L.krr_grad.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64,
                            ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _i32, _vp, _sz, _vp]
+    L.krr_kernel_dsigma_inner.restype = _i32
+    L.krr_kernel_dsigma_inner.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _vp, _i64,
+                                          _i64, _vp, _i64, ctypes.POINTER(_dbl), _i32, _vp, _sz,
+                                          _vp]
     L.krr_batch_plan_create.restype = _i32
     L.krr_batch_plan_create.argtypes = [ctypes.POINTER(BatchProblem), _i32,
                                         ctypes.POINTER(PCGOpts), ctypes.POINTER(_vp), _vp]
@@ -115,7 +119,7 @@ def lib():
 EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_defaults",
             "krr_features", "krr_precond_factor", "krr_precond_apply", "krr_kernel_matmat",
             "krr_pcg_solve",
-            "krr_grad", "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
+            "krr_grad", "krr_kernel_dsigma_inner", "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
 
 
 def last_error() -> str:
@@ -331,6 +335,31 @@ def grad(X: torch.Tensor, sigma: float, alpha: torch.Tensor, abar: torch.Tensor,
     return ds.value, dl.value
 
 
+def kernel_dsigma_inner(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Tensor,
+                        G: torch.Tensor, prec="fp64") -> float:
+    """<G, (dK(X1, X2)/dsigma) V> in FP64 (the direct sigma-term of a loss on K(X1, X2) V)."""
+    _check(X1, torch.float32, "X1")
+    _check(X2, torch.float32, "X2")
+    V2 = V[:, None] if V.dim() == 1 else V
+    G2 = G[:, None] if G.dim() == 1 else G
+    _check(V2, torch.float64, "V")
+    _check(G2, torch.float64, "G")
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    m = V2.shape[1]
+    if X2.shape[1] != d or V2.shape[0] != n2 or tuple(G2.shape) != (n1, m):
+        raise ValueError("shape mismatch")
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_DSIGMA_INNER, n1, n2, d, 0, m, p), X1.device)
+    out = _dbl(0.0)
+    st = lib().krr_kernel_dsigma_inner(X1.data_ptr(), n1, _ld(X1), X2.data_ptr(), n2, _ld(X2), d,
+                                       float(sigma), V2.data_ptr(), m, _ld(V2), G2.data_ptr(),
+                                       _ld(G2), ctypes.byref(out), p, ws.data_ptr(), ws.numel(),
+                                       _stream())
+    _raise(st)
+    return out.value
+
+
 @dataclasses.dataclass
 class BatchSolveReport:
     status: int
@@ -431,6 +460,3 @@ class BatchPlan:
         except Exception:
             pass
 
-
-def rff_scale(s: int) -> float:
-    return math.sqrt(2.0 / s)

@@ -103,6 +103,27 @@ def test_argument_validation_before_device_work():
     assert st == krr.E_ARG and "254" in krr.last_error()
 
 
+def test_dsigma_inner_validation_before_device_work():
+    L = krr.lib()
+    fake = ctypes.c_void_p(256)
+    out = ctypes.c_double(7.0)
+    st = L.krr_kernel_dsigma_inner(None, 10, 3, fake, 12, 3, 3, 1.0, fake, 2, 2, fake, 2,
+                                   ctypes.byref(out), 0, fake, 1 << 30, None)
+    assert st == krr.E_ARG and "null" in krr.last_error()
+    st = L.krr_kernel_dsigma_inner(fake, 10, 3, fake, 12, 3, 3, -1.0, fake, 2, 2, fake, 2,
+                                   ctypes.byref(out), 0, fake, 1 << 30, None)
+    assert st == krr.E_ARG and "sigma" in krr.last_error()
+    st = L.krr_kernel_dsigma_inner(fake, 10, 3, fake, 12, 3, 3, 1.0, fake, 2, 1, fake, 2,
+                                   ctypes.byref(out), 0, fake, 1 << 30, None)
+    assert st == krr.E_ARG
+    st = L.krr_kernel_dsigma_inner(fake, 10, 3, fake, 12, 3, 3, 1.0, fake, 2, 2, fake, 2,
+                                   ctypes.byref(out), 0, fake, 64, None)
+    assert st == krr.E_WORKSPACE and out.value == 7.0
+    a = krr.workspace_bytes(krr.OP_DSIGMA_INNER, 1000, 3000, 54, 0, 7, 0)
+    b = krr.workspace_bytes(krr.OP_DSIGMA_INNER, 1000, 6000, 54, 0, 7, 0)
+    assert 0 < a < b
+
+
 def test_python_binding_rejects_host_tensors():
     import torch
     with pytest.raises(TypeError):

@@ -1,0 +1,211 @@
+"""GPU parity on the method's degenerate cases, on the direct sigma-term of a loss, and on
+the preconditioner factor at sizes whose launch shapes the small cases never take.
+
+Bounds follow the arithmetic of each path (see the module docstring of test_gpu_parity):
+the mixed product is bounded per entry by tau (|K| |V|), the FP64 product by 1e-12 (|K| |V|),
+solves by the condition number times the residual tolerance.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1611_03220_amd import krr
+from paper_1611_03220_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+LN2 = math.log(2.0)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    krr.lib()
+    return torch.device("cuda:0")
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _tau(prec, X1, X2, sigma, d):
+    if prec == "fp64":
+        return 1e-12
+    kp = int(math.ceil((d + 2) / 32) * 32)
+    c = math.log2(math.e) / (2 * sigma * sigma)
+    nu = max(float((X1.astype(np.float64) ** 2).sum(1).max()),
+             float((X2.astype(np.float64) ** 2).sum(1).max()))
+    return LN2 * (2 * 2.0 ** -22 + kp * 2.0 ** -24) * 4 * c * nu + 2.0 ** -22 + 16 * 2.0 ** -24
+
+
+# ------------------------------------------------------- direct sigma-term of a loss
+@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
+def test_kernel_dsigma_inner_cross(dev, prec):
+    """<G, (dK(X1, X2)/dsigma) V> with X1 != X2 (the validation term of dL/dsigma) against
+    the oracle's dense dK/dsigma. Bound: the per-entry bound of the dK/dsigma product (as in
+    the derivative parity test) summed against |G|."""
+    rng = np.random.default_rng(41)
+    n1, n2, d, m = 300, 517, 54, 7
+    X1 = (1.2 * rng.standard_normal((n1, d))).astype(np.float32)
+    X2 = rng.standard_normal((n2, d)).astype(np.float32)
+    V = rng.standard_normal((n2, m))
+    G = rng.standard_normal((n1, m))
+    sigma = 0.8 * math.sqrt(d)
+    got = krr.kernel_dsigma_inner(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), _t(G, dev), prec=prec)
+    dK = O.gaussian_kernel_dsigma(X1, X2, sigma)
+    ref = float(np.sum(G * (dK @ V)))
+    D = O.sq_dists(X1, X2)
+    Kd = np.exp(-D / (2 * sigma ** 2))
+    tau = _tau(prec, X1, X2, sigma, d)
+    c = math.log2(math.e) / (2 * sigma ** 2)
+    extra = (tau / LN2) / c * Kd / sigma ** 3 if prec != "fp64" else 1e-12 * Kd * (1 + D) / sigma ** 3
+    entry = tau * (np.abs(dK) @ np.abs(V)) + extra @ np.abs(V)
+    bound = float(np.sum(np.abs(G) * entry)) + 1e-13 * abs(ref)
+    assert abs(got - ref) <= bound, (got, ref, bound)
+
+
+def test_kernel_dsigma_inner_feeds_autograd(dev):
+    """KernelMatmat.backward routes the sigma-gradient through the library call: a loss
+    on K(X1, X2) V differentiated by autograd equals the oracle's <G, dK/dsigma V>."""
+    from paper_1611_03220_amd import autograd as KA
+    rng = np.random.default_rng(42)
+    X1 = rng.standard_normal((120, 6)).astype(np.float32)
+    X2 = rng.standard_normal((210, 6)).astype(np.float32)
+    V = rng.standard_normal((210, 3))
+    Yt = rng.standard_normal((120, 3))
+    s0 = 2.2
+    sig = torch.tensor(s0, dtype=torch.float64, device=dev, requires_grad=True)
+    out = KA.kernel_matmat(_t(X1, dev), _t(X2, dev), sig, _t(V, dev), prec="fp64")
+    loss = 0.5 * ((out - _t(Yt, dev)) ** 2).sum()
+    loss.backward()
+    R = O.kernel_matmat(X1, X2, s0, V) - Yt
+    ref = float(np.sum(R * O.kernel_matmat(X1, X2, s0, V, deriv=True)))
+    assert float(sig.grad) == pytest.approx(ref, rel=1e-10)
+
+
+# ------------------------------------------------------------ degenerate kernels
+@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
+def test_solve_sigma_to_zero_is_identity(dev, prec):
+    """sigma -> 0: every off-diagonal kernel value underflows, K = I, and the solve is
+    c = y / (1 + lambda) (the oracle pins the same closed form). sigma is set from the data
+    so that the closest pair has k < e^-40; smaller sigma would only amplify the rounding of
+    the diagonal's zero distance (by c nu, see the product bound). Plain CG on (1 + lambda) I
+    converges in one step; the preconditioned solve reaches the same point."""
+    w = WL.plain_fp64(n=1500, d=8, s=96)
+    D = O.sq_dists(w.X, w.X)
+    np.fill_diagonal(D, np.inf)
+    sigma, lam = math.sqrt(D.min() / 80.0), 0.7
+    assert np.exp(-D.min() / (2 * sigma ** 2)) < 1e-17
+    X, Y = _t(w.X, dev), _t(w.Y, dev)
+    ref = w.Y / (1.0 + lam)
+    a, rep = krr.pcg_solve(X, sigma, lam, None, Y, tol=1e-10, prec=prec, use_precond=False,
+                           refine=6)
+    np.testing.assert_allclose(a.cpu().numpy(), ref, rtol=1e-9, atol=0)
+    if prec == "fp64":
+        assert rep.iters <= 2
+    W = torch.from_numpy(np.ascontiguousarray(w.W * (math.sqrt(8) / sigma))).to(dev)
+    Z = krr.features(X, W, _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, lam)
+    a, rep = krr.pcg_solve(X, sigma, lam, Ut, Y, tol=1e-10, prec=prec, refine=6)
+    np.testing.assert_allclose(a.cpu().numpy(), ref, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
+def test_solve_sigma_to_infinity_sherman_morrison(dev, prec):
+    """sigma -> infinity: K -> 1 1^T and c = (y - 1 (1^T y) / (n + lambda)) / lambda
+    (Sherman-Morrison). At sigma = 1e7 every kernel value is within D / (2 sigma^2) < 1e-12
+    of 1, which moves c by less than n 1e-12 / lambda relative."""
+    w = WL.plain_fp64(n=1200, d=4, s=64)
+    sigma, lam = 1e7, 1.0
+    X, Y = _t(w.X, dev), _t(w.Y, dev)
+    a, rep = krr.pcg_solve(X, sigma, lam, None, Y, tol=1e-10, prec=prec, use_precond=False,
+                           refine=4)
+    y = w.Y
+    ref = (y - y.sum(0, keepdims=True) / (w.n + lam)) / lam
+    kappa = (w.n + lam) / lam
+    err = np.linalg.norm(a.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= kappa * 1e-10 + w.n * 1e-12 / lam, err
+    if prec == "fp64":
+        assert rep.iters <= 3
+
+
+@pytest.mark.parametrize("prec", ["f16x3", "fp64"])
+def test_matmat_duplicate_and_zero_points(dev, prec):
+    """Repeated points (distance exactly zero off the diagonal: k = 1) and all-zero points
+    (nu = 0) in both operands; per-entry bound as in the parity suite."""
+    rng = np.random.default_rng(43)
+    X2 = rng.standard_normal((400, 30)).astype(np.float32)
+    X2[100:140] = X2[7]          # forty copies of one point
+    X2[200:232] = 0.0            # all-zero rows
+    X2[399] = X2[0]              # last row of the ragged tail repeats the first
+    X1 = np.concatenate([X2[:50], np.zeros((3, 30), np.float32), X2[120:130]])
+    V = rng.standard_normal((400, 5))
+    sigma = 4.0
+    got = krr.kernel_matmat(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), prec=prec).cpu().numpy()
+    K = O.gaussian_kernel(X1, X2, sigma)
+    ref = K @ V
+    bound = _tau(prec, X1, X2, sigma, 30) * (np.abs(K) @ np.abs(V))
+    assert np.all(np.abs(got - ref) <= bound), np.max(np.abs(got - ref) / bound)
+    # square product with shift on the duplicated set
+    got = krr.kernel_matmat(_t(X2, dev), _t(X2, dev), sigma, _t(V, dev), shift=0.5, prec=prec)
+    K = O.gaussian_kernel(X2, X2, sigma)
+    ref = K @ V + 0.5 * V
+    bound = _tau(prec, X2, X2, sigma, 30) * (np.abs(K) @ np.abs(V)) + 1e-15 * np.abs(V)
+    assert np.all(np.abs(got.cpu().numpy() - ref) <= bound)
+
+
+# --------------------------------------------------- preconditioner factor sizes
+def _factor_checks(Z, lam, C, Ut, ntest=2):
+    """Backward error of C against the FP64 Gram, the solve C Ut^T = Z^T, and the Woodbury
+    operator applied to (Z Z^T + lam I) w returning w. kappa(Z Z^T + lam I) comes from the
+    s x s Gram's extreme eigenvalue, so nothing n x n is formed."""
+    n, s = Z.shape
+    Z64 = Z.astype(np.float64)
+    G = Z64.T @ Z64 + lam * np.eye(s)
+    assert np.allclose(np.triu(C, 1), 0) and (np.diag(C) > 0).all()
+    back = np.linalg.norm(C @ C.T - G) / np.linalg.norm(G)
+    assert back <= 4 * (2 * 2.0 ** -22 + math.sqrt(n) * 2.0 ** -24), back
+    rel = np.linalg.norm(C @ Ut.T - Z64.T) / np.linalg.norm(Z64)
+    assert rel <= 8 * (2 * 2.0 ** -22 + math.sqrt(s) * 2.0 ** -24) * np.linalg.cond(C), rel
+    kappa = (np.linalg.eigvalsh(G).max()) / lam
+    w = np.random.default_rng(1).standard_normal((n, ntest))
+    u = Z64 @ (Z64.T @ w) + lam * w
+    got = (u - Ut @ (Ut.T @ u)) / lam
+    err = np.linalg.norm(got - w) / np.linalg.norm(w)
+    assert err <= kappa * 8 * back + 1e-12, (err, kappa, back)
+    return back, kappa
+
+
+def test_precond_factor_xcd_ordered_gram(dev):
+    """n = 16384, s = 1024: the Gram grid (36 lower tiles x 8 k splits = 288 blocks, a
+    multiple of 8) takes the XCD-remapped block order."""
+    rng = np.random.default_rng(44)
+    n, d, s, lam = 16384, 16, 1024, 1.64
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Wf = (rng.standard_normal((d, s)) / 4.0).astype(np.float32)
+    b = rng.uniform(0, 2 * np.pi, s).astype(np.float32)
+    Z = krr.features(_t(X, dev), _t(Wf, dev), _t(b, dev))
+    C, Ut = krr.precond_factor(Z, lam)
+    _factor_checks(Z.cpu().numpy(), lam, C.cpu().numpy(), Ut.cpu().numpy().astype(np.float64))
+
+
+def test_precond_factor_benchmark_size(dev):
+    """The benchmark's factor (n = 65536, s = 2048) against the oracle's precond_factor on
+    the same Z: backward error of C, the triangular relation, and the Woodbury action of the
+    GPU's Ut against the oracle's U on random vectors."""
+    w = WL.mixture_multi_rhs()
+    Z = krr.features(_t(w.X, dev), _t(w.W, dev), _t(w.b, dev))
+    C, Ut = krr.precond_factor(Z, w.lam)
+    Zh = Z.cpu().numpy()
+    Cg, Ug = C.cpu().numpy(), Ut.cpu().numpy().astype(np.float64)
+    back, kappa = _factor_checks(Zh, w.lam, Cg, Ug)
+    Co, Uo = O.precond_factor(Zh.astype(np.float64), w.lam)
+    v = np.random.default_rng(2).standard_normal((w.n, 2))
+    ref = O.precond_apply(Uo, w.lam, v)
+    got = (v - Ug @ (Ug.T @ v)) / w.lam
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= kappa * 8 * back + 1e-12
+    assert np.linalg.norm(Cg - Co) / np.linalg.norm(Co) <= np.linalg.cond(Co) * 8 * back

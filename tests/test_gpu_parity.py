@@ -335,10 +335,26 @@ def test_pcg_full_size_sampled(dev):
     alpha, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=1e-6, refine=2)
     assert max(rep.relres_true) <= 1e-6
     a = alpha.cpu().numpy()
-    rows = np.sort(np.random.default_rng(3).choice(w.n, 48, replace=False))
-    r_or = w.Y[rows] - O.kernel_matmat(w.X, w.X, w.sigma, a, shift=w.lam, rows=rows)
-    # the residual is spread over all rows: the sampled ratio estimates the full one
-    est = np.linalg.norm(r_or, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
+    rows = np.sort(np.random.default_rng(3).choice(w.n, 256, replace=False))
+    rows[-1] = w.n - 1
+    _check_fp64_residual(X, w, alpha, a, rows, rep, dev)
+
+
+def _check_fp64_residual(X, w, alpha, a, rows, rep, dev, Kr=None):
+    """The library's FP64 residual, element by element: its FP64 product (K + lambda I) alpha
+    on the sampled rows equals the oracle's within 1e-12 (|K| |alpha| + lambda |alpha|), and
+    the per-column norm of Y - (K + lambda I) alpha over all rows, formed from that product,
+    is the relres_true the solve reported."""
+    prod = krr.kernel_matmat(X, X, w.sigma, alpha, shift=w.lam, prec="fp64").cpu().numpy()
+    if Kr is None:
+        Kr = O.gaussian_kernel(w.X[rows], w.X, w.sigma)
+    ref = Kr @ a + w.lam * a[rows]
+    bound = 1e-12 * (np.abs(Kr) @ np.abs(a) + w.lam * np.abs(a[rows]))
+    assert np.all(np.abs(prod[rows] - ref) <= bound), np.max(np.abs(prod[rows] - ref) / bound)
+    rel = np.linalg.norm(w.Y - prod, axis=0) / np.linalg.norm(w.Y, axis=0)
+    np.testing.assert_allclose(rel, rep.relres_true, rtol=1e-8)
+    # the oracle's own residual on the sampled rows, as a norm estimate
+    est = np.linalg.norm(w.Y[rows] - ref, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
     assert est.max() <= 4e-6, est
 
 
@@ -505,7 +521,8 @@ def test_pixels_full_size_sampled(dev):
     residual on sampled rows confirms."""
     w = WL.pixels()
     X, Y = _t(w.X, dev), _t(w.Y, dev)
-    rows = np.sort(np.random.default_rng(11).choice(w.n, 24, replace=False))
+    rows = np.sort(np.random.default_rng(11).choice(w.n, 40, replace=False))
+    rows[-1] = w.n - 1
     V = np.random.default_rng(12).standard_normal((w.n, w.m))
     got = krr.kernel_matmat(X, X, w.sigma, _t(V, dev)).cpu().numpy()[rows]
     Kr = O.gaussian_kernel(w.X[rows], w.X, w.sigma)
@@ -518,9 +535,7 @@ def test_pixels_full_size_sampled(dev):
     alpha, rep = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=1e-6, refine=3)
     assert max(rep.relres_true) <= 1e-6
     a = alpha.cpu().numpy()
-    r = w.Y[rows] - (Kr @ a + w.lam * a[rows])
-    est = np.linalg.norm(r, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
-    assert est.max() <= 4e-6, est
+    _check_fp64_residual(X, w, alpha, a, rows, rep, dev, Kr=Kr)
 
 
 def test_differentiation_full_size_central_differences(dev):
