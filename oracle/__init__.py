@@ -6,3 +6,4 @@ and its Python binding) never imports, calls or links anything here, and nothing
 imports the product path.
 """
 from .krr_oracle import *  # noqa: F401,F403
+from . import sketch_oracle  # noqa: F401
