@@ -88,6 +88,11 @@ def test_kernel_dsigma_inner_feeds_autograd(dev):
 
 
 # ------------------------------------------------------------ degenerate kernels
+def _relerr(a, ref):
+    return float(np.linalg.norm(a.cpu().numpy() - ref) / np.linalg.norm(ref))
+
+
+
 @pytest.mark.parametrize("prec", ["fp64", "f16x3"])
 def test_solve_sigma_to_zero_is_identity(dev, prec):
     """sigma -> 0: every off-diagonal kernel value underflows, K = I, and the solve is
@@ -104,14 +109,17 @@ def test_solve_sigma_to_zero_is_identity(dev, prec):
     ref = w.Y / (1.0 + lam)
     a, rep = krr.pcg_solve(X, sigma, lam, None, Y, tol=1e-10, prec=prec, use_precond=False,
                            refine=6)
-    np.testing.assert_allclose(a.cpu().numpy(), ref, rtol=1e-9, atol=0)
+    # with A = (1 + lambda) I the residual rule bounds the error in norm: ||c - c*|| =
+    # ||r|| / (1 + lambda) <= tol ||y|| / (1 + lambda) = tol ||c*|| (small entries of c may
+    # carry a larger relative error)
+    assert _relerr(a, ref) <= 1e-10 * (1 + 1e-3), _relerr(a, ref)
     if prec == "fp64":
         assert rep.iters <= 2
     W = torch.from_numpy(np.ascontiguousarray(w.W * (math.sqrt(8) / sigma))).to(dev)
     Z = krr.features(X, W, _t(w.b, dev))
     _, Ut = krr.precond_factor(Z, lam)
     a, rep = krr.pcg_solve(X, sigma, lam, Ut, Y, tol=1e-10, prec=prec, refine=6)
-    np.testing.assert_allclose(a.cpu().numpy(), ref, rtol=1e-9, atol=0)
+    assert _relerr(a, ref) <= 1e-10 * (1 + 1e-3), _relerr(a, ref)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "f16x3"])
