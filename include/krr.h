@@ -254,6 +254,28 @@ krr_status krr_kernel_dsigma_inner(const float* X1, int64_t n1, int64_t ldx1, co
                                    int64_t ldg, double* out, int32_t prec, void* ws,
                                    size_t ws_bytes, void* stream);
 
+/*
+ * krr_kernel_matmat_noalloc -- krr_kernel_matmat without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same arguments, semantics, arithmetic and kernels as
+ * krr_kernel_matmat, minus ws / ws_bytes.
+ * Scratch space: a fixed device array of KRR_NOALLOC_SCRATCH_BYTES inside the library, one
+ * per GPU, created when the library's code is loaded on that GPU and held until the process
+ * ends; the call itself allocates nothing. Problems whose krr_workspace_bytes(
+ * KRR_OP_KERNEL_MATMAT, n1, n2, d, 0, m, prec) exceeds that size are rejected with
+ * KRR_E_WORKSPACE (for example F16X3, d <= 128, m <= 16 fits up to about n1 = n2 = 16384).
+ * Every call on one GPU shares that GPU's array and leaves its contents behind (nothing in it
+ * needs to start at zero): calls that overlap on one GPU, from different streams or threads,
+ * race on it and must be serialised by the caller. Asynchronous on `stream`. Errors:
+ * KRR_E_ARG, KRR_E_WORKSPACE (too large), KRR_E_HIP (the scratch address lookup failed).
+ */
+#define KRR_NOALLOC_SCRATCH_BYTES (64ll << 20)
+krr_status krr_kernel_matmat_noalloc(const float* X1, int64_t n1, int64_t ldx1, const float* X2,
+                                     int64_t n2, int64_t ldx2, int64_t d, double sigma,
+                                     double shift, const double* V, int64_t m, int64_t ldv,
+                                     double* OUT, int64_t ldo, int32_t deriv, int32_t prec,
+                                     void* stream);
+
 /* ----------------------------------------------------------------------------------------
  * Batched solves: many independent problems in one plan. Every iteration runs ONE persistent
  * kernel-product launch over a work queue of (problem, 128-row block, column range) items for

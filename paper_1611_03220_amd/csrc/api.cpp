@@ -379,6 +379,10 @@ void layout_grad(Bump& b, GradLayout& L, int64_t n, int64_t d, int64_t m, int pr
 
 }  // namespace
 
+namespace krr {
+krr_status report_error(krr_status code, const char* msg) { return fail(code, "%s", msg); }
+}  // namespace krr
+
 // =================================================================== C ABI
 extern "C" {
 

@@ -1,6 +1,7 @@
 // Internal launcher declarations of libkrr (not part of the C ABI).
 #pragma once
 #include <algorithm>
+#include "../../include/krr.h"
 #include "common.hpp"
 
 namespace krr {
@@ -156,5 +157,9 @@ hipError_t add2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n
 hipError_t precond_apply(const float* Ut, int64_t ldu, int64_t n, int64_t s, int64_t m,
                          double lambda_p, const double* r, double* z, double* part, int nchunk,
                          double* T, hipStream_t st);
+
+// Record `msg` as the calling thread's krr_last_error() text and return `code` (entry points
+// defined outside the main ABI source report through it).
+krr_status report_error(krr_status code, const char* msg);
 
 }  // namespace krr

@@ -101,6 +101,9 @@ def lib():
     L.krr_grad.restype = _i32
     L.krr_grad.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64,
                            ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _i32, _vp, _sz, _vp]
+    L.krr_kernel_matmat_noalloc.restype = _i32
+    L.krr_kernel_matmat_noalloc.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _dbl,
+                                            _vp, _i64, _i64, _vp, _i64, _i32, _i32, _vp]
     L.krr_kernel_dsigma_inner.restype = _i32
     L.krr_kernel_dsigma_inner.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _vp, _i64,
                                           _i64, _vp, _i64, ctypes.POINTER(_dbl), _i32, _vp, _sz,
@@ -119,7 +122,9 @@ def lib():
 EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_defaults",
             "krr_features", "krr_precond_factor", "krr_precond_apply", "krr_kernel_matmat",
             "krr_pcg_solve",
-            "krr_grad", "krr_kernel_dsigma_inner", "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
+            "krr_grad", "krr_kernel_dsigma_inner", "krr_kernel_matmat_noalloc",
+            "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
+NOALLOC_SCRATCH_BYTES = 64 << 20   # KRR_NOALLOC_SCRATCH_BYTES
 
 
 def last_error() -> str:
@@ -243,6 +248,32 @@ def kernel_matmat(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Ten
                                  ws.numel(), _stream())
     _raise(st)
     return out[:, 0] if vec else out
+
+
+def kernel_matmat_noalloc(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Tensor,
+                          out: torch.Tensor, shift: float = 0.0, deriv: bool = False,
+                          prec="f16x3") -> torch.Tensor:
+    """kernel_matmat through the allocation-free entry point: the library's fixed per-GPU
+    scratch array instead of a workspace; `out` (n1 x m FP64) is caller-provided, so this
+    call allocates no device memory."""
+    _check(X1, torch.float32, "X1")
+    _check(X2, torch.float32, "X2")
+    vec = V.dim() == 1
+    V2 = V[:, None] if vec else V
+    O2 = out[:, None] if out.dim() == 1 else out
+    _check(V2, torch.float64, "V")
+    _check(O2, torch.float64, "out")
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    m = V2.shape[1]
+    if X2.shape[1] != d or V2.shape[0] != n2 or tuple(O2.shape) != (n1, m):
+        raise ValueError("shape mismatch")
+    st = lib().krr_kernel_matmat_noalloc(X1.data_ptr(), n1, _ld(X1), X2.data_ptr(), n2, _ld(X2),
+                                         d, float(sigma), float(shift), V2.data_ptr(), m, _ld(V2),
+                                         O2.data_ptr(), _ld(O2), int(bool(deriv)), _prec(prec),
+                                         _stream())
+    _raise(st)
+    return out
 
 
 @dataclasses.dataclass
