@@ -46,7 +46,8 @@ BIGD_KERNEL = ("matmat_f16pv_bigd_kernel (large d: FP16 hi/lo split MFMA distanc
                "operands through LDS, FP32 exp2, split MFMA accumulation of K V, FP64 partials)")
 SMALLD_KERNEL = ("matmat_f16pv_kernel (d + 2 <= 128: register-resident row operand, FP16 hi/lo "
                  "split MFMA distances, FP32 exp2, split MFMA accumulation of K V)")
-LEGS = ["mixture", "pixels", "plain", "ablation", "batched", "differentiation"]
+LEGS = ["mixture", "pixels", "plain", "ablation", "batched", "differentiation", "polynomial",
+        "multilevel", "adaptive"]
 
 
 def parse():
@@ -64,6 +65,7 @@ def parse():
     ap.add_argument("--calib-bytes", type=int, default=0,
                     help="run a plain device copy of this many bytes (counter calibration)")
     ap.add_argument("--refine", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch rule")
     return ap.parse_args()
 
 
@@ -226,20 +228,128 @@ def pixels_run(dev, args):
     """The pixels workload (n = 262144, d = 784, m = 10, s = 8192) to 1e-6: one warm-up and
     one timed solve, the roofline of its large-d kernel product and its FP64 path."""
     from paper_1611_03220_amd import workloads as WL
+    from paper_1611_03220_amd import krr
     P = Problem(WL.pixels(), dev)
-    reps, wall = timed_steps(P, 1, 1, args.refine)
     w = P.w
+    tune = krr.autotune_matmat(krr.Kernel.gaussian(w.sigma), P.X, w.m) if not args.no_tune else None
+    reps, wall = timed_steps(P, 1, 1, args.refine)
     out = {"workload": f"pixels n={w.n} d={w.d} m={w.m} s={w.s}",
            "ms_per_step": wall * 1e3, "time_to_tol_mixed_s": wall,
            "iterations": [r.iters for r in reps], "refine_steps": [r.refine_steps for r in reps],
            "relres_true_max": max(max(r.relres_true) for r in reps),
            "tol_met": all(tol_met(r, w.tol) for r in reps),
            "value_tflops": sum(r.matmat_calls for r in reps) * 2.0 * w.n * w.n * (w.d + w.m) / wall / 1e12,
-           "roofline": roofline_of(w, reps, BIGD_KERNEL, "traffic_matmat_f16pv_bigd_pixels_n262144.md")}
+           "roofline": roofline_of(w, reps, BIGD_KERNEL, "traffic_matmat_f16pv_bigd_pixels_n262144.md"),
+           "autotune": tune.as_dict() if tune is not None else None}
     if not args.no_fp64:
         out["fp64_path"] = fp64_leg(P, args.refine)
         out["fp64_path"]["speedup_mixed_vs_fp64"] = out["fp64_path"]["time_to_tol_s"] / wall
     return out
+
+
+def polynomial_run(dev, args):
+    """Polynomial kernel (x^T z / d + 1)^3 on the mixture points (n = 65536, d = 54, m = 7) with
+    s = 2048 TensorSketch features (Sec. 2.2, Thm. 1; the paper's polynomial experiments,
+    Sec. 6): features, factor and mixed PCG to 1e-6 (one warm-up, one timed solve), the
+    roofline of the polynomial kernel product, the FP64 path, and plain CG for comparison."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+    w = WL.polynomial_mixture()
+    X = torch.from_numpy(w.X).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+    h, g = torch.from_numpy(w.hash).to(dev), torch.from_numpy(w.sign).to(dev)
+    k = krr.Kernel.polynomial(w.gamma, w.coef0, w.degree)
+
+    def solve(prec, use_precond=True):
+        Ut = None
+        if use_precond:
+            Z = krr.tensorsketch(X, w.gamma, w.coef0, w.degree, h, g, w.s)
+            _, Ut = krr.precond_factor(Z, w.lam)
+            del Z
+        return krr.pcg_solve_k(k, X, w.lam, Ut, Y, tol=w.tol, prec=prec, refine=args.refine,
+                               use_precond=use_precond, raise_on_error=False)
+
+    solve("f16x3")
+    t0 = _sync_time()
+    _, rep = solve("f16x3")
+    wall = _sync_time() - t0
+    out = {"workload": f"polynomial (x^T z/{w.d} + 1)^{w.degree} on mixture n={w.n} d={w.d} "
+                       f"m={w.m} s={w.s} TensorSketch",
+           **solve_summary(rep, wall, w.tol, w),
+           "roofline": roofline_of(w, [rep], "matmat_f16pv_kernel, polynomial epilogue",
+                                   "traffic_matmat_f16pv_poly_mixture_n65536.md")}
+    if not args.no_fp64:
+        t0 = _sync_time()
+        _, r64 = solve("fp64")
+        out["fp64_path"] = solve_summary(r64, _sync_time() - t0, w.tol, w)
+    t0 = _sync_time()
+    _, rpl = solve("f16x3", use_precond=False)
+    out["no_preconditioner"] = solve_summary(rpl, _sync_time() - t0, w.tol, w)
+    return out
+
+
+def multilevel_run(dev, args):
+    """Multiple-level sketching (Alg. 2, Thm. 3) on the mixture workload: s1 = 8192 random
+    Fourier features, an SRHT to s2 = 4096 and a Gaussian projection to s3 = 2048, then the
+    factor and mixed PCG to 1e-6; beside it the one-level s = 2048 and s = 8192 sketches."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+    s1, s2, s3 = 8192, 4096, 2048
+    w = WL.mixture_multi_rhs(s=s1)
+    signs, sample, S3 = WL.multilevel_draw(s1, s2, s3, WL.rng_for(1, 5))
+    X = torch.from_numpy(w.X).to(dev)
+    Y = torch.from_numpy(np.ascontiguousarray(w.Y)).to(dev)
+    W, b = torch.from_numpy(w.W).to(dev), torch.from_numpy(w.b).to(dev)
+    tsg, tsm, tS3 = (torch.from_numpy(signs).to(dev), torch.from_numpy(sample).to(dev),
+                     torch.from_numpy(S3).to(dev))
+
+    def three_level():
+        Z1 = krr.features(X, W, b)
+        Z3 = krr.gaussian_project(krr.srht(Z1, tsg, tsm), tS3)
+        del Z1
+        _, Ut = krr.precond_factor(Z3, w.lam)
+        return krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, prec="f16x3",
+                             refine=args.refine, raise_on_error=False)
+
+    def one_level(s):
+        Z = krr.features(X, W[:, :s].contiguous(), b[:s].contiguous())
+        _, Ut = krr.precond_factor(Z, w.lam)
+        del Z
+        return krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=w.tol, prec="f16x3",
+                             refine=args.refine, raise_on_error=False)
+
+    out = {"workload": f"Gaussian mixture n={w.n} d={w.d} m={w.m}: RFF s1={s1} -> SRHT s2={s2} "
+                       f"-> Gaussian s3={s3}"}
+    for name, fn in (("three_level", three_level), ("one_level_s2048", lambda: one_level(2048)),
+                     ("one_level_s8192", lambda: one_level(8192))):
+        fn()
+        t0 = _sync_time()
+        _, rep = fn()
+        out[name] = solve_summary(rep, _sync_time() - t0, w.tol, w)
+    return out
+
+
+def adaptive_run(dev, args):
+    """Adaptive sketch size (Sec. 5, Thm. 4) on the polynomial workload: TensorSketch sizes
+    double from 256 until the preconditioner test passes or s reaches 2048."""
+    import numpy as np
+    import torch
+    from paper_1611_03220_amd import krr
+    from paper_1611_03220_amd import workloads as WL
+    w = WL.polynomial_mixture(s=4096)
+    X = torch.from_numpy(w.X).to(dev)
+    k = krr.Kernel.polynomial(w.gamma, w.coef0, w.degree)
+    h, g = torch.from_numpy(w.hash).to(dev), torch.from_numpy(w.sign).to(dev)
+    t0 = _sync_time()
+    _, s, hist = krr.adaptive_features(k, X, w.lam, 256, 2048, hash_=h, sign=g, power_iters=30)
+    return {"workload": f"polynomial mixture n={w.n} d={w.d}, TensorSketch s from 256 to 2048",
+            "chosen_s": s, "time_s": _sync_time() - t0,
+            "history": [{k2: (round(v, 6) if isinstance(v, float) else v) for k2, v in hh.items()}
+                        for hh in hist]}
 
 
 def plain_run(dev, args):
@@ -427,6 +537,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     P = Problem(w, dev)
+    # the product's launch choice for this shape, by timing candidates (stored in the
+    # library's tuning table and used by every product of the timed steps)
+    tune = krr.autotune_matmat(krr.Kernel.gaussian(w.sigma), P.X, w.m) if not args.no_tune else None
     torch.cuda.synchronize()
     reps, wall = timed_steps(P, args.steps, args.warmup, args.refine)
     _log(f"timed {args.steps} {args.headline} steps in {wall:.3f} s")
@@ -456,6 +569,7 @@ def main():
         "tol_met": met,
         "kernel_matmat_tflops": roofline_of(w, reps, kname, summary)["achieved"],
         "roofline": roofline_of(w, reps, kname, summary),
+        "autotune": tune.as_dict() if tune is not None else None,
     }
     if not args.no_fp64:
         out["fp64_path"] = fp64_leg(P, args.refine)
@@ -466,7 +580,9 @@ def main():
     misses = [] if met else ["headline"]
     if "fp64_path" in out and not out["fp64_path"]["tol_met"]:
         misses.append("fp64_path")
-    runners = {"mixture": mixture_run, "pixels": pixels_run, "plain": plain_run, "ablation": ablation_run,
+    runners = {"mixture": mixture_run, "pixels": pixels_run, "plain": plain_run,
+               "ablation": ablation_run, "polynomial": polynomial_run,
+               "multilevel": multilevel_run, "adaptive": adaptive_run,
                "batched": batched_run, "differentiation": differentiation_run}
     for leg in [x for x in args.legs.split(",") if x]:
         if leg == args.headline:
@@ -479,6 +595,10 @@ def main():
             for k in ("lambda_p=lambda", "lambda_p=10lambda"):
                 if not res[k]["tol_met"]:
                     misses.append(f"ablation.{k}")
+        elif leg == "multilevel":
+            for k in ("three_level", "one_level_s2048"):
+                if not res[k]["tol_met"]:
+                    misses.append(f"multilevel.{k}")
         elif "tol_met" in res and not res["tol_met"]:
             misses.append(leg)
         elif leg in ("mixture", "pixels") and "fp64_path" in res and not res["fp64_path"]["tol_met"]:

@@ -69,7 +69,11 @@ typedef enum krr_op {
   KRR_OP_PCG_SOLVE = 3,
   KRR_OP_GRAD = 4,
   KRR_OP_PRECOND_APPLY = 5,
-  KRR_OP_DSIGMA_INNER = 6
+  KRR_OP_DSIGMA_INNER = 6,
+  KRR_OP_GAUSSIAN_PROJECT = 7,  /* n1 = n, d = s2 (input width), s = s3 (output width) */
+  KRR_OP_PRECOND_TEST = 8,      /* n1 = n, d, s (candidate width), prec */
+  KRR_OP_ADAPTIVE_FEATURES = 9, /* n1 = n, d, s = s_max, prec */
+  KRR_OP_AUTOTUNE = 10          /* n1 = n, d, m, prec */
 } krr_op;
 
 /*
@@ -159,6 +163,172 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
                              int64_t m, int64_t ldv, double* OUT, int64_t ldo, int32_t deriv,
                              int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
+/* ----------------------------------------------------------------------------------------
+ * Kernel descriptor. The Gaussian kernel k(x, z) = exp(-||x - z||^2 / (2 sigma^2)) and the
+ * polynomial kernel k(x, z) = (gamma x^T z + c)^q are the two kernels of the paper's
+ * experiments (Sec. 6); the homogeneous polynomial kernel (gamma = 1, c = 0) is the kernel
+ * of Sec. 2.2 and Thm. 1. The *_k entry points take it; the others are the Gaussian case.
+ */
+typedef enum krr_kernel_kind {
+  KRR_KERNEL_GAUSSIAN = 0,
+  KRR_KERNEL_POLYNOMIAL = 1
+} krr_kernel_kind;
+
+#define KRR_POLY_MAX_DEGREE 16
+
+typedef struct krr_kernel {
+  int32_t kind;     /* krr_kernel_kind */
+  int32_t degree;   /* polynomial: q, 1 <= q <= KRR_POLY_MAX_DEGREE */
+  double sigma;     /* Gaussian: bandwidth, > 0 */
+  double gamma;     /* polynomial: scale, finite, >= 0 */
+  double coef0;     /* polynomial: offset c, finite, >= 0 */
+} krr_kernel;
+
+/*
+ * krr_kernel_matmat_k -- krr_kernel_matmat for a kernel descriptor. For the polynomial
+ * kernel the F16X3 product forms gamma <x_i, x_j> + c on MFMA from FP16 hi+lo splits of
+ * augmented rows [sqrt(gamma/T) x, sqrt(c/T)] (T the even power of two at or above
+ * gamma max ||x||^2 + c, so the scaled value lies in [-1, 1]), raises it to q in FP32, splits
+ * it into FP16 hi+lo for the MFMA product with V and multiplies the FP64 partial sums by T^q;
+ * KRR_PREC_FP64 forms <x_i, x_j> exactly as for the Gaussian kernel and (gamma g + c)^q in
+ * FP64. deriv must be 0 and prec must not be KRR_PREC_BF16X3 for the polynomial kernel.
+ * Other arguments, workspace (krr_workspace_bytes with KRR_OP_KERNEL_MATMAT) and errors as
+ * krr_kernel_matmat.
+ */
+krr_status krr_kernel_matmat_k(const krr_kernel* kernel, const float* X1, int64_t n1, int64_t ldx1,
+                               const float* X2, int64_t n2, int64_t ldx2, int64_t d, double shift,
+                               const double* V, int64_t m, int64_t ldv, double* OUT, int64_t ldo,
+                               int32_t deriv, int32_t prec, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/*
+ * krr_tensorsketch -- TensorSketch features for the polynomial kernel (gamma x^T z + c)^q
+ * (Sec. 2.2; the feature map of Thm. 1): each point is augmented to
+ * x' = [sqrt(gamma) x, sqrt(c)] (one constant feature, the remark after Thm. 1) and mapped to
+ *     Z[i, :] = IFFT( prod_{k<q} FFT( CountSketch_k(x'_i) ) ),
+ * CountSketch_k(x')[b] = sum over j with hash[k][j] = b of sign[k][j] x'_j, which equals the
+ * TensorSketch matrix (hash H = sum_k h_k(i_k) mod s, sign G = prod_k g_k(i_k)) applied to the
+ * degree-q monomials of x', so E[Z Z^T] = K over random hashes and signs.
+ *   X    : n x d FP32 (ldx >= d).
+ *   gamma, coef0 : >= 0;  degree : q, 1 <= q <= KRR_POLY_MAX_DEGREE.
+ *   hash : q x (d + 1) int32, row-major, DEVICE; values are taken modulo s; column d hashes
+ *          the constant feature. Drawn by the caller (fully random tables satisfy the
+ *          3-wise independence the definition asks for).
+ *   sign : q x (d + 1) FP32 of +1 / -1, DEVICE, drawn by the caller.
+ *   s    : a power of two, 2 <= s <= KRR_TENSORSKETCH_MAX_S.
+ *   Z    : n x s FP32 output (ldz >= s).
+ * One 256-thread block per point: the CountSketches are scattered into LDS, transformed by a
+ * radix-2 FFT in LDS (FP32, accurate twiddles), multiplied, and transformed back. No
+ * workspace. Asynchronous on `stream`. Errors: KRR_E_ARG.
+ */
+#define KRR_TENSORSKETCH_MAX_S 8192
+krr_status krr_tensorsketch(const float* X, int64_t n, int64_t d, int64_t ldx, double gamma,
+                            double coef0, int32_t degree, const int32_t* hash, const float* sign,
+                            int64_t s, float* Z, int64_t ldz, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Multiple-level sketching (Sec. 4, Alg. 2): a first-level sketch Z_1 (n x s_1: random
+ * Fourier features or TensorSketch) is compressed to Z_2 = Z_1 S_2^T by an SRHT, then to
+ * Z_3 = s_3^{-1/2} Z_2 S_3^T by a Gaussian projection; krr_precond_factor(Z_3, lambda) then
+ * gives the preconditioner Z_3 Z_3^T + lambda I of Alg. 2 (Thm. 3: O(s_lambda log s_lambda)
+ * columns suffice after the SRHT).
+ */
+#define KRR_SRHT_MAX_S1 16384
+
+/*
+ * krr_srht -- Z2 = Z1 S^T for the subsampled randomized Walsh-Hadamard transform of Def. 2,
+ *     S = s2^{-1/2} P H D  (s2 x s1),
+ * D = diag(signs), H the +-1 Walsh-Hadamard matrix (H_m = [[H, H], [H, -H]]), P the rows
+ * `sample` of the identity. A width s1 that is not a power of two is zero-padded to the next
+ * power of two p (zero columns of Z1 do not change Z1 Z1^T); then H is p x p.
+ *   Z1     : n x s1 FP32 (ldz1 >= s1);  p <= KRR_SRHT_MAX_S1.
+ *   signs  : s1 FP32 of +1 / -1, DEVICE, drawn by the caller.
+ *   sample : s2 int32 coordinates in [0, p) (taken modulo p), DEVICE, drawn by the caller
+ *            (uniformly, without replacement, for Thm. 3's setting).
+ *   Z2     : n x s2 FP32 output (ldz2 >= s2), 1 <= s2 <= p.
+ * One 256-thread block per row: the signed row in LDS, the fast transform in place (log2 p
+ * butterfly stages, FP32), a gather of the sampled coordinates. No workspace. Asynchronous on
+ * `stream`. Errors: KRR_E_ARG.
+ */
+krr_status krr_srht(const float* Z1, int64_t n, int64_t s1, int64_t ldz1, const float* signs,
+                    const int32_t* sample, int64_t s2, float* Z2, int64_t ldz2, void* stream);
+
+/*
+ * krr_gaussian_project -- Z3 = s3^{-1/2} Z2 S3^T, the dense third level of Alg. 2.
+ *   Z2 : n x s2 FP32 (ldz2 >= s2).   S3 : s3 x s2 FP32 row-major, entries N(0, 1) drawn by
+ *   the caller.   Z3 : n x s3 FP32 output (ldz3 >= s3).
+ * One MFMA GEMM from FP16 hi+lo splits of both operands (three products, FP32 accumulate).
+ * Workspace: krr_workspace_bytes(KRR_OP_GAUSSIAN_PROJECT, n, n, s2, s3, 0, KRR_PREC_F16X3).
+ * Asynchronous on `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE.
+ */
+krr_status krr_gaussian_project(const float* Z2, int64_t n, int64_t s2, int64_t ldz2,
+                                const float* S3, int64_t s3, float* Z3, int64_t ldz3, void* ws,
+                                size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Adaptive sketch size (Sec. 5, Thm. 4). For a candidate sketch Z (n x s) let P project on the
+ * eigenvectors of Z Z^T whose eigenvalues exceed 0.05 lambda. Thm. 4: if
+ *   (1) ||(I - P) K (I - P)||_2 <= 0.1 lambda, and
+ *   (2) ||V^T P x||^2 = (1 +- 0.1) ||Z^T P x||^2 for all x (K = V V^T),
+ * then Z Z^T + lambda I is as good a preconditioner as Thm. 1 guarantees. The test below
+ * estimates both sides by power iteration, as the paper suggests for condition 1; for
+ * condition 2 (whose test the paper leaves open) it estimates the extreme eigenvalues of
+ * W U^T K U W on range(P) (U the eigenvectors, W = diag(eigenvalue^-1/2)), which are the
+ * extremes of that ratio. The adaptive driver doubles s until the test passes.
+ */
+typedef struct krr_precond_test_report {
+  double cond1;           /* Rayleigh-quotient estimate of ||(I - P) K (I - P)||_2 (from below) */
+  double ratio_lo;        /* estimate of the smallest ratio ||V^T P x||^2 / ||Z^T P x||^2 */
+  double ratio_hi;        /* estimate of the largest ratio */
+  int32_t rank;           /* dim range(P) */
+  int32_t passed;         /* cond1 <= 0.1 lambda and 0.9 <= ratio_lo, ratio_hi <= 1.1 */
+  int32_t power_iters;    /* iterations of each power iteration */
+  int32_t jacobi_sweeps;  /* sweeps of the eigen-decomposition of Z^T Z */
+} krr_precond_test_report;
+
+/*
+ * krr_precond_test -- the Thm. 4 test of a candidate sketch.
+ *   kernel : the kernel of K (krr_kernel).  X : n x d FP32 (ldx >= d).
+ *   Z      : n x s FP32 candidate (ldz >= s), 1 <= s < n.   lambda > 0.
+ *   power_iters : iterations of each power iteration (>= 1; 30-50 is typical).
+ *   prec   : arithmetic of the kernel products (a krr_prec).
+ *   rep    : HOST pointer, filled.
+ * Steps: Z^T Z + 5e-6 lambda I (split MFMA Gram, FP64 Cholesky C), eigen-decomposition of
+ * C C^T by one-sided Jacobi rotations on the rows of C (FP64), U = Z V_k diag(e_k^-1/2) for
+ * the eigenvalues above 0.05 lambda (split MFMA GEMM), then power iterations whose products
+ * are matrix-free kernel products, Woodbury-type projections (I - U U^T) and GEMVs with U.
+ * Workspace: krr_workspace_bytes(KRR_OP_PRECOND_TEST, n, n, d, s, 0, prec). Synchronises
+ * `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE, KRR_E_NOT_SPD (non-finite Z).
+ */
+krr_status krr_precond_test(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                            int64_t ldx, const float* Z, int64_t s, int64_t ldz, double lambda,
+                            int32_t power_iters, int32_t prec, krr_precond_test_report* rep,
+                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * krr_adaptive_features -- Sec. 5: starting from s = s0 features, form Z, run
+ * krr_precond_test, and double s until the test passes or 2 s would exceed s_max.
+ *   Gaussian kernel: W (d x s_max FP32, row-major) and b (s_max) are one random Fourier
+ *     feature draw; the sketch of size s uses its first s columns (iid, so a valid draw of s
+ *     features), scaled by sqrt(2/s).
+ *   Polynomial kernel: hash, sign (degree x (d + 1), as krr_tensorsketch) with hash values in
+ *     [0, s_max); size s takes them modulo s (s0 and every doubling must be powers of two
+ *     <= KRR_TENSORSKETCH_MAX_S).
+ *   Z       : n x s_max FP32 buffer (ldz >= s_max); on return its first *s_out columns hold
+ *             the accepted sketch (the last one tried when none passed).
+ *   s_out   : HOST, the chosen s.   history: HOST array of history_cap reports (may be NULL),
+ *   history_len: HOST, the number of sizes tried.
+ * Workspace: krr_workspace_bytes(KRR_OP_ADAPTIVE_FEATURES, n, n, d, s_max, 0, prec).
+ * Synchronises `stream`. Errors: as krr_precond_test, KRR_E_ARG for a missing draw.
+ */
+krr_status krr_adaptive_features(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                                 int64_t ldx, double lambda, const float* W, const float* b,
+                                 const int32_t* hash, const float* sign, int64_t s0,
+                                 int64_t s_max, float* Z, int64_t ldz, int64_t* s_out,
+                                 krr_precond_test_report* history, int32_t history_cap,
+                                 int32_t* history_len, int32_t power_iters, int32_t prec, void* ws,
+                                 size_t ws_bytes, void* stream);
+
 /* Options of krr_pcg_solve (zero-initialise, then set what you need; see krr_pcg_defaults). */
 typedef struct krr_pcg_opts {
   double tol;            /* stop when ||y_j - A c_j|| <= tol ||y_j|| for every column j (Sec. 6),
@@ -215,6 +385,19 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
                          int64_t ldy, double* alpha, int64_t lda, int64_t m,
                          const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws, size_t ws_bytes,
                          void* stream);
+
+/*
+ * krr_pcg_solve_k -- krr_pcg_solve for a kernel descriptor: PCG on (K + lambda I) alpha = Y
+ * with K from `kernel` (Gaussian or polynomial), the preconditioner from Ut (for the
+ * polynomial kernel, built from krr_tensorsketch features as in Thm. 1), the same options,
+ * report, workspace (KRR_OP_PCG_SOLVE) and errors. The polynomial kernel needs opts->prec
+ * F16X3 or FP64; its FP64 true residual uses the FP64 product.
+ */
+krr_status krr_pcg_solve_k(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                           int64_t ldx, double lambda, const float* Ut, int64_t s, int64_t ldu,
+                           const double* Y, int64_t ldy, double* alpha, int64_t lda, int64_t m,
+                           const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws,
+                           size_t ws_bytes, void* stream);
 
 /*
  * krr_grad -- hyper-parameter gradients of a loss through the solve of Eq. 1 (adjoint
@@ -275,6 +458,44 @@ krr_status krr_kernel_matmat_noalloc(const float* X1, int64_t n1, int64_t ldx1, 
                                      double shift, const double* V, int64_t m, int64_t ldv,
                                      double* OUT, int64_t ldo, int32_t deriv, int32_t prec,
                                      void* stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Autotuning of the kernel products. Launch choices (column splits of the product, and for
+ * large d the right-hand-side pass width) are found by timing candidates on the device and
+ * kept in a process-wide table keyed by (precision, padded width, ceil log2 m, floor log2 n);
+ * every later product of that shape (krr_kernel_matmat*, krr_pcg_solve*, krr_grad, ...) uses
+ * them. With the environment variable KRR_TUNE_CACHE set to a file path, the table is read
+ * from it at first use and written back after every tuning; entries of another architecture
+ * or another build of the kernels (krr_tune_digest) are ignored. Different split counts sum
+ * the partial products in a different (still fixed) order, so a tuned product may differ from
+ * the untuned one by rounding, within the product's error bound.
+ */
+typedef struct krr_tune_report {
+  int32_t candidates;          /* launch choices timed */
+  int32_t default_nsplit, default_pass_width;
+  int32_t nsplit, pass_width;  /* the choice stored in the table */
+  double default_ms, best_ms;  /* device time of one product: rule vs stored choice */
+} krr_tune_report;
+
+/*
+ * krr_autotune_matmat -- time the candidate launch choices of the square product K(X, X) V
+ * (m synthetic right-hand sides) and store the fastest (the rule's own choice unless a
+ * candidate is at least 3 % faster).
+ * Workspace: krr_workspace_bytes(KRR_OP_AUTOTUNE, n, n, d, 0, m, prec). rep: HOST pointer.
+ * Synchronises `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE, KRR_E_HIP.
+ */
+krr_status krr_autotune_matmat(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                               int64_t ldx, int64_t m, int32_t prec, krr_tune_report* rep,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* Host-side tuning table: write it to / read it from `path` (1 on success, 0 otherwise; a file
+ * of another architecture or build reads as 0 entries), drop every entry, count the entries,
+ * and the digest of the kernel sources this library was built from. */
+int32_t krr_tune_cache_save(const char* path);
+int32_t krr_tune_cache_load(const char* path);
+void krr_tune_cache_clear(void);
+int32_t krr_tune_cache_size(void);
+const char* krr_tune_digest(void);
 
 /* ----------------------------------------------------------------------------------------
  * Batched solves: many independent problems in one plan. Every iteration runs ONE persistent

@@ -88,6 +88,8 @@ struct MatmatCtx {
   int64_t n1 = 0, n2 = 0, d = 0, m = 0;
   int64_t rp1 = 0, rp2 = 0, Kp = 0, dp = 0;
   int nsplit = 1;
+  int nsplit_max = 1;       // splits the partial buffer holds (tuned choices stay within it)
+  int pass_w = 0;           // right-hand-side pass width (0: pv_pass_width)
   float* stats = nullptr;   // [0] max|x|, [1] max nu, [2] 1/q^2
   void *Ahi = nullptr, *Alo = nullptr, *Bhi = nullptr, *Blo = nullptr;
   double *nuA = nullptr, *nuB = nullptr;
@@ -98,6 +100,8 @@ struct MatmatCtx {
   int64_t part_stride = 0;
   double c2 = 0;            // log2(e) / (2 sigma^2)
   double sigma = 0;
+  bool poly = false;        // polynomial kernel (gamma x^T z + c)^q instead of the Gaussian
+  PolyF64 pk;               // its parameters
 };
 
 void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int64_t m, int prec,
@@ -130,6 +134,7 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     // large-d MFMA product on many row blocks: 8 column splits, launched in XCD groups
     if (c.pv && c.Kp > 128 && ceil_div(n1, 128) >= 64) c.nsplit = 8;
     if (c.pv) {
+      // (a tuned pass width for large d is 32 or 64, never above the default 64)
       c.mpad = pv_pass_rows(std::min<int64_t>(m, pv_pass_width(c.Kp)));
       c.Vth = b.take<_Float16>(c.mpad * c.rp2);
       c.Vtl = b.take<_Float16>(c.mpad * c.rp2);
@@ -141,15 +146,33 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     c.Bhi = b.take<uint16_t>(c.rp2 * c.Kp);
     c.Blo = b.take<uint16_t>(c.rp2 * c.Kp);
   }
+  // the tuning table may pick fewer splits, or 8 where the rule picks fewer; the partial
+  // buffer holds the larger of the two so the workspace size does not depend on the table
+  c.nsplit_max = std::max(c.nsplit, 8);
+  TuneChoice tc;
+  if (tune_lookup(prec, 0, prec == KRR_PREC_FP64 ? c.dp : c.Kp, m, n1, &tc)) {
+    if (tc.nsplit >= 1 && tc.nsplit <= c.nsplit_max) c.nsplit = tc.nsplit;
+    if (tc.pass_width == 32 || tc.pass_width == 64) c.pass_w = tc.pass_width;
+  }
   c.part_stride = c.rp1 * m;
-  c.part = b.take<double>(c.nsplit * c.part_stride);
+  c.part = b.take<double>(c.nsplit_max * c.part_stride);
 }
 
-// Prepare both point sets for a given sigma (X2 == nullptr: square product of X1).
+// Prepare both point sets for a kernel (X2 == nullptr: square product of X1).
 hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const float* X2,
-                          int64_t ldx2, double sigma, hipStream_t st) {
-  c.sigma = sigma;
-  c.c2 = 1.4426950408889634 / (2.0 * sigma * sigma);
+                          int64_t ldx2, const krr_kernel& k, hipStream_t st) {
+  c.poly = k.kind == KRR_KERNEL_POLYNOMIAL;
+  c.sigma = c.poly ? 1.0 : k.sigma;
+  c.c2 = 1.4426950408889634 / (2.0 * c.sigma * c.sigma);
+  c.pk.gamma = k.gamma;
+  c.pk.coef0 = k.coef0;
+  c.pk.deg = c.poly ? k.degree : 1;
+  RowSpec rs;
+  rs.poly = c.poly ? 1 : 0;
+  rs.deg = c.pk.deg;
+  rs.c2 = c.c2;
+  rs.gamma = k.gamma;
+  rs.coef0 = k.coef0;
   hipError_t e;
   if (c.prec == KRR_PREC_FP64) {
     if (c.XAf) {
@@ -168,17 +191,25 @@ hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const flo
   const int64_t ldb = X2 ? ldx2 : ldx1;
   const int ps = c.pv ? PSHIFT : 0;
   if (c.prec == KRR_PREC_F16X3) {
-    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0, ps,
+    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, rs, c.stats, 0, ps,
                                    (_Float16*)c.Ahi, (_Float16*)c.Alo, c.stats + 2, st)))
       return e;
-    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1, ps,
+    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, rs, c.stats, 1, ps,
                                  (_Float16*)c.Bhi, (_Float16*)c.Blo, nullptr, st);
   }
-  if ((e = prep_points<__bf16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, c.c2, c.stats, 0, 0,
+  if (c.poly) return hipErrorInvalidValue;  // BF16X3 products are Gaussian only
+  if ((e = prep_points<__bf16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, rs, c.stats, 0, 0,
                                (__bf16*)c.Ahi, (__bf16*)c.Alo, c.stats + 2, st)))
     return e;
-  return prep_points<__bf16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, c.c2, c.stats, 1, 0, (__bf16*)c.Bhi,
+  return prep_points<__bf16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, rs, c.stats, 1, 0, (__bf16*)c.Bhi,
                              (__bf16*)c.Blo, nullptr, st);
+}
+hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const float* X2,
+                          int64_t ldx2, double sigma, hipStream_t st) {
+  krr_kernel k{};
+  k.kind = KRR_KERNEL_GAUSSIAN;
+  k.sigma = sigma;
+  return prepare_points(c, X1, ldx1, X2, ldx2, k, st);
 }
 
 // Partial sums of K V (or dK/dsigma V) into c.part. V is FP32 (mixed) or FP64 (FP64 path).
@@ -190,7 +221,8 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
   if (c.prec == KRR_PREC_FP64) {
     F64Points A{c.nuA, c.n1, c.dp, c.XAf, c.SA, c.scA, c.d};
     F64Points B{c.nuB, c.n2, c.dp, c.XBf, c.SB, c.scB, c.d};
-    return matmat_f64(A, B, V64, ldv, c.m, deriv, 1.0 / (2.0 * c.sigma * c.sigma), 1.0 / sig3,
+    const int epi = c.poly ? KV_POLY : deriv ? KV_DSIGMA : KV_GAUSS;
+    return matmat_f64(A, B, V64, ldv, c.m, epi, 1.0 / (2.0 * c.sigma * c.sigma), 1.0 / sig3, c.pk,
                       c.part, c.m, c.part_stride, c.nsplit, st);
   }
   const float dscale = (float)(1.0 / (c.c2 * sig3));  // dk/dsigma = k * (-log2 k) / (c2 sigma^3)
@@ -198,7 +230,7 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
     MixedPoints<_Float16> A{(const _Float16*)c.Ahi, (const _Float16*)c.Alo, c.n1, c.Kp, c.stats + 2};
     MixedPoints<_Float16> B{(const _Float16*)c.Bhi, (const _Float16*)c.Blo, c.n2, c.Kp, c.stats + 2};
     if (c.pv) {
-      const int64_t W = pv_pass_width(c.Kp);
+      const int64_t W = c.Kp > 128 && c.pass_w ? c.pass_w : pv_pass_width(c.Kp);
       for (int64_t c0 = 0; c0 < c.m; c0 += W) {
         const int64_t mc = std::min<int64_t>(W, c.m - c0);
         const int64_t mp = pv_pass_rows(mc);
@@ -208,14 +240,17 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
                                    c.Vth, c.Vtl, c.vscale, st);
         if (e != hipSuccess) return e;
         SplitRhs V{c.Vth, c.Vtl, c.vscale, c.rp2, mp, packed};
-        e = matmat_f16pv(A, B, V, mc, deriv, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st);
+        const int epi = c.poly ? KV_POLY : deriv ? KV_DSIGMA : KV_GAUSS;
+        e = matmat_f16pv(A, B, V, mc, epi, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     }
+    if (c.poly) return hipErrorInvalidValue;
     return matmat_mixed<_Float16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.part_stride,
                                   c.nsplit, st);
   }
+  if (c.poly) return hipErrorInvalidValue;
   MixedPoints<__bf16> A{(const __bf16*)c.Ahi, (const __bf16*)c.Alo, c.n1, c.Kp, c.stats + 2};
   MixedPoints<__bf16> B{(const __bf16*)c.Bhi, (const __bf16*)c.Blo, c.n2, c.Kp, c.stats + 2};
   return matmat_mixed<__bf16>(A, B, Vf, ldv, c.m, deriv, dscale, c.part, c.m, c.part_stride,
@@ -248,7 +283,26 @@ void layout_features(Bump& b, FeatLayout& L, int64_t n, int64_t d, int64_t s) {
   L.Wl = b.take<_Float16>(L.sp * L.dk);
 }
 
+// ------------------------------------------------------- Gaussian projection (Alg. 2)
+struct ProjLayout {
+  float* stats;
+  _Float16 *Ah, *Al, *Bh, *Bl;
+  int64_t kp, np, sp;
+};
+void layout_project(Bump& b, ProjLayout& L, int64_t n, int64_t s2, int64_t s3) {
+  L.kp = round_up(s2, 32);
+  L.np = round_up(n, GEMM_TILE);
+  L.sp = round_up(s3, GEMM_TILE);
+  L.stats = b.take<float>(64);
+  L.Ah = b.take<_Float16>(L.np * L.kp);
+  L.Al = b.take<_Float16>(L.np * L.kp);
+  L.Bh = b.take<_Float16>(L.sp * L.kp);
+  L.Bl = b.take<_Float16>(L.sp * L.kp);
+}
+
 // ---------------------------------------------------------------- precond factor
+krr_status gram_cholesky(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
+                         struct FactorLayout& L, int64_t* info, const char* fn, hipStream_t st);
 int64_t pow2_pad(int64_t s) {
   int64_t p = 64;
   while (p < s) p *= 2;
@@ -288,6 +342,32 @@ void layout_factor(Bump& b, FactorLayout& L, int64_t n, int64_t s) {
   L.G = b.take<double>(L.s_pad * L.s_pad);
   L.Cinv = b.take<double>(L.s_pad * L.s_pad);
   L.tmp = b.take<double>(L.s_pad * L.s_pad / 2);
+}
+
+// G = Z^T Z + lambda_p I (split MFMA Gram, FP64 sums) and its FP64 Cholesky factor in L.G
+// (stride s_pad); KRR_E_NOT_SPD with *info = failing pivot + 1.
+krr_status gram_cholesky(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
+                         FactorLayout& L, int64_t* info, const char* fn, hipStream_t st) {
+  CHECK_HIP(fill_f32(L.stats, 4, 0.0f, st));
+  CHECK_HIP(fill_i32(L.info, 1, 0, st));
+  // Gram G = Z^T Z: A = B = Z^T (s x n, contraction over points)
+  CHECK_HIP(absmax<float>(Z, n, s, ldz, L.stats + 0, st));
+  CHECK_HIP((split_operand<float, _Float16>(Z, n, s, ldz, L.stats + 0, 1, L.sp64, L.nk, L.h1, L.l1, st)));
+  SplitOperand Zt{L.h1, L.l1, L.nk, L.stats + 0};
+  CHECK_HIP(gemm_nt_f16x3(Zt, Zt, s, s, L.nk, L.nsplit, EPI_PART64, 1, 0, 1.0, L.part, s * s,
+                          nullptr, s, nullptr, 0.0f, st));
+  CHECK_HIP(gram_finalize(L.part, L.nsplit, s, s, s * s, lambda_p, L.s_pad, L.G, st));
+  // Cholesky (FP64)
+  CHECK_HIP(fill_f64(L.Cinv, L.s_pad * L.s_pad, 0.0, st));
+  CHECK_HIP(cholesky_blocked(L.G, L.s_pad, L.Cinv, L.info, st));
+  int hinfo = 0;
+  CHECK_HIP(hipMemcpyAsync(&hinfo, L.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  if (hinfo != 0) {
+    if (info) *info = hinfo;
+    return fail(KRR_E_NOT_SPD, "%s: Z^T Z + lambda_p I not positive definite at pivot %d", fn, hinfo);
+  }
+  return KRR_OK;
 }
 
 // ---------------------------------------------------------------------- PCG
@@ -370,6 +450,56 @@ void layout_inner(Bump& b, InnerLayout& L, int64_t n1, int64_t n2, int64_t d, in
   L.part = b.take<double>(NBLK * m);
 }
 
+// The Thm. 4 test of a candidate sketch Z (n x s): factor of Z^T Z + jitter, Jacobi
+// eigen-decomposition, the orthonormal basis U_k of range(P) (n x s FP32 buffer), the kernel
+// product of one vector, power-iteration vectors and reduction scratch.
+struct TestLayout {
+  FactorLayout F;
+  MatmatCtx mm;
+  double *Zd, *A, *Vt, *ev, *scale, *v, *w, *t, *x, *y, *part, *gpart, *T, *pc_part;
+  float *Bk, *Uk, *vf;
+  int* idx;
+  unsigned long long* off;
+  int nchunk;
+};
+void layout_test(Bump& b, TestLayout& L, int64_t n, int64_t d, int64_t s, int prec) {
+  layout_factor(b, L.F, n, s);
+  layout_matmat(b, L.mm, n, n, d, 1, prec, true);
+  L.Zd = b.take<double>(n * s);
+  L.A = b.take<double>(s * s);
+  L.Vt = b.take<double>(s * s);
+  L.ev = b.take<double>(s);
+  L.scale = b.take<double>(s);
+  L.idx = b.take<int>(s);
+  L.off = b.take<unsigned long long>(1);
+  L.Bk = b.take<float>(s * s);
+  L.Uk = b.take<float>(n * s);
+  L.vf = b.take<float>(round_up(n, ROW_PAD));
+  L.v = b.take<double>(n);
+  L.w = b.take<double>(n);
+  L.t = b.take<double>(n);
+  L.x = b.take<double>(s);
+  L.y = b.take<double>(s);
+  L.part = b.take<double>(NBLK * 2);
+  L.gpart = b.take<double>(GEMV_PARTS_MAX * s);
+  L.nchunk = precond_nchunk(n, s);
+  L.pc_part = b.take<double>((int64_t)L.nchunk * s);
+  L.T = b.take<double>(s);
+}
+
+// autotuning: the product, synthetic right-hand sides and their FP32 copy
+struct TuneLayout {
+  MatmatCtx mm;
+  double *V, *out;
+  float* Vf;
+};
+void layout_tune(Bump& b, TuneLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
+  layout_matmat(b, L.mm, n, n, d, m, prec, true);
+  L.V = b.take<double>(n * m);
+  L.out = b.take<double>(n * m);
+  L.Vf = b.take<float>(round_up(n, ROW_PAD) * m);
+}
+
 void layout_grad(Bump& b, GradLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
   layout_matmat(b, L.mm, n, n, d, m, prec, true);
   L.af = b.take<float>(round_up(n, ROW_PAD) * m);
@@ -419,6 +549,28 @@ size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_
     case KRR_OP_PCG_SOLVE: { PCGLayout L; layout_pcg(b, L, n1, d, s, m, prec); break; }
     case KRR_OP_GRAD: { GradLayout L; layout_grad(b, L, n1, d, m, prec); break; }
     case KRR_OP_PRECOND_APPLY: { ApplyLayout L; layout_apply(b, L, n1, s, m); break; }
+    case KRR_OP_AUTOTUNE: { TuneLayout L; layout_tune(b, L, n1, d, m, prec); break; }
+    case KRR_OP_ADAPTIVE_FEATURES: {
+      if (s < 1) return 0;
+      TestLayout L;
+      layout_test(b, L, n1, d, s, prec);
+      FeatLayout F;
+      Bump fb(nullptr);
+      layout_features(fb, F, n1, d, s);
+      return std::max(b.off, fb.off) + 256;
+    }
+    case KRR_OP_PRECOND_TEST: {
+      if (s < 1) return 0;
+      TestLayout L;
+      layout_test(b, L, n1, d, s, prec);
+      break;
+    }
+    case KRR_OP_GAUSSIAN_PROJECT: {
+      if (s < 1) return 0;
+      ProjLayout L;
+      layout_project(b, L, n1, d, s);
+      break;
+    }
     case KRR_OP_DSIGMA_INNER: {
       if (n2 < 1) return 0;
       InnerLayout L;
@@ -431,6 +583,13 @@ size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_
 }
 
 // ------------------------------------------------------------------ features
+namespace {
+// Random Fourier features from the first s columns of W (d x ldw) and entries of b.
+krr_status features_impl(const char* fn, const float* X, int64_t n, int64_t d, int64_t ldx,
+                         const float* W, int64_t ldw, const float* b, int64_t s, float* Z,
+                         int64_t ldz, void* ws, size_t ws_bytes, hipStream_t st);
+}  // namespace
+
 krr_status krr_features(const float* X, int64_t n, int64_t d, int64_t ldx, const float* W,
                         const float* b, int64_t s, float* Z, int64_t ldz, void* ws,
                         size_t ws_bytes, void* stream) {
@@ -439,24 +598,33 @@ krr_status krr_features(const float* X, int64_t n, int64_t d, int64_t ldx, const
   if (n < 1 || d < 1 || s < 1 || ldx < d || ldz < s)
     return fail(KRR_E_ARG, "krr_features: bad sizes n=%lld d=%lld s=%lld", (long long)n,
                 (long long)d, (long long)s);
+  return features_impl("krr_features", X, n, d, ldx, W, s, b, s, Z, ldz, ws, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+namespace {
+krr_status features_impl(const char* fn, const float* X, int64_t n, int64_t d, int64_t ldx,
+                         const float* W, int64_t ldw, const float* b, int64_t s, float* Z,
+                         int64_t ldz, void* ws, size_t ws_bytes, hipStream_t st) {
   Bump probe(nullptr);
   FeatLayout L;
   layout_features(probe, L, n, d, s);
   CHECK_ST(check_ws(ws, ws_bytes, probe.off + 256));
+  (void)fn;
   Bump bb(ws);
   layout_features(bb, L, n, d, s);
-  hipStream_t st = (hipStream_t)stream;
   CHECK_HIP(fill_f32(L.stats, 4, 0.0f, st));
   CHECK_HIP(absmax<float>(X, n, d, ldx, L.stats + 0, st));
-  CHECK_HIP(absmax<float>(W, d, s, s, L.stats + 1, st));
+  CHECK_HIP(absmax<float>(W, d, s, ldw, L.stats + 1, st));
   CHECK_HIP((split_operand<float, _Float16>(X, n, d, ldx, L.stats + 0, 0, L.np, L.dk, L.Xh, L.Xl, st)));
   // W is d x s; its transpose (s x d, contraction index contiguous) is the B operand
-  CHECK_HIP((split_operand<float, _Float16>(W, d, s, s, L.stats + 1, 1, L.sp, L.dk, L.Wh, L.Wl, st)));
+  CHECK_HIP((split_operand<float, _Float16>(W, d, s, ldw, L.stats + 1, 1, L.sp, L.dk, L.Wh, L.Wl, st)));
   SplitOperand A{L.Xh, L.Xl, L.dk, L.stats + 0}, B{L.Wh, L.Wl, L.dk, L.stats + 1};
   CHECK_HIP(gemm_nt_f16x3(A, B, n, s, L.dk, 1, EPI_COS, 0, 0, 1.0, nullptr, 0, Z, ldz, b,
                           (float)std::sqrt(2.0 / (double)s), st));
   return KRR_OK;
 }
+}  // namespace
 
 // ---------------------------------------------------------------- precond factor
 krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
@@ -477,25 +645,7 @@ krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz,
   Bump bb(ws);
   layout_factor(bb, L, n, s);
   hipStream_t st = (hipStream_t)stream;
-  CHECK_HIP(fill_f32(L.stats, 4, 0.0f, st));
-  CHECK_HIP(fill_i32(L.info, 1, 0, st));
-  // Gram G = Z^T Z: A = B = Z^T (s x n, contraction over points)
-  CHECK_HIP(absmax<float>(Z, n, s, ldz, L.stats + 0, st));
-  CHECK_HIP((split_operand<float, _Float16>(Z, n, s, ldz, L.stats + 0, 1, L.sp64, L.nk, L.h1, L.l1, st)));
-  SplitOperand Zt{L.h1, L.l1, L.nk, L.stats + 0};
-  CHECK_HIP(gemm_nt_f16x3(Zt, Zt, s, s, L.nk, L.nsplit, EPI_PART64, 1, 0, 1.0, L.part, s * s,
-                          nullptr, s, nullptr, 0.0f, st));
-  CHECK_HIP(gram_finalize(L.part, L.nsplit, s, s, s * s, lambda_p, L.s_pad, L.G, st));
-  // Cholesky (FP64) and inverse of the factor
-  CHECK_HIP(fill_f64(L.Cinv, L.s_pad * L.s_pad, 0.0, st));
-  CHECK_HIP(cholesky_blocked(L.G, L.s_pad, L.Cinv, L.info, st));
-  int hinfo = 0;
-  CHECK_HIP(hipMemcpyAsync(&hinfo, L.info, sizeof(int), hipMemcpyDeviceToHost, st));
-  CHECK_HIP(hipStreamSynchronize(st));
-  if (hinfo != 0) {
-    *info = hinfo;
-    return fail(KRR_E_NOT_SPD, "krr_precond_factor: Z^T Z + lambda_p I not positive definite at pivot %d", hinfo);
-  }
+  CHECK_ST(gram_cholesky(Z, n, s, ldz, lambda_p, L, info, "krr_precond_factor", st));
   CHECK_HIP(tri_inverse_doubling(L.G, L.s_pad, L.Cinv, L.tmp, st));
   CHECK_HIP(copy_lower(L.G, L.s_pad, s, C, st));
   // Ut = Z C^{-T}: A = Z (n x s), B = C^{-1} (rows j, contraction k), lower triangular
@@ -538,19 +688,41 @@ krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu,
 }
 
 // ---------------------------------------------------------------- kernel matmat
-krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const float* X2, int64_t n2,
-                             int64_t ldx2, int64_t d, double sigma, double shift, const double* V,
-                             int64_t m, int64_t ldv, double* OUT, int64_t ldo, int32_t deriv,
-                             int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+namespace {
+
+// Kernel descriptor checks (Gaussian: sigma > 0; polynomial: degree 1..KRR_POLY_MAX_DEGREE,
+// gamma >= 0, c >= 0, FP16X3 or FP64 products, no sigma-derivative).
+krr_status check_kernel(const krr_kernel* k, int32_t prec, int32_t deriv, const char* fn) {
+  if (!k) return fail(KRR_E_ARG, "%s: null kernel descriptor", fn);
+  if (k->kind == KRR_KERNEL_GAUSSIAN) {
+    if (!(k->sigma > 0.0) || !std::isfinite(k->sigma)) return fail(KRR_E_ARG, "%s: sigma must be > 0", fn);
+    return KRR_OK;
+  }
+  if (k->kind != KRR_KERNEL_POLYNOMIAL) return fail(KRR_E_ARG, "%s: unknown kernel kind %d", fn, k->kind);
+  if (k->degree < 1 || k->degree > KRR_POLY_MAX_DEGREE)
+    return fail(KRR_E_ARG, "%s: polynomial degree must be in [1, %d]", fn, KRR_POLY_MAX_DEGREE);
+  if (!(k->gamma >= 0.0) || !std::isfinite(k->gamma) || !(k->coef0 >= 0.0) || !std::isfinite(k->coef0))
+    return fail(KRR_E_ARG, "%s: polynomial gamma and c must be finite and >= 0", fn);
+  if (prec == KRR_PREC_BF16X3)
+    return fail(KRR_E_ARG, "%s: polynomial kernel products use KRR_PREC_F16X3 or KRR_PREC_FP64", fn);
+  if (deriv) return fail(KRR_E_ARG, "%s: deriv applies to the Gaussian kernel only", fn);
+  return KRR_OK;
+}
+
+krr_status kernel_matmat_impl(const char* fn, const krr_kernel* kern, const float* X1, int64_t n1,
+                              int64_t ldx1, const float* X2, int64_t n2, int64_t ldx2, int64_t d,
+                              double shift, const double* V, int64_t m, int64_t ldv, double* OUT,
+                              int64_t ldo, int32_t deriv, int32_t prec, void* ws, size_t ws_bytes,
+                              void* stream) {
   g_err[0] = 0;
-  if (!X1 || !X2 || !V || !OUT) return fail(KRR_E_ARG, "krr_kernel_matmat: null pointer");
+  if (!X1 || !X2 || !V || !OUT) return fail(KRR_E_ARG, "%s: null pointer", fn);
   if (n1 < 1 || n2 < 1 || d < 1 || m < 1 || ldx1 < d || ldx2 < d || ldv < m || ldo < m)
-    return fail(KRR_E_ARG, "krr_kernel_matmat: bad sizes or strides");
-  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(KRR_E_ARG, "krr_kernel_matmat: sigma must be > 0");
-  if (shift != 0.0 && n1 != n2) return fail(KRR_E_ARG, "krr_kernel_matmat: shift needs n1 == n2");
-  if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_kernel_matmat: unknown precision %d", prec);
+    return fail(KRR_E_ARG, "%s: bad sizes or strides", fn);
+  CHECK_ST(check_kernel(kern, prec, deriv, fn));
+  if (shift != 0.0 && n1 != n2) return fail(KRR_E_ARG, "%s: shift needs n1 == n2", fn);
+  if (!prec_ok(prec)) return fail(KRR_E_ARG, "%s: unknown precision %d", fn, prec);
   if (prec == KRR_PREC_BF16X3 && kp_for(d) > 256)
-    return fail(KRR_E_ARG, "krr_kernel_matmat: BF16X3 supports d <= 254 (d=%lld)", (long long)d);
+    return fail(KRR_E_ARG, "%s: BF16X3 supports d <= 254 (d=%lld)", fn, (long long)d);
   const size_t need = krr_workspace_bytes(KRR_OP_KERNEL_MATMAT, n1, n2, d, 0, m, prec);
   CHECK_ST(check_ws(ws, ws_bytes, need));
   Bump bb(ws);
@@ -558,7 +730,7 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
   layout_matmat(bb, c, n1, n2, d, m, prec, false);
   float* Vf = prec != KRR_PREC_FP64 ? bb.take<float>(round_up(n2, ROW_PAD) * m) : nullptr;
   hipStream_t st = (hipStream_t)stream;
-  CHECK_HIP(prepare_points(c, X1, ldx1, X2, ldx2, sigma, st));
+  CHECK_HIP(prepare_points(c, X1, ldx1, X2, ldx2, *kern, st));
   if (Vf) {
     CHECK_HIP(vec_to_f32(V, n2, m, ldv, round_up(n2, ROW_PAD), m, Vf, st));
     CHECK_HIP(run_matmat(c, Vf, nullptr, m, deriv != 0, st));
@@ -567,6 +739,120 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
   }
   CHECK_HIP(matmat_finalize<double>(c.part, c.part_stride, c.nsplit, n1, m, m, shift, V, ldv, OUT,
                                     ldo, st));
+  return KRR_OK;
+}
+
+krr_kernel gaussian(double sigma) {
+  krr_kernel k{};
+  k.kind = KRR_KERNEL_GAUSSIAN;
+  k.sigma = sigma;
+  return k;
+}
+
+}  // namespace
+
+krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const float* X2, int64_t n2,
+                             int64_t ldx2, int64_t d, double sigma, double shift, const double* V,
+                             int64_t m, int64_t ldv, double* OUT, int64_t ldo, int32_t deriv,
+                             int32_t prec, void* ws, size_t ws_bytes, void* stream) {
+  const krr_kernel k = gaussian(sigma);
+  return kernel_matmat_impl("krr_kernel_matmat", &k, X1, n1, ldx1, X2, n2, ldx2, d, shift, V, m,
+                            ldv, OUT, ldo, deriv, prec, ws, ws_bytes, stream);
+}
+
+krr_status krr_kernel_matmat_k(const krr_kernel* kernel, const float* X1, int64_t n1, int64_t ldx1,
+                               const float* X2, int64_t n2, int64_t ldx2, int64_t d, double shift,
+                               const double* V, int64_t m, int64_t ldv, double* OUT, int64_t ldo,
+                               int32_t deriv, int32_t prec, void* ws, size_t ws_bytes,
+                               void* stream) {
+  return kernel_matmat_impl("krr_kernel_matmat_k", kernel, X1, n1, ldx1, X2, n2, ldx2, d, shift, V,
+                            m, ldv, OUT, ldo, deriv, prec, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------ autotuning
+krr_status krr_autotune_matmat(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                               int64_t ldx, int64_t m, int32_t prec, krr_tune_report* rep,
+                               void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X || !rep) return fail(KRR_E_ARG, "krr_autotune_matmat: null pointer");
+  if (n < 1 || d < 1 || m < 1 || ldx < d) return fail(KRR_E_ARG, "krr_autotune_matmat: bad sizes");
+  if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_autotune_matmat: unknown precision %d", prec);
+  CHECK_ST(check_kernel(kernel, prec, 0, "krr_autotune_matmat"));
+  const size_t need = krr_workspace_bytes(KRR_OP_AUTOTUNE, n, n, d, 0, m, prec);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  hipStream_t st = (hipStream_t)stream;
+  Bump bb(ws);
+  TuneLayout L;
+  layout_tune(bb, L, n, d, m, prec);
+  MatmatCtx& c = L.mm;
+  const int64_t key_k = prec == KRR_PREC_FP64 ? c.dp : c.Kp;
+  // the rule's choice (the table entry for this shape, if any, is ignored while timing)
+  int ns0 = choose_nsplit(n, n);
+  if (c.pv && c.Kp > 128 && ceil_div(n, 128) >= 64) ns0 = 8;
+  const int w0 = (int)pv_pass_width(c.Kp);
+  CHECK_HIP(prepare_points(c, X, ldx, nullptr, 0, *kernel, st));
+  CHECK_HIP(hash_fill(L.V, n * m, 0x7e57, st));
+  // candidates: the rule, fewer splits, and 8 splits (the grouped launch for large d); for
+  // large d with more than 32 right-hand sides also 32-column passes
+  std::vector<std::pair<int, int>> cand;
+  auto add = [&](int ns, int w) {
+    if (ns < 1 || ns > c.nsplit_max) return;
+    for (auto& p : cand)
+      if (p.first == ns && p.second == w) return;
+    cand.push_back({ns, w});
+  };
+  std::vector<int> ws_opts = {w0};
+  if (c.pv && c.Kp > 128 && m > 32) ws_opts.push_back(32);
+  for (int w : ws_opts) {
+    add(ns0, w);
+    add(ns0 / 2, w);
+    add(ns0 / 4, w);
+    add(8, w);
+  }
+  hipEvent_t e0, e1;
+  CHECK_HIP(hipEventCreate(&e0));
+  CHECK_HIP(hipEventCreate(&e1));
+  double best_ms = 1e30, def_ms = 0.0;
+  int best = 0;
+  hipError_t err = hipSuccess;
+  for (size_t ci = 0; ci < cand.size() && err == hipSuccess; ++ci) {
+    c.nsplit = cand[ci].first;
+    c.pass_w = cand[ci].second;
+    double tmin = 1e30;
+    for (int rep_i = 0; rep_i < 4 && err == hipSuccess; ++rep_i) {
+      if (prec != KRR_PREC_FP64)
+        err = vec_to_f32(L.V, n, m, m, round_up(n, ROW_PAD), m, L.Vf, st);
+      if (err == hipSuccess) err = hipEventRecord(e0, st);
+      if (err == hipSuccess)
+        err = prec == KRR_PREC_FP64 ? run_matmat(c, nullptr, L.V, m, false, st)
+                                    : run_matmat(c, L.Vf, nullptr, m, false, st);
+      if (err == hipSuccess) err = hipEventRecord(e1, st);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float t = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+      if (rep_i > 0) tmin = std::min(tmin, (double)t);  // the first run warms up
+    }
+    if (ci == 0) def_ms = tmin;
+    if (tmin < best_ms) { best_ms = tmin; best = (int)ci; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  CHECK_HIP(err);
+  // keep the rule unless a candidate is clearly faster (timing noise must not flip it)
+  if (best_ms > 0.97 * def_ms) { best = 0; best_ms = def_ms; }
+  TuneChoice tc;
+  tc.nsplit = cand[best].first;
+  tc.pass_width = cand[best].second;
+  tc.ms_default = def_ms;
+  tc.ms_best = best_ms;
+  tune_store(prec, 0, key_k, m, n, tc);
+  rep->candidates = (int32_t)cand.size();
+  rep->default_nsplit = cand[0].first;
+  rep->default_pass_width = cand[0].second;
+  rep->nsplit = tc.nsplit;
+  rep->pass_width = tc.pass_width;
+  rep->default_ms = def_ms;
+  rep->best_ms = best_ms;
   return KRR_OK;
 }
 
@@ -755,11 +1041,12 @@ krr_status true_residual(PCGLayout& L, const SolveArgs& a, const double* Y, int6
 
 }  // namespace
 
-krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, double sigma,
-                         double lambda, const float* Ut, int64_t s, int64_t ldu, const double* Y,
-                         int64_t ldy, double* alpha, int64_t lda, int64_t m,
-                         const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws, size_t ws_bytes,
-                         void* stream) {
+namespace {
+krr_status pcg_solve_impl(const krr_kernel* kern, const float* X, int64_t n, int64_t d,
+                          int64_t ldx, double lambda, const float* Ut, int64_t s, int64_t ldu,
+                          const double* Y, int64_t ldy, double* alpha, int64_t lda, int64_t m,
+                          const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws,
+                          size_t ws_bytes, void* stream) {
   g_err[0] = 0;
   krr_pcg_opts o;
   krr_pcg_defaults(&o);
@@ -767,7 +1054,7 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
   if (!X || !Y || !alpha) return fail(KRR_E_ARG, "krr_pcg_solve: null pointer");
   if (n < 1 || d < 1 || m < 1 || ldx < d || ldy < m || lda < m)
     return fail(KRR_E_ARG, "krr_pcg_solve: bad sizes or strides");
-  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(KRR_E_ARG, "krr_pcg_solve: sigma must be > 0");
+  CHECK_ST(check_kernel(kern, o.prec, 0, "krr_pcg_solve"));
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(KRR_E_ARG, "krr_pcg_solve: lambda must be > 0");
   if (!(o.tol > 0.0)) return fail(KRR_E_ARG, "krr_pcg_solve: tol must be > 0");
   if (o.max_iter < 1) return fail(KRR_E_ARG, "krr_pcg_solve: max_iter must be >= 1");
@@ -789,9 +1076,9 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
   layout_pcg(bb, L, n, d, s, m, o.prec);
   hipStream_t st = (hipStream_t)stream;
   const bool mixed = o.prec != KRR_PREC_FP64;
-  CHECK_HIP(prepare_points(L.mm, X, ldx, nullptr, 0, sigma, st));
+  CHECK_HIP(prepare_points(L.mm, X, ldx, nullptr, 0, *kern, st));
   if (mixed && (o.true_residual || o.refine > 0))
-    CHECK_HIP(prepare_points(L.mm64, X, ldx, nullptr, 0, sigma, st));
+    CHECK_HIP(prepare_points(L.mm64, X, ldx, nullptr, 0, *kern, st));
 
   MMTimer timer;
   CHECK_HIP(timer.init());
@@ -866,6 +1153,310 @@ krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, doub
     ok = conv == m;
   }
   if (!ok) return fail(KRR_E_NO_CONV, "krr_pcg_solve: not converged after %d iterations", total_iters);
+  return KRR_OK;
+}
+}  // namespace
+
+krr_status krr_pcg_solve(const float* X, int64_t n, int64_t d, int64_t ldx, double sigma,
+                         double lambda, const float* Ut, int64_t s, int64_t ldu, const double* Y,
+                         int64_t ldy, double* alpha, int64_t lda, int64_t m,
+                         const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws, size_t ws_bytes,
+                         void* stream) {
+  const krr_kernel k = gaussian(sigma);
+  return pcg_solve_impl(&k, X, n, d, ldx, lambda, Ut, s, ldu, Y, ldy, alpha, lda, m, opts, rep,
+                        ws, ws_bytes, stream);
+}
+
+krr_status krr_pcg_solve_k(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                           int64_t ldx, double lambda, const float* Ut, int64_t s, int64_t ldu,
+                           const double* Y, int64_t ldy, double* alpha, int64_t lda, int64_t m,
+                           const krr_pcg_opts* opts, krr_pcg_report* rep, void* ws,
+                           size_t ws_bytes, void* stream) {
+  return pcg_solve_impl(kernel, X, n, d, ldx, lambda, Ut, s, ldu, Y, ldy, alpha, lda, m, opts, rep,
+                        ws, ws_bytes, stream);
+}
+
+// -------------------------------------------------------------- TensorSketch
+krr_status krr_tensorsketch(const float* X, int64_t n, int64_t d, int64_t ldx, double gamma,
+                            double coef0, int32_t degree, const int32_t* hash, const float* sign,
+                            int64_t s, float* Z, int64_t ldz, void* stream) {
+  g_err[0] = 0;
+  if (!X || !hash || !sign || !Z) return fail(KRR_E_ARG, "krr_tensorsketch: null pointer");
+  if (n < 1 || d < 1 || ldx < d || ldz < s) return fail(KRR_E_ARG, "krr_tensorsketch: bad sizes or strides");
+  if (degree < 1 || degree > KRR_POLY_MAX_DEGREE)
+    return fail(KRR_E_ARG, "krr_tensorsketch: degree must be in [1, %d]", KRR_POLY_MAX_DEGREE);
+  if (!(gamma >= 0.0) || !std::isfinite(gamma) || !(coef0 >= 0.0) || !std::isfinite(coef0))
+    return fail(KRR_E_ARG, "krr_tensorsketch: gamma and c must be finite and >= 0");
+  if (s < 2 || s > KRR_TENSORSKETCH_MAX_S || (s & (s - 1)))
+    return fail(KRR_E_ARG, "krr_tensorsketch: s must be a power of two in [2, %d]",
+                KRR_TENSORSKETCH_MAX_S);
+  int logs = 0;
+  while ((int64_t(1) << logs) < s) ++logs;
+  CHECK_HIP(tensor_sketch(X, n, d, ldx, gamma, coef0, degree, hash, sign, logs, Z, ldz,
+                          (hipStream_t)stream));
+  return KRR_OK;
+}
+
+// ---------------------------------------------------- multiple-level sketching (Alg. 2)
+krr_status krr_srht(const float* Z1, int64_t n, int64_t s1, int64_t ldz1, const float* signs,
+                    const int32_t* sample, int64_t s2, float* Z2, int64_t ldz2, void* stream) {
+  g_err[0] = 0;
+  if (!Z1 || !signs || !sample || !Z2) return fail(KRR_E_ARG, "krr_srht: null pointer");
+  if (n < 1 || s1 < 1 || s2 < 1 || ldz1 < s1 || ldz2 < s2)
+    return fail(KRR_E_ARG, "krr_srht: bad sizes or strides");
+  int64_t p = 1;
+  while (p < s1) p *= 2;
+  if (p > KRR_SRHT_MAX_S1)
+    return fail(KRR_E_ARG, "krr_srht: s1 padded to a power of two must be <= %d", KRR_SRHT_MAX_S1);
+  if (s2 > p) return fail(KRR_E_ARG, "krr_srht: s2 must not exceed the padded s1 (%lld)", (long long)p);
+  CHECK_HIP(srht_rows(Z1, n, s1, ldz1, signs, sample, s2, Z2, ldz2, (hipStream_t)stream));
+  return KRR_OK;
+}
+
+krr_status krr_gaussian_project(const float* Z2, int64_t n, int64_t s2, int64_t ldz2,
+                                const float* S3, int64_t s3, float* Z3, int64_t ldz3, void* ws,
+                                size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!Z2 || !S3 || !Z3) return fail(KRR_E_ARG, "krr_gaussian_project: null pointer");
+  if (n < 1 || s2 < 1 || s3 < 1 || ldz2 < s2 || ldz3 < s3)
+    return fail(KRR_E_ARG, "krr_gaussian_project: bad sizes or strides");
+  const size_t need = krr_workspace_bytes(KRR_OP_GAUSSIAN_PROJECT, n, n, s2, s3, 0, KRR_PREC_F16X3);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  Bump bb(ws);
+  ProjLayout L;
+  layout_project(bb, L, n, s2, s3);
+  hipStream_t st = (hipStream_t)stream;
+  CHECK_HIP(fill_f32(L.stats, 4, 0.0f, st));
+  CHECK_HIP(absmax<float>(Z2, n, s2, ldz2, L.stats + 0, st));
+  CHECK_HIP(absmax<float>(S3, s3, s2, s2, L.stats + 1, st));
+  CHECK_HIP((split_operand<float, _Float16>(Z2, n, s2, ldz2, L.stats + 0, 0, L.np, L.kp, L.Ah, L.Al, st)));
+  CHECK_HIP((split_operand<float, _Float16>(S3, s3, s2, s2, L.stats + 1, 0, L.sp, L.kp, L.Bh, L.Bl, st)));
+  SplitOperand A{L.Ah, L.Al, L.kp, L.stats + 0}, B{L.Bh, L.Bl, L.kp, L.stats + 1};
+  CHECK_HIP(gemm_nt_f16x3(A, B, n, s3, L.kp, 1, EPI_F32, 0, 0, 1.0 / std::sqrt((double)s3),
+                          nullptr, 0, Z3, ldz3, nullptr, 1.0f, st));
+  return KRR_OK;
+}
+
+// ------------------------------------------ preconditioner test and adaptive sketch size
+namespace {
+
+// dot products <a, b> (and optionally <c, d>) of n-vectors, summed on the host in fixed order
+krr_status dots(const double* a, const double* b, const double* c, const double* d, int64_t n,
+                double* part, double* r1, double* r2, hipStream_t st) {
+  CHECK_HIP((dot_partial<double, double>(a, 1, b, 1, n, 1, part, NBLK, st)));
+  if (c) CHECK_HIP((dot_partial<double, double>(c, 1, d, 1, n, 1, part + NBLK, NBLK, st)));
+  double h[2 * NBLK];
+  CHECK_HIP(hipMemcpyAsync(h, part, sizeof(double) * (c ? 2 : 1) * NBLK, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  double s1 = 0.0, s2 = 0.0;
+  for (int i = 0; i < NBLK; ++i) s1 += h[i];
+  if (c)
+    for (int i = 0; i < NBLK; ++i) s2 += h[NBLK + i];
+  *r1 = s1;
+  if (r2) *r2 = s2;
+  return KRR_OK;
+}
+
+// out = K v (the kernel alone) with the test's one-column product
+krr_status kernel_vec(TestLayout& L, const double* v, double* out, int64_t n, hipStream_t st) {
+  if (L.mm.prec == KRR_PREC_FP64) {
+    CHECK_HIP(run_matmat(L.mm, nullptr, v, 1, false, st));
+  } else {
+    CHECK_HIP(vec_to_f32(v, n, 1, 1, round_up(n, ROW_PAD), 1, L.vf, st));
+    CHECK_HIP(run_matmat(L.mm, L.vf, nullptr, 1, false, st));
+  }
+  CHECK_HIP(matmat_finalize<double>(L.mm.part, L.mm.part_stride, L.mm.nsplit, n, 1, 1, 0.0,
+                                    (const double*)nullptr, 1, out, 1, st));
+  return KRR_OK;
+}
+
+krr_status precond_test_impl(const krr_kernel* kern, const float* X, int64_t n, int64_t d,
+                             int64_t ldx, const float* Z, int64_t s, int64_t ldz, double lambda,
+                             int32_t iters, int32_t prec, krr_precond_test_report* rep, void* ws,
+                             hipStream_t st) {
+  Bump bb(ws);
+  TestLayout L;
+  layout_test(bb, L, n, d, s, prec);
+  // eigen-decomposition of Z^T Z through the Cholesky factor of Z^T Z + jitter I. The Gram
+  // is formed in FP64 from the exact FP64 values of Z (products of FP32 numbers are exact),
+  // so its rounding (~1e-16 ||G||) stays far below the jitter, which is far below the
+  // threshold and is subtracted from the eigenvalues again.
+  const double thr = 0.05 * lambda, jitter = 1e-4 * thr;
+  CHECK_HIP(f32_to_f64_2d(Z, n, s, ldz, L.Zd, st));
+  CHECK_HIP(dgemm(s, s, n, 1.0, L.Zd, 1, s, 0, L.Zd, s, 1, 0, 0.0, L.F.part, s, 0, 1, 1, st));
+  CHECK_HIP(gram_finalize(L.F.part, 1, s, s, s * s, jitter, L.F.s_pad, L.F.G, st));
+  CHECK_HIP(fill_i32(L.F.info, 1, 0, st));
+  CHECK_HIP(fill_f64(L.F.Cinv, L.F.s_pad * L.F.s_pad, 0.0, st));
+  CHECK_HIP(cholesky_blocked(L.F.G, L.F.s_pad, L.F.Cinv, L.F.info, st));
+  int hinfo = 0;
+  CHECK_HIP(hipMemcpyAsync(&hinfo, L.F.info, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  if (hinfo != 0)
+    return fail(KRR_E_NOT_SPD, "krr_precond_test: Z^T Z + jitter not positive definite at pivot %d "
+                "(non-finite Z?)", hinfo);
+  CHECK_HIP(copy_lower(L.F.G, L.F.s_pad, s, L.A, st));
+  int sweeps = 0;
+  CHECK_HIP(jacobi_eig(L.A, (int)s, L.Vt, L.ev, L.off, 1e-14, 40, &sweeps, st));
+  std::vector<double> ev(s);
+  CHECK_HIP(hipMemcpyAsync(ev.data(), L.ev, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  CHECK_HIP(hipStreamSynchronize(st));
+  // P projects on the eigenvectors of Z Z^T with eigenvalue above 0.05 lambda (Thm. 4):
+  // u_i = Z v_i / sqrt(e_i) with e_i the eigenvalue of Z^T Z
+  std::vector<int> idx;
+  std::vector<double> sc, w;
+  for (int64_t i = 0; i < s; ++i) {
+    const double e = ev[i] - jitter;
+    if (e > thr) {
+      idx.push_back((int)i);
+      sc.push_back(1.0 / std::sqrt(e));
+      w.push_back(1.0 / std::sqrt(e));
+    }
+  }
+  const int k = (int)idx.size();
+  rep->rank = k;
+  rep->jacobi_sweeps = sweeps;
+  rep->power_iters = iters;
+  if (k > 0) {
+    CHECK_HIP(hipMemcpyAsync(L.idx, idx.data(), sizeof(int) * k, hipMemcpyHostToDevice, st));
+    CHECK_HIP(hipMemcpyAsync(L.scale, sc.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    CHECK_HIP(gather_scaled_rows(L.Vt, (int)s, L.idx, L.scale, k, L.Bk, st));
+    // U_k = Z Bk^T (n x k, leading dimension s) on the split MFMA GEMM
+    FactorLayout& F = L.F;
+    CHECK_HIP(fill_f32(F.stats, 4, 0.0f, st));
+    CHECK_HIP(absmax<float>(Z, n, s, ldz, F.stats + 0, st));
+    CHECK_HIP(absmax<float>(L.Bk, k, s, s, F.stats + 1, st));
+    CHECK_HIP((split_operand<float, _Float16>(Z, n, s, ldz, F.stats + 0, 0, F.np, F.sk, F.h1, F.l1, st)));
+    CHECK_HIP((split_operand<float, _Float16>(L.Bk, k, s, s, F.stats + 1, 0, F.sp64, F.sk, F.ch, F.cl, st)));
+    SplitOperand A{F.h1, F.l1, F.sk, F.stats + 0}, B{F.ch, F.cl, F.sk, F.stats + 1};
+    CHECK_HIP(gemm_nt_f16x3(A, B, n, k, F.sk, 1, EPI_F32, 0, 0, 1.0, nullptr, 0, L.Uk, s, nullptr,
+                            0.0f, st));
+    // the weights 1 / sqrt(e_i) of condition 2 go to the device (reuse the scale array)
+  }
+  CHECK_HIP(prepare_points(L.mm, X, ldx, nullptr, 0, *kern, st));
+  // condition 1: power iteration on (I - P) K (I - P)
+  double num = 0.0, den = 0.0, mu1 = 0.0;
+  CHECK_HIP(hash_fill(L.v, n, 0x5eed, st));
+  for (int it = 0; it < iters; ++it) {
+    const double* pv = L.v;
+    if (k > 0) {
+      CHECK_HIP(precond_apply(L.Uk, s, n, k, 1, 1.0, L.v, L.t, L.pc_part, L.nchunk, L.T, st));
+      pv = L.t;
+    }
+    CHECK_ST(kernel_vec(L, pv, L.w, n, st));
+    double* pw = L.w;
+    if (k > 0) {
+      CHECK_HIP(precond_apply(L.Uk, s, n, k, 1, 1.0, L.w, L.v, L.pc_part, L.nchunk, L.T, st));
+      pw = L.v;
+    }
+    CHECK_ST(dots(pv, pw, pw, pw, n, L.part, &num, &den, st));
+    double vv = 0.0;
+    CHECK_ST(dots(pv, pv, nullptr, nullptr, n, L.part, &vv, nullptr, st));
+    mu1 = vv > 0.0 ? num / vv : 0.0;
+    if (!(den > 0.0)) break;
+    CHECK_HIP(axpby(n, 1.0 / std::sqrt(den), pw, 0.0, nullptr, L.v, st));
+  }
+  rep->cond1 = mu1;
+  // condition 2: extreme eigenvalues of B = W U_k^T K U_k W, W = diag(1 / sqrt(e_i)), by power
+  // iteration on B and on mu_hi I - B
+  double hi = 1.0, lo = 1.0;
+  if (k > 0) {
+    CHECK_HIP(hipMemcpyAsync(L.scale, w.data(), sizeof(double) * k, hipMemcpyHostToDevice, st));
+    for (int pass = 0; pass < 2; ++pass) {
+      CHECK_HIP(hash_fill(L.x, k, 0x5eed + 17 * (pass + 1), st));
+      double mu = 0.0;
+      for (int it = 0; it < iters; ++it) {
+        CHECK_HIP(gemv_n(L.Uk, s, n, k, L.x, L.scale, L.t, st));
+        CHECK_ST(kernel_vec(L, L.t, L.w, n, st));
+        CHECK_HIP(gemv_t(L.Uk, s, n, k, L.w, L.scale, L.y, L.gpart, st));
+        if (pass == 1) CHECK_HIP(axpby(k, hi, L.x, -1.0, L.y, L.y, st));  // (hi I - B) x
+        double xy = 0.0, xx = 0.0, yy = 0.0;
+        CHECK_ST(dots(L.x, L.y, L.x, L.x, k, L.part, &xy, &xx, st));
+        CHECK_ST(dots(L.y, L.y, nullptr, nullptr, k, L.part, &yy, nullptr, st));
+        mu = xx > 0.0 ? xy / xx : 0.0;
+        if (!(yy > 0.0)) break;
+        CHECK_HIP(axpby(k, 1.0 / std::sqrt(yy), L.y, 0.0, nullptr, L.x, st));
+      }
+      if (pass == 0) hi = mu;
+      else lo = hi - mu;
+    }
+  }
+  rep->ratio_lo = lo;
+  rep->ratio_hi = hi;
+  rep->passed = (rep->cond1 <= 0.1 * lambda && lo >= 0.9 && hi <= 1.1) ? 1 : 0;
+  return KRR_OK;
+}
+
+}  // namespace
+
+krr_status krr_precond_test(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                            int64_t ldx, const float* Z, int64_t s, int64_t ldz, double lambda,
+                            int32_t power_iters, int32_t prec, krr_precond_test_report* rep,
+                            void* ws, size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X || !Z || !rep) return fail(KRR_E_ARG, "krr_precond_test: null pointer");
+  if (n < 2 || d < 1 || s < 1 || s >= n || ldx < d || ldz < s)
+    return fail(KRR_E_ARG, "krr_precond_test: need 1 <= s < n, ldx >= d, ldz >= s");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(KRR_E_ARG, "krr_precond_test: lambda must be > 0");
+  if (power_iters < 1) return fail(KRR_E_ARG, "krr_precond_test: power_iters must be >= 1");
+  if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_precond_test: unknown precision %d", prec);
+  CHECK_ST(check_kernel(kernel, prec, 0, "krr_precond_test"));
+  const size_t need = krr_workspace_bytes(KRR_OP_PRECOND_TEST, n, n, d, s, 0, prec);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  *rep = krr_precond_test_report{};
+  return precond_test_impl(kernel, X, n, d, ldx, Z, s, ldz, lambda, power_iters, prec, rep, ws,
+                           (hipStream_t)stream);
+}
+
+krr_status krr_adaptive_features(const krr_kernel* kernel, const float* X, int64_t n, int64_t d,
+                                 int64_t ldx, double lambda, const float* W, const float* b,
+                                 const int32_t* hash, const float* sign, int64_t s0,
+                                 int64_t s_max, float* Z, int64_t ldz, int64_t* s_out,
+                                 krr_precond_test_report* history, int32_t history_cap,
+                                 int32_t* history_len, int32_t power_iters, int32_t prec, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!X || !Z || !s_out || !kernel) return fail(KRR_E_ARG, "krr_adaptive_features: null pointer");
+  if (n < 2 || d < 1 || ldx < d || s0 < 1 || s_max < s0 || s_max >= n || ldz < s_max)
+    return fail(KRR_E_ARG, "krr_adaptive_features: need 1 <= s0 <= s_max < n, ldz >= s_max");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(KRR_E_ARG, "krr_adaptive_features: lambda must be > 0");
+  if (power_iters < 1) return fail(KRR_E_ARG, "krr_adaptive_features: power_iters must be >= 1");
+  if (!prec_ok(prec)) return fail(KRR_E_ARG, "krr_adaptive_features: unknown precision %d", prec);
+  CHECK_ST(check_kernel(kernel, prec, 0, "krr_adaptive_features"));
+  const bool poly = kernel->kind == KRR_KERNEL_POLYNOMIAL;
+  if (poly ? (!hash || !sign) : (!W || !b))
+    return fail(KRR_E_ARG, "krr_adaptive_features: the kernel's feature draw is missing");
+  if (poly) {
+    for (int64_t t = s0; t <= s_max; t *= 2)
+      if ((t & (t - 1)) || t > KRR_TENSORSKETCH_MAX_S)
+        return fail(KRR_E_ARG, "krr_adaptive_features: TensorSketch sizes must be powers of two <= %d",
+                    KRR_TENSORSKETCH_MAX_S);
+  }
+  const size_t need = krr_workspace_bytes(KRR_OP_ADAPTIVE_FEATURES, n, n, d, s_max, 0, prec);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  hipStream_t st = (hipStream_t)stream;
+  int32_t len = 0;
+  int64_t s = s0;
+  for (;;) {
+    // the first s features of the draw (Gaussian: columns of W and entries of b; polynomial:
+    // the same hashes reduced modulo s)
+    if (poly) {
+      int logs = 0;
+      while ((int64_t(1) << logs) < s) ++logs;
+      CHECK_HIP(tensor_sketch(X, n, d, ldx, kernel->gamma, kernel->coef0, kernel->degree, hash,
+                              sign, logs, Z, ldz, st));
+    } else {
+      CHECK_ST(features_impl("krr_adaptive_features", X, n, d, ldx, W, s_max, b, s, Z, ldz, ws,
+                             ws_bytes, st));
+    }
+    krr_precond_test_report r{};
+    CHECK_ST(precond_test_impl(kernel, X, n, d, ldx, Z, s, ldz, lambda, power_iters, prec, &r, ws, st));
+    if (history && len < history_cap) history[len] = r;
+    ++len;
+    if (r.passed || 2 * s > s_max) break;
+    s *= 2;
+  }
+  if (history_len) *history_len = len;
+  *s_out = s;
   return KRR_OK;
 }
 
@@ -969,6 +1560,7 @@ struct krr_batch_plan {
   BatchItem* items = nullptr;
   int nitems = 0, grid = 0, tiles_per_item = 0;
   int* counter = nullptr;
+  int *live_list = nullptr, *live_count = nullptr, *chunk_cnt = nullptr;  // compacted queue
   RedItem* red = nullptr;
   int nred = 0;
   PCItem* pitems = nullptr;
@@ -1055,7 +1647,11 @@ hipError_t batch_product(krr_batch_plan* P, hipStream_t st) {
                                P->red, P->nred, P->colmax, P->Vth, P->Vtl, P->vscale,
                                P->M <= 8, st);
   if (e != hipSuccess) return e;
-  e = matmat_batch(P->items, P->nitems, P->inst, P->S.live, P->counter, P->M <= 8, P->grid, st);
+  e = batch_compact_live(P->items, P->nitems, P->S.live, P->chunk_cnt, P->live_list,
+                         P->live_count, st);
+  if (e != hipSuccess) return e;
+  e = matmat_batch(P->items, P->live_list, P->live_count, P->inst, P->counter, P->M <= 8, P->grid,
+                   st);
   if (e != hipSuccess) return e;
   return batch_finalize(P->meta, P->row_inst, P->S.live, P->N, P->M, P->pf, P->q, st);
 }
@@ -1276,9 +1872,11 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
     const double c2 = 1.4426950408889634 / (2.0 * b.sigma * b.sigma);
     PLAN_HIP(fill_f32(stats, 4, 0.0f, st));
     PLAN_HIP(point_stats(b.X, b.n, b.d, b.ldx, stats, st));
-    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, c2, stats, 0, 0, ah, al,
+    RowSpec rs;
+    rs.c2 = c2;
+    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, rs, stats, 0, 0, ah, al,
                                    stats + 2, st));
-    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, c2, stats, 1, 0, bh, bl,
+    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, rs, stats, 1, 0, bh, bl,
                                    nullptr, st));
     BatchInst& I = P->inst_h[i];
     I.Ahi = ah; I.Alo = al; I.Bhi = bh; I.Blo = bl;
@@ -1307,7 +1905,13 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
   P->grid = 2 * cus;
   // autotune the work-item granularity on the real problem set (the finest granularity
   // has the most items, so its buffer holds every candidate's list)
-  PLAN_HIP(plan_alloc(P, &P->items, (int64_t)build_items(P, cands[0]).size()));
+  {
+    const int64_t maxitems = (int64_t)build_items(P, cands[0]).size();
+    PLAN_HIP(plan_alloc(P, &P->items, maxitems));
+    PLAN_HIP(plan_alloc(P, &P->live_list, maxitems));
+    PLAN_HIP(plan_alloc(P, &P->live_count, 64));
+    PLAN_HIP(plan_alloc(P, &P->chunk_cnt, ceil_div(maxitems, 256) + 64));
+  }
   hipEvent_t e0, e1;
   PLAN_HIP(hipEventCreate(&e0));
   PLAN_HIP(hipEventCreate(&e1));

@@ -457,4 +457,58 @@ hipError_t batch_pack(const int* row_inst, const BatchMeta* meta, int64_t nrows,
   return hipSuccess;
 }
 
+// ------------------------------------------------------ live work-item compaction
+// The product's work queue keeps only the items of problems that still have an active
+// column, in the queue's own (cost-sorted) order: pass 1 counts the live items of each chunk
+// of BC_CHUNK items, pass 2 gives every chunk its offset (the sum of the counts before it) and
+// writes its live item indices in order with a block-wide scan. The product kernel then
+// walks `count` entries instead of skipping converged problems' items one by one.
+constexpr int BC_CHUNK = 256;
+__global__ __launch_bounds__(BC_CHUNK) void batch_count_live_kernel(
+    const BatchItem* __restrict__ items, int nitems, const int* __restrict__ live,
+    int* __restrict__ chunk_cnt) {
+  __shared__ int red[4];
+  const int i = blockIdx.x * BC_CHUNK + threadIdx.x;
+  const int f = (i < nitems && live[items[i].inst]) ? 1 : 0;
+  const int w = wave_sum(f);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) chunk_cnt[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+__global__ __launch_bounds__(BC_CHUNK) void batch_write_live_kernel(
+    const BatchItem* __restrict__ items, int nitems, const int* __restrict__ live,
+    const int* __restrict__ chunk_cnt, int* __restrict__ list, int* __restrict__ count) {
+  __shared__ int base, wsum[4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) {
+    int b = 0;
+    for (int c = 0; c < (int)blockIdx.x; ++c) b += chunk_cnt[c];
+    base = b;
+    if (blockIdx.x == gridDim.x - 1) *count = b + chunk_cnt[blockIdx.x];
+  }
+  const int i = blockIdx.x * BC_CHUNK + tid;
+  const int f = (i < nitems && live[items[i].inst]) ? 1 : 0;
+  // inclusive scan within the wave, then across the four waves
+  int x = f;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int pre = 0;
+  for (int k = 0; k < w; ++k) pre += wsum[k];
+  if (f) list[base + pre + x - 1] = i;
+}
+hipError_t batch_compact_live(const BatchItem* items, int nitems, const int* live, int* chunk_cnt,
+                              int* list, int* count, hipStream_t st) {
+  const int nb = (int)ceil_div(nitems, BC_CHUNK);
+  if (nb <= 0) return fill_i32(count, 1, 0, st);
+  batch_count_live_kernel<<<nb, BC_CHUNK, 0, st>>>(items, nitems, live, chunk_cnt);
+  KRR_LAUNCH_CHECK();
+  batch_write_live_kernel<<<nb, BC_CHUNK, 0, st>>>(items, nitems, live, chunk_cnt, list, count);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 }  // namespace krr

@@ -11,7 +11,8 @@ template <typename T> struct MixedPoints {
   const T* lo;
   int64_t n;      // valid rows (arrays hold round_up(n, ROW_PAD) rows)
   int64_t Kp;     // padded augmented width (multiple of 32)
-  const float* qinv2;  // device scalar 1/q^2
+  const float* qinv2;  // device kernel parameters: 1/q^2, then (polynomial rows) log2 of the
+                       // output multiplier and the degree
 };
 
 struct F64Points {
@@ -44,10 +45,18 @@ hipError_t fill_f64(double* p, int64_t count, double v, hipStream_t st);
 hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st);
 hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float* stats,
                        hipStream_t st);
+// What the augmented rows of the mixed products encode (see prep.hip).
+struct RowSpec {
+  int poly = 0;        // 0: Gaussian kernel, 1: polynomial kernel
+  int deg = 1;         // polynomial degree
+  double c2 = 0.0;     // Gaussian: log2(e) / (2 sigma^2)
+  double gamma = 0.0;  // polynomial scale
+  double coef0 = 0.0;  // polynomial offset
+};
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                       int64_t Kp, double c2, const float* stats, int side, int pshift, T* hi,
-                       T* lo, float* qinv2, hipStream_t st);
+                       int64_t Kp, const RowSpec& rs, const float* stats, int side, int pshift,
+                       T* hi, T* lo, float* kpar, hipStream_t st);
 hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
                        float* colmax, int pshift, bool packed, _Float16* hi, _Float16* lo,
                        float* vscale, hipStream_t st);
@@ -80,16 +89,32 @@ struct SplitRhs {          // right-hand sides prepared for the MFMA accumulatio
 // to the shift; measured, that raised the solve's residual floor, so no shift is applied:
 // k in (0, 1] is split directly (absolute error <= 2^-25 where k is below FP16's normal range).
 constexpr int PSHIFT = 0;
+// Epilogues of the fused kernel products (the value formed from each pair's inner product)
+constexpr int KV_GAUSS = 0;   // Gaussian kernel (Sec. 6)
+constexpr int KV_DSIGMA = 1;  // its sigma-derivative
+constexpr int KV_POLY = 2;    // polynomial kernel (gamma x^T z + c)^q (Sec. 6, Thm. 1)
+// Polynomial kernel value in FP64 from the inner product g = <x_i, x_j>: (gamma g + c)^deg.
+struct PolyF64 {
+  double gamma = 0.0, coef0 = 0.0;
+  int deg = 1;
+  __device__ inline double value(double g) const {
+    const double t = fma(gamma, g, coef0);
+    double p = t;
+    for (int e = 1; e < deg; ++e) p *= t;
+    return p;
+  }
+};
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
-                        const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
+                        const SplitRhs& V, int64_t m, int epi, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
 template <typename T>
 hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
                         int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
-                      int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
-                      int64_t part_stride, int nsplit, hipStream_t st);
+                      int64_t m, int epi, double c, double dscale, const PolyF64& pk,
+                      double* part, int64_t ldp, int64_t part_stride, int nsplit,
+                      hipStream_t st);
 template <typename VS>
 hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, int64_t n,
                            int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,
@@ -110,8 +135,12 @@ struct BatchItem {          // a 128-row block of one problem against one column
   int tiles_per_split;
   int64_t rb, split;
 };
-hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
-                        const int* live, int* counter, bool packed, int grid, hipStream_t st);
+// items[list[0 .. *nlist)] are the live work items (batch_compact_live)
+hipError_t matmat_batch(const BatchItem* items, const int* list, const int* nlist,
+                        const BatchInst* inst, int* counter, bool packed, int grid,
+                        hipStream_t st);
+hipError_t batch_compact_live(const BatchItem* items, int nitems, const int* live, int* chunk_cnt,
+                              int* list, int* count, hipStream_t st);
 
 // gemm.hip
 hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M, int64_t N,
@@ -157,6 +186,45 @@ hipError_t add2d(const double* a, int64_t lda, double* b, int64_t ldb, int64_t n
 hipError_t precond_apply(const float* Ut, int64_t ldu, int64_t n, int64_t s, int64_t m,
                          double lambda_p, const double* r, double* z, double* part, int nchunk,
                          double* T, hipStream_t st);
+
+// tsketch.hip: TensorSketch features of the augmented points [sqrt(gamma) x, sqrt(c)]
+// (hash q x (d + 1) in [0, s), sign q x (d + 1) of +-1), s = 2^logs <= 8192.
+hipError_t tensor_sketch(const float* X, int64_t n, int64_t d, int64_t ldx, double gamma,
+                         double coef0, int q, const int* hash, const float* sign, int logs,
+                         float* Z, int64_t ldz, hipStream_t st);
+
+// srht.hip: Z2 = Z1 S^T for the SRHT S = s2^{-1/2} P H D (rows of Z1 zero-padded to a power
+// of two <= 16384; sample holds s2 coordinates of the padded width).
+hipError_t srht_rows(const float* Z1, int64_t n, int64_t s1, int64_t ldz1, const float* signs,
+                     const int* sample, int64_t s2, float* Z2, int64_t ldz2, hipStream_t st);
+
+// jacobi.hip: eigen-decomposition of C C^T by one-sided Jacobi on the rows of C (A in: C,
+// out: rotated rows; Vt: eigenvectors as rows; ev: eigenvalues), and the small kernels of the
+// preconditioner test.
+hipError_t jacobi_eig(double* A, int s, double* Vt, double* ev, unsigned long long* off,
+                      double tol, int max_sweeps, int* sweeps, hipStream_t st);
+hipError_t gather_scaled_rows(const double* Vt, int s, const int* idx, const double* scale, int k,
+                              float* Bk, hipStream_t st);
+constexpr int GEMV_PARTS_MAX = 128;
+hipError_t gemv_t(const float* U, int64_t ldu, int64_t n, int k, const double* r, const double* w,
+                  double* y, double* part, hipStream_t st);
+hipError_t gemv_n(const float* U, int64_t ldu, int64_t n, int k, const double* x, const double* w,
+                  double* r, hipStream_t st);
+hipError_t hash_fill(double* v, int64_t n, uint64_t seed, hipStream_t st);
+hipError_t axpby(int64_t n, double a, const double* x, double b, const double* y, double* out,
+                 hipStream_t st);
+hipError_t f32_to_f64_2d(const float* a, int64_t n, int64_t cols, int64_t lda, double* out,
+                         hipStream_t st);
+
+// tune.cpp: launch choices of the kernel products found by timing (0 = the default rule)
+struct TuneChoice {
+  int nsplit = 0;       // column splits of the product
+  int pass_width = 0;   // right-hand-side columns per pass (large d)
+  double ms_default = 0.0, ms_best = 0.0;
+};
+bool tune_lookup(int prec, int kind, int64_t Kp, int64_t m, int64_t n, TuneChoice* out);
+void tune_store(int prec, int kind, int64_t Kp, int64_t m, int64_t n, const TuneChoice& c);
+const char* tune_digest();
 
 // Record `msg` as the calling thread's krr_last_error() text and return `code` (entry points
 // defined outside the main ABI source report through it).

@@ -250,6 +250,30 @@ template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const Mixed
 // padding, no bank conflicts on the fragment reads). When q = 1 (operands already in
 // FP16's comfortable range) the kernel skips the 1/q^2 scaling: a uniform branch at entry
 // selects that instantiation of the body.
+// Kernel value of the fused epilogue from l = <a_i, b_j> / q^2 of the augmented rows:
+//   KV_GAUSS   l = log2 k(x_i, x_j) (Gaussian rows):       k = 2^l;
+//   KV_DSIGMA  same rows:                                   dk/dsigma = k (-l) dscale;
+//   KV_POLY    l = (gamma <x_i, x_j> + c) / t_max (polynomial rows, |l| <= 1):
+//               k / t_max^deg = l^deg (the output is multiplied back by pmul = t_max^deg).
+template <int EPI>
+__device__ __forceinline__ float epi_value(float l, float dscale, int deg) {
+  if (EPI == KV_POLY) {
+    float p = l;
+    for (int e = 1; e < deg; ++e) p *= l;
+    return p;
+  }
+  float p = __builtin_amdgcn_exp2f(l);
+  if (EPI == KV_DSIGMA) p *= -l * dscale;
+  return p;
+}
+// Degree and output multiplier of the polynomial epilogue from the kernel parameters that
+// follow 1/q^2 on the device: kp[1] = log2 of the multiplier, kp[2] = degree.
+template <int EPI>
+__device__ __forceinline__ void epi_params(const float* kp, int& deg, double& pmul) {
+  deg = EPI == KV_POLY ? (int)kp[2] : 1;
+  pmul = EPI == KV_POLY ? ldexp(1.0, (int)kp[1]) : 1.0;
+}
+
 constexpr int MM2_BM = 128;   // rows per block (4 waves x 32)
 constexpr int MM2_FLUSH = 2;  // tiles between FP32 -> FP64 flushes
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
@@ -311,14 +335,14 @@ struct PVSmem {
   _Float16 Vl[2][PACK ? 8 : NCT * 16 * MM_BN];  // unused with packed V^T
 };
 
-template <int KS, int NCT, bool UNIT, bool DERIV, bool PACK>
+template <int KS, int NCT, bool UNIT, int EPI, bool PACK>
 __device__ __forceinline__ void f16pv_body(
     PVSmem<KS, NCT, PACK>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
-    float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
-    int tiles_per_split) {
+    float qinv2, float dscale, int deg, double pmul, double* __restrict__ part, int64_t ldp,
+    int64_t part_stride, int tiles_per_split) {
   constexpr int KP = KS * 32;
   constexpr int CPR = KP / 8;                 // 16-byte chunks per B row
   constexpr int SWZ = (KS == 1 || KS == 3) ? 3 : 7;
@@ -447,11 +471,8 @@ __device__ __forceinline__ void f16pv_body(
         for (int r = 0; r < 4; r += 2) {
           float l2a = S[jb][ib][r], l2b = S[jb][ib][r + 1];
           if (!UNIT) { l2a *= qinv2; l2b *= qinv2; }
-          float pa = __builtin_amdgcn_exp2f(l2a), pb = __builtin_amdgcn_exp2f(l2b);
-          if (DERIV) {
-            pa *= -l2a * dscale;
-            pb *= -l2b * dscale;
-          }
+          const float pa = epi_value<EPI>(l2a, dscale, deg);
+          const float pb = epi_value<EPI>(l2b, dscale, deg);
           // round-to-nearest split: |(hi + lo) - p| <= 2^-22 |p| (2^-25 absolute below the
           // FP16 normal range), unbiased
           const half2v h = half2v{(_Float16)pa, (_Float16)pb};
@@ -555,7 +576,7 @@ __device__ __forceinline__ void f16pv_body(
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
     if (c < m && (!PACK || li < 8)) {
-      const double vs = (double)vscale[c];
+      const double vs = (double)vscale[c] * pmul;
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -567,7 +588,7 @@ __device__ __forceinline__ void f16pv_body(
   }
 }
 
-template <int KS, int NCT, bool DERIV, bool PACK>
+template <int KS, int NCT, int EPI, bool PACK>
 __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16pv_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -576,13 +597,18 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
     int64_t part_stride, int tiles_per_split) {
   __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT, PACK> sm;
-  const float qinv2 = *qinv2_ptr;
+  const float qinv2 = qinv2_ptr[0];
+  int deg;
+  double pmul;
+  epi_params<EPI>(qinv2_ptr, deg, pmul);
   if (qinv2 == 1.0f)
-    f16pv_body<KS, NCT, true, DERIV, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                     qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+    f16pv_body<KS, NCT, true, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                     qinv2, dscale, deg, pmul, part, ldp, part_stride,
+                                     tiles_per_split);
   else
-    f16pv_body<KS, NCT, false, DERIV, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                      qinv2, dscale, part, ldp, part_stride, tiles_per_split);
+    f16pv_body<KS, NCT, false, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
+                                      qinv2, dscale, deg, pmul, part, ldp, part_stride,
+                                      tiles_per_split);
 }
 
 // Large-d variant: the row operands no longer fit in registers, so both operands stream
@@ -597,14 +623,14 @@ template <int NCT, int NJB>
 constexpr int bigd_smem_halves() {
   return 2 * 2 * BD_BM * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB);
 }
-template <int NCT, bool UNIT, bool DERIV, int NJB, bool PACK>
+template <int NCT, bool UNIT, int EPI, int NJB, bool PACK>
 __device__ __forceinline__ void f16pv_bigd_body(
     _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
-    float qinv2, float dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
-    int tiles_per_split, int64_t rb, int64_t split) {
+    float qinv2, float dscale, int deg, double pmul, double* __restrict__ part, int64_t ldp,
+    int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split) {
   constexpr int TN = 16 * NJB;
   constexpr int BPT = TN * 4 / 256;          // B chunk pieces per thread
   constexpr int VR = NCT * 16;
@@ -800,11 +826,8 @@ __device__ __forceinline__ void f16pv_bigd_body(
             for (int r = 0; r < 4; r += 2) {
               float l2a = S[2 * jp + jj][ib][r], l2b = S[2 * jp + jj][ib][r + 1];
               if (!UNIT) { l2a *= qinv2; l2b *= qinv2; }
-              float pa = __builtin_amdgcn_exp2f(l2a), pb = __builtin_amdgcn_exp2f(l2b);
-              if (DERIV) {
-                pa *= -l2a * dscale;
-                pb *= -l2b * dscale;
-              }
+              const float pa = epi_value<EPI>(l2a, dscale, deg);
+              const float pb = epi_value<EPI>(l2b, dscale, deg);
               const half2v h = half2v{(_Float16)pa, (_Float16)pb};
               const half2v l = split_lo2(h, pa, pb);
               ph[4 * jj + r] = h[0];
@@ -854,7 +877,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
     if (c < m && (!PACK || li < 8)) {
-      const double vs = (double)vscale[c];
+      const double vs = (double)vscale[c] * pmul;
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -874,7 +897,7 @@ constexpr int bd_njb(int nct) { return nct == 4 ? 4 : BD_NJB; }
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
-template <int NCT, bool DERIV, bool PACK>
+template <int NCT, int EPI, bool PACK>
 __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -896,20 +919,24 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f16pv_bigd_kerne
     sp = u % BD_GROUP;
     if (rb * BD_BM >= n1) return;  // padding block
   }
-  const float qinv2 = *qinv2_ptr;
+  const float qinv2 = qinv2_ptr[0];
+  int deg;
+  double pmul;
+  epi_params<EPI>(qinv2_ptr, deg, pmul);
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, DERIV, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
-                                              n1, n2, m, KP, qinv2, dscale, part, ldp,
+    f16pv_bigd_body<NCT, true, EPI, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+                                              n1, n2, m, KP, qinv2, dscale, deg, pmul, part, ldp,
                                               part_stride, tiles_per_split, rb, sp);
   else
-    f16pv_bigd_body<NCT, false, DERIV, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
-                                               n1, n2, m, KP, qinv2, dscale, part, ldp,
+    f16pv_bigd_body<NCT, false, EPI, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
+                                               n1, n2, m, KP, qinv2, dscale, deg, pmul, part, ldp,
                                                part_stride, tiles_per_split, rb, sp);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
-                        const SplitRhs& V, int64_t m, bool deriv, float dscale, double* part,
+                        const SplitRhs& V, int64_t m, int epi, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
+  if (epi != KV_GAUSS && epi != KV_DSIGMA && epi != KV_POLY) return hipErrorInvalidValue;
   if (A.Kp != B.Kp || V.mpad < round_up(m, 16)) return hipErrorInvalidValue;
   // passes of up to 32 columns (64 for large d, NCT = 4)
   if (A.Kp > 128 ? !(V.mpad <= 32 || V.mpad == 64) : V.mpad > 32) return hipErrorInvalidValue;
@@ -929,33 +956,33 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   matmat_f16pv_bigd_kernel<NCT_, D_, P_><<<grid, 256, 0, st>>>(                               \
       A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, \
       part, ldp, part_stride, tps, grouped)
+#define KRR_BD_EPI(NCT_, P_)                     \
+  if (epi == KV_DSIGMA) KRR_BD(NCT_, KV_DSIGMA, P_); \
+  else if (epi == KV_POLY) KRR_BD(NCT_, KV_POLY, P_); \
+  else KRR_BD(NCT_, KV_GAUSS, P_);
     if (nct == 1 && V.packed) {
-      if (deriv) KRR_BD(1, true, true);
-      else KRR_BD(1, false, true);
+      KRR_BD_EPI(1, true)
     } else if (nct == 1) {
-      if (deriv) KRR_BD(1, true, false);
-      else KRR_BD(1, false, false);
+      KRR_BD_EPI(1, false)
     } else if (nct == 2) {
-      if (deriv) KRR_BD(2, true, false);
-      else KRR_BD(2, false, false);
+      KRR_BD_EPI(2, false)
     } else {
-      if (deriv) KRR_BD(4, true, false);
-      else KRR_BD(4, false, false);
+      KRR_BD_EPI(4, false)
     }
+#undef KRR_BD_EPI
 #undef KRR_BD
     KRR_LAUNCH_CHECK();
     return hipSuccess;
   }
+#define KRR_PV1(KS_, NCT_, E_, PK_)                                                           \
+  matmat_f16pv_kernel<KS_, NCT_, E_, PK_><<<grid, 256, 0, st>>>(                              \
+      A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2, dscale,  \
+      part, ldp, part_stride, tps)
 #define KRR_PV(KS_, NCT_, PK_)                                                                \
   if (A.Kp == KS_ * 32 && nct == NCT_ && V.packed == PK_) {                                   \
-    if (deriv)                                                                                \
-      matmat_f16pv_kernel<KS_, NCT_, true, PK_><<<grid, 256, 0, st>>>(                        \
-          A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
-          dscale, part, ldp, part_stride, tps);                                               \
-    else                                                                                      \
-      matmat_f16pv_kernel<KS_, NCT_, false, PK_><<<grid, 256, 0, st>>>(                       \
-          A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2,      \
-          dscale, part, ldp, part_stride, tps);                                               \
+    if (epi == KV_DSIGMA) KRR_PV1(KS_, NCT_, KV_DSIGMA, PK_);                              \
+    else if (epi == KV_POLY) KRR_PV1(KS_, NCT_, KV_POLY, PK_);                             \
+    else KRR_PV1(KS_, NCT_, KV_GAUSS, PK_);                                                  \
     KRR_LAUNCH_CHECK();                                                                       \
     return hipSuccess;                                                                        \
   }
@@ -963,6 +990,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   KRR_PV(1, 1, false) KRR_PV(2, 1, false) KRR_PV(3, 1, false) KRR_PV(4, 1, false)
   KRR_PV(1, 2, false) KRR_PV(2, 2, false) KRR_PV(3, 2, false) KRR_PV(4, 2, false)
 #undef KRR_PV
+#undef KRR_PV1
   return hipErrorInvalidValue;
 }
 
@@ -972,27 +1000,28 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
 // large-d body (runtime feature width) on each. Items are ordered largest first; items of a
 // problem whose columns have all converged (live[inst] == 0) are skipped.
 __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* __restrict__ items,
-                                                              int nitems,
+                                                              const int* __restrict__ list,
+                                                              const int* __restrict__ nlist,
                                                               const BatchInst* __restrict__ inst,
-                                                              const int* __restrict__ live,
                                                               int* __restrict__ counter,
                                                               int packed) {
   __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<1, 4>()];
   __shared__ int cur;
+  const int nitems = *nlist;  // live items only (batch_compact_live)
   for (;;) {
     if (threadIdx.x == 0) cur = atomicAdd(counter, 1);
     __syncthreads();
     const int it = cur;
     __syncthreads();
     if (it >= nitems) break;  // uniform: every wave of the block leaves together
-    const BatchItem wi = items[it];
-    if (!live[wi.inst]) continue;  // uniform per block
+    const BatchItem wi = items[list[it]];
     const BatchInst I = inst[wi.inst];
     const float qinv2 = *I.qinv2;
 #define KRR_BATCH_BODY(U, PK)                                                                    \
-  f16pv_bigd_body<1, U, false, 4, PK>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,   \
-                                      I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, I.part, I.ldp,     \
-                                      I.part_stride, wi.tiles_per_split, wi.rb, wi.split)
+  f16pv_bigd_body<1, U, KV_GAUSS, 4, PK>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl,        \
+                                          I.vscale, I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, 1,  \
+                                          1.0, I.part, I.ldp, I.part_stride, wi.tiles_per_split,  \
+                                          wi.rb, wi.split)
     if (packed) {
       if (qinv2 == 1.0f) KRR_BATCH_BODY(true, true);
       else KRR_BATCH_BODY(false, true);
@@ -1005,11 +1034,12 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
   }
 }
 
-hipError_t matmat_batch(const BatchItem* items, int nitems, const BatchInst* inst,
-                        const int* live, int* counter, bool packed, int grid, hipStream_t st) {
+hipError_t matmat_batch(const BatchItem* items, const int* list, const int* nlist,
+                        const BatchInst* inst, int* counter, bool packed, int grid,
+                        hipStream_t st) {
   hipError_t e = fill_i32(counter, 1, 0, st);
   if (e != hipSuccess) return e;
-  matmat_batch_kernel<<<grid, 256, 0, st>>>(items, nitems, inst, live, counter, packed ? 1 : 0);
+  matmat_batch_kernel<<<grid, 256, 0, st>>>(items, list, nlist, inst, counter, packed ? 1 : 0);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
@@ -1055,7 +1085,7 @@ template <int NCT>
 __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
     const float* __restrict__ Xa, const double* __restrict__ nua, const float* __restrict__ Xb,
     const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
-    int64_t n2, int64_t m, int c0, int dp, double c, int deriv, double dscale,
+    int64_t n2, int64_t m, int c0, int dp, double c, int epi, double dscale, PolyF64 pk,
     double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split) {
   constexpr int VC = 16 * NCT;
   constexpr int LV = VC + 1;
@@ -1169,9 +1199,14 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int jj = 16 * jb + lg + 4 * r;
-            const double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];  // >= 0 up to rounding
-            double p = exp_neg_tab(D * c, sE);
-            if (deriv) p *= D * dscale;
+            double p;
+            if (epi == KV_POLY) {
+              p = pk.value(g[jb][ib][r]);
+            } else {
+              const double D = nui[ib] + sN[jj] - 2.0 * g[jb][ib][r];  // >= 0 up to rounding
+              p = exp_neg_tab(D * c, sE);
+              if (epi == KV_DSIGMA) p *= D * dscale;
+            }
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct)
               acc[ib][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[jj * LV + 16 * ct + li],
@@ -1215,12 +1250,12 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 // fixed order (4 m FMAs per lane and block instead of four FP64 MFMAs padded to 16 columns).
 constexpr int F64I_TJ = 32;
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-template <int KC, int NCT, bool VPV, bool DERIV>
+template <int KC, int NCT, bool VPV, int EPI>
 __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8_kernel(
     const int8_t* __restrict__ Sa, const double* __restrict__ sca, const double* __restrict__ nua,
     const int8_t* __restrict__ Sb, const double* __restrict__ scb, const double* __restrict__ nub,
     const double* __restrict__ V, int64_t ldv, int64_t n1, int64_t n2, int64_t m, int c0, double c,
-    double dscale, double* __restrict__ part, int64_t ldp, int64_t part_stride,
+    double dscale, PolyF64 pk, double* __restrict__ part, int64_t ldp, int64_t part_stride,
     int tiles_per_split) {
   constexpr int KP = 64 * KC;              // bytes per slice row
   constexpr int RB = OZ_SLICES * KP;       // bytes per point
@@ -1345,9 +1380,14 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
         g = fma(g, 256.0, (double)E[6][r]);  // = G_int / 2^32
         // D >= 0 up to rounding (|D| ~ 1e-15 nu for duplicate points): no clamp needed, the
         // exp below is exact in form for small negative arguments, and a NaN stays NaN
-        const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
-        double p = exp_neg_tab(D * c, sE);
-        if (DERIV) p *= D * dscale;
+        double p;
+        if (EPI == KV_POLY) {
+          p = pk.value((-0.5 * ai) * sC[buf][jj] * g);  // <x_i, x_j> (power-of-two scales)
+        } else {
+          const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
+          p = exp_neg_tab(D * c, sE);
+          if (EPI == KV_DSIGMA) p *= D * dscale;
+        }
         if (VPV) {
           const double* vr = &sV[buf][jj * LV];
 #pragma unroll
@@ -1393,9 +1433,11 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
 }
 
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
-                      int64_t m, bool deriv, double c, double dscale, double* part, int64_t ldp,
-                      int64_t part_stride, int nsplit, hipStream_t st) {
+                      int64_t m, int epi, double c, double dscale, const PolyF64& pk,
+                      double* part, int64_t ldp, int64_t part_stride, int nsplit,
+                      hipStream_t st) {
   if (A.dp != B.dp) return hipErrorInvalidValue;
+  if (epi != KV_GAUSS && epi != KV_DSIGMA && epi != KV_POLY) return hipErrorInvalidValue;
   dim3 grid(ceil_div(A.n, 64), nsplit);
   if (A.S && B.S) {
     // int8-slice kernel (d <= 128): 32-point column tiles, up to 32 right-hand sides per pass
@@ -1406,12 +1448,13 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
       const int nct = m - c0 > 16 ? 2 : 1;
 #define KRR_I8(KC_, NCT_, VPV_, DV_)                                                           \
   matmat_f64i8_kernel<KC_, NCT_, VPV_, DV_><<<grid, 256, 0, st>>>(                             \
-      A.S, A.scale, A.nu, B.S, B.scale, B.nu, V, ldv, A.n, B.n, m, (int)c0, c, dscale, part,    \
-      ldp, part_stride, tps)
+      A.S, A.scale, A.nu, B.S, B.scale, B.nu, V, ldv, A.n, B.n, m, (int)c0, c, dscale, pk,     \
+      part, ldp, part_stride, tps)
 #define KRR_I8D(KC_, NCT_, VPV_)                                                               \
   do {                                                                                         \
-    if (deriv) KRR_I8(KC_, NCT_, VPV_, true);                                                  \
-    else KRR_I8(KC_, NCT_, VPV_, false);                                                       \
+    if (epi == KV_DSIGMA) KRR_I8(KC_, NCT_, VPV_, KV_DSIGMA);                                  \
+    else if (epi == KV_POLY) KRR_I8(KC_, NCT_, VPV_, KV_POLY);                                 \
+    else KRR_I8(KC_, NCT_, VPV_, KV_GAUSS);                                                    \
   } while (0)
       const bool vpv = m - c0 <= 8;  // P V on the VALU
       if (kc == 1 && vpv) KRR_I8D(1, 1, true);
@@ -1433,8 +1476,8 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
   for (int64_t c0 = 0; c0 < m; c0 += 64) {
 #define KRR_F64B(NCT_)                                                                        \
   matmat_f64big_kernel<NCT_><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m, \
-                                                    (int)c0, (int)A.dp, c, deriv ? 1 : 0,      \
-                                                    dscale, part, ldp, part_stride, tpsb)
+                                                    (int)c0, (int)A.dp, c, epi, dscale, pk,    \
+                                                    part, ldp, part_stride, tpsb)
     if (m - c0 > 32) KRR_F64B(4);
     else if (m - c0 > 16) KRR_F64B(2);
     else KRR_F64B(1);

@@ -81,22 +81,46 @@ hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float*
 }
 
 // Augmented, scaled, split rows (one wave per row). side 0 writes a_i, side 1 writes b_j.
-// With pshift > 0 a third augmented column (a: q, b: q * pshift) adds pshift to every
-// log2 k, i.e. the products return k * 2^pshift. Rows n..rows_pad-1 and the remaining
-// columns up to Kp are zero. Thread 0 of block 0 also stores 1/q^2 into *qinv2 (identical
-// for both sides: q depends only on the shared stats).
+// Gaussian rows (see the top of the file): <a_i, b_j> = q^2 log2 k. With pshift > 0 a third
+// augmented column (a: q, b: q * pshift) adds pshift to every log2 k, i.e. the products
+// return k * 2^pshift.
+// Polynomial rows (kernel (gamma x^T z + c)^deg, Sec. 6): a_i = q [sqrt(gamma / T) x_i,
+// sqrt(c / T)] on both sides, so <a_i, b_j> = q^2 (gamma <x_i, x_j> + c) / T, where T is the
+// even power of two at or above t_max = gamma max ||x||^2 + c (the Cauchy-Schwarz bound of
+// |gamma x^T z + c|): the scaled value lies in [-1, 1] and its deg-th power cannot overflow;
+// the products are multiplied back by T^deg.
+// Rows n..rows_pad-1 and the remaining columns up to Kp are zero. Thread 0 of block 0 of
+// side 0 also stores the kernel parameters kpar[0] = 1/q^2, kpar[1] = log2 T^deg and
+// kpar[2] = deg (identical for both sides: they depend only on the shared stats).
 template <typename T>
 __global__ __launch_bounds__(256) void prep_points_kernel(
     const float* __restrict__ X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad, int64_t Kp,
-    double c2, const float* __restrict__ stats, int side, int pshift, T* __restrict__ hi,
-    T* __restrict__ lo, float* __restrict__ qinv2) {
+    RowSpec rs, const float* __restrict__ stats, int side, int pshift, T* __restrict__ hi,
+    T* __restrict__ lo, float* __restrict__ kpar) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const double t = sqrt(2.0 * c2);
-  const float amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(c2 * stats[1])),
-                           fmaxf(1.0f, (float)pshift));
+  double t, cterm = 0.0;
+  float amax;
+  int tlog = 0;
+  if (rs.poly) {
+    int e;
+    frexp(rs.gamma * (double)stats[1] + rs.coef0, &e);  // t_max < 2^e
+    tlog = e + (e & 1);                                  // even, so sqrt(1/T) is exact
+    const double tinv = ldexp(1.0, -tlog);
+    t = sqrt(rs.gamma * tinv);
+    cterm = sqrt(rs.coef0 * tinv);
+    amax = fmaxf(fmaxf((float)(t * stats[0]), (float)cterm), 1.0f);
+  } else {
+    t = sqrt(2.0 * rs.c2);
+    amax = fmaxf(fmaxf((float)(t * stats[0]), (float)(rs.c2 * stats[1])),
+                 fmaxf(1.0f, (float)pshift));
+  }
   const float q = point_scale(amax);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && qinv2) *qinv2 = 1.0f / (q * q);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && kpar) {
+    kpar[0] = 1.0f / (q * q);
+    kpar[1] = (float)(tlog * rs.deg);
+    kpar[2] = (float)rs.deg;
+  }
   if (row >= rows_pad) return;
   T* h = hi + row * Kp;
   T* l = lo + row * Kp;
@@ -106,13 +130,16 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
   }
   const float* x = X + row * ldx;
   double nu = 0.0;
-  for (int64_t k = lane; k < d; k += 64) nu += (double)x[k] * (double)x[k];
-  nu = wave_sum(nu);
+  if (!rs.poly) {
+    for (int64_t k = lane; k < d; k += 64) nu += (double)x[k] * (double)x[k];
+    nu = wave_sum(nu);
+  }
   const double qt = (double)q * t;
-  const double qnu = -(double)q * c2 * nu;
+  const double qnu = -(double)q * rs.c2 * nu;
   for (int64_t k = lane; k < Kp; k += 64) {
     double v;
     if (k < d) v = qt * (double)x[k];
+    else if (rs.poly) v = k == d ? (double)q * cterm : 0.0;
     else if (k == d) v = side == 0 ? qnu : (double)q;
     else if (k == d + 1) v = side == 0 ? (double)q : qnu;
     else if (k == d + 2 && pshift > 0) v = side == 0 ? (double)q : (double)q * pshift;
@@ -126,19 +153,19 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
 
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
-                       int64_t Kp, double c2, const float* stats, int side, int pshift, T* hi,
-                       T* lo, float* qinv2, hipStream_t st) {
-  prep_points_kernel<T><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, Kp, c2,
-                                                               stats, side, pshift, hi, lo, qinv2);
+                       int64_t Kp, const RowSpec& rs, const float* stats, int side, int pshift,
+                       T* hi, T* lo, float* kpar, hipStream_t st) {
+  prep_points_kernel<T><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, Kp, rs,
+                                                               stats, side, pshift, hi, lo, kpar);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 template hipError_t prep_points<_Float16>(const float*, int64_t, int64_t, int64_t, int64_t,
-                                          int64_t, double, const float*, int, int, _Float16*,
-                                          _Float16*, float*, hipStream_t);
+                                          int64_t, const RowSpec&, const float*, int, int,
+                                          _Float16*, _Float16*, float*, hipStream_t);
 template hipError_t prep_points<__bf16>(const float*, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                        double, const float*, int, int, __bf16*, __bf16*, float*,
-                                        hipStream_t);
+                                        const RowSpec&, const float*, int, int, __bf16*, __bf16*,
+                                        float*, hipStream_t);
 
 // ------------------------------------------- right-hand sides for the MFMA accumulation
 // colmax[c] = max_i |V[i, c]| (atomic max on the float bit pattern; colmax starts at 0).

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_NOT_SPD", 3: "E_NO_CONV", 4: "E_BREAK
                 5: "E_HIP", 6: "E_WORKSPACE"}
 PREC = {"fp64": 0, "f16x3": 1, "bf16x3": 2}
 (OP_FEATURES, OP_PRECOND_FACTOR, OP_KERNEL_MATMAT, OP_PCG_SOLVE, OP_GRAD, OP_PRECOND_APPLY,
- OP_DSIGMA_INNER) = range(7)
+ OP_DSIGMA_INNER, OP_GAUSSIAN_PROJECT, OP_PRECOND_TEST, OP_ADAPTIVE_FEATURES,
+ OP_AUTOTUNE) = range(11)
 
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -56,6 +57,38 @@ class BatchProblem(ctypes.Structure):
     _fields_ = [("X", _vp), ("n", _i64), ("d", _i64), ("ldx", _i64), ("sigma", _dbl),
                 ("lam", _dbl), ("lambda_p", _dbl), ("Ut", _vp), ("s", _i64), ("ldu", _i64),
                 ("Y", _vp), ("ldy", _i64), ("alpha", _vp), ("lda", _i64), ("m", _i64)]
+
+
+class Kernel(ctypes.Structure):
+    """krr_kernel: the Gaussian or the polynomial kernel (Sec. 6)."""
+    _fields_ = [("kind", _i32), ("degree", _i32), ("sigma", _dbl), ("gamma", _dbl),
+                ("coef0", _dbl)]
+
+    @classmethod
+    def gaussian(cls, sigma: float) -> "Kernel":
+        return cls(0, 1, float(sigma), 0.0, 0.0)
+
+    @classmethod
+    def polynomial(cls, gamma: float, coef0: float, degree: int) -> "Kernel":
+        return cls(1, int(degree), 1.0, float(gamma), float(coef0))
+
+
+class PrecondTestReport(ctypes.Structure):
+    """krr_precond_test_report (Thm. 4 test of a candidate sketch)."""
+    _fields_ = [("cond1", _dbl), ("ratio_lo", _dbl), ("ratio_hi", _dbl), ("rank", _i32),
+                ("passed", _i32), ("power_iters", _i32), ("jacobi_sweeps", _i32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    """krr_tune_report."""
+    _fields_ = [("candidates", _i32), ("default_nsplit", _i32), ("default_pass_width", _i32),
+                ("nsplit", _i32), ("pass_width", _i32), ("default_ms", _dbl), ("best_ms", _dbl)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class BatchReport(ctypes.Structure):
@@ -101,6 +134,40 @@ def lib():
     L.krr_grad.restype = _i32
     L.krr_grad.argtypes = [_vp, _i64, _i64, _i64, _dbl, _vp, _vp, _i64, _i64,
                            ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _i32, _vp, _sz, _vp]
+    L.krr_kernel_matmat_k.restype = _i32
+    L.krr_kernel_matmat_k.argtypes = [ctypes.POINTER(Kernel), _vp, _i64, _i64, _vp, _i64, _i64,
+                                      _i64, _dbl, _vp, _i64, _i64, _vp, _i64, _i32, _i32, _vp,
+                                      _sz, _vp]
+    L.krr_pcg_solve_k.restype = _i32
+    L.krr_pcg_solve_k.argtypes = [ctypes.POINTER(Kernel), _vp, _i64, _i64, _i64, _dbl, _vp, _i64,
+                                  _i64, _vp, _i64, _vp, _i64, _i64, ctypes.POINTER(PCGOpts),
+                                  ctypes.POINTER(PCGReport), _vp, _sz, _vp]
+    L.krr_tensorsketch.restype = _i32
+    L.krr_tensorsketch.argtypes = [_vp, _i64, _i64, _i64, _dbl, _dbl, _i32, _vp, _vp, _i64, _vp,
+                                   _i64, _vp]
+    L.krr_srht.restype = _i32
+    L.krr_srht.argtypes = [_vp, _i64, _i64, _i64, _vp, _vp, _i64, _vp, _i64, _vp]
+    L.krr_gaussian_project.restype = _i32
+    L.krr_gaussian_project.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp]
+    L.krr_precond_test.restype = _i32
+    L.krr_precond_test.argtypes = [ctypes.POINTER(Kernel), _vp, _i64, _i64, _i64, _vp, _i64, _i64,
+                                   _dbl, _i32, _i32, ctypes.POINTER(PrecondTestReport), _vp, _sz,
+                                   _vp]
+    L.krr_adaptive_features.restype = _i32
+    L.krr_adaptive_features.argtypes = [ctypes.POINTER(Kernel), _vp, _i64, _i64, _i64, _dbl, _vp,
+                                        _vp, _vp, _vp, _i64, _i64, _vp, _i64,
+                                        ctypes.POINTER(_i64), ctypes.POINTER(PrecondTestReport),
+                                        _i32, ctypes.POINTER(_i32), _i32, _i32, _vp, _sz, _vp]
+    L.krr_autotune_matmat.restype = _i32
+    L.krr_autotune_matmat.argtypes = [ctypes.POINTER(Kernel), _vp, _i64, _i64, _i64, _i64, _i32,
+                                      ctypes.POINTER(TuneReport), _vp, _sz, _vp]
+    L.krr_tune_cache_save.restype = _i32
+    L.krr_tune_cache_save.argtypes = [ctypes.c_char_p]
+    L.krr_tune_cache_load.restype = _i32
+    L.krr_tune_cache_load.argtypes = [ctypes.c_char_p]
+    L.krr_tune_cache_clear.restype = None
+    L.krr_tune_cache_size.restype = _i32
+    L.krr_tune_digest.restype = ctypes.c_char_p
     L.krr_kernel_matmat_noalloc.restype = _i32
     L.krr_kernel_matmat_noalloc.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _dbl,
                                             _vp, _i64, _i64, _vp, _i64, _i32, _i32, _vp]
@@ -123,6 +190,10 @@ EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_def
             "krr_features", "krr_precond_factor", "krr_precond_apply", "krr_kernel_matmat",
             "krr_pcg_solve",
             "krr_grad", "krr_kernel_dsigma_inner", "krr_kernel_matmat_noalloc",
+            "krr_kernel_matmat_k", "krr_pcg_solve_k", "krr_tensorsketch", "krr_srht",
+            "krr_gaussian_project", "krr_precond_test", "krr_adaptive_features",
+            "krr_autotune_matmat", "krr_tune_cache_save", "krr_tune_cache_load",
+            "krr_tune_cache_clear", "krr_tune_cache_size", "krr_tune_digest",
             "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KRR_NOALLOC_SCRATCH_BYTES
 
@@ -224,6 +295,179 @@ def precond_apply(Ut: torch.Tensor, lambda_p: float, R: torch.Tensor) -> torch.T
     return out[:, 0] if vec else out
 
 
+def kernel_matmat_k(kernel: "Kernel", X1: torch.Tensor, X2: torch.Tensor, V: torch.Tensor,
+                    shift: float = 0.0, deriv: bool = False, prec="f16x3",
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """OUT = K(X1, X2) V + shift V for a kernel descriptor (krr_kernel_matmat_k)."""
+    _check(X1, torch.float32, "X1")
+    _check(X2, torch.float32, "X2")
+    vec = V.dim() == 1
+    V2 = V[:, None] if vec else V
+    _check(V2, torch.float64, "V")
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    m = V2.shape[1]
+    if X2.shape[1] != d or V2.shape[0] != n2:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((n1, m), dtype=torch.float64, device=X1.device)
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_KERNEL_MATMAT, n1, n2, d, 0, m, p), X1.device)
+    st = lib().krr_kernel_matmat_k(ctypes.byref(kernel), X1.data_ptr(), n1, _ld(X1), X2.data_ptr(),
+                                   n2, _ld(X2), d, float(shift), V2.data_ptr(), m, _ld(V2),
+                                   out.data_ptr(), _ld(out), int(bool(deriv)), p, ws.data_ptr(),
+                                   ws.numel(), _stream())
+    _raise(st)
+    return out[:, 0] if vec else out
+
+
+def tensorsketch(X: torch.Tensor, gamma: float, coef0: float, degree: int, hash_: torch.Tensor,
+                 sign: torch.Tensor, s: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """TensorSketch features (krr_tensorsketch) of [sqrt(gamma) x, sqrt(c)]: n x s FP32.
+    hash_: q x (d + 1) int32, sign: q x (d + 1) FP32 of +-1 (device tensors)."""
+    _check(X, torch.float32, "X")
+    n, d = X.shape
+    h = hash_.to(torch.int32) if hash_.dtype != torch.int32 else hash_
+    _check(h, torch.int32, "hash")
+    _check(sign, torch.float32, "sign")
+    if tuple(h.shape) != (int(degree), d + 1) or tuple(sign.shape) != (int(degree), d + 1):
+        raise ValueError("hash and sign must be degree x (d + 1)")
+    if not h.is_contiguous() or not sign.is_contiguous():
+        raise ValueError("hash and sign must be contiguous")
+    if out is None:
+        out = torch.empty((n, int(s)), dtype=torch.float32, device=X.device)
+    _check(out, torch.float32, "out")
+    st = lib().krr_tensorsketch(X.data_ptr(), n, d, _ld(X), float(gamma), float(coef0),
+                                int(degree), h.data_ptr(), sign.data_ptr(), int(s),
+                                out.data_ptr(), _ld(out), _stream())
+    _raise(st)
+    return out
+
+
+def srht(Z1: torch.Tensor, signs: torch.Tensor, sample: torch.Tensor,
+         out: torch.Tensor | None = None) -> torch.Tensor:
+    """Z2 = Z1 S^T, S = s2^{-1/2} P H D (krr_srht); signs: s1 FP32 +-1, sample: s2 int32."""
+    _check(Z1, torch.float32, "Z1")
+    n, s1 = Z1.shape
+    smp = sample.to(torch.int32) if sample.dtype != torch.int32 else sample
+    _check(smp, torch.int32, "sample")
+    _check(signs, torch.float32, "signs")
+    if signs.numel() != s1 or not signs.is_contiguous() or not smp.is_contiguous():
+        raise ValueError("signs must hold s1 values; signs and sample must be contiguous")
+    s2 = smp.numel()
+    if out is None:
+        out = torch.empty((n, s2), dtype=torch.float32, device=Z1.device)
+    _check(out, torch.float32, "out")
+    st = lib().krr_srht(Z1.data_ptr(), n, s1, _ld(Z1), signs.data_ptr(), smp.data_ptr(), s2,
+                        out.data_ptr(), _ld(out), _stream())
+    _raise(st)
+    return out
+
+
+def gaussian_project(Z2: torch.Tensor, S3: torch.Tensor,
+                     out: torch.Tensor | None = None) -> torch.Tensor:
+    """Z3 = s3^{-1/2} Z2 S3^T (krr_gaussian_project); S3: s3 x s2 FP32, N(0, 1) entries."""
+    _check(Z2, torch.float32, "Z2")
+    _check(S3, torch.float32, "S3")
+    n, s2 = Z2.shape
+    s3 = S3.shape[0]
+    if S3.shape[1] != s2 or not S3.is_contiguous():
+        raise ValueError("S3 must be a contiguous s3 x s2 matrix")
+    if out is None:
+        out = torch.empty((n, s3), dtype=torch.float32, device=Z2.device)
+    _check(out, torch.float32, "out")
+    ws = _ws(workspace_bytes(OP_GAUSSIAN_PROJECT, n, n, s2, s3, 0, 1), Z2.device)
+    st = lib().krr_gaussian_project(Z2.data_ptr(), n, s2, _ld(Z2), S3.data_ptr(), s3,
+                                    out.data_ptr(), _ld(out), ws.data_ptr(), ws.numel(), _stream())
+    _raise(st)
+    return out
+
+
+def autotune_matmat(kernel: "Kernel", X: torch.Tensor, m: int, prec="f16x3") -> TuneReport:
+    """Time the product's launch candidates for K(X, X) V with m columns and store the best
+    in the library's tuning table (krr_autotune_matmat)."""
+    _check(X, torch.float32, "X")
+    n, d = X.shape
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_AUTOTUNE, n, n, d, 0, int(m), p), X.device)
+    rep = TuneReport()
+    st = lib().krr_autotune_matmat(ctypes.byref(kernel), X.data_ptr(), n, d, _ld(X), int(m), p,
+                                   ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream())
+    _raise(st)
+    return rep
+
+
+def tune_cache_save(path: str) -> bool:
+    return bool(lib().krr_tune_cache_save(path.encode()))
+
+
+def tune_cache_load(path: str) -> bool:
+    return bool(lib().krr_tune_cache_load(path.encode()))
+
+
+def tune_cache_clear() -> None:
+    lib().krr_tune_cache_clear()
+
+
+def tune_cache_size() -> int:
+    return int(lib().krr_tune_cache_size())
+
+
+def tune_digest() -> str:
+    return lib().krr_tune_digest().decode()
+
+
+def precond_test(kernel: "Kernel", X: torch.Tensor, Z: torch.Tensor, lam: float,
+                 power_iters: int = 40, prec="f16x3") -> PrecondTestReport:
+    """The Thm. 4 test of a candidate sketch Z (krr_precond_test)."""
+    _check(X, torch.float32, "X")
+    _check(Z, torch.float32, "Z")
+    n, d = X.shape
+    s = Z.shape[1]
+    if Z.shape[0] != n:
+        raise ValueError("Z rows must match X")
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_PRECOND_TEST, n, n, d, s, 0, p), X.device)
+    rep = PrecondTestReport()
+    st = lib().krr_precond_test(ctypes.byref(kernel), X.data_ptr(), n, d, _ld(X), Z.data_ptr(), s,
+                                _ld(Z), float(lam), int(power_iters), p, ctypes.byref(rep),
+                                ws.data_ptr(), ws.numel(), _stream())
+    _raise(st)
+    return rep
+
+
+def adaptive_features(kernel: "Kernel", X: torch.Tensor, lam: float, s0: int, s_max: int,
+                      W: torch.Tensor | None = None, b: torch.Tensor | None = None,
+                      hash_: torch.Tensor | None = None, sign: torch.Tensor | None = None,
+                      power_iters: int = 40, prec="f16x3"):
+    """Sec. 5 doubling rule (krr_adaptive_features). Returns (Z[:, :s], s, history)."""
+    _check(X, torch.float32, "X")
+    n, d = X.shape
+    ptrs = []
+    for t, name, dt in ((W, "W", torch.float32), (b, "b", torch.float32),
+                        (hash_, "hash", torch.int32), (sign, "sign", torch.float32)):
+        if t is not None:
+            _check(t, dt, name)
+            if not t.is_contiguous():
+                raise ValueError(f"{name} must be contiguous")
+        ptrs.append(t.data_ptr() if t is not None else None)
+    Z = torch.empty((n, int(s_max)), dtype=torch.float32, device=X.device)
+    p = _prec(prec)
+    ws = _ws(workspace_bytes(OP_ADAPTIVE_FEATURES, n, n, d, int(s_max), 0, p), X.device)
+    cap = 32
+    hist = (PrecondTestReport * cap)()
+    hlen = _i32(0)
+    s_out = _i64(0)
+    st = lib().krr_adaptive_features(ctypes.byref(kernel), X.data_ptr(), n, d, _ld(X), float(lam),
+                                     ptrs[0], ptrs[1], ptrs[2], ptrs[3], int(s0), int(s_max),
+                                     Z.data_ptr(), _ld(Z), ctypes.byref(s_out), hist, cap,
+                                     ctypes.byref(hlen), int(power_iters), p, ws.data_ptr(),
+                                     ws.numel(), _stream())
+    _raise(st)
+    s = int(s_out.value)
+    return Z[:, :s], s, [hist[i].as_dict() for i in range(min(hlen.value, cap))]
+
+
 def kernel_matmat(X1: torch.Tensor, X2: torch.Tensor, sigma: float, V: torch.Tensor,
                   shift: float = 0.0, deriv: bool = False, prec="f16x3",
                   out: torch.Tensor | None = None) -> torch.Tensor:
@@ -290,12 +534,20 @@ class SolveReport:
     matmat_ms: float = 0.0
 
 
-def pcg_solve(X: torch.Tensor, sigma: float, lam: float, Ut: torch.Tensor | None,
+def pcg_solve_k(kernel: "Kernel", X: torch.Tensor, lam: float, Ut: torch.Tensor | None,
+                Y: torch.Tensor, **kw):
+    """pcg_solve for a kernel descriptor (krr_pcg_solve_k). Returns (alpha, SolveReport)."""
+    return pcg_solve(X, None, lam, Ut, Y, kernel=kernel, **kw)
+
+
+def pcg_solve(X: torch.Tensor, sigma: float | None, lam: float, Ut: torch.Tensor | None,
               Y: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000, prec="f16x3",
               use_precond: bool = True, lambda_p: float | None = None, check_every: int = 1,
               true_residual: bool = True, refine: int = 0, alpha0: torch.Tensor | None = None,
-              raise_on_error: bool = True, history_cap: int = 4096):
-    """Solve (K + lam I) alpha = Y by PCG. Returns (alpha, SolveReport)."""
+              raise_on_error: bool = True, history_cap: int = 4096,
+              kernel: "Kernel | None" = None):
+    """Solve (K + lam I) alpha = Y by PCG (Gaussian kernel of bandwidth sigma, or `kernel`).
+    Returns (alpha, SolveReport)."""
     _check(X, torch.float32, "X")
     vec = Y.dim() == 1
     Y2 = Y[:, None] if vec else Y
@@ -331,9 +583,16 @@ def pcg_solve(X: torch.Tensor, sigma: float, lam: float, Ut: torch.Tensor | None
     rep.history = ctypes.cast(hist, ctypes.POINTER(_dbl))
     rep.history_cap = history_cap
     ws = _ws(workspace_bytes(OP_PCG_SOLVE, n, n, d, s, m, p), X.device)
-    st = lib().krr_pcg_solve(X.data_ptr(), n, d, _ld(X), float(sigma), float(lam), uptr, s, ldu,
-                             Y2.data_ptr(), _ld(Y2), alpha.data_ptr(), m, m, ctypes.byref(opts),
-                             ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream())
+    if kernel is None:
+        st = lib().krr_pcg_solve(X.data_ptr(), n, d, _ld(X), float(sigma), float(lam), uptr, s,
+                                 ldu, Y2.data_ptr(), _ld(Y2), alpha.data_ptr(), m, m,
+                                 ctypes.byref(opts), ctypes.byref(rep), ws.data_ptr(), ws.numel(),
+                                 _stream())
+    else:
+        st = lib().krr_pcg_solve_k(ctypes.byref(kernel), X.data_ptr(), n, d, _ld(X), float(lam),
+                                   uptr, s, ldu, Y2.data_ptr(), _ld(Y2), alpha.data_ptr(), m, m,
+                                   ctypes.byref(opts), ctypes.byref(rep), ws.data_ptr(),
+                                   ws.numel(), _stream())
     report = SolveReport(st, rep.iters, rep.converged_cols, rep.breakdown_cols, rep.refine_steps,
                          [rec[i] for i in range(m)], [tru[i] for i in range(m)],
                          [hist[i] for i in range(rep.history_len)], rep.matmat_calls,

@@ -183,3 +183,63 @@ def batched_instances(count: int = 64, n_lo: int = 1024, n_hi: int = 16384,
         W, b = rff_draw(d, s, sigma, rng_for(family, 2, salt * 1000 + t + 1))
         out.append(Workload(f"batched_{t}", X, Y, sigma, lam, s, W, b, tol))
     return out
+
+
+# ------------------------------------------------------------ polynomial kernel workloads
+@dataclasses.dataclass
+class PolyWorkload:
+    """A polynomial-kernel problem (gamma x^T z + c)^q with its TensorSketch draw."""
+    name: str
+    X: np.ndarray            # n x d float32
+    Y: np.ndarray            # n x m float64
+    gamma: float
+    coef0: float
+    degree: int
+    lam: float
+    s: int
+    hash: np.ndarray         # degree x (d + 1) int32 in [0, s)
+    sign: np.ndarray         # degree x (d + 1) float32 of +-1
+    tol: float
+
+    @property
+    def n(self):
+        return self.X.shape[0]
+
+    @property
+    def d(self):
+        return self.X.shape[1]
+
+    @property
+    def m(self):
+        return self.Y.shape[1]
+
+
+def tensorsketch_draw(d: int, q: int, s: int, rng: np.random.Generator):
+    """Hashes h_k: [d + 1] -> [s] and signs g_k: [d + 1] -> {+1, -1} for q CountSketches of the
+    augmented points (fully random tables)."""
+    h = rng.integers(0, s, size=(q, d + 1)).astype(np.int32)
+    g = rng.choice(np.array([-1.0, 1.0], np.float32), size=(q, d + 1)).astype(np.float32)
+    return h, g
+
+
+def polynomial_mixture(n: int = 65536, d: int = 54, k: int = 7, s: int = 2048, degree: int = 3,
+                       lam_per_n: float = 1e-4, tol: float = 1e-6, salt: int = 0) -> PolyWorkload:
+    """The mixture points and labels of mixture_multi_rhs with the polynomial kernel
+    (x^T z / d + 1)^3 (gamma = 1/d, c = 1, q = 3) and s TensorSketch features."""
+    w = mixture_multi_rhs(n=n, d=d, k=k, s=2, lam_per_n=lam_per_n, tol=tol, salt=salt)
+    h, g = tensorsketch_draw(d, degree, s, rng_for(6, 2, salt))
+    return PolyWorkload("polynomial_mixture", w.X, w.Y, 1.0 / d, 1.0, degree, lam_per_n * n, s,
+                        h, g, tol)
+
+
+def multilevel_draw(s1: int, s2: int, s3: int, rng: np.random.Generator):
+    """Random parts of the multiple-level sketch: SRHT signs (s1), s2 coordinates sampled
+    without replacement from the power-of-two padded width, and the s3 x s2 standard normal
+    projection, all FP32 / int32."""
+    p = 1
+    while p < s1:
+        p *= 2
+    signs = rng.choice(np.array([-1.0, 1.0], np.float32), size=s1).astype(np.float32)
+    sample = np.sort(rng.choice(p, size=s2, replace=False)).astype(np.int32)
+    S3 = rng.standard_normal((s3, s2)).astype(np.float32)
+    return signs, sample, S3

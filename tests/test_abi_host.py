@@ -148,7 +148,9 @@ def _c_layout(struct, fields):
 @pytest.mark.parametrize("struct,cls", [("krr_pcg_opts", krr.PCGOpts),
                                         ("krr_pcg_report", krr.PCGReport),
                                         ("krr_batch_problem", krr.BatchProblem),
-                                        ("krr_batch_report", krr.BatchReport)])
+                                        ("krr_batch_report", krr.BatchReport),
+                                        ("krr_kernel", krr.Kernel),
+                                        ("krr_precond_test_report", krr.PrecondTestReport)])
 def test_binding_structs_match_header_layout(struct, cls):
     names = [f[0] for f in cls._fields_]
     cnames = ["lambda" if n == "lam" else n for n in names]
@@ -205,3 +207,73 @@ def test_batch_plan_validation_before_device_work():
     st = L.krr_batch_solve(None, None, None)
     assert st == krr.E_ARG
     L.krr_batch_plan_destroy(None)
+
+
+def test_kernel_descriptor_validation_before_device_work():
+    L = krr.lib()
+    fake = ctypes.c_void_p(256)
+    null = None
+
+    def mm(k, prec=1, deriv=0):
+        return L.krr_kernel_matmat_k(ctypes.byref(k) if k is not None else None, fake, 10, 3, fake,
+                                     10, 3, 3, 0.0, fake, 1, 1, fake, 1, deriv, prec, fake, 1 << 30,
+                                     null)
+    assert mm(None) == krr.E_ARG and "descriptor" in krr.last_error()
+    assert mm(krr.Kernel.gaussian(-1.0)) == krr.E_ARG and "sigma" in krr.last_error()
+    assert mm(krr.Kernel.polynomial(1.0, 1.0, 0)) == krr.E_ARG and "degree" in krr.last_error()
+    assert mm(krr.Kernel.polynomial(1.0, 1.0, 17)) == krr.E_ARG
+    assert mm(krr.Kernel.polynomial(-0.5, 1.0, 2)) == krr.E_ARG and "gamma" in krr.last_error()
+    assert mm(krr.Kernel.polynomial(1.0, float("nan"), 2)) == krr.E_ARG
+    assert mm(krr.Kernel.polynomial(1.0, 1.0, 2), prec=2) == krr.E_ARG and "F16X3" in krr.last_error()
+    assert mm(krr.Kernel.polynomial(1.0, 1.0, 2), deriv=1) == krr.E_ARG and "deriv" in krr.last_error()
+    k = krr.Kernel(7, 1, 1.0, 0.0, 0.0)
+    assert mm(k) == krr.E_ARG and "kind" in krr.last_error()
+    o = krr.PCGOpts()
+    L.krr_pcg_defaults(ctypes.byref(o))
+    st = L.krr_pcg_solve_k(None, fake, 10, 3, 3, 1.0, fake, 4, 4, fake, 1, fake, 1, 1,
+                           ctypes.byref(o), None, fake, 1 << 30, null)
+    assert st == krr.E_ARG and "descriptor" in krr.last_error()
+    o.prec = 2
+    st = L.krr_pcg_solve_k(ctypes.byref(krr.Kernel.polynomial(1.0, 1.0, 3)), fake, 10, 3, 3, 1.0,
+                           fake, 4, 4, fake, 1, fake, 1, 1, ctypes.byref(o), None, fake, 1 << 30, null)
+    assert st == krr.E_ARG and "F16X3" in krr.last_error()
+
+
+def test_tensorsketch_validation_before_device_work():
+    L = krr.lib()
+    fake = ctypes.c_void_p(256)
+    ts = L.krr_tensorsketch
+    assert ts(None, 10, 3, 3, 1.0, 1.0, 2, fake, fake, 64, fake, 64, None) == krr.E_ARG
+    assert ts(fake, 10, 3, 3, 1.0, 1.0, 2, fake, fake, 48, fake, 64, None) == krr.E_ARG
+    assert "power of two" in krr.last_error()
+    assert ts(fake, 10, 3, 3, 1.0, 1.0, 2, fake, fake, 16384, fake, 16384, None) == krr.E_ARG
+    assert ts(fake, 10, 3, 3, 1.0, 1.0, 0, fake, fake, 64, fake, 64, None) == krr.E_ARG
+    assert ts(fake, 10, 3, 3, -1.0, 1.0, 2, fake, fake, 64, fake, 64, None) == krr.E_ARG
+    assert ts(fake, 10, 3, 3, 1.0, 1.0, 2, fake, fake, 64, fake, 32, None) == krr.E_ARG
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The tuning table's file: entries written for this build's digest read back; a file of
+    another build (digest) or architecture is ignored."""
+    dg = krr.tune_digest()
+    assert dg and dg != "unversioned"
+    src = tmp_path / "tune.json"
+    src.write_text('{"arch": "gfx950", "digest": "%s", "entries": [\n'
+                   '  [1, 0, 64, 3, 16, 4, 0, 1.500000, 1.400000],\n'
+                   '  [0, 0, 800, 4, 18, 8, 32, 420.0, 400.0]\n]}\n' % dg)
+    krr.tune_cache_clear()
+    assert krr.tune_cache_size() == 0
+    assert krr.tune_cache_load(str(src))
+    assert krr.tune_cache_size() == 2
+    out = tmp_path / "out.json"
+    assert krr.tune_cache_save(str(out))
+    krr.tune_cache_clear()
+    assert krr.tune_cache_load(str(out)) and krr.tune_cache_size() == 2
+    txt = out.read_text()
+    assert "[1, 0, 64, 3, 16, 4, 0, 1.500000, 1.400000]" in txt and dg in txt
+    krr.tune_cache_clear()
+    other = tmp_path / "other.json"
+    other.write_text(txt.replace(dg, "0000000000000000"))
+    assert not krr.tune_cache_load(str(other)) and krr.tune_cache_size() == 0
+    assert not krr.tune_cache_load(str(tmp_path / "missing.json"))
+    krr.tune_cache_clear()

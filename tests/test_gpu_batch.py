@@ -161,3 +161,26 @@ def test_batch_full_recipe(dev):
         r = w.Y[rows] - O.kernel_matmat(w.X, w.X, w.sigma, a, shift=w.lam, rows=rows)
         est = np.linalg.norm(r, axis=0) / np.linalg.norm(w.Y[rows], axis=0)
         assert est.max() <= 4e-6, (i, est)
+
+
+def test_batch_small_lambda_members_follow_oracle_iterations(dev):
+    """The full recipe's small-lambda members (lambda <= 1e-4 n, n <= 3000): each first solve
+    stops on the tolerance well before max_iter, and its iteration count follows the oracle's
+    FP64 PCG with the oracle's own preconditioner from the same W, b (mixed products add a
+    few percent of iterations near the floor; Thm. 1 fixes no count for random Fourier
+    features, so the margin is empirical: 15 % + 10 either way)."""
+    ws = WL.batched_instances()
+    probs = _problems(ws, dev)
+    plan = krr.BatchPlan(probs, tol=1e-6, refine=4)
+    _, rep = plan.solve()
+    plan.close()
+    assert all(max(c[:w.m]) < 1000 for c, w in zip(rep.col_iters, ws))
+    picked = [i for i, w in enumerate(ws) if w.lam <= 1e-4 * w.n and w.n <= 3000]
+    assert len(picked) >= 4
+    for i in picked:
+        w = ws[i]
+        Z = O.rff_features(w.X, w.W, w.b)
+        _, U = O.precond_factor(Z, w.lam)
+        res = O.krr_pcg(w.X, w.sigma, w.lam, w.Y, U=U, tol=1e-6, max_iter=3000)
+        gpu = max(rep.col_iters[i][:w.m])
+        assert 0.85 * res.iters - 10 <= gpu <= 1.15 * res.iters + 10, (i, w.n, gpu, res.iters)
