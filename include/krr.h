@@ -164,6 +164,47 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
                              int32_t prec, void* ws, size_t ws_bytes, void* stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Set-up of many problems at once (features and factor of Alg. 1 for each, e.g. before a
+ * batched solve). The factor of one problem is a chain of short, latency-bound kernels (the
+ * blocked Cholesky); krr_setup_many spreads the problems over up to KRR_SETUP_MAX_STREAMS
+ * internal streams (default priority), largest first to the least loaded stream, so the
+ * chains of different problems overlap on the device, and checks all pivots once at the end.
+ */
+#define KRR_SETUP_MAX_STREAMS 4
+
+typedef struct krr_setup_problem {
+  const float* X;            /* n x d FP32 points (ldx >= d), DEVICE */
+  int64_t n, d, ldx;
+  const float* W;            /* d x s FP32 random Fourier feature draw (leading dimension s) */
+  const float* b;            /* s FP32 offsets */
+  int64_t s;                 /* 1 <= s < n */
+  double lambda_p;           /* > 0 */
+  float* Z;                  /* n x s FP32 features, written (ldz >= s) */
+  int64_t ldz;
+  double* C;                 /* s x s FP64 factor, written (as krr_precond_factor) */
+  float* Ut;                 /* n x s FP32, written (ldu >= s) */
+  int64_t ldu;
+  int64_t info;              /* written: 0, or the failing pivot + 1 */
+} krr_setup_problem;
+
+/* Workspace of krr_setup_many: one slot (the largest problem's features or factor
+ * workspace) per stream, plus the pivot flags. */
+size_t krr_setup_many_workspace_bytes(const krr_setup_problem* probs, int32_t count,
+                                      int32_t nstreams);
+
+/*
+ * krr_setup_many -- krr_features then krr_precond_factor for each of `count` problems (HOST
+ * array; each problem's info is written back), on min(nstreams, KRR_SETUP_MAX_STREAMS)
+ * internal streams that start after the work already queued on `stream`; `stream` waits for
+ * them and is synchronised before the call returns. Same arithmetic as the two single calls.
+ * Errors: KRR_E_ARG (checked for every problem before any device work), KRR_E_WORKSPACE,
+ * KRR_E_NOT_SPD (the first failing problem named in krr_last_error; every info is set),
+ * KRR_E_HIP.
+ */
+krr_status krr_setup_many(krr_setup_problem* probs, int32_t count, int32_t nstreams, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------------------------------
  * Kernel descriptor. The Gaussian kernel k(x, z) = exp(-||x - z||^2 / (2 sigma^2)) and the
  * polynomial kernel k(x, z) = (gamma x^T z + c)^q are the two kernels of the paper's
  * experiments (Sec. 6); the homogeneous polynomial kernel (gamma = 1, c = 0) is the kernel

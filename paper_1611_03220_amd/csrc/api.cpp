@@ -370,6 +370,37 @@ krr_status gram_cholesky(const float* Z, int64_t n, int64_t s, int64_t ldz, doub
   return KRR_OK;
 }
 
+// gram_cholesky without the host check of the pivot (L.info holds it on the device)
+hipError_t gram_cholesky_async(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
+                               FactorLayout& L, hipStream_t st) {
+  hipError_t e;
+  if ((e = fill_f32(L.stats, 4, 0.0f, st))) return e;
+  if ((e = fill_i32(L.info, 1, 0, st))) return e;
+  if ((e = absmax<float>(Z, n, s, ldz, L.stats + 0, st))) return e;
+  if ((e = split_operand<float, _Float16>(Z, n, s, ldz, L.stats + 0, 1, L.sp64, L.nk, L.h1, L.l1, st))) return e;
+  SplitOperand Zt{L.h1, L.l1, L.nk, L.stats + 0};
+  if ((e = gemm_nt_f16x3(Zt, Zt, s, s, L.nk, L.nsplit, EPI_PART64, 1, 0, 1.0, L.part, s * s,
+                         nullptr, s, nullptr, 0.0f, st))) return e;
+  if ((e = gram_finalize(L.part, L.nsplit, s, s, s * s, lambda_p, L.s_pad, L.G, st))) return e;
+  if ((e = fill_f64(L.Cinv, L.s_pad * L.s_pad, 0.0, st))) return e;
+  return cholesky_blocked(L.G, L.s_pad, L.Cinv, L.info, st);
+}
+
+// after the Cholesky factor in L.G: C (lower, s x s), C^{-1} by doubling, Ut = Z C^{-T}
+hipError_t factor_finish(FactorLayout& L, const float* Z, int64_t n, int64_t s, int64_t ldz,
+                         double* C, float* Ut, int64_t ldu, hipStream_t st) {
+  hipError_t e;
+  if ((e = tri_inverse_doubling(L.G, L.s_pad, L.Cinv, L.tmp, st))) return e;
+  if ((e = copy_lower(L.G, L.s_pad, s, C, st))) return e;
+  // Ut = Z C^{-T}: A = Z (n x s), B = C^{-1} (rows j, contraction k), lower triangular
+  if ((e = absmax<double>(L.Cinv, s, s, L.s_pad, L.stats + 1, st))) return e;
+  if ((e = split_operand<float, _Float16>(Z, n, s, ldz, L.stats + 0, 0, L.np, L.sk, L.h1, L.l1, st))) return e;
+  if ((e = split_operand<double, _Float16>(L.Cinv, s, s, L.s_pad, L.stats + 1, 0, L.sp64, L.sk, L.ch, L.cl, st))) return e;
+  SplitOperand A{L.h1, L.l1, L.sk, L.stats + 0}, B{L.ch, L.cl, L.sk, L.stats + 1};
+  return gemm_nt_f16x3(A, B, n, s, L.sk, 1, EPI_F32, 0, 1, 1.0, nullptr, 0, Ut, ldu, nullptr, 0.0f,
+                       st);
+}
+
 // ---------------------------------------------------------------------- PCG
 struct PCGLayout {
   MatmatCtx mm;      // kernel product in the solve precision
@@ -646,16 +677,116 @@ krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz,
   layout_factor(bb, L, n, s);
   hipStream_t st = (hipStream_t)stream;
   CHECK_ST(gram_cholesky(Z, n, s, ldz, lambda_p, L, info, "krr_precond_factor", st));
-  CHECK_HIP(tri_inverse_doubling(L.G, L.s_pad, L.Cinv, L.tmp, st));
-  CHECK_HIP(copy_lower(L.G, L.s_pad, s, C, st));
-  // Ut = Z C^{-T}: A = Z (n x s), B = C^{-1} (rows j, contraction k), lower triangular
-  CHECK_HIP(absmax<double>(L.Cinv, s, s, L.s_pad, L.stats + 1, st));
-  CHECK_HIP((split_operand<float, _Float16>(Z, n, s, ldz, L.stats + 0, 0, L.np, L.sk, L.h1, L.l1, st)));
-  CHECK_HIP((split_operand<double, _Float16>(L.Cinv, s, s, L.s_pad, L.stats + 1, 0, L.sp64, L.sk, L.ch, L.cl, st)));
-  SplitOperand A{L.h1, L.l1, L.sk, L.stats + 0}, B{L.ch, L.cl, L.sk, L.stats + 1};
-  CHECK_HIP(gemm_nt_f16x3(A, B, n, s, L.sk, 1, EPI_F32, 0, 1, 1.0, nullptr, 0, Ut, ldu, nullptr,
-                          0.0f, st));
+  CHECK_HIP(factor_finish(L, Z, n, s, ldz, C, Ut, ldu, st));
   CHECK_HIP(hipStreamSynchronize(st));
+  return KRR_OK;
+}
+
+// ------------------------------------------------ set-up of many problems on several streams
+namespace {
+size_t setup_slot_bytes(const krr_setup_problem& p) {
+  Bump f(nullptr), g(nullptr);
+  FeatLayout FL;
+  layout_features(f, FL, p.n, p.d, p.s);
+  FactorLayout L;
+  layout_factor(g, L, p.n, p.s);
+  return round_up((int64_t)std::max(f.off, g.off), 256) + 256;
+}
+}  // namespace
+
+size_t krr_setup_many_workspace_bytes(const krr_setup_problem* probs, int32_t count,
+                                      int32_t nstreams) {
+  if (!probs || count < 1) return 0;
+  size_t slot = 0;
+  for (int i = 0; i < count; ++i)
+    if (probs[i].n >= 2 && probs[i].s >= 1 && probs[i].d >= 1) slot = std::max(slot, setup_slot_bytes(probs[i]));
+  const int k = std::max(1, std::min<int32_t>(nstreams, KRR_SETUP_MAX_STREAMS));
+  return k * slot + round_up((int64_t)count * (int64_t)sizeof(int), 256) + 512;
+}
+
+krr_status krr_setup_many(krr_setup_problem* probs, int32_t count, int32_t nstreams, void* ws,
+                          size_t ws_bytes, void* stream) {
+  g_err[0] = 0;
+  if (!probs || count < 1) return fail(KRR_E_ARG, "krr_setup_many: no problems");
+  for (int i = 0; i < count; ++i) {
+    krr_setup_problem& p = probs[i];
+    p.info = 0;
+    if (!p.X || !p.W || !p.b || !p.Z || !p.C || !p.Ut)
+      return fail(KRR_E_ARG, "krr_setup_many: problem %d: null pointer", i);
+    if (p.n < 2 || p.d < 1 || p.s < 1 || p.s >= p.n || p.ldx < p.d || p.ldz < p.s || p.ldu < p.s)
+      return fail(KRR_E_ARG, "krr_setup_many: problem %d: need 1 <= s < n, ld >= row length", i);
+    if (!(p.lambda_p > 0.0) || !std::isfinite(p.lambda_p))
+      return fail(KRR_E_ARG, "krr_setup_many: problem %d: lambda_p must be > 0", i);
+  }
+  const int k = std::max(1, std::min<int32_t>(nstreams, KRR_SETUP_MAX_STREAMS));
+  const size_t need = krr_setup_many_workspace_bytes(probs, count, k);
+  CHECK_ST(check_ws(ws, ws_bytes, need));
+  size_t slot = 0;
+  for (int i = 0; i < count; ++i) slot = std::max(slot, setup_slot_bytes(probs[i]));
+  char* base = static_cast<char*>(ws);
+  int* infos = reinterpret_cast<int*>(base + k * slot);
+  hipStream_t st = (hipStream_t)stream;
+  // streams at the default priority; they start after the work already on `stream` and the
+  // caller's stream waits for all of them at the end
+  std::vector<hipStream_t> ss(k, nullptr);
+  std::vector<hipEvent_t> ev(k + 1, nullptr);
+  auto cleanup = [&]() {
+    for (auto& e : ev) if (e) (void)hipEventDestroy(e);
+    for (auto& q : ss) if (q) (void)hipStreamDestroy(q);
+  };
+  hipError_t e = hipSuccess;
+  for (int j = 0; j <= k && e == hipSuccess; ++j) e = hipEventCreateWithFlags(&ev[j], hipEventDisableTiming);
+  for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamCreateWithFlags(&ss[j], hipStreamNonBlocking);
+  if (e == hipSuccess) e = fill_i32(infos, count, 0, st);
+  if (e == hipSuccess) e = hipEventRecord(ev[k], st);
+  for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamWaitEvent(ss[j], ev[k], 0);
+  if (e != hipSuccess) { cleanup(); return fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e)); }
+  // largest problems first, each to the stream with the least estimated work so far
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  auto cost = [&](int i) { return (double)probs[i].n * (double)probs[i].s * (double)(probs[i].s + probs[i].d); };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  std::vector<double> load(k, 0.0);
+  krr_status status = KRR_OK;
+  for (int i : order) {
+    const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[j] += cost(i);
+    krr_setup_problem& p = probs[i];
+    void* wsj = base + j * slot;
+    status = features_impl("krr_setup_many", p.X, p.n, p.d, p.ldx, p.W, p.s, p.b, p.s, p.Z, p.ldz,
+                           wsj, slot, ss[j]);
+    if (status != KRR_OK) break;
+    Bump bb(wsj);
+    FactorLayout L;
+    layout_factor(bb, L, p.n, p.s);
+    e = gram_cholesky_async(p.Z, p.n, p.s, p.ldz, p.lambda_p, L, ss[j]);
+    if (e == hipSuccess) e = hipMemcpyAsync(infos + i, L.info, sizeof(int), hipMemcpyDeviceToDevice, ss[j]);
+    if (e == hipSuccess) e = factor_finish(L, p.Z, p.n, p.s, p.ldz, p.C, p.Ut, p.ldu, ss[j]);
+    if (e != hipSuccess) { status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e)); break; }
+  }
+  for (int j = 0; j < k; ++j) {
+    hipError_t e2 = hipEventRecord(ev[j], ss[j]);
+    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(st, ev[j], 0);
+    if (e2 != hipSuccess && status == KRR_OK) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e2));
+  }
+  std::vector<int> h(count, 0);
+  if (status == KRR_OK) {
+    e = hipMemcpyAsync(h.data(), infos, sizeof(int) * count, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
+  } else {
+    (void)hipStreamSynchronize(st);
+  }
+  cleanup();
+  if (status != KRR_OK) return status;
+  int bad = -1;
+  for (int i = 0; i < count; ++i) {
+    probs[i].info = h[i];
+    if (h[i] != 0 && bad < 0) bad = i;
+  }
+  if (bad >= 0)
+    return fail(KRR_E_NOT_SPD, "krr_setup_many: problem %d: Z^T Z + lambda_p I not positive definite at pivot %d",
+                bad, h[bad]);
   return KRR_OK;
 }
 
@@ -915,11 +1046,7 @@ hipError_t timed_matmat(MMTimer* tm, const MatmatCtx& c, float* Vf, const double
 
 hipError_t fill2d_zero(double* a, int64_t lda, int64_t n, int64_t m, hipStream_t st) {
   if (lda == m) return fill_f64(a, n * m, 0.0, st);
-  for (int64_t i = 0; i < n; ++i) {  // strided: one small fill per row is acceptable here
-    hipError_t e = fill_f64(a + i * lda, m, 0.0, st);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  return fill2d_f64(a, lda, n, m, 0.0, st);  // strided: one launch over the n x m block
 }
 
 struct SolveArgs {

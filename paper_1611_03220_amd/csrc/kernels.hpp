@@ -43,6 +43,7 @@ enum { EPI_PART64 = 0, EPI_F32 = 1, EPI_COS = 2 };
 hipError_t fill_f32(float* p, int64_t count, float v, hipStream_t st);
 hipError_t fill_f64(double* p, int64_t count, double v, hipStream_t st);
 hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st);
+hipError_t fill2d_f64(double* p, int64_t ld, int64_t rows, int64_t cols, double v, hipStream_t st);
 hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float* stats,
                        hipStream_t st);
 // What the augmented rows of the mixed products encode (see prep.hip).

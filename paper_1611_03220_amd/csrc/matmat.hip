@@ -258,6 +258,9 @@ template hipError_t matmat_mixed<__bf16>(const MixedPoints<__bf16>&, const Mixed
 template <int EPI>
 __device__ __forceinline__ float epi_value(float l, float dscale, int deg) {
   if (EPI == KV_POLY) {
+    // the degree is uniform across the launch: the common degrees take straight-line code
+    if (deg == 3) return l * l * l;
+    if (deg == 2) return l * l;
     float p = l;
     for (int e = 1; e < deg; ++e) p *= l;
     return p;

@@ -36,6 +36,16 @@ hipError_t fill_f64(double* p, int64_t count, double v, hipStream_t st) {
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
+__global__ void fill2d_f64_kernel(double* p, int64_t ld, int64_t rows, int64_t cols, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < rows * cols) p[(e / cols) * ld + e % cols] = v;
+}
+hipError_t fill2d_f64(double* p, int64_t ld, int64_t rows, int64_t cols, double v, hipStream_t st) {
+  if (rows * cols <= 0) return hipSuccess;
+  fill2d_f64_kernel<<<ceil_div(rows * cols, 256), 256, 0, st>>>(p, ld, rows, cols, v);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
 hipError_t fill_i32(int* p, int64_t count, int v, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   fill_i32_kernel<<<ceil_div(count, 256), 256, 0, st>>>(p, count, v);

@@ -91,6 +91,13 @@ class TuneReport(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SetupProblem(ctypes.Structure):
+    """krr_setup_problem."""
+    _fields_ = [("X", _vp), ("n", _i64), ("d", _i64), ("ldx", _i64), ("W", _vp), ("b", _vp),
+                ("s", _i64), ("lambda_p", _dbl), ("Z", _vp), ("ldz", _i64), ("C", _vp),
+                ("Ut", _vp), ("ldu", _i64), ("info", _i64)]
+
+
 class BatchReport(ctypes.Structure):
     _fields_ = [("iters", _i32), ("converged_cols", _i32), ("breakdown_cols", _i32),
                 ("refine_steps", _i32),
@@ -168,6 +175,10 @@ def lib():
     L.krr_tune_cache_clear.restype = None
     L.krr_tune_cache_size.restype = _i32
     L.krr_tune_digest.restype = ctypes.c_char_p
+    L.krr_setup_many_workspace_bytes.restype = _sz
+    L.krr_setup_many_workspace_bytes.argtypes = [ctypes.POINTER(SetupProblem), _i32, _i32]
+    L.krr_setup_many.restype = _i32
+    L.krr_setup_many.argtypes = [ctypes.POINTER(SetupProblem), _i32, _i32, _vp, _sz, _vp]
     L.krr_kernel_matmat_noalloc.restype = _i32
     L.krr_kernel_matmat_noalloc.argtypes = [_vp, _i64, _i64, _vp, _i64, _i64, _i64, _dbl, _dbl,
                                             _vp, _i64, _i64, _vp, _i64, _i32, _i32, _vp]
@@ -194,6 +205,7 @@ EXPORTED = ["krr_workspace_bytes", "krr_last_error", "krr_version", "krr_pcg_def
             "krr_gaussian_project", "krr_precond_test", "krr_adaptive_features",
             "krr_autotune_matmat", "krr_tune_cache_save", "krr_tune_cache_load",
             "krr_tune_cache_clear", "krr_tune_cache_size", "krr_tune_digest",
+            "krr_setup_many", "krr_setup_many_workspace_bytes",
             "krr_batch_plan_create", "krr_batch_solve", "krr_batch_plan_destroy"]
 NOALLOC_SCRATCH_BYTES = 64 << 20   # KRR_NOALLOC_SCRATCH_BYTES
 
@@ -381,6 +393,34 @@ def gaussian_project(Z2: torch.Tensor, S3: torch.Tensor,
                                     out.data_ptr(), _ld(out), ws.data_ptr(), ws.numel(), _stream())
     _raise(st)
     return out
+
+
+def setup_many(problems: list, nstreams: int = 4) -> list:
+    """Features and factor for many problems at once (krr_setup_many). Each problem is a dict
+    with X, W, b, lam (lambda_p); returns [(Z, C, Ut), ...] in the same order."""
+    arr = (SetupProblem * len(problems))()
+    keep = []
+    for i, pr in enumerate(problems):
+        X, W, b = pr["X"], pr["W"], pr["b"]
+        _check(X, torch.float32, "X")
+        _check(W, torch.float32, "W")
+        _check(b, torch.float32, "b")
+        n, d = X.shape
+        s = W.shape[1]
+        if W.shape[0] != d or not W.is_contiguous() or b.numel() != s:
+            raise ValueError("W must be a contiguous d x s matrix and b hold s values")
+        Z = torch.empty((n, s), dtype=torch.float32, device=X.device)
+        C = torch.empty((s, s), dtype=torch.float64, device=X.device)
+        Ut = torch.empty((n, s), dtype=torch.float32, device=X.device)
+        arr[i] = SetupProblem(X.data_ptr(), n, d, _ld(X), W.data_ptr(), b.data_ptr(), s,
+                              float(pr["lam"]), Z.data_ptr(), s, C.data_ptr(), Ut.data_ptr(), s, 0)
+        keep.append((Z, C, Ut))
+    nb = lib().krr_setup_many_workspace_bytes(arr, len(problems), int(nstreams))
+    ws = _ws(nb, problems[0]["X"].device)
+    st = lib().krr_setup_many(arr, len(problems), int(nstreams), ws.data_ptr(), ws.numel(),
+                              _stream())
+    _raise(st, info=max(int(arr[i].info) for i in range(len(problems))))
+    return keep
 
 
 def autotune_matmat(kernel: "Kernel", X: torch.Tensor, m: int, prec="f16x3") -> TuneReport:

@@ -184,3 +184,24 @@ def test_batch_small_lambda_members_follow_oracle_iterations(dev):
         res = O.krr_pcg(w.X, w.sigma, w.lam, w.Y, U=U, tol=1e-6, max_iter=3000)
         gpu = max(rep.col_iters[i][:w.m])
         assert 0.85 * res.iters - 10 <= gpu <= 1.15 * res.iters + 10, (i, w.n, gpu, res.iters)
+
+
+def test_setup_many_matches_single_calls_and_reports_pivots(dev):
+    """krr_setup_many (features and factor of many problems over several streams) gives the
+    same Z and Ut as the single calls (same kernels, same launch shapes: bit for bit), and a
+    problem whose features are not finite fails its pivot check while the others succeed."""
+    ws = WL.batched_instances(count=7, n_lo=500, n_hi=3000, salt=5)
+    probs = []
+    for w in ws:
+        probs.append({"X": torch.from_numpy(w.X).to(dev), "W": torch.from_numpy(w.W).to(dev),
+                      "b": torch.from_numpy(w.b).to(dev), "lam": w.lam})
+    out = krr.setup_many(probs, nstreams=4)
+    for pr, (Z, C, Ut) in zip(probs, out):
+        Z1 = krr.features(pr["X"], pr["W"], pr["b"])
+        C1, U1 = krr.precond_factor(Z1, pr["lam"])
+        assert torch.equal(Z, Z1) and torch.equal(Ut, U1) and torch.equal(torch.tril(C), torch.tril(C1))
+    probs[3]["W"] = probs[3]["W"].clone()
+    probs[3]["W"][0, 0] = float("nan")
+    with pytest.raises(krr.KRRError) as e:
+        krr.setup_many(probs, nstreams=3)
+    assert e.value.status == krr.E_NOT_SPD and "problem 3" in str(e.value)

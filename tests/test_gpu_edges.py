@@ -217,3 +217,31 @@ def test_precond_factor_benchmark_size(dev):
     got = (v - Ug @ (Ug.T @ v)) / w.lam
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= kappa * 8 * back + 1e-12
     assert np.linalg.norm(Cg - Co) / np.linalg.norm(Co) <= np.linalg.cond(Co) * 8 * back
+
+
+def test_pcg_strided_alpha_and_y(dev):
+    """krr_pcg_solve with leading dimensions larger than m (alpha and Y inside wider buffers):
+    the solution equals the contiguous solve bit for bit, and the padding columns of alpha
+    are left as they were."""
+    import ctypes
+    w = WL.mixture_multi_rhs(n=1500, s=96)
+    X, Y = _t(w.X, dev), _t(w.Y, dev)
+    Z = krr.features(X, _t(w.W, dev), _t(w.b, dev))
+    _, Ut = krr.precond_factor(Z, w.lam)
+    a_ref, _ = krr.pcg_solve(X, w.sigma, w.lam, Ut, Y, tol=1e-6, prec="f16x3", refine=2)
+    n, m, ld = w.n, w.m, w.m + 3
+    Yw = torch.full((n, ld), 7.0, dtype=torch.float64, device=dev)
+    Yw[:, :m] = Y
+    Aw = torch.full((n, ld), -5.0, dtype=torch.float64, device=dev)
+    L = krr.lib()
+    o = krr.PCGOpts()
+    L.krr_pcg_defaults(ctypes.byref(o))
+    o.refine = 2
+    ws = krr._ws(krr.workspace_bytes(krr.OP_PCG_SOLVE, n, n, w.d, Ut.shape[1], m, 1), dev)
+    st = L.krr_pcg_solve(X.data_ptr(), n, w.d, w.d, w.sigma, w.lam, Ut.data_ptr(), Ut.shape[1],
+                         Ut.shape[1], Yw.data_ptr(), ld, Aw.data_ptr(), ld, m, ctypes.byref(o),
+                         None, ws.data_ptr(), ws.numel(), None)
+    torch.cuda.synchronize()
+    assert st == krr.OK, krr.last_error()
+    assert torch.equal(Aw[:, :m], a_ref)
+    assert bool((Aw[:, m:] == -5.0).all())
