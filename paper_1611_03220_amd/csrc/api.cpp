@@ -98,15 +98,23 @@ struct MatmatCtx {
   double *scA = nullptr, *scB = nullptr;  // their row scales
   double* part = nullptr;   // nsplit x rp1 x m
   int64_t part_stride = 0;
+  // square large-d products: column-side accumulator of the symmetric kernel
+  unsigned long long* fx = nullptr;  // [rp1][32]
+  unsigned* fxflag = nullptr;        // [rp1]
+  bool square = false;
   double c2 = 0;            // log2(e) / (2 sigma^2)
   double sigma = 0;
   bool poly = false;        // polynomial kernel (gamma x^T z + c)^q instead of the Gaussian
   PolyF64 pk;               // its parameters
 };
 
+// square: both sides are the same points (the symmetric large-d kernel may be used);
+// sym_buf: reserve its column-side accumulator (square, or a product whose sides may be the
+// same points, sized before that is known)
 void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int64_t m, int prec,
-                   bool square) {
+                   bool square, bool sym_buf) {
   c.prec = prec;
+  c.square = square;
   c.n1 = n1; c.n2 = n2; c.d = d; c.m = m;
   c.rp1 = round_up(n1, ROW_PAD);
   c.rp2 = round_up(n2, ROW_PAD);
@@ -140,6 +148,10 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
       c.Vtl = b.take<_Float16>(c.mpad * c.rp2);
       c.colmax = b.take<float>(m);
       c.vscale = b.take<float>(c.mpad);
+    }
+    if (c.pv && c.Kp > 128 && sym_buf) {
+      c.fx = b.take<unsigned long long>(c.rp1 * 32);
+      c.fxflag = b.take<unsigned>(c.rp1);
     }
     c.Ahi = b.take<uint16_t>(c.rp1 * c.Kp);
     c.Alo = b.take<uint16_t>(c.rp1 * c.Kp);
@@ -241,7 +253,9 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
         if (e != hipSuccess) return e;
         SplitRhs V{c.Vth, c.Vtl, c.vscale, c.rp2, mp, packed};
         const int epi = c.poly ? KV_POLY : deriv ? KV_DSIGMA : KV_GAUSS;
-        e = matmat_f16pv(A, B, V, mc, epi, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st);
+        const SymBuf sb{c.fx, c.fxflag, 32};
+        e = matmat_f16pv(A, B, V, mc, epi, dscale, c.part + c0, c.m, c.part_stride, c.nsplit, st,
+                         c.fx && c.square ? &sb : nullptr);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
@@ -419,8 +433,8 @@ int precond_nchunk(int64_t n, int64_t s) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(nc, 512));
 }
 void layout_pcg(Bump& b, PCGLayout& L, int64_t n, int64_t d, int64_t s, int64_t m, int prec) {
-  layout_matmat(b, L.mm, n, n, d, m, prec, true);
-  if (prec != KRR_PREC_FP64) layout_matmat(b, L.mm64, n, n, d, m, KRR_PREC_FP64, true);
+  layout_matmat(b, L.mm, n, n, d, m, prec, true, true);
+  if (prec != KRR_PREC_FP64) layout_matmat(b, L.mm64, n, n, d, m, KRR_PREC_FP64, true, true);
   const int64_t nm = n * m;
   L.pf = b.take<float>(round_up(n, ROW_PAD) * m);
   L.p = b.take<double>(nm);
@@ -475,7 +489,7 @@ struct InnerLayout {
   double* part;
 };
 void layout_inner(Bump& b, InnerLayout& L, int64_t n1, int64_t n2, int64_t d, int64_t m, int prec) {
-  layout_matmat(b, L.mm, n1, n2, d, m, prec, false);
+  layout_matmat(b, L.mm, n1, n2, d, m, prec, false, false);
   L.vf = prec != KRR_PREC_FP64 ? b.take<float>(round_up(n2, ROW_PAD) * m) : nullptr;
   L.w = b.take<double>(n1 * m);
   L.part = b.take<double>(NBLK * m);
@@ -495,7 +509,7 @@ struct TestLayout {
 };
 void layout_test(Bump& b, TestLayout& L, int64_t n, int64_t d, int64_t s, int prec) {
   layout_factor(b, L.F, n, s);
-  layout_matmat(b, L.mm, n, n, d, 1, prec, true);
+  layout_matmat(b, L.mm, n, n, d, 1, prec, true, true);
   L.Zd = b.take<double>(n * s);
   L.A = b.take<double>(s * s);
   L.Vt = b.take<double>(s * s);
@@ -525,14 +539,14 @@ struct TuneLayout {
   float* Vf;
 };
 void layout_tune(Bump& b, TuneLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
-  layout_matmat(b, L.mm, n, n, d, m, prec, true);
+  layout_matmat(b, L.mm, n, n, d, m, prec, true, true);
   L.V = b.take<double>(n * m);
   L.out = b.take<double>(n * m);
   L.Vf = b.take<float>(round_up(n, ROW_PAD) * m);
 }
 
 void layout_grad(Bump& b, GradLayout& L, int64_t n, int64_t d, int64_t m, int prec) {
-  layout_matmat(b, L.mm, n, n, d, m, prec, true);
+  layout_matmat(b, L.mm, n, n, d, m, prec, true, true);
   L.af = b.take<float>(round_up(n, ROW_PAD) * m);
   L.w = b.take<double>(n * m);
   L.part = b.take<double>(NBLK * m * 2);
@@ -573,7 +587,7 @@ size_t krr_workspace_bytes(int32_t op, int64_t n1, int64_t n2, int64_t d, int64_
     case KRR_OP_PRECOND_FACTOR: { FactorLayout L; layout_factor(b, L, n1, s); break; }
     case KRR_OP_KERNEL_MATMAT: {
       MatmatCtx c;
-      layout_matmat(b, c, n1, n2, d, m, prec, false);
+      layout_matmat(b, c, n1, n2, d, m, prec, false, n1 == n2);
       if (prec != KRR_PREC_FP64) b.take<float>(round_up(n2, ROW_PAD) * m);
       break;
     }
@@ -858,10 +872,13 @@ krr_status kernel_matmat_impl(const char* fn, const krr_kernel* kern, const floa
   CHECK_ST(check_ws(ws, ws_bytes, need));
   Bump bb(ws);
   MatmatCtx c;
-  layout_matmat(bb, c, n1, n2, d, m, prec, false);
+  // K(X, X) V with the same points on both sides: the square layout (the sizing above holds
+  // for it: it shares the FP64 arrays and reserves the same column-side accumulator)
+  const bool same = X1 == X2 && n1 == n2 && ldx1 == ldx2;
+  layout_matmat(bb, c, n1, n2, d, m, prec, same, n1 == n2);
   float* Vf = prec != KRR_PREC_FP64 ? bb.take<float>(round_up(n2, ROW_PAD) * m) : nullptr;
   hipStream_t st = (hipStream_t)stream;
-  CHECK_HIP(prepare_points(c, X1, ldx1, X2, ldx2, *kern, st));
+  CHECK_HIP(prepare_points(c, X1, ldx1, same ? nullptr : X2, ldx2, *kern, st));
   if (Vf) {
     CHECK_HIP(vec_to_f32(V, n2, m, ldv, round_up(n2, ROW_PAD), m, Vf, st));
     CHECK_HIP(run_matmat(c, Vf, nullptr, m, deriv != 0, st));
@@ -1807,7 +1824,7 @@ struct BatchResid {
   double *ax, *res, *prr, *pyy;
 };
 void layout_batch_resid(Bump& b, BatchResid& R, int64_t n, int64_t d, int64_t m) {
-  layout_matmat(b, R.c, n, n, d, m, KRR_PREC_FP64, true);
+  layout_matmat(b, R.c, n, n, d, m, KRR_PREC_FP64, true, true);
   R.ax = b.take<double>(n * m);
   R.res = b.take<double>(n * m);
   R.prr = b.take<double>(NBLK * m);

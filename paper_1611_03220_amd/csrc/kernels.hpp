@@ -105,9 +105,29 @@ struct PolyF64 {
     return p;
   }
 };
+// Column-side accumulator of the symmetric large-d product K(X, X) V: 64-bit fixed-point
+// sums (value times 2^F, two's complement) and per-row flags of non-finite contributions
+// (bit c: column c). Each holds rows_pad rows; the product clears what it uses.
+struct SymBuf {
+  unsigned long long* fx;  // [rows_pad][ldfx]
+  unsigned* flag;          // [rows_pad]
+  int64_t ldfx;            // >= the pass's V^T rows (16)
+};
+struct SymOut {            // what the symmetric kernel receives
+  unsigned long long* fx = nullptr;
+  unsigned* flag = nullptr;
+  int64_t ldfx = 0;
+  float fxs = 1.0f;        // 2^F
+  int nsplit = 1;
+  int64_t nrb = 0;         // 128-row blocks
+};
+// OUT partial sums of K(A, B) V (or dK/dsigma, or the polynomial kernel) on MFMA. With sym
+// (square products only: A and B prepared from the same points), large-d passes of up to
+// 16 columns form each off-diagonal tile pair once and use it for both triangles.
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
                         const SplitRhs& V, int64_t m, int epi, float dscale, double* part,
-                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st,
+                        const SymBuf* sym = nullptr);
 template <typename T>
 hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
                         int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,

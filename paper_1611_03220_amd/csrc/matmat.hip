@@ -621,19 +621,31 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16
 // accumulation against V^T). Wider tiles re-stream the row operand less often: its chunks
 // are read once per column tile. Chunk rows are 64 bytes whose 16-byte pieces are
 // XOR-swizzled with (row >> 1) & 3 so fragment reads are conflict-free.
+//
+// Symmetric mode (SYM, the square product K(X, X) V with TN = 128): K is symmetric, so
+// only the tile pairs (I, J) with J >= I of the 128-row blocks are formed. A block owns a
+// pair of row blocks (p, nrb - 1 - p), whose two tile lists together hold nrb + 1 tiles,
+// and takes one of nsplit equal parts of their concatenation. The row side P_IJ V_J is
+// accumulated as above; an off-diagonal pair also yields the column side P_IJ^T V_I for the
+// rows of J: P is transposed per 16 x 16 block by an MFMA against a 0/1 selection matrix
+// (exact: FP16 values times one), multiplied by the register-resident V_I^T on MFMA, the
+// four waves' partial sums (over their 32 rows of I) are added through the LDS buffer of
+// the stage not in use, and the result goes to the column-side accumulator as 64-bit
+// fixed-point atomic adds (exact, so the total does not depend on the order of the adds).
 constexpr int BD_BM = 128;
 template <int NCT, int NJB>
 constexpr int bigd_smem_halves() {
   return 2 * 2 * BD_BM * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB);
 }
-template <int NCT, bool UNIT, int EPI, int NJB, bool PACK>
+template <int NCT, bool UNIT, int EPI, int NJB, bool PACK, bool SYM = false>
 __device__ __forceinline__ void f16pv_bigd_body(
     _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     float qinv2, float dscale, int deg, double pmul, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split) {
+    int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split,
+    const SymOut& so = SymOut{}) {
   constexpr int TN = 16 * NJB;
   constexpr int BPT = TN * 4 / 256;          // B chunk pieces per thread
   constexpr int VR = NCT * 16;
@@ -642,6 +654,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   constexpr int FLUSH = TN >= 128 ? 1 : MM2_FLUSH;  // flush every 128 columns
   static_assert(BPT >= 1 && BPT <= 2 && VPT <= 2, "tile shape");
   static_assert(!PACK || NCT == 1, "packed right-hand sides use one 16-row operand");
+  static_assert(!SYM || (TN == BD_BM && NCT == 1), "symmetric mode: square tiles, NCT = 1");
   // LDS layout (halves): A[2][2][128*32], B[2][2][TN*32], V[2][2][VR*TN]
   _Float16* sA = smem;
   _Float16* sB = sA + 2 * 2 * BD_BM * 32;
@@ -652,13 +665,33 @@ __device__ __forceinline__ void f16pv_bigd_body(
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int64_t blk_i0 = rb * BD_BM;
-  const int64_t i0 = blk_i0 + 32 * w;
   const int64_t ntiles = ceil_div(n2, TN);
-  const int64_t t_begin = split * tiles_per_split;
-  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = KP / 32;
-  const int nsteps = (int)((t_end - t_begin) * KC);
+  // Work list: items t = 0 .. count-1, each a (row block, column tile) pair. Items below nA
+  // belong to row block rbA with tile jA + t, the rest to rbB with tile jB + (t - nA).
+  int64_t rbA = rb, rbB = rb, jA = 0, jB = 0;
+  int nA = 0, count = 0;
+  if (SYM) {
+    rbB = so.nrb - 1 - rb;
+    const int64_t len1 = ntiles - rbA;
+    const int64_t len2 = rbB > rbA ? ntiles - rbB : 0;
+    const int64_t L = len1 + len2;
+    const int64_t b0 = split * L / so.nsplit, b1 = (split + 1) * L / so.nsplit;
+    count = (int)(b1 - b0);
+    const int64_t na = len1 - b0;
+    nA = na < 0 ? 0 : na > count ? count : (int)na;
+    jA = rbA + b0;
+    jB = rbB + (b0 + nA - len1);
+  } else {
+    const int64_t t_begin = split * tiles_per_split;
+    const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+    count = t_end > t_begin ? (int)(t_end - t_begin) : 0;
+    nA = count;
+    jA = t_begin;
+  }
+  auto item_rb = [&](int t) __attribute__((always_inline)) { return t < nA ? rbA : rbB; };
+  auto item_j = [&](int t) __attribute__((always_inline)) { return t < nA ? jA + t : jB + (t - nA); };
+  const int nsteps = count * KC;
 
   f32x4 acc[2][NCT];
   double acc64[2][NCT][4];
@@ -672,7 +705,32 @@ __device__ __forceinline__ void f16pv_bigd_body(
     }
   f32x4 S[NJB][2];
 
-  // chunk loaders: A rows blk_i0 + tid/4 and + 64; B rows j0 + tid/4 (+ 64 when TN = 128)
+  // V_I^T as the A operand of the column-side product: lane (c = li, g) holds V^T[c][i] for
+  // i = 32 w + 16 b + 4 g + r at position 4 b + r (the k order of the transposed P)
+  half8 vIh[NCT], vIl[NCT];
+  auto load_vI = [&](int64_t I) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int64_t o = (int64_t)(16 * ct + li) * ldvt + I * BD_BM + 32 * w + 4 * lg;
+      const u32x2 a = *reinterpret_cast<const u32x2*>(Vth + o);
+      const u32x2 b = *reinterpret_cast<const u32x2*>(Vth + o + 16);
+      vIh[ct] = __builtin_bit_cast(half8, u32x4{a.x, a.y, b.x, b.y});
+      if (!PACK) {
+        const u32x2 c = *reinterpret_cast<const u32x2*>(Vtl + o);
+        const u32x2 d = *reinterpret_cast<const u32x2*>(Vtl + o + 16);
+        vIl[ct] = __builtin_bit_cast(half8, u32x4{c.x, c.y, d.x, d.y});
+      }
+    }
+  };
+  // 0/1 selection operand of the transposing MFMA: lane (col li, k group g) holds
+  // E[4 g + r][li] = (4 g + r == li)
+  half4 esel;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) esel[r] = (_Float16)(4 * lg + r == li ? 1.0f : 0.0f);
+  if (SYM && count > 0) load_vI(item_rb(0));
+
+  // chunk loaders: A rows of the item's row block + tid/4 and + 64; B rows j0 + tid/4
+  // (+ 64 when TN = 128)
   const int arow0 = tid >> 2, arow1 = arow0 + 64, acol = tid & 3;
   const int sa0 = arow0 * 32 + ((acol ^ ((arow0 >> 1) & 3)) * 8);
   const int sa1 = arow1 * 32 + ((acol ^ ((arow1 >> 1) & 3)) * 8);
@@ -698,8 +756,8 @@ __device__ __forceinline__ void f16pv_bigd_body(
     u32x4 ra0h, ra0l, ra1h, ra1l, rb0h, rb0l, rb1h, rb1l, rv0h, rv0l, rv1h, rv1l;
   };
   Regs R0 = {}, R1 = {};
-  // position of a step: column tile (relative to t_begin) and k chunk, advanced one step at
-  // a time (no division in the loop)
+  // position of a step: item (relative to the block's first) and k chunk, advanced one step
+  // at a time (no division in the loop)
   struct Pos {
     int t, kc;
   };
@@ -710,7 +768,8 @@ __device__ __forceinline__ void f16pv_bigd_body(
     }
   };
   auto gload = [&](const Pos& p, Regs& R) __attribute__((always_inline)) {
-    const int64_t t = t_begin + p.t;
+    const int64_t t = item_j(p.t);
+    const int64_t blk_i0 = item_rb(p.t) * BD_BM;
     const int kc = p.kc;
     const int64_t ko = (int64_t)kc * 32 + acol * 8;
     R.ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
@@ -767,6 +826,25 @@ __device__ __forceinline__ void f16pv_bigd_body(
       }
     }
   };
+  // row-side output of row block I: lane holds OUT[I * 128 + 32 w + 16 ib + 4 lg + r][16 ct + li]
+  double* pout = part + split * part_stride;
+  auto write_rows = [&](int64_t I, bool zero) __attribute__((always_inline)) {
+    const int64_t i0 = I * BD_BM + 32 * w;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int64_t c = 16 * ct + li;
+      if (c < m && (!PACK || li < 8)) {
+        const double vs = (double)vscale[c] * pmul;
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + 16 * ib + 4 * lg + r;
+            if (i < n1) pout[i * ldp + c] = zero ? 0.0 : acc64[ib][ct][r] * vs;
+          }
+      }
+    }
+  };
 
   // pc, pn, pg: positions of steps q, q + 1 and min(q + 2, nsteps - 1)
   Pos pc{0, 0}, pn{0, 0}, pg{0, 0};
@@ -774,9 +852,11 @@ __device__ __forceinline__ void f16pv_bigd_body(
     gload(pc, R0);
     lstore(0, pc, R0);
     if (nsteps > 1) advance(pn);
-    gload(pn, R0);
-    pg = pn;
-    if (nsteps > 2) advance(pg);
+    if (!SYM) {
+      gload(pn, R0);
+      pg = pn;
+      if (nsteps > 2) advance(pg);
+    }
   }
   // complete the prologue's loads once here, so the loop does not inherit them as pending
   // (that makes the compiler wait for every outstanding load at the top of each step)
@@ -809,8 +889,21 @@ __device__ __forceinline__ void f16pv_bigd_body(
         S[jb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(bh, ah[ib], v, 0, 0, 0);
       }
     }
-    if (kc == KC - 1) {
+  };
+  // epilogue of a tile (after the chunk kc = KC - 1)
+  auto epilogue = [&](int q, const Pos& p) __attribute__((always_inline)) {
+    const int buf = q & 1;
+    {
       const int vb = p.t & 1;
+      const int64_t I = item_rb(p.t), J = item_j(p.t);
+      const bool col = SYM && J > I;  // uniform over the block
+      // column-side partial sums of wave w: [128 columns j][16 columns c] FP32 in the LDS
+      // stage the next chunk is stored to after the epilogue (free until then)
+      constexpr int CW = 16 * NCT;
+      auto red_at = [&](int ww) __attribute__((always_inline)) {
+        _Float16* base = ww < 2 ? A_at(buf ^ 1, 0) : B_at(buf ^ 1, 0);
+        return reinterpret_cast<float*>(base) + (ww & 1) * TN * CW;
+      };
 #pragma unroll
       for (int jp = 0; jp < NJB / 2; ++jp) {
         half8 vh[NCT], vl[NCT];
@@ -820,9 +913,9 @@ __device__ __forceinline__ void f16pv_bigd_body(
           vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
           if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
         }
+        half8 ph[2], pl[2];
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib) {
-          half8 ph, pl;
 #pragma unroll
           for (int jj = 0; jj < 2; ++jj)
 #pragma unroll
@@ -833,22 +926,57 @@ __device__ __forceinline__ void f16pv_bigd_body(
               const float pb = epi_value<EPI>(l2b, dscale, deg);
               const half2v h = half2v{(_Float16)pa, (_Float16)pb};
               const half2v l = split_lo2(h, pa, pb);
-              ph[4 * jj + r] = h[0];
-              ph[4 * jj + r + 1] = h[1];
-              pl[4 * jj + r] = l[0];
-              pl[4 * jj + r + 1] = l[1];
+              ph[ib][4 * jj + r] = h[0];
+              ph[ib][4 * jj + r + 1] = h[1];
+              pl[ib][4 * jj + r] = l[0];
+              pl[ib][4 * jj + r + 1] = l[1];
             }
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
-            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl, vh[ct], acc[ib][ct], 0, 0, 0);
+            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[ib], vh[ct], acc[ib][ct], 0, 0, 0);
             if (!PACK)
               acc[ib][ct] =
-                  __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vl[ct], acc[ib][ct], 0, 0, 0);
-            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph, vh[ct], acc[ib][ct], 0, 0, 0);
+                  __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vl[ct], acc[ib][ct], 0, 0, 0);
+            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vh[ct], acc[ib][ct], 0, 0, 0);
+          }
+        }
+        if (col) {
+#pragma unroll
+          for (int jj = 0; jj < 2; ++jj) {
+            // transpose the 32 x 16 block (rows of the wave, columns 16 jb ..): lane (j = li,
+            // g) gets P[32 w + 16 b + 4 g + r][16 jb + li] at position 4 b + r
+            half8 th, tl;
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+              const half4 a_h = half4{ph[ib][4 * jj], ph[ib][4 * jj + 1], ph[ib][4 * jj + 2],
+                                      ph[ib][4 * jj + 3]};
+              const half4 a_l = half4{pl[ib][4 * jj], pl[ib][4 * jj + 1], pl[ib][4 * jj + 2],
+                                      pl[ib][4 * jj + 3]};
+              const f32x4 z = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+              const f32x4 xh = __builtin_amdgcn_mfma_f32_16x16x16f16(a_h, esel, z, 0, 0, 0);
+              const f32x4 xl = __builtin_amdgcn_mfma_f32_16x16x16f16(a_l, esel, z, 0, 0, 0);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                th[4 * ib + r] = (_Float16)xh[r];
+                tl[4 * ib + r] = (_Float16)xl[r];
+              }
+            }
+            const int jb = 2 * jp + jj;
+            float* red = red_at(w);
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct) {
+              // D[c][j] = sum_i V_I^T[c][i] P[i][j] over the wave's 32 rows i
+              f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_f16(vIh[ct], tl, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+              if (!PACK) d = __builtin_amdgcn_mfma_f32_16x16x32_f16(vIl[ct], th, d, 0, 0, 0);
+              d = __builtin_amdgcn_mfma_f32_16x16x32_f16(vIh[ct], th, d, 0, 0, 0);
+              // lane (j = li, g) holds D[4 g + r][16 jb + li]
+              *reinterpret_cast<f32x4*>(red + (16 * jb + li) * CW + 16 * ct + 4 * lg) = d;
+            }
           }
         }
       }
-      if (++since_flush == FLUSH || q + 1 == nsteps) {
+      const bool switch_rb = SYM && p.t == nA - 1 && nA < count;
+      if (++since_flush == FLUSH || q + 1 == nsteps || switch_rb) {
         since_flush = 0;
 #pragma unroll
         for (int ib = 0; ib < 2; ++ib)
@@ -859,36 +987,85 @@ __device__ __forceinline__ void f16pv_bigd_body(
             acc[ib][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
           }
       }
+      if (switch_rb) {
+        // the first row block of the pair is done: write it and start on the second
+        if (PACK) pack_combine<NCT>(acc64);
+        write_rows(rbA, false);
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc64[ib][ct][r] = 0.0;
+        load_vI(rbB);
+      }
+      if (col) {
+        __syncthreads();
+        // wave w finishes columns 32 w .. 32 w + 31: the four waves' partials added in a
+        // fixed order, then one fixed-point atomic add per (row, column)
+        const int mv = PACK ? (m < 8 ? (int)m : 8) : (m < CW ? (int)m : CW);
+#pragma unroll 1
+        for (int u = 0; u < 32 * CW / 64; ++u) {
+          const int e = u * 64 + lane;
+          const int jj = e / CW, c = e % CW;
+          const int j = 32 * w + jj;
+          if (c < mv) {
+            float s = 0.0f;
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) {
+              const float* rr = red_at(ww) + j * CW;
+              s += PACK ? rr[c] + rr[c + 8] : rr[c];
+            }
+            const int64_t row = J * TN + j;
+            if (__builtin_isfinite(s))
+              atomicAdd(so.fx + row * so.ldfx + c,
+                        (unsigned long long)(long long)__builtin_rintf(s * so.fxs));
+            else
+              atomicOr(so.flag + row, 1u << c);
+          }
+        }
+        __syncthreads();
+      }
     }
   };
   auto step = [&](int q, const Regs& hold, Regs& spare) __attribute__((always_inline)) {
     if (UNIFORM || q + 2 < nsteps) gload(pg, spare);
     compute(q, pc);
+    if (pc.kc == KC - 1) epilogue(q, pc);
     if (q + 1 < nsteps) lstore(q + 1, pn, hold);
     __syncthreads();
     advance(pc);
     advance(pn);
     if (q + 3 < nsteps) advance(pg);
   };
-  for (int q = 0; q < nsteps; q += 2) {
-    step(q, R0, R1);
-    if (q + 1 < nsteps) step(q + 1, R1, R0);
+  if (SYM) {
+    // one register set (the column side's registers leave no room for two): the next
+    // chunk is loaded at the start of a step and stored at its end
+    for (int q = 0; q < nsteps; ++q) {
+      const bool more = q + 1 < nsteps;
+      if (more) gload(pn, R0);
+      compute(q, pc);
+      if (pc.kc == KC - 1) epilogue(q, pc);
+      if (more) lstore(q + 1, pn, R0);
+      __syncthreads();
+      advance(pc);
+      advance(pn);
+    }
+  } else {
+    for (int q = 0; q < nsteps; q += 2) {
+      step(q, R0, R1);
+      if (q + 1 < nsteps) step(q + 1, R1, R0);
+    }
   }
   if (PACK) pack_combine<NCT>(acc64);
-  double* pout = part + split * part_stride;
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    const int64_t c = 16 * ct + li;
-    if (c < m && (!PACK || li < 8)) {
-      const double vs = (double)vscale[c] * pmul;
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = i0 + 16 * ib + 4 * lg + r;
-          if (i < n1) pout[i * ldp + c] = acc64[ib][ct][r] * vs;
-        }
-    }
+  if (SYM) {
+    const bool hasA = nA > 0, hasB = nA < count;
+    write_rows(hasB ? rbB : rbA, false);
+    // a row block of the pair with no item in this part still gets its (zero) partial sums
+    if (!hasA && hasB) write_rows(rbA, true);
+    if (!hasB && rbB != rbA) write_rows(rbB, true);
+  } else {
+    write_rows(rb, false);
   }
 }
 
@@ -900,45 +1077,67 @@ constexpr int bd_njb(int nct) { return nct == 4 ? 4 : BD_NJB; }
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
-template <int NCT, int EPI, bool PACK>
+template <int NCT, int EPI, bool PACK, bool SYM>
 __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m, int KP,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split, int grouped) {
+    int64_t part_stride, int tiles_per_split, int grouped, int64_t nunits, SymOut so) {
   constexpr int NJB = bd_njb(NCT);
   __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, NJB>()];
   int64_t rb = blockIdx.x, sp = blockIdx.y;
   if (grouped) {
-    // 1-D grid of (row block, split) pairs with BD_GROUP splits, ordered so that the blocks
+    // 1-D grid of (row unit, split) pairs with BD_GROUP splits, ordered so that the blocks
     // one XCD runs together (workgroups go round-robin to the 8 XCDs) form groups of
-    // BD_GROUP row blocks x BD_GROUP splits: each group shares its row operand chunks and its
-    // column tiles in that XCD's L2 instead of streaming them per block.
+    // BD_GROUP row units x BD_GROUP splits: each group shares its row operand chunks and its
+    // column tiles in that XCD's L2 instead of streaming them per block. A row unit is a
+    // 128-row block, or in symmetric mode a pair of them.
     const int64_t b = blockIdx.x, x = b % 8, t = b / 8;
     const int64_t gid = (t / (BD_GROUP * BD_GROUP)) * 8 + x, u = t % (BD_GROUP * BD_GROUP);
     rb = gid * BD_GROUP + u / BD_GROUP;
     sp = u % BD_GROUP;
-    if (rb * BD_BM >= n1) return;  // padding block
+    if (rb >= nunits) return;  // padding block
   }
   const float qinv2 = qinv2_ptr[0];
   int deg;
   double pmul;
   epi_params<EPI>(qinv2_ptr, deg, pmul);
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, EPI, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
-                                              n1, n2, m, KP, qinv2, dscale, deg, pmul, part, ldp,
-                                              part_stride, tiles_per_split, rb, sp);
+    f16pv_bigd_body<NCT, true, EPI, NJB, PACK, SYM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
+                                                   ldvt, n1, n2, m, KP, qinv2, dscale, deg, pmul,
+                                                   part, ldp, part_stride, tiles_per_split, rb,
+                                                   sp, so);
   else
-    f16pv_bigd_body<NCT, false, EPI, NJB, PACK>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt,
-                                               n1, n2, m, KP, qinv2, dscale, deg, pmul, part, ldp,
-                                               part_stride, tiles_per_split, rb, sp);
+    f16pv_bigd_body<NCT, false, EPI, NJB, PACK, SYM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
+                                                    ldvt, n1, n2, m, KP, qinv2, dscale, deg, pmul,
+                                                    part, ldp, part_stride, tiles_per_split, rb,
+                                                    sp, so);
+}
+
+// Adds the column side of a symmetric product to split 0 of the partial sums:
+// part[i][c] += fx[i][c] 2^-F vscale[c] pmul (NaN where a contribution was not finite).
+__global__ __launch_bounds__(256) void sym_fold_kernel(const unsigned long long* __restrict__ fx,
+                                                       const unsigned* __restrict__ flag,
+                                                       int64_t ldfx, int64_t n, int64_t mc,
+                                                       double inv_fxs,
+                                                       const float* __restrict__ vscale,
+                                                       const float* __restrict__ kpar, int epi,
+                                                       double* __restrict__ part, int64_t ldp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * mc) return;
+  const int64_t i = e / mc, c = e % mc;
+  const double pmul = epi == KV_POLY ? ldexp(1.0, (int)kpar[1]) : 1.0;
+  double v = (double)(long long)fx[i * ldfx + c] * inv_fxs;
+  if ((flag[i] >> c) & 1u) v = __builtin_nan("");
+  part[i * ldp + c] += v * ((double)vscale[c] * pmul);
 }
 
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
                         const SplitRhs& V, int64_t m, int epi, float dscale, double* part,
-                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st) {
+                        int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st,
+                        const SymBuf* sym) {
   if (epi != KV_GAUSS && epi != KV_DSIGMA && epi != KV_POLY) return hipErrorInvalidValue;
   if (A.Kp != B.Kp || V.mpad < round_up(m, 16)) return hipErrorInvalidValue;
   // passes of up to 32 columns (64 for large d, NCT = 4)
@@ -951,30 +1150,67 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   const int nct = (int)(V.mpad / 16);
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
+    const bool symm = sym && nct == 1 && A.n == B.n;
+    if (symm && (sym->ldfx < V.mpad || V.rows_pad < round_up(A.n, BD_BM)))
+      return hipErrorInvalidValue;
     const int tps = (int)ceil_div(ceil_div(B.n, 16 * (nct == 4 ? bd_njb(4) : BD_NJB)), nsplit);
     const int64_t nrb = ceil_div(A.n, BD_BM);
-    const int grouped = nsplit == BD_GROUP && nrb >= 8 * BD_GROUP ? 1 : 0;
-    if (grouped) grid = dim3((unsigned)(round_up(nrb, 8 * BD_GROUP) * BD_GROUP), 1);
-#define KRR_BD(NCT_, D_, P_)                                                                  \
-  matmat_f16pv_bigd_kernel<NCT_, D_, P_><<<grid, 256, 0, st>>>(                               \
+    const int64_t nunits = symm ? (nrb + 1) / 2 : nrb;
+    const int grouped = nsplit == BD_GROUP && nunits >= 8 * BD_GROUP ? 1 : 0;
+    grid = grouped ? dim3((unsigned)(round_up(nunits, 8 * BD_GROUP) * BD_GROUP), 1)
+                   : dim3((unsigned)nunits, nsplit);
+    SymOut so;
+    double inv_fxs = 1.0;
+    if (symm) {
+      // F from a bound on any column-side total: n terms of |P| <= pmax (exp2 of a
+      // non-positive value up to rounding, a power of a value in [-1, 1], or
+      // x 2^-x dscale <= 0.531 dscale) times |V'| <= SPLIT_TARGET, below 2^62
+      const double pmax = epi == KV_DSIGMA ? 0.54 * std::fabs((double)dscale) : 2.0;
+      const double bound = (double)A.n * std::max(pmax, 1e-30) * SPLIT_TARGET;
+      const int F = (int)std::floor(62.0 - std::log2(bound));
+      so.fx = sym->fx;
+      so.flag = sym->flag;
+      so.ldfx = sym->ldfx;
+      so.fxs = std::ldexp(1.0f, F);
+      so.nsplit = nsplit;
+      so.nrb = nrb;
+      inv_fxs = std::ldexp(1.0, -F);
+      hipError_t e = fill_f64(reinterpret_cast<double*>(so.fx), V.rows_pad * so.ldfx, 0.0, st);
+      if (e == hipSuccess) e = fill_i32(reinterpret_cast<int*>(so.flag), V.rows_pad, 0, st);
+      if (e != hipSuccess) return e;
+    }
+#define KRR_BD(NCT_, D_, P_, S_)                                                                 \
+  matmat_f16pv_bigd_kernel<NCT_, D_, P_, S_><<<grid, 256, 0, st>>>(                              \
       A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, \
-      part, ldp, part_stride, tps, grouped)
-#define KRR_BD_EPI(NCT_, P_)                     \
-  if (epi == KV_DSIGMA) KRR_BD(NCT_, KV_DSIGMA, P_); \
-  else if (epi == KV_POLY) KRR_BD(NCT_, KV_POLY, P_); \
-  else KRR_BD(NCT_, KV_GAUSS, P_);
-    if (nct == 1 && V.packed) {
-      KRR_BD_EPI(1, true)
+      part, ldp, part_stride, tps, grouped, nunits, so)
+#define KRR_BD_EPI(NCT_, P_, S_)                          \
+  if (epi == KV_DSIGMA) KRR_BD(NCT_, KV_DSIGMA, P_, S_);  \
+  else if (epi == KV_POLY) KRR_BD(NCT_, KV_POLY, P_, S_); \
+  else KRR_BD(NCT_, KV_GAUSS, P_, S_);
+    if (symm) {
+      if (V.packed) {
+        KRR_BD_EPI(1, true, true)
+      } else {
+        KRR_BD_EPI(1, false, true)
+      }
+    } else if (nct == 1 && V.packed) {
+      KRR_BD_EPI(1, true, false)
     } else if (nct == 1) {
-      KRR_BD_EPI(1, false)
+      KRR_BD_EPI(1, false, false)
     } else if (nct == 2) {
-      KRR_BD_EPI(2, false)
+      KRR_BD_EPI(2, false, false)
     } else {
-      KRR_BD_EPI(4, false)
+      KRR_BD_EPI(4, false, false)
     }
 #undef KRR_BD_EPI
 #undef KRR_BD
     KRR_LAUNCH_CHECK();
+    if (symm) {
+      const int64_t mc = V.packed ? std::min<int64_t>(m, 8) : m;
+      sym_fold_kernel<<<(unsigned)ceil_div(A.n * mc, 256), 256, 0, st>>>(
+          so.fx, so.flag, so.ldfx, A.n, mc, inv_fxs, V.vscale, A.qinv2, epi, part, ldp);
+      KRR_LAUNCH_CHECK();
+    }
     return hipSuccess;
   }
 #define KRR_PV1(KS_, NCT_, E_, PK_)                                                           \
