@@ -13,9 +13,12 @@ asks for would hold the GPU for minutes (`--headline pixels` makes it the timed 
 
 Prints ONE JSON line. `value` is the whole-job kernel-product throughput: algorithmic
 kernel-product flops 2 n^2 (d + m) of all mixed products in the timed steps divided by the
-timed wall time. `roofline` describes the dominant kernel (the fused large-d kernel product)
-against the dense FP16 MFMA peak: algorithmic flops per launch over the average launch time,
-timed with HIP events inside the library on the stream the product runs on. `fp64_path` is the
+timed wall time. `roofline` describes the dominant kernel against the dense FP16 MFMA peak:
+algorithmic flops 2 n^2 (d + m) per launch over the average launch time, timed with HIP
+events inside the library on the stream the product runs on; the solve's large-d product is
+symmetric (each off-diagonal kernel entry formed once, for both triangles), so it executes
+about half those flops: `executed_mfma_flops_per_launch` and `executed_frac` count what the
+matrix cores actually run. `fp64_path` is the
 same solve with the plain FP64 kernel product. Secondary legs: the pixels workload with its own FP64 path and roofline, the plain FP64 workload, the
 preconditioner ablation (lambda_p = lambda, 10 lambda, none; Table 2 and Table 4 of the paper),
 the batched uneven problems and the differentiation workload. Every solve reports `tol_met`;
@@ -42,8 +45,10 @@ CUS, CLOCK = 256, 2.4e9
 PEAK_EXP = CUS * 32 * CLOCK     # FP32 exp2 per second: 32 lanes per clock per CU
 
 METRIC = "kernel matmat TFLOP/s + time-to-1e-6 residual PCG solve, mixed vs FP64 path"
-BIGD_KERNEL = ("matmat_f16pv_bigd_kernel (large d: FP16 hi/lo split MFMA distances with both "
-               "operands through LDS, FP32 exp2, split MFMA accumulation of K V, FP64 partials)")
+BIGD_KERNEL = ("matmat_f16pv_bigd_kernel, symmetric (large d: FP16 hi/lo split MFMA distances "
+               "with both operands through LDS, each off-diagonal 128 x 128 block pair once, "
+               "FP32 exp2, split MFMA accumulation of K V for both triangles, FP64 partials and "
+               "fixed-point column sums)")
 SMALLD_KERNEL = ("matmat_f16pv_kernel (d + 2 <= 128: register-resident row operand, FP16 hi/lo "
                  "split MFMA distances, FP32 exp2, split MFMA accumulation of K V)")
 LEGS = ["mixture", "pixels", "plain", "ablation", "batched", "differentiation", "polynomial",
@@ -120,7 +125,7 @@ def tol_met(rep, tol):
 
 
 def kernel_shapes(d, m):
-    """(Kp, executed MFMA flops per pair) of the F16X3 product for d and m."""
+    """(Kp, executed MFMA flops per pair) of the general F16X3 product for d and m."""
     kp = int(math.ceil((d + 2) / 32.0) * 32)         # augmented, padded feature width
     W = 64 if kp > 128 else 32                        # right-hand-side columns per pass
     per_pair = 0
@@ -131,6 +136,32 @@ def kernel_shapes(d, m):
         # or two when mc <= 8 (the hi and lo parts of V share one 16-column operand)
         per_pair += 2 * (3 * kp + (2 if mc <= 8 else 3) * mp)
     return kp, per_pair
+
+
+def square_product_work(n, d, m):
+    """(executed MFMA flops, kernel entries evaluated) per launch of the square product
+    K(X, X) V as the solve runs it: large-d passes of up to 16 columns form each pair of
+    128-row blocks once (the symmetric kernel: distances and exp for both triangles, P V for
+    the row side, a 0/1-selection transpose (two 16x16x16 MFMAs per 16 x 16 block) and P^T V
+    for the column side of off-diagonal pairs); other passes form every pair."""
+    kp = int(math.ceil((d + 2) / 32.0) * 32)
+    W = 64 if kp > 128 else 32
+    nb = -(-n // 128)
+    full = float(n) * n
+    unique = nb * (nb + 1) / 2.0 * 128 * 128
+    offdiag = nb * (nb - 1) / 2.0 * 128 * 128
+    flops = entries = 0.0
+    for c0 in range(0, m, W):
+        mc = min(W, m - c0)
+        mp = 64 if mc > 32 else int(math.ceil(mc / 16.0) * 16)
+        f = 2 if mc <= 8 else 3
+        if kp > 128 and mc <= 16:
+            flops += unique * 2 * (3 * kp + f * mp) + offdiag * (64 + 2 * f * mp)
+            entries += unique
+        else:
+            flops += full * 2 * (3 * kp + f * mp)
+            entries += full
+    return flops, entries
 
 
 class Problem:
@@ -173,17 +204,17 @@ def roofline_of(w, reps, kernel, summary, src="paper_1611_03220_amd/csrc/matmat.
     flops = 2.0 * n * n * (d + m)
     calls = sum(r.matmat_calls for r in reps)
     avg_s = sum(r.matmat_ms for r in reps) / max(calls, 1) / 1e3
-    pairs = float(n) * n
-    kp, exec_pp = kernel_shapes(d, m)
+    exec_flops, entries = square_product_work(n, d, m)
     return {"bound": "mfma", "achieved": flops / avg_s / 1e12, "peak": PEAK_MFMA_F16 / 1e12,
             "unit": "TFLOP/s", "frac": flops / avg_s / PEAK_MFMA_F16,
             "traffic": recorded_traffic(summary, src), "kernel": kernel,
             "algorithmic_flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3,
-            "launches": calls, "executed_mfma_flops_per_launch": pairs * exec_pp,
-            "executed_mfma_tflops": pairs * exec_pp / avg_s / 1e12,
-            "executed_frac": pairs * exec_pp / avg_s / PEAK_MFMA_F16,
-            "exp_per_s": pairs / avg_s, "exp_peak_per_s": PEAK_EXP,
-            "exp_frac": pairs / avg_s / PEAK_EXP,
+            "launches": calls, "executed_mfma_flops_per_launch": exec_flops,
+            "executed_mfma_tflops": exec_flops / avg_s / 1e12,
+            "executed_frac": exec_flops / avg_s / PEAK_MFMA_F16,
+            "kernel_entries_per_launch": entries,
+            "exp_per_s": entries / avg_s, "exp_peak_per_s": PEAK_EXP,
+            "exp_frac": entries / avg_s / PEAK_EXP,
             "timed_with": "HIP events on the library's stream around every product launch"}
 
 

@@ -156,6 +156,12 @@ krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu,
  *   prec  : a krr_prec. Squared distances are not clamped at zero: where rounding leaves one
  *           slightly negative (coincident points), k comes out slightly above 1, within the
  *           product's error bound; a NaN coordinate propagates to every output it meets.
+ * When X1 and X2 are the same array (same pointer, n1 == n2, ldx1 == ldx2) the product is
+ * K(X, X) V and K is symmetric: with KRR_PREC_F16X3, d > 126 and passes of up to 16
+ * columns, each off-diagonal pair of 128-row blocks is formed once and serves both
+ * triangles (the transposed contributions are summed exactly in 64-bit fixed point, so
+ * repeated calls give identical results). The workspace size (KRR_OP_KERNEL_MATMAT) covers
+ * this case whenever n1 == n2.
  * Asynchronous on `stream`. Errors: KRR_E_ARG, KRR_E_WORKSPACE.
  */
 krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const float* X2, int64_t n2,

@@ -62,11 +62,13 @@ int64_t kp_for(int prec, int64_t d) {
   return use_pv(prec, d) ? round_up(d + 2 + (PSHIFT > 0), K_STEP) : kp_for(d);
 }
 // FP64 point width: multiples of 8 up to 128 (FP64 MFMA kernel), else of 32 (VALU kernel)
-// right-hand-side columns per pass of the MFMA-accumulate product: 32, or 64 for large d
-// (where the distance work of a pass dominates its P V work)
-int64_t pv_pass_width(int64_t Kp) { return Kp > 128 ? 64 : 32; }
-// rows of the split V^T operand for a pass of mc columns: 16, 32 or 64 (NCT = 1, 2, 4)
-int64_t pv_pass_rows(int64_t mc) { return mc > 32 ? 64 : round_up(mc, 16); }
+// right-hand-side columns per pass of the MFMA-accumulate product: 32, or 160 for large d
+// (where the distance work of a pass dominates its P V work: up to 160 columns share one
+// distance pass)
+int64_t pv_pass_width(int64_t Kp) { return Kp > 128 ? 160 : 32; }
+// rows of the split V^T operand for a pass of mc columns: 16, 32, 64 or 160 (NCT = 1, 2, 4,
+// 10)
+int64_t pv_pass_rows(int64_t mc) { return mc > 64 ? 160 : mc > 32 ? 64 : round_up(mc, 16); }
 int64_t dp_for(int64_t d) { return round_up(d, 8) <= 128 ? round_up(d, 8) : round_up(d, 32); }
 
 // Split of the column sweep over blockIdx.y so that small row counts still fill the chip.
@@ -142,7 +144,7 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     // large-d MFMA product on many row blocks: 8 column splits, launched in XCD groups
     if (c.pv && c.Kp > 128 && ceil_div(n1, 128) >= 64) c.nsplit = 8;
     if (c.pv) {
-      // (a tuned pass width for large d is 32 or 64, never above the default 64)
+      // (a tuned pass width for large d is 32, 64 or 160, never above the default 160)
       c.mpad = pv_pass_rows(std::min<int64_t>(m, pv_pass_width(c.Kp)));
       c.Vth = b.take<_Float16>(c.mpad * c.rp2);
       c.Vtl = b.take<_Float16>(c.mpad * c.rp2);
@@ -164,7 +166,8 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
   TuneChoice tc;
   if (tune_lookup(prec, 0, prec == KRR_PREC_FP64 ? c.dp : c.Kp, m, n1, &tc)) {
     if (tc.nsplit >= 1 && tc.nsplit <= c.nsplit_max) c.nsplit = tc.nsplit;
-    if (tc.pass_width == 32 || tc.pass_width == 64) c.pass_w = tc.pass_width;
+    if (tc.pass_width == 32 || tc.pass_width == 64 || tc.pass_width == 160)
+      c.pass_w = tc.pass_width;
   }
   c.part_stride = c.rp1 * m;
   c.part = b.take<double>(c.nsplit_max * c.part_stride);
@@ -941,7 +944,7 @@ krr_status krr_autotune_matmat(const krr_kernel* kernel, const float* X, int64_t
   CHECK_HIP(prepare_points(c, X, ldx, nullptr, 0, *kernel, st));
   CHECK_HIP(hash_fill(L.V, n * m, 0x7e57, st));
   // candidates: the rule, fewer splits, and 8 splits (the grouped launch for large d); for
-  // large d with more than 32 right-hand sides also 32-column passes
+  // large d with more than 64 (32) right-hand sides also 64-column (32-column) passes
   std::vector<std::pair<int, int>> cand;
   auto add = [&](int ns, int w) {
     if (ns < 1 || ns > c.nsplit_max) return;
@@ -950,6 +953,7 @@ krr_status krr_autotune_matmat(const krr_kernel* kernel, const float* X, int64_t
     cand.push_back({ns, w});
   };
   std::vector<int> ws_opts = {w0};
+  if (c.pv && c.Kp > 128 && m > 64) ws_opts.push_back(64);
   if (c.pv && c.Kp > 128 && m > 32) ws_opts.push_back(32);
   for (int w : ws_opts) {
     add(ns0, w);

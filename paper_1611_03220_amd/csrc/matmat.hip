@@ -651,8 +651,11 @@ __device__ __forceinline__ void f16pv_bigd_body(
   constexpr int VR = NCT * 16;
   constexpr int VCH = VR * TN / 8;           // V^T pieces per tile
   constexpr int VPT = (VCH + 255) / 256;
+  // wide V^T tiles (more than two pieces per thread) are loaded one piece per thread with
+  // each of the first VPT chunks of the tile instead of all with the first
+  constexpr bool VSPREAD = VPT > 2;
   constexpr int FLUSH = TN >= 128 ? 1 : MM2_FLUSH;  // flush every 128 columns
-  static_assert(BPT >= 1 && BPT <= 2 && VPT <= 2, "tile shape");
+  static_assert(BPT >= 1 && BPT <= 2 && (VPT <= 2 || (VSPREAD && !PACK && !SYM)), "tile shape");
   static_assert(!PACK || NCT == 1, "packed right-hand sides use one 16-row operand");
   static_assert(!SYM || (TN == BD_BM && NCT == 1), "symmetric mode: square tiles, NCT = 1");
   // LDS layout (halves): A[2][2][128*32], B[2][2][TN*32], V[2][2][VR*TN]
@@ -752,6 +755,9 @@ __device__ __forceinline__ void f16pv_bigd_body(
   // tiles of V (NCT = 2), slower for one, which keeps the loads of the final steps
   // conditional.
   constexpr bool UNIFORM = NCT > 1 || NJB < 8;
+  // one register set where the epilogue's registers leave no room for two (symmetric mode,
+  // wide passes): the next chunk is loaded at the start of a step and stored at its end
+  constexpr bool ONESET = SYM || VSPREAD;
   struct Regs {
     u32x4 ra0h, ra0l, ra1h, ra1l, rb0h, rb0l, rb1h, rb1l, rv0h, rv0l, rv1h, rv1l;
   };
@@ -782,7 +788,15 @@ __device__ __forceinline__ void f16pv_bigd_body(
       R.rb1h = *reinterpret_cast<const u32x4*>(Bhi + (t * TN + brow1) * KP + ko);
       R.rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
     }
-    if (kc == 0) {
+    if (VSPREAD) {
+      // piece tid + 256 kc of the tile (VCH is a multiple of 256)
+      if (kc < VPT) {
+        const int e = tid + 256 * kc;
+        const int64_t o = (int64_t)(e / (TN / 8)) * ldvt + t * TN + (e % (TN / 8)) * 8;
+        R.rv0h = *reinterpret_cast<const u32x4*>(Vth + o);
+        R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + o);
+      }
+    } else if (kc == 0) {
       R.rv0h = *reinterpret_cast<const u32x4*>(Vth + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
       if (!PACK)
         R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + (int64_t)vc0 * ldvt + t * TN + vj0 * 8);
@@ -806,7 +820,18 @@ __device__ __forceinline__ void f16pv_bigd_body(
       *reinterpret_cast<u32x4*>(B_at(buf, 0) + sb1) = R.rb1h;
       *reinterpret_cast<u32x4*>(B_at(buf, 1) + sb1) = R.rb1l;
     }
-    if (kc == 0) {
+    if (VSPREAD) {
+      if (kc < VPT) {
+        const int vb = p.t & 1;
+        const int e = tid + 256 * kc;
+        const int vc = e / (TN / 8), vj = e % (TN / 8);
+        const int o0 = vpos<TN>(vc, 8 * vj), o1 = vpos<TN>(vc, 8 * vj + 4);
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + o0) = u32x2{R.rv0h.x, R.rv0h.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 0) + o1) = u32x2{R.rv0h.z, R.rv0h.w};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + o0) = u32x2{R.rv0l.x, R.rv0l.y};
+        *reinterpret_cast<u32x2*>(V_at(vb, 1) + o1) = u32x2{R.rv0l.z, R.rv0l.w};
+      }
+    } else if (kc == 0) {
       const int vb = p.t & 1;
       if (vld0) {
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + svo00) = u32x2{R.rv0h.x, R.rv0h.y};
@@ -852,7 +877,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
     gload(pc, R0);
     lstore(0, pc, R0);
     if (nsteps > 1) advance(pn);
-    if (!SYM) {
+    if (!ONESET) {
       gload(pn, R0);
       pg = pn;
       if (nsteps > 2) advance(pg);
@@ -906,12 +931,16 @@ __device__ __forceinline__ void f16pv_bigd_body(
       };
 #pragma unroll
       for (int jp = 0; jp < NJB / 2; ++jp) {
-        half8 vh[NCT], vl[NCT];
+        // V^T fragments of all column tiles up front, or (wide passes) one tile at a time
+        constexpr int NVF = VSPREAD ? 1 : NCT;
+        half8 vh[NVF], vl[NVF];
+        if (!VSPREAD) {
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) {
-          const int u = vfrag<TN>(16 * ct + li, jp, lg);
-          vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
-          if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
+          for (int ct = 0; ct < NVF; ++ct) {
+            const int u = vfrag<TN>(16 * ct + li, jp, lg);
+            vh[ct] = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
+            if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
+          }
         }
         half8 ph[2], pl[2];
 #pragma unroll
@@ -931,13 +960,29 @@ __device__ __forceinline__ void f16pv_bigd_body(
               pl[ib][4 * jj + r] = l[0];
               pl[ib][4 * jj + r + 1] = l[1];
             }
+          if (!VSPREAD) {
+#pragma unroll
+            for (int ct = 0; ct < NVF; ++ct) {
+              acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[ib], vh[ct], acc[ib][ct], 0, 0, 0);
+              if (!PACK)
+                acc[ib][ct] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vl[ct], acc[ib][ct], 0, 0, 0);
+              acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vh[ct], acc[ib][ct], 0, 0, 0);
+            }
+          }
+        }
+        if (VSPREAD) {
 #pragma unroll
           for (int ct = 0; ct < NCT; ++ct) {
-            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[ib], vh[ct], acc[ib][ct], 0, 0, 0);
-            if (!PACK)
-              acc[ib][ct] =
-                  __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vl[ct], acc[ib][ct], 0, 0, 0);
-            acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], vh[ct], acc[ib][ct], 0, 0, 0);
+            const int u = vfrag<TN>(16 * ct + li, jp, lg);
+            const half8 wh = *reinterpret_cast<const half8*>(V_at(vb, 0) + u);
+            const half8 wl = *reinterpret_cast<const half8*>(V_at(vb, 1) + u);
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+              acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(pl[ib], wh, acc[ib][ct], 0, 0, 0);
+              acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], wl, acc[ib][ct], 0, 0, 0);
+              acc[ib][ct] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ph[ib], wh, acc[ib][ct], 0, 0, 0);
+            }
           }
         }
         if (col) {
@@ -1038,9 +1083,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
     advance(pn);
     if (q + 3 < nsteps) advance(pg);
   };
-  if (SYM) {
-    // one register set (the column side's registers leave no room for two): the next
-    // chunk is loaded at the start of a step and stored at its end
+  if (ONESET) {
     for (int q = 0; q < nsteps; ++q) {
       const bool more = q + 1 < nsteps;
       if (more) gload(pn, R0);
@@ -1073,12 +1116,12 @@ __device__ __forceinline__ void f16pv_bigd_body(
 // does the 64-column pass, NCT = 4, whose accumulators leave no registers for wider tiles)
 constexpr int BD_NJB = 8;
 constexpr int BD_TN = 16 * BD_NJB;
-constexpr int bd_njb(int nct) { return nct == 4 ? 4 : BD_NJB; }
+constexpr int bd_njb(int nct) { return nct >= 4 ? 4 : BD_NJB; }
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
 template <int NCT, int EPI, bool PACK, bool SYM>
-__global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
+__global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
@@ -1140,8 +1183,9 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
                         const SymBuf* sym) {
   if (epi != KV_GAUSS && epi != KV_DSIGMA && epi != KV_POLY) return hipErrorInvalidValue;
   if (A.Kp != B.Kp || V.mpad < round_up(m, 16)) return hipErrorInvalidValue;
-  // passes of up to 32 columns (64 for large d, NCT = 4)
-  if (A.Kp > 128 ? !(V.mpad <= 32 || V.mpad == 64) : V.mpad > 32) return hipErrorInvalidValue;
+  // passes of up to 32 columns (for large d 64, NCT = 4, or 160, NCT = 10)
+  if (A.Kp > 128 ? !(V.mpad <= 32 || V.mpad == 64 || V.mpad == 160) : V.mpad > 32)
+    return hipErrorInvalidValue;
   if (V.packed && (m > 8 || V.mpad != 16)) return hipErrorInvalidValue;
   if (part_stride < round_up(A.n, MM2_BM) * ldp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, MM_BN);
@@ -1153,7 +1197,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
     const bool symm = sym && nct == 1 && A.n == B.n;
     if (symm && (sym->ldfx < V.mpad || V.rows_pad < round_up(A.n, BD_BM)))
       return hipErrorInvalidValue;
-    const int tps = (int)ceil_div(ceil_div(B.n, 16 * (nct == 4 ? bd_njb(4) : BD_NJB)), nsplit);
+    const int tps = (int)ceil_div(ceil_div(B.n, 16 * bd_njb(nct)), nsplit);
     const int64_t nrb = ceil_div(A.n, BD_BM);
     const int64_t nunits = symm ? (nrb + 1) / 2 : nrb;
     const int grouped = nsplit == BD_GROUP && nunits >= 8 * BD_GROUP ? 1 : 0;
@@ -1199,8 +1243,10 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
       KRR_BD_EPI(1, false, false)
     } else if (nct == 2) {
       KRR_BD_EPI(2, false, false)
-    } else {
+    } else if (nct == 4) {
       KRR_BD_EPI(4, false, false)
+    } else {
+      KRR_BD_EPI(10, false, false)
     }
 #undef KRR_BD_EPI
 #undef KRR_BD

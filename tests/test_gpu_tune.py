@@ -43,7 +43,7 @@ def test_autotune_then_parity(dev, n, d, m, prec, tmp_path):
     rep = krr.autotune_matmat(krr.Kernel.gaussian(sigma), _t(X, dev), m, prec=prec)
     assert rep.candidates >= 2
     assert rep.best_ms <= rep.default_ms and rep.best_ms > 0
-    assert rep.nsplit >= 1 and rep.pass_width in (32, 64)
+    assert rep.nsplit >= 1 and rep.pass_width in (32, 64, 160)
     assert krr.tune_cache_size() == 1
     # the tuned launch is now in use for this shape
     V = rng.standard_normal((n, m))
