@@ -547,13 +547,19 @@ const char* krr_tune_digest(void);
 /* ----------------------------------------------------------------------------------------
  * Batched solves: many independent problems in one plan. Every iteration runs ONE persistent
  * kernel-product launch over a work queue of (problem, 128-row block, column range) items for
- * all problems at once, plus batched CG and preconditioner kernels; the iteration is captured
- * once in a hipGraph and replayed until every column of every problem has converged. The
- * work-item granularity is chosen by timing candidates when the plan is created.
+ * all problems at once, plus batched CG and preconditioner kernels; opts->check_every
+ * iterations (at most KRR_BATCH_MAX_GROUP) are captured once in a hipGraph, which is replayed
+ * until every column of every problem has converged, with one host read of the active count
+ * per replay (iterations therefore run in groups of check_every: a converged column is left
+ * unchanged by the rest of its group, and max_iter is reached rounded up to a multiple of
+ * check_every). The product's work items run the register-resident small-d body where
+ * Kp <= 128 and the LDS-streamed body above; the work-item granularity is chosen by timing
+ * candidates when the plan is created.
  * Products use KRR_PREC_F16X3. The plan owns device memory (allocated at creation, freed by
  * krr_batch_plan_destroy); krr_batch_solve allocates nothing.
  */
 #define KRR_BATCH_MAX_M 16
+#define KRR_BATCH_MAX_GROUP 16  /* iterations per replayed graph (opts->check_every cap) */
 
 /* One problem of a batch; all arrays are device memory owned by the caller and must stay
  * valid for the plan's lifetime (the plan keeps the pointers). */
@@ -592,7 +598,7 @@ typedef struct krr_batch_report {
 /*
  * krr_batch_plan_create -- prepare `count` problems (Eq. 1 each, solved as in Alg. 1) for
  * batched PCG: validates them, prepares points, builds the work queues, autotunes the
- * product's work-item size and captures one iteration in a hipGraph. The points are
+ * product's work-item size and captures opts->check_every iterations in a hipGraph. The points are
  * prepared here: a plan serves later changes of Y, Ut contents or alpha's memory, not of X
  * or sigma. opts: HOST pointer (NULL = defaults; opts->prec must be KRR_PREC_F16X3;
  * use_precond = 0 ignores every Ut; refine > 0 adds up to that many refinement steps, each

@@ -1888,6 +1888,7 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
     return fail(KRR_E_ARG, "krr_batch_plan_create: batched products use KRR_PREC_F16X3");
   if (!(o.tol > 0.0) || o.max_iter < 1) return fail(KRR_E_ARG, "krr_batch_plan_create: bad tol/max_iter");
   if (o.check_every < 1) o.check_every = 1;
+  if (o.check_every > KRR_BATCH_MAX_GROUP) o.check_every = KRR_BATCH_MAX_GROUP;
   int M = 0;
   for (int i = 0; i < count; ++i) {
     const krr_batch_problem& b = probs[i];
@@ -2110,11 +2111,13 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
     P->ws64 = w;
   }
   PLAN_HIP(hipStreamSynchronize(st));
-  // capture one iteration
+  // capture check_every iterations: one graph launch and one host read of the active count
+  // per group
   PLAN_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
   PLAN_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
   {
-    hipError_t ce = batch_iteration(P, P->cap);
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < o.check_every && ce == hipSuccess; ++k) ce = batch_iteration(P, P->cap);
     hipGraph_t g = nullptr;
     hipError_t ee = hipStreamEndCapture(P->cap, &g);
     P->graph = g;
@@ -2150,9 +2153,9 @@ static krr_status batch_pcg(krr_batch_plan* P, int* iters, double* ms, hipStream
   int it = 0;
   hipError_t err = hipEventRecord(e0, st);
   while (err == hipSuccess && h_count > 0 && it < P->opts.max_iter) {
-    err = hipGraphLaunch(P->exec, st);
-    ++it;
-    if (err == hipSuccess && (it % P->opts.check_every == 0 || it == P->opts.max_iter)) {
+    err = hipGraphLaunch(P->exec, st);  // check_every iterations
+    it += P->opts.check_every;
+    if (err == hipSuccess) {
       err = hipMemcpyAsync(&h_count, P->S.count, sizeof(int), hipMemcpyDeviceToHost, st);
       if (err == hipSuccess) err = hipStreamSynchronize(st);
     }

@@ -345,7 +345,7 @@ __device__ __forceinline__ void f16pv_body(
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
     float qinv2, float dscale, int deg, double pmul, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split) {
+    int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split) {
   constexpr int KP = KS * 32;
   constexpr int CPR = KP / 8;                 // 16-byte chunks per B row
   constexpr int SWZ = (KS == 1 || KS == 3) ? 3 : 7;
@@ -357,9 +357,9 @@ __device__ __forceinline__ void f16pv_body(
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * MM2_BM + 32 * w;
+  const int64_t i0 = rb * MM2_BM + 32 * w;
   const int64_t ntiles = ceil_div(n2, MM_BN);
-  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+  const int64_t t_begin = split * tiles_per_split;
   const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
 
   half8 ah[2][KS], al[2][KS];
@@ -574,7 +574,7 @@ __device__ __forceinline__ void f16pv_body(
 #undef KRR_PV_ST
   // lane holds OUT[i0 + 16 ib + 4 lg + r][16 ct + li]
   if (PACK) pack_combine<NCT>(acc64);
-  double* pout = part + (int64_t)blockIdx.y * part_stride;
+  double* pout = part + split * part_stride;
 #pragma unroll
   for (int ct = 0; ct < NCT; ++ct) {
     const int64_t c = 16 * ct + li;
@@ -607,11 +607,11 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16
   if (qinv2 == 1.0f)
     f16pv_body<KS, NCT, true, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
                                      qinv2, dscale, deg, pmul, part, ldp, part_stride,
-                                     tiles_per_split);
+                                     tiles_per_split, blockIdx.x, blockIdx.y);
   else
     f16pv_body<KS, NCT, false, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
                                       qinv2, dscale, deg, pmul, part, ldp, part_stride,
-                                      tiles_per_split);
+                                      tiles_per_split, blockIdx.x, blockIdx.y);
 }
 
 // Large-d variant: the row operands no longer fit in registers, so both operands stream
@@ -1281,16 +1281,22 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
 
 // ------------------------------------------------------- batched persistent kernel
 // One launch serves many independent problems: blocks take work items (instance, 128-row
-// block, column split) from an atomic counter until the list is exhausted, and run the
-// large-d body (runtime feature width) on each. Items are ordered largest first; items of a
-// problem whose columns have all converged (live[inst] == 0) are skipped.
+// block, column split) from an atomic counter until the list is exhausted, and run on each
+// the body its feature width calls for: the register-resident small-d body (Kp <= 128, the
+// row operands in registers, 64-column tiles of the other side through LDS) or the large-d
+// body (both operands through LDS). Items are ordered largest first; items of a problem
+// whose columns have all converged (live[inst] == 0) are skipped.
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int BATCH_SMEM_BYTES =
+    cmax(cmax(2 * bigd_smem_halves<1, 4>(), (int)sizeof(PVSmem<4, 1, true>)),
+         (int)sizeof(PVSmem<4, 1, false>));
 __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* __restrict__ items,
                                                               const int* __restrict__ list,
                                                               const int* __restrict__ nlist,
                                                               const BatchInst* __restrict__ inst,
                                                               int* __restrict__ counter,
                                                               int packed) {
-  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<1, 4>()];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[BATCH_SMEM_BYTES];
   __shared__ int cur;
   const int nitems = *nlist;  // live items only (batch_compact_live)
   for (;;) {
@@ -1302,19 +1308,30 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
     const BatchItem wi = items[list[it]];
     const BatchInst I = inst[wi.inst];
     const float qinv2 = *I.qinv2;
-#define KRR_BATCH_BODY(U, PK)                                                                    \
-  f16pv_bigd_body<1, U, KV_GAUSS, 4, PK>(smem, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl,        \
-                                          I.vscale, I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, 1,  \
-                                          1.0, I.part, I.ldp, I.part_stride, wi.tiles_per_split,  \
-                                          wi.rb, wi.split)
-    if (packed) {
-      if (qinv2 == 1.0f) KRR_BATCH_BODY(true, true);
-      else KRR_BATCH_BODY(false, true);
+    if (I.Kp <= 128) {
+#define KRR_BATCH_SMALL(KS, U, PK)                                                               f16pv_body<KS, 1, U, KV_GAUSS, PK>(*reinterpret_cast<PVSmem<KS, 1, PK>*>(smem), I.Ahi, I.Alo,                                       I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale, I.ldvt, I.n, I.n,                                          I.m, qinv2, 0.0f, 1, 1.0, I.part, I.ldp, I.part_stride,                                          wi.tiles_per_split, wi.rb, wi.split)
+#define KRR_BATCH_KS(U, PK)                                      switch (I.Kp) {                                                  case 32: KRR_BATCH_SMALL(1, U, PK); break;                     case 64: KRR_BATCH_SMALL(2, U, PK); break;                     case 96: KRR_BATCH_SMALL(3, U, PK); break;                     default: KRR_BATCH_SMALL(4, U, PK); break;                   }
+      if (packed) {
+        if (qinv2 == 1.0f) { KRR_BATCH_KS(true, true) }
+        else { KRR_BATCH_KS(false, true) }
+      } else {
+        if (qinv2 == 1.0f) { KRR_BATCH_KS(true, false) }
+        else { KRR_BATCH_KS(false, false) }
+      }
+#undef KRR_BATCH_KS
+#undef KRR_BATCH_SMALL
     } else {
-      if (qinv2 == 1.0f) KRR_BATCH_BODY(true, false);
-      else KRR_BATCH_BODY(false, false);
-    }
+      _Float16* sh = reinterpret_cast<_Float16*>(smem);
+#define KRR_BATCH_BODY(U, PK)                                                                      f16pv_bigd_body<1, U, KV_GAUSS, 4, PK>(sh, I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl,                                                    I.vscale, I.ldvt, I.n, I.n, I.m, I.Kp, qinv2, 0.0f, 1,                                            1.0, I.part, I.ldp, I.part_stride, wi.tiles_per_split,                                            wi.rb, wi.split)
+      if (packed) {
+        if (qinv2 == 1.0f) KRR_BATCH_BODY(true, true);
+        else KRR_BATCH_BODY(false, true);
+      } else {
+        if (qinv2 == 1.0f) KRR_BATCH_BODY(true, false);
+        else KRR_BATCH_BODY(false, false);
+      }
 #undef KRR_BATCH_BODY
+    }
     __syncthreads();
   }
 }

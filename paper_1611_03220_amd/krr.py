@@ -708,14 +708,15 @@ class BatchSolveReport:
 
 class BatchPlan:
     """Many independent problems (K_p + lam_p I) alpha_p = Y_p solved together: one persistent
-    kernel-product launch and one captured iteration graph per PCG iteration.
+    kernel-product launch per PCG iteration, check_every iterations per replayed graph (one
+    host read of the active count per replay).
 
     problems: list of dicts with keys X (n x d FP32), sigma, lam, Y (n x m FP64, m <= 16) and
     optionally Ut (n x s FP32) and lambda_p. The plan keeps references to every tensor and
     owns the solutions (``alphas``). Points are prepared at construction."""
 
     def __init__(self, problems, tol: float = 1e-6, max_iter: int = 1000,
-                 use_precond: bool = True, check_every: int = 1, true_residual: bool = True,
+                 use_precond: bool = True, check_every: int = 4, true_residual: bool = True,
                  refine: int = 0):
         self._keep = []
         n_p = len(problems)

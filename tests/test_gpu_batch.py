@@ -205,3 +205,21 @@ def test_setup_many_matches_single_calls_and_reports_pivots(dev):
     with pytest.raises(krr.KRRError) as e:
         krr.setup_many(probs, nstreams=3)
     assert e.value.status == krr.E_NOT_SPD and "problem 3" in str(e.value)
+
+
+def test_batch_grouped_iterations_match_single_iteration_graphs(dev):
+    """Replaying graphs of 4 captured iterations (one host check per 4) gives the solutions
+    and per-column iteration counts of one-iteration graphs: a converged column is left
+    unchanged by the rest of its group."""
+    ws = WL.batched_instances(count=6, n_lo=400, n_hi=1500, salt=5)
+    probs = _problems(ws, dev)
+    out = []
+    for k in (1, 4):
+        plan = krr.BatchPlan(probs, tol=1e-6, refine=2, check_every=k)
+        alphas, rep = plan.solve()
+        out.append(([a.cpu().numpy().copy() for a in alphas], [list(c) for c in rep.col_iters]))
+        plan.close()
+    (a1, c1), (a4, c4) = out
+    assert c1 == c4
+    for x, y in zip(a1, a4):
+        assert np.array_equal(x, y)
