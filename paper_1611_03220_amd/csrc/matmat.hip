@@ -1384,7 +1384,7 @@ __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
 constexpr int F64B_TJ = 64;
 constexpr int F64B_LK = 33;  // padded LDS row of a chunk (floats)
 template <int NCT>
-__global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
+__global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
     const float* __restrict__ Xa, const double* __restrict__ nua, const float* __restrict__ Xb,
     const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
     int64_t n2, int64_t m, int c0, int dp, double c, int epi, double dscale, PolyF64 pk,
@@ -1416,10 +1416,16 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
     for (int ct = 0; ct < NCT; ++ct) acc[ib][ct] = d4v{0.0, 0.0, 0.0, 0.0};
 
   // loaders: row chunk 128 x 32 floats (4 float4 per thread), column chunk 64 x 32 (2),
-  // V tile 64 x VC doubles and nu of the tile's columns at each tile's first chunk
+  // V tile 64 x VC doubles (VU per thread) and nu of the tile's columns at each tile's first
+  // chunk; a wide V tile (160 columns) comes in VU / UPS slices of UPS values per thread with
+  // the tile's first chunks, each stored at the start of the next step (the last at chunk 3,
+  // so a barrier separates it from the reads at the last chunk whenever KC >= 5)
+  constexpr int VU = F64B_TJ * VC / 256;
+  constexpr int UPS = VU > 16 ? 10 : VU;
+  static_assert(VU % UPS == 0 && VU / UPS <= 4, "V tile slices");
   const int lrow = tid >> 3, lc4 = (tid & 7) * 4;
   float4 rr[4], rc[2];
-  double rv[F64B_TJ * VC / 256];
+  double rv[UPS];
   double rn = 0.0;
   auto gload = [&](int64_t q) __attribute__((always_inline)) {
     const int64_t t = t_begin + q / KC;
@@ -1431,15 +1437,15 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
 #pragma unroll
     for (int u = 0; u < 2; ++u)
       rc[u] = *reinterpret_cast<const float4*>(Xb + (t * F64B_TJ + lrow + 32 * u) * dp + ko);
-    if (kc == 0) {
+    if (kc < VU / UPS) {
 #pragma unroll
-      for (int u = 0; u < F64B_TJ * VC / 256; ++u) {
-        const int e = tid + 256 * u, r = e / VC, cc = e % VC;
+      for (int u = 0; u < UPS; ++u) {
+        const int e = tid + 256 * (kc * UPS + u), r = e / VC, cc = e % VC;
         const int64_t j = t * F64B_TJ + r;
         rv[u] = (j < n2 && c0 + cc < m) ? V[j * ldv + c0 + cc] : 0.0;
       }
-      if (tid < F64B_TJ) rn = nub[t * F64B_TJ + tid];
     }
+    if (kc == 0 && tid < F64B_TJ) rn = nub[t * F64B_TJ + tid];
   };
   auto lstore = [&](int64_t q) __attribute__((always_inline)) {
     const int buf = (int)(q & 1);
@@ -1454,13 +1460,13 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
       d[0] = rc[u].x; d[1] = rc[u].y; d[2] = rc[u].z; d[3] = rc[u].w;
     }
   };
-  auto vstore = [&]() __attribute__((always_inline)) {
+  auto vstore = [&](int kc) __attribute__((always_inline)) {
 #pragma unroll
-    for (int u = 0; u < F64B_TJ * VC / 256; ++u) {
-      const int e = tid + 256 * u;
+    for (int u = 0; u < UPS; ++u) {
+      const int e = tid + 256 * (kc * UPS + u);
       sV[(e / VC) * LV + e % VC] = rv[u];
     }
-    if (tid < F64B_TJ) sN[tid] = rn;
+    if (kc == 0 && tid < F64B_TJ) sN[tid] = rn;
   };
 
   if (nsteps > 0) {
@@ -1471,8 +1477,8 @@ __global__ __launch_bounds__(256, NCT == 4 ? 1 : 2) void matmat_f64big_kernel(
   for (int64_t q = 0; q < nsteps; ++q) {
     const int buf = (int)(q & 1);
     const int kc = (int)(q % KC);
+    if (kc < VU / UPS) vstore(kc);  // this tile's V and nu (read at its last chunk, after a barrier)
     if (kc == 0) {
-      vstore();  // this tile's V and nu (read at its last chunk, after a barrier)
 #pragma unroll
       for (int jb = 0; jb < 4; ++jb)
 #pragma unroll
@@ -1774,13 +1780,14 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
   if (!A.Xf || !B.Xf || A.dp % 32) return hipErrorInvalidValue;
   const int tpsb = (int)ceil_div(ceil_div(B.n, F64B_TJ), nsplit);
   dim3 gridb(ceil_div(A.n, 128), nsplit);
-  // passes of up to 64 right-hand sides: the inner products dominate a pass's work
-  for (int64_t c0 = 0; c0 < m; c0 += 64) {
+  // passes of up to 160 right-hand sides: the inner products dominate a pass's work
+  for (int64_t c0 = 0; c0 < m; c0 += 160) {
 #define KRR_F64B(NCT_)                                                                        \
   matmat_f64big_kernel<NCT_><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m, \
                                                     (int)c0, (int)A.dp, c, epi, dscale, pk,    \
                                                     part, ldp, part_stride, tpsb)
-    if (m - c0 > 32) KRR_F64B(4);
+    if (m - c0 > 64) KRR_F64B(10);
+    else if (m - c0 > 32) KRR_F64B(4);
     else if (m - c0 > 16) KRR_F64B(2);
     else KRR_F64B(1);
 #undef KRR_F64B

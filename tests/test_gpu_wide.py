@@ -100,3 +100,24 @@ def test_wide_pass_grouped_launch_sampled_rows(dev):
     tau = _tau(X, X, sigma, d)
     bound = tau * (O.gaussian_kernel(X[rows], X, sigma) @ np.abs(V))
     assert np.all(np.abs(got[rows] - ref) <= bound), np.max(np.abs(got[rows] - ref) / bound)
+
+
+@pytest.mark.parametrize("n1,n2,d,m", [(300, 300, 440, 147), (200, 333, 300, 160), (129, 140, 160, 161),
+                                       (150, 150, 784, 65)])
+def test_wide_pass_fp64(dev, n1, n2, d, m):
+    """The FP64 large-d product's 160-column pass (V^T tile loaded in four slices over the
+    first chunks): 1e-12 relative to (|K| |V|)_i, value and sigma-derivative, the smallest
+    chunk count (d = 160: five 32-wide chunks) included."""
+    rng = np.random.default_rng(1300 + n1 + d + m)
+    X1 = rng.standard_normal((n1, d)).astype(np.float32)
+    X2 = X1 if n1 == n2 else rng.standard_normal((n2, d)).astype(np.float32)
+    V = rng.standard_normal((n2, m))
+    sigma = 0.8 * math.sqrt(d)
+    A = _t(X1, dev)
+    B = A if n1 == n2 else _t(X2, dev)
+    for deriv in (False, True):
+        got = krr.kernel_matmat(A, B, sigma, _t(V, dev), deriv=deriv, prec="fp64").cpu().numpy()
+        ref = O.kernel_matmat(X1, X2, sigma, V, deriv=deriv)
+        K = (O.gaussian_kernel_dsigma if deriv else O.gaussian_kernel)(X1, X2, sigma)
+        bound = 1e-12 * (np.abs(K) @ np.abs(V))
+        assert np.all(np.abs(got - ref) <= bound), (deriv, np.max(np.abs(got - ref) / bound))
