@@ -1177,6 +1177,35 @@ __global__ __launch_bounds__(256) void sym_fold_kernel(const unsigned long long*
   part[i * ldp + c] += v * ((double)vscale[c] * pmul);
 }
 
+// Column side of a symmetric product: clear the accumulator and flags, fix the fixed-point
+// scale 2^F from a bound on any column-side total (n terms of |P| <= pmax: exp2 of a
+// non-positive value up to rounding, a power of a value in [-1, 1], or x 2^-x dscale <=
+// 0.531 dscale, times |V'| <= SPLIT_TARGET, kept below 2^62).
+hipError_t sym_begin(const SymBuf& sym, int64_t n, int64_t rows_pad, int epi, float dscale,
+                     int nsplit, int64_t nrb, SymOut& so, double& inv_fxs, hipStream_t st) {
+  const double pmax = epi == KV_DSIGMA ? 0.54 * std::fabs((double)dscale) : 2.0;
+  const double bound = (double)n * std::max(pmax, 1e-30) * SPLIT_TARGET;
+  const int F = (int)std::floor(62.0 - std::log2(bound));
+  so.fx = sym.fx;
+  so.flag = sym.flag;
+  so.ldfx = sym.ldfx;
+  so.fxs = std::ldexp(1.0f, F);
+  so.nsplit = nsplit;
+  so.nrb = nrb;
+  inv_fxs = std::ldexp(1.0, -F);
+  hipError_t e = fill_f64(reinterpret_cast<double*>(so.fx), rows_pad * so.ldfx, 0.0, st);
+  if (e == hipSuccess) e = fill_i32(reinterpret_cast<int*>(so.flag), rows_pad, 0, st);
+  return e;
+}
+hipError_t sym_end(const SymOut& so, double inv_fxs, int64_t n, int64_t m, const SplitRhs& V,
+                   const float* kpar, int epi, double* part, int64_t ldp, hipStream_t st) {
+  const int64_t mc = V.packed ? std::min<int64_t>(m, 8) : m;
+  sym_fold_kernel<<<(unsigned)ceil_div(n * mc, 256), 256, 0, st>>>(
+      so.fx, so.flag, so.ldfx, n, mc, inv_fxs, V.vscale, kpar, epi, part, ldp);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
 hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float16>& B,
                         const SplitRhs& V, int64_t m, int epi, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st,
@@ -1192,37 +1221,24 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   const int tps = (int)ceil_div(ntiles, nsplit);
   dim3 grid(ceil_div(A.n, MM2_BM), nsplit);
   const int nct = (int)(V.mpad / 16);
+  // symmetric products: large d, one 16-column tile, the same points on both sides
+  const bool symm = sym && A.Kp > 128 && nct == 1 && A.n == B.n;
+  if (symm && (sym->ldfx < V.mpad || V.rows_pad < round_up(A.n, MM2_BM)))
+    return hipErrorInvalidValue;
+  const int64_t nrb = ceil_div(A.n, MM2_BM);
+  SymOut so;
+  double inv_fxs = 1.0;
+  if (symm) {
+    hipError_t e = sym_begin(*sym, A.n, V.rows_pad, epi, dscale, nsplit, nrb, so, inv_fxs, st);
+    if (e != hipSuccess) return e;
+  }
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
-    const bool symm = sym && nct == 1 && A.n == B.n;
-    if (symm && (sym->ldfx < V.mpad || V.rows_pad < round_up(A.n, BD_BM)))
-      return hipErrorInvalidValue;
     const int tps = (int)ceil_div(ceil_div(B.n, 16 * bd_njb(nct)), nsplit);
-    const int64_t nrb = ceil_div(A.n, BD_BM);
     const int64_t nunits = symm ? (nrb + 1) / 2 : nrb;
     const int grouped = nsplit == BD_GROUP && nunits >= 8 * BD_GROUP ? 1 : 0;
     grid = grouped ? dim3((unsigned)(round_up(nunits, 8 * BD_GROUP) * BD_GROUP), 1)
                    : dim3((unsigned)nunits, nsplit);
-    SymOut so;
-    double inv_fxs = 1.0;
-    if (symm) {
-      // F from a bound on any column-side total: n terms of |P| <= pmax (exp2 of a
-      // non-positive value up to rounding, a power of a value in [-1, 1], or
-      // x 2^-x dscale <= 0.531 dscale) times |V'| <= SPLIT_TARGET, below 2^62
-      const double pmax = epi == KV_DSIGMA ? 0.54 * std::fabs((double)dscale) : 2.0;
-      const double bound = (double)A.n * std::max(pmax, 1e-30) * SPLIT_TARGET;
-      const int F = (int)std::floor(62.0 - std::log2(bound));
-      so.fx = sym->fx;
-      so.flag = sym->flag;
-      so.ldfx = sym->ldfx;
-      so.fxs = std::ldexp(1.0f, F);
-      so.nsplit = nsplit;
-      so.nrb = nrb;
-      inv_fxs = std::ldexp(1.0, -F);
-      hipError_t e = fill_f64(reinterpret_cast<double*>(so.fx), V.rows_pad * so.ldfx, 0.0, st);
-      if (e == hipSuccess) e = fill_i32(reinterpret_cast<int*>(so.flag), V.rows_pad, 0, st);
-      if (e != hipSuccess) return e;
-    }
 #define KRR_BD(NCT_, D_, P_, S_)                                                                 \
   matmat_f16pv_bigd_kernel<NCT_, D_, P_, S_><<<grid, 256, 0, st>>>(                              \
       A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, \
@@ -1251,13 +1267,7 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
 #undef KRR_BD_EPI
 #undef KRR_BD
     KRR_LAUNCH_CHECK();
-    if (symm) {
-      const int64_t mc = V.packed ? std::min<int64_t>(m, 8) : m;
-      sym_fold_kernel<<<(unsigned)ceil_div(A.n * mc, 256), 256, 0, st>>>(
-          so.fx, so.flag, so.ldfx, A.n, mc, inv_fxs, V.vscale, A.qinv2, epi, part, ldp);
-      KRR_LAUNCH_CHECK();
-    }
-    return hipSuccess;
+    return symm ? sym_end(so, inv_fxs, A.n, m, V, A.qinv2, epi, part, ldp, st) : hipSuccess;
   }
 #define KRR_PV1(KS_, NCT_, E_, PK_)                                                           \
   matmat_f16pv_kernel<KS_, NCT_, E_, PK_><<<grid, 256, 0, st>>>(                              \

@@ -1,11 +1,12 @@
 """GPU parity of the symmetric large-d kernel product K(X, X) V (both sides the same points,
 d large enough for the LDS-streamed product, passes of up to 16 columns): each off-diagonal
 pair of 128-row blocks is formed once and serves both triangles, the transposed side summed
-in 64-bit fixed point. The exact symmetry K_ij = K_ji makes it the same product as the
-general one, so the same per-entry bounds apply (derived in test_gpu_parity.py and
-test_gpu_poly.py); it is checked against the oracle, against the general path on a copy of
-the points, for determinism, for non-finite propagation and at the launch shapes of the large
-workloads (grouped launch, many block pairs) on sampled rows.
+in 64-bit fixed point; small d takes the general kernel (also checked here). The exact
+symmetry K_ij = K_ji makes it the same product as the general one, so the same per-entry
+bounds apply (derived in test_gpu_parity.py and test_gpu_poly.py); it is checked against the
+oracle, against the general path on a copy of the points, for determinism, for non-finite
+propagation and at the launch shapes of the large workloads (grouped launch, many block
+pairs) on sampled rows.
 """
 import math
 
@@ -55,7 +56,11 @@ def _bound(X, sigma, V, deriv, d, rows=None):
 # n: one block, a ragged pair list with a middle block (odd count), an even count; m: packed
 # (<= 8), separate hi/lo (9..16), and 17 (two 16-row tiles: the general kernel)
 @pytest.mark.parametrize("n,d,m", [(1, 150, 3), (128, 200, 1), (677, 150, 8), (677, 300, 10),
-                                   (1000, 784, 16), (517, 440, 17), (300, 129, 5)])
+                                   (1000, 784, 16), (517, 440, 17), (300, 129, 5),
+                                   # small d: the general register-resident kernel on the
+                                   # same points
+                                   (677, 54, 7), (1000, 40, 16), (129, 80, 9), (300, 126, 1),
+                                   (257, 20, 4), (200, 54, 17), (64, 62, 2)])
 def test_sym_matches_oracle_and_general_path(dev, n, d, m):
     rng = np.random.default_rng(900 + n + d + m)
     X = rng.standard_normal((n, d)).astype(np.float32)
@@ -149,4 +154,23 @@ def test_sym_many_pairs_grouped_launch(dev):
     rows[0], rows[-1] = 0, n - 1
     ref = O.kernel_matmat(X, X, sigma, V, rows=rows)
     bound = _bound(X, sigma, V, False, d, rows=rows)
+    assert np.all(np.abs(got[rows] - ref) <= bound), np.max(np.abs(got[rows] - ref) / bound)
+
+
+def test_same_points_small_d_sampled(dev):
+    """K(X, X) V with small d at a mixture-like size (n = 20000 + 33, d = 54, 7 columns,
+    shift; the general kernel): sampled rows against the oracle, and determinism."""
+    rng = np.random.default_rng(936)
+    n, d, m = 20033, 54, 7
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    V = rng.standard_normal((n, m))
+    sigma = 0.6 * math.sqrt(d)
+    Xg, Vg = _t(X, dev), _t(V, dev)
+    got = krr.kernel_matmat(Xg, Xg, sigma, Vg, shift=0.25).cpu().numpy()
+    again = krr.kernel_matmat(Xg, Xg, sigma, Vg, shift=0.25).cpu().numpy()
+    assert np.array_equal(got, again)
+    rows = np.sort(rng.choice(n, 40, replace=False))
+    rows[0], rows[-1] = 0, n - 1
+    ref = O.kernel_matmat(X, X, sigma, V, shift=0.25, rows=rows)
+    bound = _bound(X, sigma, V, False, d, rows=rows) + 1e-15 * 0.25 * np.abs(V[rows])
     assert np.all(np.abs(got[rows] - ref) <= bound), np.max(np.abs(got[rows] - ref) / bound)
