@@ -141,6 +141,11 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
   } else {
     c.pv = use_pv(prec, d);
     c.Kp = kp_for(prec, d);
+    // the symmetric large-d kernel runs 256-row blocks: rows padded to 256
+    if (c.pv && c.Kp > 128 && sym_buf) {
+      c.rp1 = round_up(n1, 2 * ROW_PAD);
+      c.rp2 = round_up(n2, 2 * ROW_PAD);
+    }
     // large-d MFMA product on many row blocks: 8 column splits, launched in XCD groups
     if (c.pv && c.Kp > 128 && ceil_div(n1, 128) >= 64) c.nsplit = 8;
     if (c.pv) {

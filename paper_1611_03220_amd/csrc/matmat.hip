@@ -632,12 +632,17 @@ __global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16
 // four waves' partial sums (over their 32 rows of I) are added through the LDS buffer of
 // the stage not in use, and the result goes to the column-side accumulator as 64-bit
 // fixed-point atomic adds (exact, so the total does not depend on the order of the adds).
+//
+// WM row waves per block (4, or 8 for the symmetric kernel: 256-row blocks, one block per CU,
+// a quarter fewer operand bytes per MFMA flop than 128-row blocks); the symmetric kernel's
+// partial sums of waves 6 and 7 need an extra 16 KB LDS area beyond the free stage.
 constexpr int BD_BM = 128;
-template <int NCT, int NJB>
+template <int NCT, int NJB, int WM = 4>
 constexpr int bigd_smem_halves() {
-  return 2 * 2 * BD_BM * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB);
+  return 2 * 2 * (32 * WM) * 32 + 2 * 2 * (16 * NJB) * 32 + 2 * 2 * NCT * 16 * (16 * NJB) +
+         (WM == 8 ? 2 * (16 * NJB) * 16 * 2 : 0);
 }
-template <int NCT, bool UNIT, int EPI, int NJB, bool PACK, bool SYM = false>
+template <int NCT, bool UNIT, int EPI, int NJB, bool PACK, bool SYM = false, int WM = 4>
 __device__ __forceinline__ void f16pv_bigd_body(
     _Float16* __restrict__ smem, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
@@ -647,22 +652,27 @@ __device__ __forceinline__ void f16pv_bigd_body(
     int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split,
     const SymOut& so = SymOut{}) {
   constexpr int TN = 16 * NJB;
-  constexpr int BPT = TN * 4 / 256;          // B chunk pieces per thread
+  constexpr int NT = 64 * WM;                // threads
+  constexpr int BMR = 32 * WM;               // rows per block
+  constexpr int RT = BMR / TN;               // column tiles per row block (symmetric mode)
+  constexpr int BPT = TN * 4 / NT;           // B chunk pieces per thread
   constexpr int VR = NCT * 16;
   constexpr int VCH = VR * TN / 8;           // V^T pieces per tile
-  constexpr int VPT = (VCH + 255) / 256;
+  constexpr int VPT = (VCH + NT - 1) / NT;
   // wide V^T tiles (more than two pieces per thread) are loaded one piece per thread with
   // each of the first VPT chunks of the tile instead of all with the first
   constexpr bool VSPREAD = VPT > 2;
   constexpr int FLUSH = TN >= 128 ? 1 : MM2_FLUSH;  // flush every 128 columns
   static_assert(BPT >= 1 && BPT <= 2 && (VPT <= 2 || (VSPREAD && !PACK && !SYM)), "tile shape");
   static_assert(!PACK || NCT == 1, "packed right-hand sides use one 16-row operand");
-  static_assert(!SYM || (TN == BD_BM && NCT == 1), "symmetric mode: square tiles, NCT = 1");
-  // LDS layout (halves): A[2][2][128*32], B[2][2][TN*32], V[2][2][VR*TN]
+  static_assert(!SYM || (TN == 128 && NCT == 1), "symmetric mode: 128-column tiles, NCT = 1");
+  static_assert(WM == 4 || (WM == 8 && SYM), "256-row blocks in symmetric mode only");
+  // LDS layout (halves): A[2][2][BMR*32], B[2][2][TN*32], V[2][2][VR*TN] (+ X[2 TN 16 floats])
   _Float16* sA = smem;
-  _Float16* sB = sA + 2 * 2 * BD_BM * 32;
+  _Float16* sB = sA + 2 * 2 * BMR * 32;
   _Float16* sV = sB + 2 * 2 * TN * 32;
-  auto A_at = [&](int buf, int hl) { return sA + (buf * 2 + hl) * BD_BM * 32; };
+  _Float16* sX = sV + 2 * 2 * VR * TN;
+  auto A_at = [&](int buf, int hl) { return sA + (buf * 2 + hl) * BMR * 32; };
   auto B_at = [&](int buf, int hl) { return sB + (buf * 2 + hl) * TN * 32; };
   auto V_at = [&](int buf, int hl) { return sV + (buf * 2 + hl) * VR * TN; };
 
@@ -676,15 +686,15 @@ __device__ __forceinline__ void f16pv_bigd_body(
   int nA = 0, count = 0;
   if (SYM) {
     rbB = so.nrb - 1 - rb;
-    const int64_t len1 = ntiles - rbA;
-    const int64_t len2 = rbB > rbA ? ntiles - rbB : 0;
+    const int64_t len1 = ntiles - RT * rbA;
+    const int64_t len2 = rbB > rbA ? ntiles - RT * rbB : 0;
     const int64_t L = len1 + len2;
     const int64_t b0 = split * L / so.nsplit, b1 = (split + 1) * L / so.nsplit;
     count = (int)(b1 - b0);
     const int64_t na = len1 - b0;
     nA = na < 0 ? 0 : na > count ? count : (int)na;
-    jA = rbA + b0;
-    jB = rbB + (b0 + nA - len1);
+    jA = RT * rbA + b0;
+    jB = RT * rbB + (b0 + nA - len1);
   } else {
     const int64_t t_begin = split * tiles_per_split;
     const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
@@ -714,7 +724,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   auto load_vI = [&](int64_t I) __attribute__((always_inline)) {
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
-      const int64_t o = (int64_t)(16 * ct + li) * ldvt + I * BD_BM + 32 * w + 4 * lg;
+      const int64_t o = (int64_t)(16 * ct + li) * ldvt + I * BMR + 32 * w + 4 * lg;
       const u32x2 a = *reinterpret_cast<const u32x2*>(Vth + o);
       const u32x2 b = *reinterpret_cast<const u32x2*>(Vth + o + 16);
       vIh[ct] = __builtin_bit_cast(half8, u32x4{a.x, a.y, b.x, b.y});
@@ -732,17 +742,17 @@ __device__ __forceinline__ void f16pv_bigd_body(
   for (int r = 0; r < 4; ++r) esel[r] = (_Float16)(4 * lg + r == li ? 1.0f : 0.0f);
   if (SYM && count > 0) load_vI(item_rb(0));
 
-  // chunk loaders: A rows of the item's row block + tid/4 and + 64; B rows j0 + tid/4
-  // (+ 64 when TN = 128)
-  const int arow0 = tid >> 2, arow1 = arow0 + 64, acol = tid & 3;
+  // chunk loaders: A rows of the item's row block + tid/4 and + NT/4; B rows j0 + tid/4
+  // (+ 64 when TN = 128 and NT = 256)
+  const int arow0 = tid >> 2, arow1 = arow0 + NT / 4, acol = tid & 3;
   const int sa0 = arow0 * 32 + ((acol ^ ((arow0 >> 1) & 3)) * 8);
   const int sa1 = arow1 * 32 + ((acol ^ ((arow1 >> 1) & 3)) * 8);
   const int brow1 = arow0 + 64;
   const int sb1 = brow1 * 32 + ((acol ^ ((brow1 >> 1) & 3)) * 8);
-  // V^T pieces: piece e = tid + 256 u covers row e / (TN / 8), columns 8 (e % (TN / 8)) ..
+  // V^T pieces: piece e = tid + NT u covers row e / (TN / 8), columns 8 (e % (TN / 8)) ..
   // Threads past the last piece load a duplicate and do not store it.
-  const bool vld0 = tid < VCH, vld1 = VPT > 1 && tid + 256 < VCH;
-  const int ve0 = tid % VCH, ve1 = (tid + 256) % VCH;
+  const bool vld0 = tid < VCH, vld1 = VPT > 1 && tid + NT < VCH;
+  const int ve0 = tid % VCH, ve1 = (tid + NT) % VCH;
   const int vc0 = ve0 / (TN / 8), vj0 = ve0 % (TN / 8);
   const int vc1 = ve1 / (TN / 8), vj1 = ve1 % (TN / 8);
   const int svo00 = vpos<TN>(vc0, 8 * vj0), svo01 = vpos<TN>(vc0, 8 * vj0 + 4);
@@ -775,7 +785,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   };
   auto gload = [&](const Pos& p, Regs& R) __attribute__((always_inline)) {
     const int64_t t = item_j(p.t);
-    const int64_t blk_i0 = item_rb(p.t) * BD_BM;
+    const int64_t blk_i0 = item_rb(p.t) * BMR;
     const int kc = p.kc;
     const int64_t ko = (int64_t)kc * 32 + acol * 8;
     R.ra0h = *reinterpret_cast<const u32x4*>(Ahi + (blk_i0 + arow0) * KP + ko);
@@ -789,9 +799,9 @@ __device__ __forceinline__ void f16pv_bigd_body(
       R.rb1l = *reinterpret_cast<const u32x4*>(Blo + (t * TN + brow1) * KP + ko);
     }
     if (VSPREAD) {
-      // piece tid + 256 kc of the tile (VCH is a multiple of 256)
+      // piece tid + NT kc of the tile (VCH is a multiple of NT)
       if (kc < VPT) {
-        const int e = tid + 256 * kc;
+        const int e = tid + NT * kc;
         const int64_t o = (int64_t)(e / (TN / 8)) * ldvt + t * TN + (e % (TN / 8)) * 8;
         R.rv0h = *reinterpret_cast<const u32x4*>(Vth + o);
         R.rv0l = *reinterpret_cast<const u32x4*>(Vtl + o);
@@ -823,7 +833,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
     if (VSPREAD) {
       if (kc < VPT) {
         const int vb = p.t & 1;
-        const int e = tid + 256 * kc;
+        const int e = tid + NT * kc;
         const int vc = e / (TN / 8), vj = e % (TN / 8);
         const int o0 = vpos<TN>(vc, 8 * vj), o1 = vpos<TN>(vc, 8 * vj + 4);
         *reinterpret_cast<u32x2*>(V_at(vb, 0) + o0) = u32x2{R.rv0h.x, R.rv0h.y};
@@ -854,7 +864,7 @@ __device__ __forceinline__ void f16pv_bigd_body(
   // row-side output of row block I: lane holds OUT[I * 128 + 32 w + 16 ib + 4 lg + r][16 ct + li]
   double* pout = part + split * part_stride;
   auto write_rows = [&](int64_t I, bool zero) __attribute__((always_inline)) {
-    const int64_t i0 = I * BD_BM + 32 * w;
+    const int64_t i0 = I * BMR + 32 * w;
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
       const int64_t c = 16 * ct + li;
@@ -921,13 +931,18 @@ __device__ __forceinline__ void f16pv_bigd_body(
     {
       const int vb = p.t & 1;
       const int64_t I = item_rb(p.t), J = item_j(p.t);
-      const bool col = SYM && J > I;  // uniform over the block
-      // column-side partial sums of wave w: [128 columns j][16 columns c] FP32 in the LDS
-      // stage the next chunk is stored to after the epilogue (free until then)
+      // right of row block I's diagonal block (uniform over the block)
+      const bool col = SYM && J >= RT * (I + 1);
+      // column-side partial sums of wave ww: [128 columns j][16 columns c] FP32 in the LDS
+      // stage the next chunk is stored to after the epilogue (free until then): waves
+      // 0 .. 2 WM/4 - 1 in its A part, the next two in its B part, waves 6 and 7 (WM = 8) in
+      // the extra area
       constexpr int CW = 16 * NCT;
       auto red_at = [&](int ww) __attribute__((always_inline)) {
-        _Float16* base = ww < 2 ? A_at(buf ^ 1, 0) : B_at(buf ^ 1, 0);
-        return reinterpret_cast<float*>(base) + (ww & 1) * TN * CW;
+        constexpr int NA = WM / 2;  // waves in the A part
+        _Float16* base = ww < NA ? A_at(buf ^ 1, 0) : ww < NA + 2 ? B_at(buf ^ 1, 0) : sX;
+        const int k = ww < NA ? ww : ww < NA + 2 ? ww - NA : ww - NA - 2;
+        return reinterpret_cast<float*>(base) + k * TN * CW;
       };
 #pragma unroll
       for (int jp = 0; jp < NJB / 2; ++jp) {
@@ -1046,18 +1061,19 @@ __device__ __forceinline__ void f16pv_bigd_body(
       }
       if (col) {
         __syncthreads();
-        // wave w finishes columns 32 w .. 32 w + 31: the four waves' partials added in a
-        // fixed order, then one fixed-point atomic add per (row, column)
+        // wave w finishes columns TN/WM w .. TN/WM (w + 1) - 1: the WM waves' partials added
+        // in a fixed order, then one fixed-point atomic add per (row, column)
+        constexpr int JW = TN / WM;
         const int mv = PACK ? (m < 8 ? (int)m : 8) : (m < CW ? (int)m : CW);
 #pragma unroll 1
-        for (int u = 0; u < 32 * CW / 64; ++u) {
+        for (int u = 0; u < JW * CW / 64; ++u) {
           const int e = u * 64 + lane;
           const int jj = e / CW, c = e % CW;
-          const int j = 32 * w + jj;
+          const int j = JW * w + jj;
           if (c < mv) {
             float s = 0.0f;
 #pragma unroll
-            for (int ww = 0; ww < 4; ++ww) {
+            for (int ww = 0; ww < WM; ++ww) {
               const float* rr = red_at(ww) + j * CW;
               s += PACK ? rr[c] + rr[c + 8] : rr[c];
             }
@@ -1120,8 +1136,8 @@ constexpr int bd_njb(int nct) { return nct >= 4 ? 4 : BD_NJB; }
 // grouped launch: BD_GROUP column splits, row blocks padded to a multiple of 8 BD_GROUP
 constexpr int BD_GROUP = 8;
 
-template <int NCT, int EPI, bool PACK, bool SYM>
-__global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f16pv_bigd_kernel(
+template <int NCT, int EPI, bool PACK, bool SYM, int WM = 4>
+__global__ __launch_bounds__(64 * WM, (NCT >= 4 || WM == 8) ? 1 : 2) void matmat_f16pv_bigd_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
@@ -1129,17 +1145,20 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f16pv_bigd_kerne
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
     int64_t part_stride, int tiles_per_split, int grouped, int64_t nunits, SymOut so) {
   constexpr int NJB = bd_njb(NCT);
-  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, NJB>()];
+  // row units per XCD group: the blocks one XCD holds at once (two per CU for 128-row blocks,
+  // one for 256-row blocks) over BD_GROUP splits
+  constexpr int GU = WM == 8 ? BD_GROUP / 2 : BD_GROUP;
+  __shared__ __attribute__((aligned(16))) _Float16 smem[bigd_smem_halves<NCT, NJB, WM>()];
   int64_t rb = blockIdx.x, sp = blockIdx.y;
   if (grouped) {
     // 1-D grid of (row unit, split) pairs with BD_GROUP splits, ordered so that the blocks
     // one XCD runs together (workgroups go round-robin to the 8 XCDs) form groups of
-    // BD_GROUP row units x BD_GROUP splits: each group shares its row operand chunks and its
+    // GU row units x BD_GROUP splits: each group shares its row operand chunks and its
     // column tiles in that XCD's L2 instead of streaming them per block. A row unit is a
-    // 128-row block, or in symmetric mode a pair of them.
+    // 128-row block, or in symmetric mode a pair of row blocks.
     const int64_t b = blockIdx.x, x = b % 8, t = b / 8;
-    const int64_t gid = (t / (BD_GROUP * BD_GROUP)) * 8 + x, u = t % (BD_GROUP * BD_GROUP);
-    rb = gid * BD_GROUP + u / BD_GROUP;
+    const int64_t gid = (t / (GU * BD_GROUP)) * 8 + x, u = t % (GU * BD_GROUP);
+    rb = gid * GU + u / BD_GROUP;
     sp = u % BD_GROUP;
     if (rb >= nunits) return;  // padding block
   }
@@ -1148,12 +1167,12 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f16pv_bigd_kerne
   double pmul;
   epi_params<EPI>(qinv2_ptr, deg, pmul);
   if (qinv2 == 1.0f)
-    f16pv_bigd_body<NCT, true, EPI, NJB, PACK, SYM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
+    f16pv_bigd_body<NCT, true, EPI, NJB, PACK, SYM, WM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
                                                    ldvt, n1, n2, m, KP, qinv2, dscale, deg, pmul,
                                                    part, ldp, part_stride, tiles_per_split, rb,
                                                    sp, so);
   else
-    f16pv_bigd_body<NCT, false, EPI, NJB, PACK, SYM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
+    f16pv_bigd_body<NCT, false, EPI, NJB, PACK, SYM, WM>(smem, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale,
                                                     ldvt, n1, n2, m, KP, qinv2, dscale, deg, pmul,
                                                     part, ldp, part_stride, tiles_per_split, rb,
                                                     sp, so);
@@ -1235,34 +1254,44 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   if (A.Kp > 128) {
     const int kp = (int)A.Kp;
     const int tps = (int)ceil_div(ceil_div(B.n, 16 * bd_njb(nct)), nsplit);
-    const int64_t nunits = symm ? (nrb + 1) / 2 : nrb;
-    const int grouped = nsplit == BD_GROUP && nunits >= 8 * BD_GROUP ? 1 : 0;
-    grid = grouped ? dim3((unsigned)(round_up(nunits, 8 * BD_GROUP) * BD_GROUP), 1)
+    // symmetric products on 256-row blocks (8 waves) when the rows are padded for them
+    const bool rows256 = symm && V.rows_pad >= round_up(A.n, 2 * BD_BM);
+    if (rows256) so.nrb = ceil_div(A.n, 2 * BD_BM);
+    const int64_t nunits = symm ? (so.nrb + 1) / 2 : nrb;
+    const int gu = rows256 ? BD_GROUP / 2 : BD_GROUP;
+    const int grouped = nsplit == BD_GROUP && nunits >= 8 * gu ? 1 : 0;
+    grid = grouped ? dim3((unsigned)(round_up(nunits, 8 * gu) * BD_GROUP), 1)
                    : dim3((unsigned)nunits, nsplit);
-#define KRR_BD(NCT_, D_, P_, S_)                                                                 \
-  matmat_f16pv_bigd_kernel<NCT_, D_, P_, S_><<<grid, 256, 0, st>>>(                              \
+#define KRR_BD(NCT_, D_, P_, S_, WM_)                                                            \
+  matmat_f16pv_bigd_kernel<NCT_, D_, P_, S_, WM_><<<grid, 64 * WM_, 0, st>>>(                    \
       A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, kp, A.qinv2, dscale, \
       part, ldp, part_stride, tps, grouped, nunits, so)
-#define KRR_BD_EPI(NCT_, P_, S_)                          \
-  if (epi == KV_DSIGMA) KRR_BD(NCT_, KV_DSIGMA, P_, S_);  \
-  else if (epi == KV_POLY) KRR_BD(NCT_, KV_POLY, P_, S_); \
-  else KRR_BD(NCT_, KV_GAUSS, P_, S_);
-    if (symm) {
+#define KRR_BD_EPI(NCT_, P_, S_, WM_)                          \
+  if (epi == KV_DSIGMA) KRR_BD(NCT_, KV_DSIGMA, P_, S_, WM_);  \
+  else if (epi == KV_POLY) KRR_BD(NCT_, KV_POLY, P_, S_, WM_); \
+  else KRR_BD(NCT_, KV_GAUSS, P_, S_, WM_);
+    if (rows256) {
       if (V.packed) {
-        KRR_BD_EPI(1, true, true)
+        KRR_BD_EPI(1, true, true, 8)
       } else {
-        KRR_BD_EPI(1, false, true)
+        KRR_BD_EPI(1, false, true, 8)
+      }
+    } else if (symm) {
+      if (V.packed) {
+        KRR_BD_EPI(1, true, true, 4)
+      } else {
+        KRR_BD_EPI(1, false, true, 4)
       }
     } else if (nct == 1 && V.packed) {
-      KRR_BD_EPI(1, true, false)
+      KRR_BD_EPI(1, true, false, 4)
     } else if (nct == 1) {
-      KRR_BD_EPI(1, false, false)
+      KRR_BD_EPI(1, false, false, 4)
     } else if (nct == 2) {
-      KRR_BD_EPI(2, false, false)
+      KRR_BD_EPI(2, false, false, 4)
     } else if (nct == 4) {
-      KRR_BD_EPI(4, false, false)
+      KRR_BD_EPI(4, false, false, 4)
     } else {
-      KRR_BD_EPI(10, false, false)
+      KRR_BD_EPI(10, false, false, 4)
     }
 #undef KRR_BD_EPI
 #undef KRR_BD
