@@ -103,6 +103,10 @@ struct MatmatCtx {
   // square large-d products: column-side accumulator of the symmetric kernel
   unsigned long long* fx = nullptr;  // [rp1][32]
   unsigned* fxflag = nullptr;        // [rp1]
+  // square large-d FP64 products: two-word column-side accumulator of the symmetric kernel
+  unsigned long long *fh = nullptr, *fl = nullptr;  // [rp1][16]
+  unsigned* fflag = nullptr;                         // [rp1]
+  unsigned long long* fvmax = nullptr;  // [16]
   bool square = false;
   double c2 = 0;            // log2(e) / (2 sigma^2)
   double sigma = 0;
@@ -134,6 +138,12 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
     } else {
       c.XAf = b.take<float>(c.rp1 * c.dp);
       if (!square) c.XBf = b.take<float>(c.rp2 * c.dp);
+      if (sym_buf) {
+        c.fh = b.take<unsigned long long>(c.rp1 * 16);
+        c.fl = b.take<unsigned long long>(c.rp1 * 16);
+        c.fflag = b.take<unsigned>(c.rp1);
+        c.fvmax = b.take<unsigned long long>(16);
+      }
     }
     c.nuA = b.take<double>(c.rp1);
     if (square) { c.XBf = c.XAf; c.SB = c.SA; c.scB = c.scA; c.nuB = c.nuA; }
@@ -242,8 +252,9 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
     F64Points A{c.nuA, c.n1, c.dp, c.XAf, c.SA, c.scA, c.d};
     F64Points B{c.nuB, c.n2, c.dp, c.XBf, c.SB, c.scB, c.d};
     const int epi = c.poly ? KV_POLY : deriv ? KV_DSIGMA : KV_GAUSS;
+    const F64SymBuf sb{c.fh, c.fl, c.fflag, c.fvmax};
     return matmat_f64(A, B, V64, ldv, c.m, epi, 1.0 / (2.0 * c.sigma * c.sigma), 1.0 / sig3, c.pk,
-                      c.part, c.m, c.part_stride, c.nsplit, st);
+                      c.part, c.m, c.part_stride, c.nsplit, st, c.fh && c.square ? &sb : nullptr);
   }
   const float dscale = (float)(1.0 / (c.c2 * sig3));  // dk/dsigma = k * (-log2 k) / (c2 sigma^3)
   if (c.prec == KRR_PREC_F16X3) {

@@ -132,10 +132,19 @@ template <typename T>
 hipError_t matmat_mixed(const MixedPoints<T>& A, const MixedPoints<T>& B, const float* Vf,
                         int64_t ldvf, int64_t m, bool deriv, float dscale, double* part,
                         int64_t ldp, int64_t part_stride, int nsplit, hipStream_t st);
+// Column-side accumulator of the symmetric FP64 large-d product (two-word 64-bit fixed
+// point, rows_pad x 16 each, per-row non-finite flags, and 16 per-column maxima of |V|).
+struct F64SymBuf {
+  unsigned long long *fh, *fl;
+  unsigned* flag;
+  unsigned long long* vmax;
+};
+// FP64 kernel product. With sym (square products: A and B the same points), a large-d
+// Gaussian product of at most 16 columns forms each off-diagonal block pair once.
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, int epi, double c, double dscale, const PolyF64& pk,
                       double* part, int64_t ldp, int64_t part_stride, int nsplit,
-                      hipStream_t st);
+                      hipStream_t st, const F64SymBuf* sym = nullptr);
 template <typename VS>
 hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, int64_t n,
                            int64_t m, int64_t ldp, double shift, const VS* Vs, int64_t ldvs,

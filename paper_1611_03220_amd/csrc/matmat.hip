@@ -1422,32 +1422,119 @@ __device__ inline double exp_neg_tab(double x, const double* __restrict__ T) {
 // tile's readers have passed a barrier), so it needs one buffer.
 constexpr int F64B_TJ = 64;
 constexpr int F64B_LK = 33;  // padded LDS row of a chunk (floats)
-template <int NCT>
+// Column side of the symmetric FP64 product (SYM, K(X, X) V with one 16-column tile): each
+// off-diagonal (128-row block, 64-column tile) pair gives P^T V_I for the rows of the tile,
+// P transposed per 16 x 16 block by four FP64 MFMAs against 0/1 selection operands (exact)
+// and multiplied by V_I^T on FP64 MFMA, each wave's sums over its 32 rows added to a
+// two-word fixed-point accumulator: h = rint(v 2^F1) (exact remainder since |h| < 2^52),
+// l = rint((v - h 2^-F1) 2^F2). F1 and F2 come from column c's largest finite |V|
+// (f64sym_scales, also used by the fold) so that neither word's total can overflow; the
+// represented sum is accurate to far below an FP64 ulp of the largest contribution, and
+// integer adds make it independent of the order of the atomics.
+struct F64SymOut {
+  unsigned long long *fh = nullptr, *fl = nullptr;  // [rows_pad][16]
+  unsigned* flag = nullptr;                          // [rows_pad]
+  const unsigned long long* vmax = nullptr;          // [16] bits of max finite |V[:, c]|
+  double pmax = 2.0;                                 // bound on |P|
+  int nsplit = 1;
+  int64_t nrb = 0;                                   // 128-row blocks
+};
+__device__ __forceinline__ void f64sym_scales(const F64SymOut& so, int cc, int& F1, int& F2) {
+  const double vmax = fmax(__longlong_as_double((long long)so.vmax[cc]), 0x1.0p-900);
+  const int lk = 64 - __builtin_clzll((unsigned long long)(4 * so.nrb));  // > log2 K
+  int eb;
+  frexp(32.0 * so.pmax * vmax, &eb);  // 32 |P| |V| < 2^eb: one wave's contribution
+  F1 = (62 - lk < 52 ? 62 - lk : 52) - eb - 1;
+  F2 = F1 + (61 - lk < 50 ? 61 - lk : 50);
+}
+// bits of max finite |V[i][c]| per column c < m (m <= 16), into vmax[16] (cleared before):
+// non-negative doubles order like their bit patterns
+__global__ __launch_bounds__(256) void f64_colmax_kernel(const double* __restrict__ V,
+                                                         int64_t n, int64_t m, int64_t ldv,
+                                                         unsigned long long* __restrict__ vmax) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int c = tid & 15;  // 16 columns x 16 row lanes per block
+  double mx = 0.0;
+  if (c < m)
+    for (int64_t i = (int64_t)blockIdx.x * 16 + (tid >> 4); i < n; i += (int64_t)gridDim.x * 16) {
+      const double a = fabs(V[i * ldv + c]);
+      if (a <= 1.7976931348623157e308) mx = fmax(mx, a);  // finite only
+    }
+  red[tid] = mx;
+  __syncthreads();
+  for (int o = 128; o >= 16; o >>= 1) {
+    if (tid < o) red[tid] = fmax(red[tid], red[tid + o]);
+    __syncthreads();
+  }
+  if (tid < 16 && tid < m) atomicMax(vmax + tid, (unsigned long long)__double_as_longlong(red[tid]));
+}
+template <int NCT, bool SYM = false>
 __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
     const float* __restrict__ Xa, const double* __restrict__ nua, const float* __restrict__ Xb,
     const double* __restrict__ nub, const double* __restrict__ V, int64_t ldv, int64_t n1,
     int64_t n2, int64_t m, int c0, int dp, double c, int epi, double dscale, PolyF64 pk,
-    double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split) {
+    double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split,
+    F64SymOut so) {
   constexpr int VC = 16 * NCT;
   constexpr int LV = VC + 1;
+  static_assert(!SYM || NCT == 1, "symmetric FP64 product: one 16-column tile");
   __shared__ float sR[2][128 * F64B_LK];
   __shared__ float sC[2][F64B_TJ * F64B_LK];
   __shared__ double sV[F64B_TJ * LV];
   __shared__ double sN[F64B_TJ];
   __shared__ double sE[EXP_TAB];
+  __shared__ double sVI[SYM ? 4 * 32 * 16 : 1];  // V_I per wave: [32 rows][16 columns]
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int64_t blk_i0 = (int64_t)blockIdx.x * 128;
   const int64_t ntiles = ceil_div(n2, F64B_TJ);
-  const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
-  const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
   const int KC = dp / 32;
-  const int64_t nsteps = (t_end - t_begin) * KC;
+  // work list: item t < nA is tile jA + t of row block rbA, the rest tile jB + (t - nA) of
+  // rbB (symmetric mode: the pair (p, nrb - 1 - p), row block I starting at tile 2 I)
+  int64_t rbA = blockIdx.x, rbB = blockIdx.x, jA = 0, jB = 0;
+  int nA = 0, count = 0;
+  if (SYM) {
+    rbB = so.nrb - 1 - rbA;
+    const int64_t len1 = ntiles - 2 * rbA;
+    const int64_t len2 = rbB > rbA ? ntiles - 2 * rbB : 0;
+    const int64_t L = len1 + len2;
+    const int64_t b0 = (int64_t)blockIdx.y * L / so.nsplit;
+    const int64_t b1 = ((int64_t)blockIdx.y + 1) * L / so.nsplit;
+    count = (int)(b1 - b0);
+    const int64_t na = len1 - b0;
+    nA = na < 0 ? 0 : na > count ? count : (int)na;
+    jA = 2 * rbA + b0;
+    jB = 2 * rbB + (b0 + nA - len1);
+  } else {
+    const int64_t t_begin = (int64_t)blockIdx.y * tiles_per_split;
+    const int64_t t_end = t_begin + tiles_per_split < ntiles ? t_begin + tiles_per_split : ntiles;
+    count = t_end > t_begin ? (int)(t_end - t_begin) : 0;
+    nA = count;
+    jA = t_begin;
+  }
+  auto item_rb = [&](int t) __attribute__((always_inline)) { return t < nA ? rbA : rbB; };
+  auto item_j = [&](int t) __attribute__((always_inline)) { return t < nA ? jA + t : jB + (t - nA); };
+  const int64_t nsteps = (int64_t)count * KC;
   for (int e = tid; e < EXP_TAB; e += 256) sE[e] = exp2(-(double)e / EXP_TAB);
 
   double nui[2];
+  // V_I for the column-side MFMA, in the wave's own LDS rows: sVI[w][x][c] = V[I 128 + 32 w
+  // + x][c0 + c] (zero past n or m); only this wave writes and reads its rows
+  auto load_rows = [&](int64_t I) __attribute__((always_inline)) {
 #pragma unroll
-  for (int ib = 0; ib < 2; ++ib) nui[ib] = nua[blk_i0 + 32 * w + 16 * ib + li];
+    for (int ib = 0; ib < 2; ++ib) nui[ib] = nua[I * 128 + 32 * w + 16 * ib + li];
+    if (SYM) {
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int x = 16 * ib + lg + 4 * r;
+          const int64_t i = I * 128 + 32 * w + x;
+          sVI[(32 * w + x) * 16 + li] = (i < n2 && c0 + li < m) ? V[i * ldv + c0 + li] : 0.0;
+        }
+    }
+  };
+  load_rows(item_rb(0));
   d4v g[4][2], acc[2][NCT];
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
@@ -1467,7 +1554,9 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
   double rv[UPS];
   double rn = 0.0;
   auto gload = [&](int64_t q) __attribute__((always_inline)) {
-    const int64_t t = t_begin + q / KC;
+    const int tq = (int)(q / KC);
+    const int64_t t = item_j(tq);
+    const int64_t blk_i0 = item_rb(tq) * 128;
     const int kc = (int)(q % KC);
     const int64_t ko = (int64_t)kc * 32 + lc4;
 #pragma unroll
@@ -1507,6 +1596,23 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
     }
     if (kc == 0 && tid < F64B_TJ) sN[tid] = rn;
   };
+  // writes of the row side of row block I: lane holds OUT[I 128 + 32 w + 16 ib + lg + 4 r]
+  double* pout = part + (int64_t)blockIdx.y * part_stride;
+  auto write_rows = [&](int64_t I, bool zero) __attribute__((always_inline)) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int64_t cc = c0 + 16 * ct + li;
+      if (cc < m) {
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = I * 128 + 32 * w + 16 * ib + lg + 4 * r;
+            if (i < n1) pout[i * ldp + cc] = zero ? 0.0 : acc[ib][ct][r];
+          }
+      }
+    }
+  };
 
   if (nsteps > 0) {
     gload(0);
@@ -1539,10 +1645,18 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
           g[jb][ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[jb], b[ib], g[jb][ib], 0, 0, 0);
     }
     if (kc == KC - 1) {
+      const int tq = (int)(q / KC);
+      const int64_t I = item_rb(tq), J = item_j(tq);
+      const bool col = SYM && J >= 2 * (I + 1);  // right of I's diagonal block (uniform)
 #pragma unroll
-      for (int jb = 0; jb < 4; ++jb)
+      for (int jb = 0; jb < 4; ++jb) {
+        // column side: D[c][j] = sum over the wave's 32 rows i of V[i][c] P[i][j]; lane holds
+        // D[c = lg + 4 r][j = 16 jb + li]
+        d4v dc = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib)
+        for (int ib = 0; ib < 2; ++ib) {
+          // transposed P of the 16 x 16 block (jb, ib): (i = 16 ib + lg + 4 r, j = li)
+          d4v tp = d4v{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int jj = 16 * jb + lg + 4 * r;
@@ -1558,25 +1672,73 @@ __global__ __launch_bounds__(256, NCT >= 4 ? 1 : 2) void matmat_f64big_kernel(
             for (int ct = 0; ct < NCT; ++ct)
               acc[ib][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[jj * LV + 16 * ct + li],
                                                                  acc[ib][ct], 0, 0, 0);
+            // selection E_r[k][c'] = (c' == k + 4 r): lane (li, lg) holds (li == lg + 4 r)
+            if (col)
+              tp = __builtin_amdgcn_mfma_f64_16x16x4f64(p, li == lg + 4 * r ? 1.0 : 0.0, tp, 0, 0, 0);
           }
+          if (col) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              dc = __builtin_amdgcn_mfma_f64_16x16x4f64(sVI[(32 * w + 16 * ib + lg + 4 * r) * 16 + li],
+                                                        tp[r], dc, 0, 0, 0);
+          }
+        }
+        if (col) {
+          const int64_t row = J * F64B_TJ + 16 * jb + li;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cc = lg + 4 * r;
+            if (c0 + cc < m) {
+              const double v = dc[r];
+              if (__builtin_isfinite(v)) {
+                int F1, F2;
+                f64sym_scales(so, cc, F1, F2);
+                const double hd = rint(ldexp(v, F1));
+                const double lo = rint(ldexp(v - ldexp(hd, -F1), F2));
+                atomicAdd(so.fh + row * 16 + cc, (unsigned long long)(long long)hd);
+                atomicAdd(so.fl + row * 16 + cc, (unsigned long long)(long long)lo);
+              } else {
+                atomicOr(so.flag + row, 1u << cc);
+              }
+            }
+          }
+        }
+      }
+      if (SYM && tq == nA - 1 && nA < count) {
+        // the first row block of the pair is done: write it and start on the second
+        write_rows(rbA, false);
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) acc[ib][0] = d4v{0.0, 0.0, 0.0, 0.0};
+        load_rows(rbB);
+      }
     }
     if (q + 1 < nsteps) lstore(q + 1);
     __syncthreads();
   }
-  double* pout = part + (int64_t)blockIdx.y * part_stride;
-#pragma unroll
-  for (int ct = 0; ct < NCT; ++ct) {
-    const int64_t cc = c0 + 16 * ct + li;
-    if (cc < m) {
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t i = blk_i0 + 32 * w + 16 * ib + lg + 4 * r;
-          if (i < n1) pout[i * ldp + cc] = acc[ib][ct][r];
-        }
-    }
+  if (SYM) {
+    const bool hasA = nA > 0, hasB = nA < count;
+    write_rows(hasB ? rbB : rbA, false);
+    if (!hasA && hasB) write_rows(rbA, true);
+    if (!hasB && rbB != rbA) write_rows(rbB, true);
+  } else {
+    write_rows(rbA, false);
   }
+}
+
+// Adds the column side of a symmetric FP64 product to split 0 of the partial sums:
+// part[i][c] += fh 2^-F1 + fl 2^-F2 (NaN where a contribution was not finite).
+__global__ __launch_bounds__(256) void f64sym_fold_kernel(F64SymOut so, int64_t n, int64_t mc,
+                                                          double* __restrict__ part,
+                                                          int64_t ldp) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * mc) return;
+  const int64_t i = e / mc, cc = e % mc;
+  int F1, F2;
+  f64sym_scales(so, (int)cc, F1, F2);
+  double v = ldexp((double)(long long)so.fh[i * 16 + cc], -F1) +
+             ldexp((double)(long long)so.fl[i * 16 + cc], -F2);
+  if ((so.flag[i] >> cc) & 1u) v = __builtin_nan("");
+  part[i * ldp + cc] += v;
 }
 
 // FP64 kernel product with the inner products on int8 MFMA (16x16x64, exact int32 sums).
@@ -1782,7 +1944,7 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
 hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, int64_t ldv,
                       int64_t m, int epi, double c, double dscale, const PolyF64& pk,
                       double* part, int64_t ldp, int64_t part_stride, int nsplit,
-                      hipStream_t st) {
+                      hipStream_t st, const F64SymBuf* sym) {
   if (A.dp != B.dp) return hipErrorInvalidValue;
   if (epi != KV_GAUSS && epi != KV_DSIGMA && epi != KV_POLY) return hipErrorInvalidValue;
   dim3 grid(ceil_div(A.n, 64), nsplit);
@@ -1819,12 +1981,40 @@ hipError_t matmat_f64(const F64Points& A, const F64Points& B, const double* V, i
   if (!A.Xf || !B.Xf || A.dp % 32) return hipErrorInvalidValue;
   const int tpsb = (int)ceil_div(ceil_div(B.n, F64B_TJ), nsplit);
   dim3 gridb(ceil_div(A.n, 128), nsplit);
+  F64SymOut so;
+  if (sym && A.n == B.n && m <= 16 && epi != KV_POLY) {
+    // symmetric product (one 16-column pass): column side in two-word fixed point
+    const int64_t rows_pad = round_up(A.n, 128);
+    so.fh = sym->fh;
+    so.fl = sym->fl;
+    so.flag = sym->flag;
+    so.vmax = sym->vmax;
+    so.pmax = epi == KV_DSIGMA ? 1.01 * std::fabs(dscale) / (c * 2.718281828459045) + 1e-300 : 2.0;
+    so.nsplit = nsplit;
+    so.nrb = ceil_div(A.n, 128);
+    hipError_t e = fill_f64(reinterpret_cast<double*>(so.fh), rows_pad * 16, 0.0, st);
+    if (e == hipSuccess) e = fill_f64(reinterpret_cast<double*>(so.fl), rows_pad * 16, 0.0, st);
+    if (e == hipSuccess) e = fill_i32(reinterpret_cast<int*>(so.flag), rows_pad, 0, st);
+    if (e == hipSuccess) e = fill_f64(reinterpret_cast<double*>(sym->vmax), 16, 0.0, st);
+    if (e != hipSuccess) return e;
+    f64_colmax_kernel<<<(unsigned)std::min<int64_t>(1024, ceil_div(A.n, 16)), 256, 0, st>>>(
+        V, A.n, m, ldv, sym->vmax);
+    KRR_LAUNCH_CHECK();
+    const dim3 gs((unsigned)((so.nrb + 1) / 2), nsplit);
+    matmat_f64big_kernel<1, true><<<gs, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m,
+                                                      0, (int)A.dp, c, epi, dscale, pk, part, ldp,
+                                                      part_stride, tpsb, so);
+    KRR_LAUNCH_CHECK();
+    f64sym_fold_kernel<<<(unsigned)ceil_div(A.n * m, 256), 256, 0, st>>>(so, A.n, m, part, ldp);
+    KRR_LAUNCH_CHECK();
+    return hipSuccess;
+  }
   // passes of up to 160 right-hand sides: the inner products dominate a pass's work
   for (int64_t c0 = 0; c0 < m; c0 += 160) {
 #define KRR_F64B(NCT_)                                                                        \
   matmat_f64big_kernel<NCT_><<<gridb, 256, 0, st>>>(A.Xf, A.nu, B.Xf, B.nu, V, ldv, A.n, B.n, m, \
                                                     (int)c0, (int)A.dp, c, epi, dscale, pk,    \
-                                                    part, ldp, part_stride, tpsb)
+                                                    part, ldp, part_stride, tpsb, so)
     if (m - c0 > 64) KRR_F64B(10);
     else if (m - c0 > 32) KRR_F64B(4);
     else if (m - c0 > 16) KRR_F64B(2);

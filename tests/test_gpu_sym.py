@@ -174,3 +174,55 @@ def test_same_points_small_d_sampled(dev):
     ref = O.kernel_matmat(X, X, sigma, V, shift=0.25, rows=rows)
     bound = _bound(X, sigma, V, False, d, rows=rows) + 1e-15 * 0.25 * np.abs(V[rows])
     assert np.all(np.abs(got[rows] - ref) <= bound), np.max(np.abs(got[rows] - ref) / bound)
+
+
+@pytest.mark.parametrize("n,d,m", [(677, 150, 7), (300, 784, 10), (1000, 440, 16), (129, 160, 1),
+                                   (1, 200, 2), (517, 300, 17)])
+def test_sym_fp64(dev, n, d, m):
+    """The symmetric FP64 large-d product (one pass of at most 16 columns; m = 17 takes the
+    general kernel): 1e-12 relative to (|K| |V|)_i like every FP64 product, K and dK/dsigma,
+    against the oracle; bit-identical on a repeat (two-word fixed-point column side). For
+    dK/dsigma the diagonal adds the rounding of a coincident pair's distance,
+    D = nu_i + nu_i - 2 <x_i, x_i> ~ 1e-15 nu_i instead of 0, times dscale |V_i| (the oracle's
+    difference form gives exactly 0 there)."""
+    rng = np.random.default_rng(1400 + n + d + m)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    V = rng.standard_normal((n, m)) * np.exp(rng.standard_normal((n, 1)))
+    sigma = 0.8 * math.sqrt(d)
+    Xg, Vg = _t(X, dev), _t(V, dev)
+    for deriv in (False, True):
+        got = krr.kernel_matmat(Xg, Xg, sigma, Vg, deriv=deriv, prec="fp64")
+        again = krr.kernel_matmat(Xg, Xg, sigma, Vg, deriv=deriv, prec="fp64")
+        assert torch.equal(got, again)
+        got = got.cpu().numpy()
+        ref = O.kernel_matmat(X, X, sigma, V, deriv=deriv)
+        K = (O.gaussian_kernel_dsigma if deriv else O.gaussian_kernel)(X, X, sigma)
+        bound = 1e-12 * (np.abs(K) @ np.abs(V))
+        if deriv:
+            nu = (X.astype(np.float64) ** 2).sum(1)[:, None]
+            bound = bound + 1e-14 * nu / sigma ** 3 * np.abs(V)
+        assert np.all(np.abs(got - ref) <= bound), (deriv, np.max(np.abs(got - ref) / bound))
+
+
+def test_sym_fp64_nonfinite_and_sampled_large(dev):
+    """FP64 symmetric product: a NaN in V reaches its whole column through both triangles; and
+    at n = 16384 + 300 (66 block pairs, 8 splits) 24 sampled rows meet the 1e-12 bound."""
+    rng = np.random.default_rng(1450)
+    n, d, m = 700, 180, 3
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    V = rng.standard_normal((n, m))
+    V[9, 2] = np.nan
+    Xg = _t(X, dev)
+    got = krr.kernel_matmat(Xg, Xg, 0.9 * math.sqrt(d), _t(V, dev), prec="fp64").cpu().numpy()
+    assert np.isnan(got[:, 2]).all() and np.isfinite(got[:, :2]).all()
+    n, d, m = 16384 + 300, 200, 10
+    X = rng.random((n, d)).astype(np.float32)
+    V = rng.standard_normal((n, m))
+    sigma = 0.5 * math.sqrt(d)
+    Xg = _t(X, dev)
+    got = krr.kernel_matmat(Xg, Xg, sigma, _t(V, dev), prec="fp64").cpu().numpy()
+    rows = np.sort(rng.choice(n, 24, replace=False))
+    rows[0], rows[-1] = 0, n - 1
+    ref = O.kernel_matmat(X, X, sigma, V, rows=rows)
+    bound = 1e-12 * (O.gaussian_kernel(X[rows], X, sigma) @ np.abs(V))
+    assert np.all(np.abs(got[rows] - ref) <= bound), np.max(np.abs(got[rows] - ref) / bound)
