@@ -46,9 +46,9 @@ PEAK_EXP = CUS * 32 * CLOCK     # FP32 exp2 per second: 32 lanes per clock per C
 
 METRIC = "kernel matmat TFLOP/s + time-to-1e-6 residual PCG solve, mixed vs FP64 path"
 BIGD_KERNEL = ("matmat_f16pv_bigd_kernel, symmetric (large d: FP16 hi/lo split MFMA distances "
-               "with both operands through LDS, each off-diagonal 128 x 128 block pair once, "
-               "FP32 exp2, split MFMA accumulation of K V for both triangles, FP64 partials and "
-               "fixed-point column sums)")
+               "with both operands through LDS, 256-row blocks against 128-column tiles right "
+               "of the diagonal only, FP32 exp2, split MFMA accumulation of K V for both "
+               "triangles, FP64 partials and fixed-point column sums)")
 SMALLD_KERNEL = ("matmat_f16pv_kernel (d + 2 <= 128: register-resident row operand, FP16 hi/lo "
                  "split MFMA distances, FP32 exp2, split MFMA accumulation of K V)")
 LEGS = ["mixture", "pixels", "plain", "ablation", "batched", "differentiation", "polynomial",
@@ -124,40 +124,29 @@ def tol_met(rep, tol):
     return rep.status == krr.OK and bool(vals) and all(v <= tol for v in vals)
 
 
-def kernel_shapes(d, m):
-    """(Kp, executed MFMA flops per pair) of the general F16X3 product for d and m."""
-    kp = int(math.ceil((d + 2) / 32.0) * 32)         # augmented, padded feature width
-    W = 64 if kp > 128 else 32                        # right-hand-side columns per pass
-    per_pair = 0
-    for c0 in range(0, m, W):
-        mc = min(W, m - c0)
-        mp = 64 if mc > 32 else int(math.ceil(mc / 16.0) * 16)
-        # three split products for the distances per pass; P V takes three split products,
-        # or two when mc <= 8 (the hi and lo parts of V share one 16-column operand)
-        per_pair += 2 * (3 * kp + (2 if mc <= 8 else 3) * mp)
-    return kp, per_pair
-
-
 def square_product_work(n, d, m):
     """(executed MFMA flops, kernel entries evaluated) per launch of the square product
-    K(X, X) V as the solve runs it: large-d passes of up to 16 columns form each pair of
-    128-row blocks once (the symmetric kernel: distances and exp for both triangles, P V for
-    the row side, a 0/1-selection transpose (two 16x16x16 MFMAs per 16 x 16 block) and P^T V
-    for the column side of off-diagonal pairs); other passes form every pair."""
+    K(X, X) V as the solve runs it: large-d passes of up to 16 columns run the symmetric
+    kernel on 256-row blocks against 128-column tiles, forming tile J of row block I only for
+    J >= 2 I (the 256 x 256 diagonal block in full, row side only; distances and exp once for
+    both triangles, P V for the row side, and for tiles right of the diagonal block a 0/1
+    selection transpose (two 16x16x16 MFMAs per 16 x 16 block) and P^T V for the column
+    side); other passes form every pair."""
     kp = int(math.ceil((d + 2) / 32.0) * 32)
-    W = 64 if kp > 128 else 32
-    nb = -(-n // 128)
+    W = 160 if kp > 128 else 32
+    nb = -(-n // 256)
+    nt = -(-n // 128)
     full = float(n) * n
-    unique = nb * (nb + 1) / 2.0 * 128 * 128
-    offdiag = nb * (nb - 1) / 2.0 * 128 * 128
+    formed = sum(256.0 * 128 * (nt - 2 * i) for i in range(nb))
+    offdiag = sum(256.0 * 128 * max(nt - 2 * i - 2, 0) for i in range(nb))
     flops = entries = 0.0
     for c0 in range(0, m, W):
         mc = min(W, m - c0)
-        mp = 64 if mc > 32 else int(math.ceil(mc / 16.0) * 16)
+        mp = 160 if mc > 64 else 64 if mc > 32 else int(math.ceil(mc / 16.0) * 16)
         f = 2 if mc <= 8 else 3
         if kp > 128 and mc <= 16:
-            flops += unique * 2 * (3 * kp + f * mp) + offdiag * (64 + 2 * f * mp)
-            entries += unique
+            flops += formed * 2 * (3 * kp + f * mp) + offdiag * (64 + 2 * f * mp)
+            entries += formed
         else:
             flops += full * 2 * (3 * kp + f * mp)
             entries += full
