@@ -336,11 +336,6 @@ void layout_project(Bump& b, ProjLayout& L, int64_t n, int64_t s2, int64_t s3) {
 // ---------------------------------------------------------------- precond factor
 krr_status gram_cholesky(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
                          struct FactorLayout& L, int64_t* info, const char* fn, hipStream_t st);
-int64_t pow2_pad(int64_t s) {
-  int64_t p = 64;
-  while (p < s) p *= 2;
-  return p;
-}
 int gram_nsplit(int64_t s, int64_t n) {
   const int64_t t = ceil_div(s, GEMM_TILE);
   const int64_t tiles = t * (t + 1) / 2;
@@ -362,7 +357,7 @@ void layout_factor(Bump& b, FactorLayout& L, int64_t n, int64_t s) {
   L.sk = round_up(s, 32);
   L.np = round_up(n, GEMM_TILE);
   L.sp64 = round_up(s, GEMM_TILE);
-  L.s_pad = pow2_pad(s);
+  L.s_pad = round_up(s, 64);  // 64 x 64 factor blocks
   L.nsplit = gram_nsplit(s, n);
   L.stats = b.take<float>(64);
   L.info = b.take<int>(64);

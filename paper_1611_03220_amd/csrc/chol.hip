@@ -6,8 +6,8 @@
 // inverses of all diagonal blocks are then formed at once, one workgroup per block, and
 // the full inverse C^{-1} is assembled from them by recursive doubling,
 // inv([A 0; B D]) = [A^-1 0; -D^-1 B A^-1  D^-1], with batched FP64 GEMMs. The matrix
-// order is padded to 64 * 2^k with an identity block, which leaves the leading factor
-// and its inverse unchanged.
+// order is padded to a multiple of 64 with an identity block, which leaves the leading
+// factor and its inverse unchanged; the last block of a doubling level may be short.
 #include "kernels.hpp"
 
 namespace krr {
@@ -142,20 +142,37 @@ hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, h
 }
 
 // Off-diagonal blocks of C^{-1} by recursive doubling; Cinv holds the inverted diagonal
-// 64 x 64 blocks on entry. tmp needs s_pad * s_pad / 2 doubles. s_pad = 64 * 2^k.
+// 64 x 64 blocks on entry, s_pad is a multiple of 64, tmp needs s_pad * s_pad / 2 doubles.
+// Level b joins the aligned blocks [2pb, 2pb + b) and [2pb + b, min(2pb + 2b, s_pad)), both
+// already inverted by the levels before it (the second may be shorter than b, or absent at
+// the end, where the first block carries over unchanged). The full pairs of a level go
+// through one batched GEMM pair; a short second block gets a GEMM pair of its own.
 hipError_t tri_inverse_doubling(const double* C, int64_t s_pad, double* Cinv, double* tmp,
                                 hipStream_t st) {
+  if (s_pad % NB) return hipErrorInvalidValue;
   for (int64_t b = NB; b < s_pad; b *= 2) {
-    const int pairs = (int)(s_pad / (2 * b));
+    const int full = (int)(s_pad / (2 * b));
     const int64_t pair_stride = 2 * b * s_pad + 2 * b;  // element offset between pairs
-    // T_p = B_p * Ainv_p, B_p = C[o2:o2+b, o1:o1+b], Ainv_p = Cinv[o1:o1+b, o1:o1+b]
-    hipError_t e = dgemm(b, b, b, 1.0, C + b * s_pad, s_pad, 1, pair_stride, Cinv, s_pad, 1,
-                         pair_stride, 0.0, tmp, b, b * b, pairs, 0, st);
-    if (e != hipSuccess) return e;
-    // X_p = -Dinv_p * T_p -> Cinv[o2:o2+b, o1:o1+b]
-    e = dgemm(b, b, b, -1.0, Cinv + b * s_pad + b, s_pad, 1, pair_stride, tmp, b, 1, b * b, 0.0,
-              Cinv + b * s_pad, s_pad, pair_stride, pairs, 0, st);
-    if (e != hipSuccess) return e;
+    hipError_t e;
+    if (full > 0) {
+      // T_p = B_p * Ainv_p, B_p = C[o2:o2+b, o1:o1+b], Ainv_p = Cinv[o1:o1+b, o1:o1+b]
+      e = dgemm(b, b, b, 1.0, C + b * s_pad, s_pad, 1, pair_stride, Cinv, s_pad, 1, pair_stride,
+                0.0, tmp, b, b * b, full, 0, st);
+      if (e != hipSuccess) return e;
+      // X_p = -Dinv_p * T_p -> Cinv[o2:o2+b, o1:o1+b]
+      e = dgemm(b, b, b, -1.0, Cinv + b * s_pad + b, s_pad, 1, pair_stride, tmp, b, 1, b * b,
+                0.0, Cinv + b * s_pad, s_pad, pair_stride, full, 0, st);
+      if (e != hipSuccess) return e;
+    }
+    const int64_t o1 = 2 * b * full, o2 = o1 + b, m2 = s_pad - o2;  // short pair, if any
+    if (m2 > 0) {
+      e = dgemm(m2, b, b, 1.0, C + o2 * s_pad + o1, s_pad, 1, 0, Cinv + o1 * s_pad + o1, s_pad,
+                1, 0, 0.0, tmp, b, 0, 1, 0, st);
+      if (e != hipSuccess) return e;
+      e = dgemm(m2, b, m2, -1.0, Cinv + o2 * s_pad + o2, s_pad, 1, 0, tmp, b, 1, 0, 0.0,
+                Cinv + o2 * s_pad + o1, s_pad, 0, 1, 0, st);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }

@@ -160,7 +160,8 @@ def _factor_case(n=2000, d=8, s=200, lam=2.0, seed=0):
     return Z, lam
 
 
-@pytest.mark.parametrize("shape", [(2000, 200), (1000, 130), (700, 64), (3000, 520)])
+@pytest.mark.parametrize("shape", [(2000, 200), (1000, 130), (700, 64), (3000, 520), (3000, 400),
+                                   (2500, 1100)])
 def test_precond_factor_parity(dev, shape):
     n, s = shape
     Z, lam = _factor_case(n=n, s=s)
