@@ -171,10 +171,14 @@ krr_status krr_kernel_matmat(const float* X1, int64_t n1, int64_t ldx1, const fl
 
 /* ----------------------------------------------------------------------------------------
  * Set-up of many problems at once (features and factor of Alg. 1 for each, e.g. before a
- * batched solve). The factor of one problem is a chain of short, latency-bound kernels (the
- * blocked Cholesky); krr_setup_many spreads the problems over up to KRR_SETUP_MAX_STREAMS
- * internal streams (default priority), largest first to the least loaded stream, so the
- * chains of different problems overlap on the device, and checks all pivots once at the end.
+ * batched solve). The features and Gram matrices are spread over up to
+ * KRR_SETUP_MAX_STREAMS internal streams (default priority), largest problem first to the
+ * least loaded stream. The factor of one problem alone is a chain of short, latency-bound
+ * kernels (the blocked Cholesky and the doubling inverse), so the FP64 factors of all
+ * problems then advance together on `stream`: one launch per 64-column step (and per
+ * doubling level) covers every problem that still has that step. C and Ut = Z C^{-T} are
+ * formed on the streams again, and all pivots are checked once at the end. Results are
+ * bit for bit those of krr_features and krr_precond_factor per problem.
  */
 #define KRR_SETUP_MAX_STREAMS 4
 
@@ -193,8 +197,10 @@ typedef struct krr_setup_problem {
   int64_t info;              /* written: 0, or the failing pivot + 1 */
 } krr_setup_problem;
 
-/* Workspace of krr_setup_many: one slot (the largest problem's features or factor
- * workspace) per stream, plus the pivot flags. */
+/* Workspace of krr_setup_many: one slot (the largest problem's features, or its factor's
+ * operand splits and Gram partials) per stream, every problem's FP64 factor storage (about
+ * 20 s_pad^2 bytes, s_pad = s rounded up to 64), pivot flags and launch descriptors.
+ * Returns 0 when a problem's sizes are invalid (krr_setup_many then names it). */
 size_t krr_setup_many_workspace_bytes(const krr_setup_problem* probs, int32_t count,
                                       int32_t nstreams);
 

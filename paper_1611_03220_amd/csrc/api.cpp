@@ -352,25 +352,28 @@ struct FactorLayout {
   int64_t nk, sk, np, sp64, s_pad;
   int nsplit;
 };
-void layout_factor(Bump& b, FactorLayout& L, int64_t n, int64_t s) {
+// `own` receives what one problem's factor keeps from the Gram to the end (scales, pivot
+// flag, G, C^{-1}, doubling scratch), `scratch` the operand splits and Gram partials.
+void layout_factor_parts(Bump& scratch, Bump& own, FactorLayout& L, int64_t n, int64_t s) {
   L.nk = round_up(n, 32);
   L.sk = round_up(s, 32);
   L.np = round_up(n, GEMM_TILE);
   L.sp64 = round_up(s, GEMM_TILE);
   L.s_pad = round_up(s, 64);  // 64 x 64 factor blocks
   L.nsplit = gram_nsplit(s, n);
-  L.stats = b.take<float>(64);
-  L.info = b.take<int>(64);
+  L.stats = own.take<float>(64);
+  L.info = own.take<int>(64);
   const int64_t big = std::max(L.sp64 * L.nk, L.np * L.sk);
-  L.h1 = b.take<_Float16>(big);
-  L.l1 = b.take<_Float16>(big);
-  L.ch = b.take<_Float16>(L.sp64 * L.sk);
-  L.cl = b.take<_Float16>(L.sp64 * L.sk);
-  L.part = b.take<double>((int64_t)L.nsplit * s * s);
-  L.G = b.take<double>(L.s_pad * L.s_pad);
-  L.Cinv = b.take<double>(L.s_pad * L.s_pad);
-  L.tmp = b.take<double>(L.s_pad * L.s_pad / 2);
+  L.h1 = scratch.take<_Float16>(big);
+  L.l1 = scratch.take<_Float16>(big);
+  L.ch = scratch.take<_Float16>(L.sp64 * L.sk);
+  L.cl = scratch.take<_Float16>(L.sp64 * L.sk);
+  L.part = scratch.take<double>((int64_t)L.nsplit * s * s);
+  L.G = own.take<double>(L.s_pad * L.s_pad);
+  L.Cinv = own.take<double>(L.s_pad * L.s_pad);
+  L.tmp = own.take<double>(L.s_pad * L.s_pad / 2);
 }
+void layout_factor(Bump& b, FactorLayout& L, int64_t n, int64_t s) { layout_factor_parts(b, b, L, n, s); }
 
 // G = Z^T Z + lambda_p I (split MFMA Gram, FP64 sums) and its FP64 Cholesky factor in L.G
 // (stride s_pad); KRR_E_NOT_SPD with *info = failing pivot + 1.
@@ -398,9 +401,10 @@ krr_status gram_cholesky(const float* Z, int64_t n, int64_t s, int64_t ldz, doub
   return KRR_OK;
 }
 
-// gram_cholesky without the host check of the pivot (L.info holds it on the device)
-hipError_t gram_cholesky_async(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
-                               FactorLayout& L, hipStream_t st) {
+// G = Z^T Z + lambda_p I in L.G (as gram_cholesky), C^{-1} cleared and the pivot flag reset,
+// without the factor itself
+hipError_t gram_form_async(const float* Z, int64_t n, int64_t s, int64_t ldz, double lambda_p,
+                           FactorLayout& L, hipStream_t st) {
   hipError_t e;
   if ((e = fill_f32(L.stats, 4, 0.0f, st))) return e;
   if ((e = fill_i32(L.info, 1, 0, st))) return e;
@@ -410,15 +414,13 @@ hipError_t gram_cholesky_async(const float* Z, int64_t n, int64_t s, int64_t ldz
   if ((e = gemm_nt_f16x3(Zt, Zt, s, s, L.nk, L.nsplit, EPI_PART64, 1, 0, 1.0, L.part, s * s,
                          nullptr, s, nullptr, 0.0f, st))) return e;
   if ((e = gram_finalize(L.part, L.nsplit, s, s, s * s, lambda_p, L.s_pad, L.G, st))) return e;
-  if ((e = fill_f64(L.Cinv, L.s_pad * L.s_pad, 0.0, st))) return e;
-  return cholesky_blocked(L.G, L.s_pad, L.Cinv, L.info, st);
+  return fill_f64(L.Cinv, L.s_pad * L.s_pad, 0.0, st);
 }
 
-// after the Cholesky factor in L.G: C (lower, s x s), C^{-1} by doubling, Ut = Z C^{-T}
-hipError_t factor_finish(FactorLayout& L, const float* Z, int64_t n, int64_t s, int64_t ldz,
-                         double* C, float* Ut, int64_t ldu, hipStream_t st) {
+// after the Cholesky factor in L.G and C^{-1} in L.Cinv: C (lower, s x s), Ut = Z C^{-T}
+hipError_t factor_tail(FactorLayout& L, const float* Z, int64_t n, int64_t s, int64_t ldz,
+                       double* C, float* Ut, int64_t ldu, hipStream_t st) {
   hipError_t e;
-  if ((e = tri_inverse_doubling(L.G, L.s_pad, L.Cinv, L.tmp, st))) return e;
   if ((e = copy_lower(L.G, L.s_pad, s, C, st))) return e;
   // Ut = Z C^{-T}: A = Z (n x s), B = C^{-1} (rows j, contraction k), lower triangular
   if ((e = absmax<double>(L.Cinv, s, s, L.s_pad, L.stats + 1, st))) return e;
@@ -427,6 +429,14 @@ hipError_t factor_finish(FactorLayout& L, const float* Z, int64_t n, int64_t s, 
   SplitOperand A{L.h1, L.l1, L.sk, L.stats + 0}, B{L.ch, L.cl, L.sk, L.stats + 1};
   return gemm_nt_f16x3(A, B, n, s, L.sk, 1, EPI_F32, 0, 1, 1.0, nullptr, 0, Ut, ldu, nullptr, 0.0f,
                        st);
+}
+
+// after the Cholesky factor in L.G: C^{-1} by doubling, then factor_tail
+hipError_t factor_finish(FactorLayout& L, const float* Z, int64_t n, int64_t s, int64_t ldz,
+                         double* C, float* Ut, int64_t ldu, hipStream_t st) {
+  hipError_t e;
+  if ((e = tri_inverse_doubling(L.G, L.s_pad, L.Cinv, L.tmp, st))) return e;
+  return factor_tail(L, Z, n, s, ldz, C, Ut, ldu, st);
 }
 
 // ---------------------------------------------------------------------- PCG
@@ -712,24 +722,134 @@ krr_status krr_precond_factor(const float* Z, int64_t n, int64_t s, int64_t ldz,
 
 // ------------------------------------------------ set-up of many problems on several streams
 namespace {
-size_t setup_slot_bytes(const krr_setup_problem& p) {
-  Bump f(nullptr), g(nullptr);
+// Per problem: its stream slot (the features, or the factor's operand splits and Gram
+// partials) and what it keeps from its Gram to the end of the set-up (G, C^{-1}, scratch).
+void setup_sizes(const krr_setup_problem& p, size_t& slot, size_t& own) {
+  Bump f(nullptr), g(nullptr), o(nullptr);
   FeatLayout FL;
   layout_features(f, FL, p.n, p.d, p.s);
   FactorLayout L;
-  layout_factor(g, L, p.n, p.s);
-  return round_up((int64_t)std::max(f.off, g.off), 256) + 256;
+  layout_factor_parts(g, o, L, p.n, p.s);
+  slot = (size_t)round_up((int64_t)std::max(f.off, g.off), 256) + 256;
+  own = (size_t)round_up((int64_t)o.off, 256) + 256;
+}
+
+// The FP64 factors of all problems advance together: one launch per step covers every
+// problem that still has it. GEMM lists: the trailing update after each 64-column block,
+// then per doubling level the T = B A^{-1} products and the X = -D^{-1} T products (the
+// pairs of tri_inverse_doubling, each pair one product, every problem's T in its own tmp).
+struct GroupLaunch {
+  int64_t off = 0, count = 0, max_m = 0, max_n = 0;
+};
+struct GroupedFactorPlan {
+  std::vector<DgemmProblem> probs;
+  std::vector<GroupLaunch> trail;   // column block k0 = 64 t
+  std::vector<GroupLaunch> levels;  // T then X for b = 64, 128, ...
+  int64_t max_s_pad = 0;
+};
+void add_problem(GroupLaunch& g, std::vector<DgemmProblem>& v, const DgemmProblem& p) {
+  v.push_back(p);
+  ++g.count;
+  g.max_m = std::max(g.max_m, p.M);
+  g.max_n = std::max(g.max_n, p.N);
+}
+void plan_grouped_factor(const std::vector<FactorLayout>& Ls, GroupedFactorPlan& P) {
+  P = GroupedFactorPlan{};
+  for (const FactorLayout& L : Ls) P.max_s_pad = std::max(P.max_s_pad, L.s_pad);
+  for (int64_t k0 = 0; k0 < P.max_s_pad; k0 += 64) {
+    GroupLaunch g;
+    g.off = (int64_t)P.probs.size();
+    for (const FactorLayout& L : Ls) {
+      const int64_t sp = L.s_pad, rest = sp - k0 - 64;
+      if (rest <= 0) continue;
+      double* panel = L.G + (k0 + 64) * sp + k0;
+      add_problem(g, P.probs, DgemmProblem{panel, panel, panel + 64, sp, 1, 1, sp, sp, rest, rest,
+                                           64, -1.0, 1.0, 1});
+    }
+    P.trail.push_back(g);
+  }
+  for (int64_t b = 64; b < P.max_s_pad; b *= 2) {
+    GroupLaunch t, x;
+    t.off = (int64_t)P.probs.size();
+    for (const FactorLayout& L : Ls) {
+      const int64_t sp = L.s_pad;
+      if (b >= sp) continue;
+      const int64_t full = sp / (2 * b);
+      for (int64_t q = 0; q <= full; ++q) {
+        const int64_t o1 = 2 * b * q, o2 = o1 + b, rows = std::min(b, sp - o2);
+        if (rows <= 0) break;
+        add_problem(t, P.probs, DgemmProblem{L.G + o2 * sp + o1, L.Cinv + o1 * sp + o1,
+                                             L.tmp + q * b * b, sp, 1, sp, 1, b, rows, b, b, 1.0,
+                                             0.0, 0});
+      }
+    }
+    x.off = (int64_t)P.probs.size();
+    for (const FactorLayout& L : Ls) {
+      const int64_t sp = L.s_pad;
+      if (b >= sp) continue;
+      const int64_t full = sp / (2 * b);
+      for (int64_t q = 0; q <= full; ++q) {
+        const int64_t o1 = 2 * b * q, o2 = o1 + b, rows = std::min(b, sp - o2);
+        if (rows <= 0) break;
+        add_problem(x, P.probs, DgemmProblem{L.Cinv + o2 * sp + o2, L.tmp + q * b * b,
+                                             L.Cinv + o2 * sp + o1, sp, 1, b, 1, sp, rows, b, rows,
+                                             -1.0, 0.0, 0});
+      }
+    }
+    P.levels.push_back(t);
+    P.levels.push_back(x);
+  }
+}
+
+struct SetupPlan {
+  size_t slot = 0, own_total = 0;
+  std::vector<size_t> own_off;
+  size_t infos_off = 0, members_off = 0, probs_off = 0, total = 0;
+  std::vector<FactorLayout> Ls;
+  GroupedFactorPlan G;
+};
+// Workspace: k stream slots, every problem's own factor region, pivot flags, the member
+// and GEMM descriptors. With base == nullptr only the sizes are formed.
+void plan_setup(const krr_setup_problem* probs, int count, int k, char* base, SetupPlan& S) {
+  S = SetupPlan{};
+  std::vector<size_t> own(count);
+  for (int i = 0; i < count; ++i) {
+    size_t sl;
+    setup_sizes(probs[i], sl, own[i]);
+    S.slot = std::max(S.slot, sl);
+  }
+  size_t off = (size_t)k * S.slot;
+  S.own_off.resize(count);
+  S.Ls.resize(count);
+  for (int i = 0; i < count; ++i) {
+    S.own_off[i] = off;
+    Bump scratch(nullptr), mine(base ? base + off : nullptr);
+    layout_factor_parts(scratch, mine, S.Ls[i], probs[i].n, probs[i].s);
+    off += own[i];
+  }
+  plan_grouped_factor(S.Ls, S.G);
+  S.infos_off = off;
+  off += (size_t)round_up((int64_t)count * (int64_t)sizeof(int), 256);
+  S.members_off = off;
+  off += (size_t)round_up((int64_t)count * (int64_t)sizeof(FactorMember), 256);
+  S.probs_off = off;
+  off += (size_t)round_up((int64_t)std::max<size_t>(S.G.probs.size(), 1) * (int64_t)sizeof(DgemmProblem), 256);
+  S.total = off + 256;
+}
+bool setup_problem_ok(const krr_setup_problem& p) {
+  return p.n >= 2 && p.s >= 1 && p.d >= 1 && p.s < p.n;
 }
 }  // namespace
 
 size_t krr_setup_many_workspace_bytes(const krr_setup_problem* probs, int32_t count,
                                       int32_t nstreams) {
   if (!probs || count < 1) return 0;
-  size_t slot = 0;
   for (int i = 0; i < count; ++i)
-    if (probs[i].n >= 2 && probs[i].s >= 1 && probs[i].d >= 1) slot = std::max(slot, setup_slot_bytes(probs[i]));
+    if (!setup_problem_ok(probs[i])) return 0;
   const int k = std::max(1, std::min<int32_t>(nstreams, KRR_SETUP_MAX_STREAMS));
-  return k * slot + round_up((int64_t)count * (int64_t)sizeof(int), 256) + 512;
+  SetupPlan S;
+  plan_setup(probs, count, k, nullptr, S);
+  return S.total;
 }
 
 krr_status krr_setup_many(krr_setup_problem* probs, int32_t count, int32_t nstreams, void* ws,
@@ -749,53 +869,109 @@ krr_status krr_setup_many(krr_setup_problem* probs, int32_t count, int32_t nstre
   const int k = std::max(1, std::min<int32_t>(nstreams, KRR_SETUP_MAX_STREAMS));
   const size_t need = krr_setup_many_workspace_bytes(probs, count, k);
   CHECK_ST(check_ws(ws, ws_bytes, need));
-  size_t slot = 0;
-  for (int i = 0; i < count; ++i) slot = std::max(slot, setup_slot_bytes(probs[i]));
   char* base = static_cast<char*>(ws);
-  int* infos = reinterpret_cast<int*>(base + k * slot);
+  SetupPlan S;
+  plan_setup(probs, count, k, base, S);
+  int* infos = reinterpret_cast<int*>(base + S.infos_off);
+  FactorMember* mem_d = reinterpret_cast<FactorMember*>(base + S.members_off);
+  DgemmProblem* probs_d = reinterpret_cast<DgemmProblem*>(base + S.probs_off);
+  std::vector<FactorMember> mem_h(count);
+  for (int i = 0; i < count; ++i) mem_h[i] = FactorMember{S.Ls[i].G, S.Ls[i].Cinv, S.Ls[i].info, S.Ls[i].s_pad};
   hipStream_t st = (hipStream_t)stream;
   // streams at the default priority; they start after the work already on `stream` and the
-  // caller's stream waits for all of them at the end
+  // caller's stream waits for all of them at the end of each phase
   std::vector<hipStream_t> ss(k, nullptr);
   std::vector<hipEvent_t> ev(k + 1, nullptr);
   auto cleanup = [&]() {
     for (auto& e : ev) if (e) (void)hipEventDestroy(e);
     for (auto& q : ss) if (q) (void)hipStreamDestroy(q);
   };
+  auto fork = [&]() -> hipError_t {
+    hipError_t e = hipEventRecord(ev[k], st);
+    for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamWaitEvent(ss[j], ev[k], 0);
+    return e;
+  };
+  auto join = [&]() -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < k && e == hipSuccess; ++j) {
+      e = hipEventRecord(ev[j], ss[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, ev[j], 0);
+    }
+    return e;
+  };
   hipError_t e = hipSuccess;
   for (int j = 0; j <= k && e == hipSuccess; ++j) e = hipEventCreateWithFlags(&ev[j], hipEventDisableTiming);
   for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamCreateWithFlags(&ss[j], hipStreamNonBlocking);
+  // descriptors: the host vectors live until the synchronisation at the end
+  if (e == hipSuccess) e = hipMemcpyAsync(mem_d, mem_h.data(), sizeof(FactorMember) * count, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !S.G.probs.empty())
+    e = hipMemcpyAsync(probs_d, S.G.probs.data(), sizeof(DgemmProblem) * S.G.probs.size(),
+                       hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = fill_i32(infos, count, 0, st);
-  if (e == hipSuccess) e = hipEventRecord(ev[k], st);
-  for (int j = 0; j < k && e == hipSuccess; ++j) e = hipStreamWaitEvent(ss[j], ev[k], 0);
-  if (e != hipSuccess) { cleanup(); return fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e)); }
+  if (e == hipSuccess) e = fork();
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    return fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
+  }
   // largest problems first, each to the stream with the least estimated work so far
-  std::vector<int> order(count);
+  std::vector<int> order(count), stream_of(count, 0);
   for (int i = 0; i < count; ++i) order[i] = i;
   auto cost = [&](int i) { return (double)probs[i].n * (double)probs[i].s * (double)(probs[i].s + probs[i].d); };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
   std::vector<double> load(k, 0.0);
-  krr_status status = KRR_OK;
   for (int i : order) {
     const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
     load[j] += cost(i);
+    stream_of[i] = j;
+  }
+  krr_status status = KRR_OK;
+  // phase 1 (streams): features and Gram of every problem, scratch in the stream's slot
+  for (int i : order) {
     krr_setup_problem& p = probs[i];
-    void* wsj = base + j * slot;
+    const int j = stream_of[i];
+    void* wsj = base + (size_t)j * S.slot;
     status = features_impl("krr_setup_many", p.X, p.n, p.d, p.ldx, p.W, p.s, p.b, p.s, p.Z, p.ldz,
-                           wsj, slot, ss[j]);
+                           wsj, S.slot, ss[j]);
     if (status != KRR_OK) break;
-    Bump bb(wsj);
+    Bump scratch(wsj), mine(base + S.own_off[i]);
     FactorLayout L;
-    layout_factor(bb, L, p.n, p.s);
-    e = gram_cholesky_async(p.Z, p.n, p.s, p.ldz, p.lambda_p, L, ss[j]);
-    if (e == hipSuccess) e = hipMemcpyAsync(infos + i, L.info, sizeof(int), hipMemcpyDeviceToDevice, ss[j]);
-    if (e == hipSuccess) e = factor_finish(L, p.Z, p.n, p.s, p.ldz, p.C, p.Ut, p.ldu, ss[j]);
+    layout_factor_parts(scratch, mine, L, p.n, p.s);
+    e = gram_form_async(p.Z, p.n, p.s, p.ldz, p.lambda_p, L, ss[j]);
     if (e != hipSuccess) { status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e)); break; }
   }
-  for (int j = 0; j < k; ++j) {
-    hipError_t e2 = hipEventRecord(ev[j], ss[j]);
-    if (e2 == hipSuccess) e2 = hipStreamWaitEvent(st, ev[j], 0);
-    if (e2 != hipSuccess && status == KRR_OK) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e2));
+  e = join();
+  if (e != hipSuccess && status == KRR_OK) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
+  // phase 2 (caller's stream): the grouped FP64 factor and inverse of all problems
+  if (status == KRR_OK) {
+    const GroupedFactorPlan& G = S.G;
+    for (size_t t = 0; t < G.trail.size() && e == hipSuccess; ++t) {
+      const GroupLaunch& g = G.trail[t];
+      e = cholesky_step_grouped(mem_d, count, 64 * (int64_t)t, g.max_m, st);
+      if (e == hipSuccess) e = dgemm_grouped(probs_d + g.off, (int)g.count, g.max_m, g.max_n, st);
+    }
+    if (e == hipSuccess) e = diag_inverse_grouped(mem_d, count, G.max_s_pad, st);
+    for (size_t l = 0; l < G.levels.size() && e == hipSuccess; ++l) {
+      const GroupLaunch& g = G.levels[l];
+      e = dgemm_grouped(probs_d + g.off, (int)g.count, g.max_m, g.max_n, st);
+    }
+    if (e == hipSuccess) e = fork();
+    if (e != hipSuccess) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
+  }
+  // phase 3 (streams): C, the operand splits and Ut = Z C^{-T} of every problem
+  if (status == KRR_OK) {
+    for (int i : order) {
+      krr_setup_problem& p = probs[i];
+      const int j = stream_of[i];
+      Bump scratch(base + (size_t)j * S.slot), mine(base + S.own_off[i]);
+      FactorLayout L;
+      layout_factor_parts(scratch, mine, L, p.n, p.s);
+      e = hipMemcpyAsync(infos + i, L.info, sizeof(int), hipMemcpyDeviceToDevice, ss[j]);
+      if (e == hipSuccess) e = factor_tail(L, p.Z, p.n, p.s, p.ldz, p.C, p.Ut, p.ldu, ss[j]);
+      if (e != hipSuccess) { status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e)); break; }
+    }
+    e = join();
+    if (e != hipSuccess && status == KRR_OK) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
   }
   std::vector<int> h(count, 0);
   if (status == KRR_OK) {
@@ -803,6 +979,7 @@ krr_status krr_setup_many(krr_setup_problem* probs, int32_t count, int32_t nstre
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) status = fail(KRR_E_HIP, "krr_setup_many: %s", hipGetErrorString(e));
   } else {
+    (void)join();
     (void)hipStreamSynchronize(st);
   }
   cleanup();

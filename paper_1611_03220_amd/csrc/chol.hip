@@ -51,9 +51,8 @@ __device__ __forceinline__ void potrf_steps(double (&w)[NB], double* col, int r,
   }
 }
 
-__global__ __launch_bounds__(64, 2) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
-                                                        int64_t k0, int* __restrict__ info) {
-  __shared__ double col[NB];
+__device__ __forceinline__ void potrf_diag_body(double* __restrict__ A, int64_t lda, int64_t k0,
+                                                int* __restrict__ info, double* col) {
   const int r = threadIdx.x;
   double w[NB];  // the whole row; entries above the diagonal (stale) are never used, and
                  // loading them keeps lane-dependent masks out of the steps
@@ -64,6 +63,21 @@ __global__ __launch_bounds__(64, 2) void potrf_diag_kernel(double* __restrict__ 
   if (r == 0 && first_bad != 0 && *info == 0) *info = (int)(k0 + first_bad);
 #pragma unroll
   for (int c = 0; c < NB; ++c) A[(k0 + r) * lda + k0 + c] = c <= r ? w[c] : 0.0;
+}
+
+__global__ __launch_bounds__(64, 2) void potrf_diag_kernel(double* __restrict__ A, int64_t lda,
+                                                        int64_t k0, int* __restrict__ info) {
+  __shared__ double col[NB];
+  potrf_diag_body(A, lda, k0, info, col);
+}
+
+// member blockIdx.x of a grouped factor
+__global__ __launch_bounds__(64, 2) void potrf_diag_grouped_kernel(const FactorMember* __restrict__ mem,
+                                                                int64_t k0) {
+  const FactorMember f = mem[blockIdx.x];
+  if (k0 >= f.s_pad) return;
+  __shared__ double col[NB];
+  potrf_diag_body(f.G, f.s_pad, k0, f.info, col);
 }
 
 // Forward substitution against the 64 x 64 lower factor held in LDS (Ls, reciprocal
@@ -82,10 +96,9 @@ __device__ __forceinline__ void lower_solve64(const double (*Ls)[NB + 1], const 
 
 // Panel below the diagonal block k0: P <- P L^{-T} (row i of P solves x L^T = p_i), one
 // thread per row, L staged in LDS.
-__global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ G, int64_t ld,
-                                                         int64_t k0, int64_t rows) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double dinv[NB];
+__device__ __forceinline__ void trsm_panel_body(double* __restrict__ G, int64_t ld, int64_t k0,
+                                                int64_t rows, double (&Ls)[NB][NB + 1],
+                                                double* dinv) {
   for (int e = threadIdx.x; e < NB * NB; e += 256) Ls[e / NB][e % NB] = G[(k0 + e / NB) * ld + k0 + e % NB];
   __syncthreads();
   if (threadIdx.x < NB) dinv[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
@@ -101,13 +114,29 @@ __global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ G,
   for (int j = 0; j < NB; ++j) p[j] = x[j];
 }
 
-// Inverses of all diagonal 64 x 64 blocks of the factor (block b = blockIdx.x), written to
-// the same positions of Cinv: thread c solves L x = e_c for column c of the inverse.
-__global__ __launch_bounds__(64) void diag_inverse_kernel(const double* __restrict__ G,
-                                                          int64_t ld, double* __restrict__ Cinv) {
+__global__ __launch_bounds__(256) void trsm_panel_kernel(double* __restrict__ G, int64_t ld,
+                                                         int64_t k0, int64_t rows) {
   __shared__ double Ls[NB][NB + 1];
   __shared__ double dinv[NB];
-  const int64_t k0 = (int64_t)blockIdx.x * NB;
+  trsm_panel_body(G, ld, k0, rows, Ls, dinv);
+}
+
+// member blockIdx.y of a grouped factor; blocks past its panel return before any barrier
+__global__ __launch_bounds__(256) void trsm_panel_grouped_kernel(const FactorMember* __restrict__ mem,
+                                                                 int64_t k0) {
+  const FactorMember f = mem[blockIdx.y];
+  const int64_t rows = f.s_pad - k0 - NB;
+  if ((int64_t)blockIdx.x * 256 >= rows) return;
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
+  trsm_panel_body(f.G, f.s_pad, k0, rows, Ls, dinv);
+}
+
+// Inverse of the diagonal 64 x 64 block at k0 of the factor, written to the same position of
+// Cinv: thread c solves L x = e_c for column c of the inverse (one block per diagonal block).
+__device__ __forceinline__ void diag_inverse_body(const double* __restrict__ G, int64_t ld,
+                                                  double* __restrict__ Cinv, int64_t k0,
+                                                  double (&Ls)[NB][NB + 1], double* dinv) {
   for (int e = threadIdx.x; e < NB * NB; e += 64) Ls[e / NB][e % NB] = G[(k0 + e / NB) * ld + k0 + e % NB];
   __syncthreads();
   dinv[threadIdx.x] = 1.0 / Ls[threadIdx.x][threadIdx.x];
@@ -119,6 +148,23 @@ __global__ __launch_bounds__(64) void diag_inverse_kernel(const double* __restri
   lower_solve64(Ls, dinv, x);
 #pragma unroll
   for (int j = 0; j < NB; ++j) Cinv[(k0 + j) * ld + k0 + c] = x[j];
+}
+
+__global__ __launch_bounds__(64) void diag_inverse_kernel(const double* __restrict__ G,
+                                                          int64_t ld, double* __restrict__ Cinv) {
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
+  diag_inverse_body(G, ld, Cinv, (int64_t)blockIdx.x * NB, Ls, dinv);
+}
+
+// block blockIdx.x of member blockIdx.y of a grouped factor
+__global__ __launch_bounds__(64) void diag_inverse_grouped_kernel(const FactorMember* __restrict__ mem) {
+  const FactorMember f = mem[blockIdx.y];
+  const int64_t k0 = (int64_t)blockIdx.x * NB;
+  if (k0 >= f.s_pad) return;
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
+  diag_inverse_body(f.G, f.s_pad, f.Cinv, k0, Ls, dinv);
 }
 
 // G (s_pad x s_pad, lower part used) -> C in place; Cinv diagonal blocks filled.
@@ -137,6 +183,26 @@ hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, h
     if (e != hipSuccess) return e;
   }
   diag_inverse_kernel<<<s_pad / NB, 64, 0, st>>>(G, s_pad, Cinv);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t cholesky_step_grouped(const FactorMember* mem, int count, int64_t k0, int64_t max_rest,
+                                 hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  potrf_diag_grouped_kernel<<<count, NB, 0, st>>>(mem, k0);
+  KRR_LAUNCH_CHECK();
+  if (max_rest > 0) {
+    trsm_panel_grouped_kernel<<<dim3(ceil_div(max_rest, 256), count), 256, 0, st>>>(mem, k0);
+    KRR_LAUNCH_CHECK();
+  }
+  return hipSuccess;
+}
+
+hipError_t diag_inverse_grouped(const FactorMember* mem, int count, int64_t max_s_pad,
+                                hipStream_t st) {
+  if (count <= 0 || max_s_pad <= 0) return hipSuccess;
+  diag_inverse_grouped_kernel<<<dim3(ceil_div(max_s_pad, NB), count), 64, 0, st>>>(mem);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

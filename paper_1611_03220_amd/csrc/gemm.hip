@@ -162,20 +162,15 @@ hipError_t gemm_nt_f16x3(const SplitOperand& A, const SplitOperand& B, int64_t M
 // loads of a chunk are issued before any is used), each thread 4 x 4 outputs. lower_only
 // skips tiles that lie strictly above the block diagonal and entries with j > i.
 constexpr int D_BK = 64;
-__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K,
-                                                    double alpha, const double* __restrict__ A,
-                                                    int64_t sai, int64_t sak, int64_t bA,
-                                                    const double* __restrict__ B, int64_t sbk,
-                                                    int64_t sbj, int64_t bB, double beta,
-                                                    double* __restrict__ C, int64_t ldc,
-                                                    int64_t bC, int lower_only) {
-  const int64_t bi = blockIdx.y, bj = blockIdx.x;
-  if (lower_only && bj > bi) return;
-  A += (int64_t)blockIdx.z * bA;
-  B += (int64_t)blockIdx.z * bB;
-  C += (int64_t)blockIdx.z * bC;
-  __shared__ double sA[D_BK][64 + 1];
-  __shared__ double sB[D_BK][64 + 1];
+// One 64 x 64 output tile (bi, bj) of one product; sA and sB are the block's LDS tiles.
+__device__ __forceinline__ void dgemm_tile(int64_t bi, int64_t bj, int64_t M, int64_t N,
+                                           int64_t K, double alpha, const double* __restrict__ A,
+                                           int64_t sai, int64_t sak,
+                                           const double* __restrict__ B, int64_t sbk,
+                                           int64_t sbj, double beta, double* __restrict__ C,
+                                           int64_t ldc, int lower_only,
+                                           double (&sA)[D_BK][64 + 1],
+                                           double (&sB)[D_BK][64 + 1]) {
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int64_t row0 = bi * 64, col0 = bj * 64;
   double acc[4][4];
@@ -239,6 +234,34 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_
     }
 }
 
+__global__ __launch_bounds__(256) void dgemm_kernel(int64_t M, int64_t N, int64_t K,
+                                                    double alpha, const double* __restrict__ A,
+                                                    int64_t sai, int64_t sak, int64_t bA,
+                                                    const double* __restrict__ B, int64_t sbk,
+                                                    int64_t sbj, int64_t bB, double beta,
+                                                    double* __restrict__ C, int64_t ldc,
+                                                    int64_t bC, int lower_only) {
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (lower_only && bj > bi) return;
+  __shared__ double sA[D_BK][64 + 1];
+  __shared__ double sB[D_BK][64 + 1];
+  dgemm_tile(bi, bj, M, N, K, alpha, A + (int64_t)blockIdx.z * bA, sai, sak,
+             B + (int64_t)blockIdx.z * bB, sbk, sbj, beta, C + (int64_t)blockIdx.z * bC, ldc,
+             lower_only, sA, sB);
+}
+
+// Products of different shapes in one launch: blockIdx.z selects the product, blocks
+// outside its tile range return.
+__global__ __launch_bounds__(256) void dgemm_grouped_kernel(const DgemmProblem* __restrict__ probs) {
+  const DgemmProblem p = probs[blockIdx.z];
+  const int64_t bi = blockIdx.y, bj = blockIdx.x;
+  if (bi * 64 >= p.M || bj * 64 >= p.N || (p.lower_only && bj > bi)) return;
+  __shared__ double sA[D_BK][64 + 1];
+  __shared__ double sB[D_BK][64 + 1];
+  dgemm_tile(bi, bj, p.M, p.N, p.K, p.alpha, p.A, p.sai, p.sak, p.B, p.sbk, p.sbj, p.beta, p.C,
+             p.ldc, p.lower_only, sA, sB);
+}
+
 hipError_t dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t sai,
                  int64_t sak, int64_t bA, const double* B, int64_t sbk, int64_t sbj, int64_t bB,
                  double beta, double* C, int64_t ldc, int64_t bC, int batch, int lower_only,
@@ -247,6 +270,15 @@ hipError_t dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
   dim3 grid(ceil_div(N, 64), ceil_div(M, 64), batch);
   dgemm_kernel<<<grid, 256, 0, st>>>(M, N, K, alpha, A, sai, sak, bA, B, sbk, sbj, bB, beta, C,
                                      ldc, bC, lower_only);
+  KRR_LAUNCH_CHECK();
+  return hipSuccess;
+}
+
+hipError_t dgemm_grouped(const DgemmProblem* probs, int count, int64_t max_m, int64_t max_n,
+                         hipStream_t st) {
+  if (count <= 0 || max_m <= 0 || max_n <= 0) return hipSuccess;
+  dim3 grid(ceil_div(max_n, 64), ceil_div(max_m, 64), count);
+  dgemm_grouped_kernel<<<grid, 256, 0, st>>>(probs);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }

@@ -181,9 +181,38 @@ hipError_t dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                  int64_t sak, int64_t bA, const double* B, int64_t sbk, int64_t sbj, int64_t bB,
                  double beta, double* C, int64_t ldc, int64_t bC, int batch, int lower_only,
                  hipStream_t st);
+// One product of a grouped FP64 GEMM launch (device memory): C = beta C + alpha A B with
+// A(i, k) = A[i*sai + k*sak], B(k, j) = B[k*sbk + j*sbj], C(i, j) = C[i*ldc + j].
+struct DgemmProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  int64_t sai, sak, sbk, sbj, ldc;
+  int64_t M, N, K;
+  double alpha, beta;
+  int lower_only;
+};
+// `count` products of at most max_m x max_n outputs each in one launch
+hipError_t dgemm_grouped(const DgemmProblem* probs, int count, int64_t max_m, int64_t max_n,
+                         hipStream_t st);
 
 // chol.hip
 hipError_t cholesky_blocked(double* G, int64_t s_pad, double* Cinv, int* info, hipStream_t st);
+// One factor of a grouped Cholesky (device memory): G (s_pad x s_pad, factored in place),
+// Cinv (its inverted diagonal 64 x 64 blocks are written), the pivot flag.
+struct FactorMember {
+  double* G;
+  double* Cinv;
+  int* info;
+  int64_t s_pad;
+};
+// Column block k0 of every member whose s_pad exceeds k0: diagonal factor, then the panel
+// below it (rows up to max_rest); members with nothing left return at once.
+hipError_t cholesky_step_grouped(const FactorMember* mem, int count, int64_t k0, int64_t max_rest,
+                                 hipStream_t st);
+// Inverses of every member's diagonal 64 x 64 blocks (max_s_pad the largest order).
+hipError_t diag_inverse_grouped(const FactorMember* mem, int count, int64_t max_s_pad,
+                                hipStream_t st);
 hipError_t tri_inverse_doubling(const double* C, int64_t s_pad, double* Cinv, double* tmp,
                                 hipStream_t st);
 hipError_t gram_finalize(const double* part, int nsplit, int64_t s, int64_t ldp, int64_t pstride,
