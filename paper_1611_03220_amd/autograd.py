@@ -9,8 +9,11 @@ KRRSolve:      alpha = (K(X; sigma) + lambda I)^{-1} Y by preconditioned CG (Eq.
                The preconditioner (Z, Ut) is treated as a constant: the exact solution does not
                depend on it, only the iteration count does.
                dL/dsigma is the difference of two terms that nearly cancel (here by two orders of
-               magnitude), so its dK/dsigma products run in FP64 (`deriv_prec`) while both solves
-               may run mixed.
+               magnitude), so its dK/dsigma products run in `deriv_prec`, FP64 by default, while
+               both solves may run mixed. Mixed dK/dsigma products (errors about 1e-7 of each
+               term, the factor D of dK/dsigma carrying the FP32 distance's absolute error) keep
+               the gradient within 5e-6 of the oracle's on the 147-class recipe, but miss 1e-4
+               (3.7e-4) on a 20-class recipe whose terms cancel by about 3.5 orders.
 KernelMatmat:  OUT = K(X1, X2; sigma) V (e.g. validation predictions; the loss below runs this
                forward product in FP64 because the validation residual cancels). Backward:
                  dL/dV     = K(X2, X1) G,
@@ -33,7 +36,7 @@ class KRRSolve(torch.autograd.Function):
     def forward(ctx, sigma, lam, X, Y, Ut, opts):
         s, l = _scalar(sigma), _scalar(lam)
         opts = dict(opts)
-        ctx.deriv_prec = opts.pop("deriv_prec", "fp64")
+        ctx.deriv_prec = opts.pop("deriv_prec", None) or "fp64"
         alpha, rep = krr.pcg_solve(X, s, l, Ut, Y, **opts)
         ctx.save_for_backward(X, alpha, Ut if Ut is not None else torch.empty(0, device=X.device))
         ctx.sig, ctx.lam, ctx.opts, ctx.has_u = s, l, opts, Ut is not None
@@ -88,12 +91,13 @@ def kernel_matmat(X1, X2, sigma, V, prec="f16x3", deriv_prec="fp64", fwd_prec=No
 
 
 def validation_loss(Xtr, Ytr, Xv, Yv, sigma, lam, Ut=None, prec="f16x3", deriv_prec="fp64",
-                    **opts):
+                    pred_prec="fp64", **opts):
     """L = 1/2 ||K(Xv, Xtr) alpha - Yv||_F^2 with alpha from the differentiable solve.
     The residual K(Xv, Xtr) alpha - Yv cancels most of the prediction when the model fits,
-    so the prediction product runs in `deriv_prec` (FP64 by default), like the dK/dsigma
-    products; the solves and the transposed product of the backward run in `prec`."""
+    so the prediction product runs in `pred_prec` (FP64 by default); the solves and the
+    transposed product of the backward run in `prec`, the dK/dsigma products in
+    `deriv_prec` (FP64 by default)."""
     alpha = krr_solve(Xtr, Ytr, sigma, lam, Ut, prec=prec, deriv_prec=deriv_prec, **opts)
     pred = kernel_matmat(Xv, Xtr, sigma, alpha, prec=prec, deriv_prec=deriv_prec,
-                         fwd_prec=deriv_prec)
+                         fwd_prec=pred_prec)
     return 0.5 * ((pred - Yv) ** 2).sum()

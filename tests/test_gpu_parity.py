@@ -469,11 +469,12 @@ def _diff_workload():
     return WL.correlated_differentiation(n=3072, n_val=384, d=440, k=147, s=256)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "f16x3"])
-def test_validation_gradient_matches_oracle(dev, prec):
+@pytest.mark.parametrize("prec,deriv_prec", [("fp64", "fp64"), ("f16x3", "fp64"), ("f16x3", "f16x3")])
+def test_validation_gradient_matches_oracle(dev, prec, deriv_prec):
     """The differentiation workload's recipe (d = 440, 147 classes) at n = 3072 + 384:
     validation loss and its sigma / lambda gradients through the adjoint PCG against the
-    oracle's dense FP64 adjoint gradients (bound: 1e-4 relative)."""
+    oracle's dense FP64 adjoint gradients (bound: 1e-4 relative), with the dK/dsigma
+    products in FP64 (the default) or mixed (measured within 5e-6 on this recipe)."""
     from paper_1611_03220_amd import autograd as KA
     w = _diff_workload()
     Xtr, Xv = _t(w.X, dev), _t(w.Xv, dev)
@@ -482,7 +483,8 @@ def test_validation_gradient_matches_oracle(dev, prec):
     _, Ut = krr.precond_factor(Z, w.lam)
     sig = torch.tensor(w.sigma, dtype=torch.float64, device=dev, requires_grad=True)
     lam = torch.tensor(w.lam, dtype=torch.float64, device=dev, requires_grad=True)
-    L = KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, prec=prec, tol=1e-9, refine=3)
+    L = KA.validation_loss(Xtr, Ytr, Xv, Yv, sig, lam, Ut, prec=prec, deriv_prec=deriv_prec,
+                           tol=1e-9, refine=3)
     L.backward()
     ref = O.validation_loss_and_grads(w.X, w.Y, w.Xv, w.Yv, w.sigma, w.lam)
     assert float(L) == pytest.approx(ref["loss"], rel=1e-6)
