@@ -1847,6 +1847,61 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
     else if (tid < 2 * F64I_TJ) sC[buf][tid - F64I_TJ] = rn;
   };
 
+  // digit-diagonal sums E_s of the 16 x 16 pair block jb of the tile in buffer buf
+  auto i8_block = [&](int buf, int jb, i32x4 (&E)[7]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) E[q] = i32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      i32x4 cf[OZ_SLICES];
+#pragma unroll
+      for (int b = 0; b < OZ_SLICES; ++b)
+        cf[b] = *reinterpret_cast<const i32x4*>(&sS[buf][(16 * jb + li) * RS + b * KP +
+                                                         kc * 64 + 16 * lg]);
+#pragma unroll
+      for (int b = 0; b < OZ_SLICES; ++b)
+#pragma unroll
+        for (int a = 0; a < OZ_SLICES; ++a)
+          if (a + b <= 6)
+            E[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cf[b], xr[a][kc], E[a + b], 0, 0, 0);
+    }
+  };
+  // kernel values of block jb from its diagonal sums, accumulated against V
+  auto i8_epi = [&](int buf, int jb, const i32x4 (&E)[7]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jj = 16 * jb + 4 * lg + r;
+      const int H = E[0][r] * 256 + E[1][r];  // |H| < 2^28, |L| < 2^31 (int32, exact)
+      const int L = E[2][r] * 256 + E[3][r];
+      double g = fma((double)H, 65536.0, (double)L);
+      if (KC == 1)  // |256 E_4 + E_5| < 2^31 for one 64-wide chunk
+        g = fma(g, 65536.0, (double)(E[4][r] * 256 + E[5][r]));
+      else
+        g = fma(g, 65536.0, fma((double)E[4][r], 256.0, (double)E[5][r]));
+      g = fma(g, 256.0, (double)E[6][r]);  // = G_int / 2^32
+      // D >= 0 up to rounding (|D| ~ 1e-15 nu for duplicate points): no clamp needed, the
+      // exp below is exact in form for small negative arguments, and a NaN stays NaN
+      double p;
+      if (EPI == KV_POLY) {
+        p = pk.value((-0.5 * ai) * sC[buf][jj] * g);  // <x_i, x_j> (power-of-two scales)
+      } else {
+        const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
+        p = exp_neg_tab(D * c, sE);
+        if (EPI == KV_DSIGMA) p *= D * dscale;
+      }
+      if (VPV) {
+        const double* vr = &sV[buf][jj * LV];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) accv[cc] = fma(p, vr[cc], accv[cc]);
+      } else {
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+          acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li],
+                                                         acc[ct], 0, 0, 0);
+      }
+    }
+  };
+
   if (t_begin < t_end) {
     gload(t_begin);
     lstore(t_begin, 0);
@@ -1860,54 +1915,8 @@ __global__ __launch_bounds__(256, KC == 1 ? (VPV ? 2 : 3) : 1) void matmat_f64i8
 #pragma unroll 1
     for (int jb = 0; jb < F64I_TJ / 16; ++jb) {
       i32x4 E[7];
-#pragma unroll
-      for (int q = 0; q < 7; ++q) E[q] = i32x4{0, 0, 0, 0};
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        i32x4 cf[OZ_SLICES];
-#pragma unroll
-        for (int b = 0; b < OZ_SLICES; ++b)
-          cf[b] = *reinterpret_cast<const i32x4*>(&sS[buf][(16 * jb + li) * RS + b * KP +
-                                                           kc * 64 + 16 * lg]);
-#pragma unroll
-        for (int b = 0; b < OZ_SLICES; ++b)
-#pragma unroll
-          for (int a = 0; a < OZ_SLICES; ++a)
-            if (a + b <= 6)
-              E[a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(cf[b], xr[a][kc], E[a + b], 0, 0, 0);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int jj = 16 * jb + 4 * lg + r;
-        const int H = E[0][r] * 256 + E[1][r];  // |H| < 2^28, |L| < 2^31 (int32, exact)
-        const int L = E[2][r] * 256 + E[3][r];
-        double g = fma((double)H, 65536.0, (double)L);
-        if (KC == 1)  // |256 E_4 + E_5| < 2^31 for one 64-wide chunk
-          g = fma(g, 65536.0, (double)(E[4][r] * 256 + E[5][r]));
-        else
-          g = fma(g, 65536.0, fma((double)E[4][r], 256.0, (double)E[5][r]));
-        g = fma(g, 256.0, (double)E[6][r]);  // = G_int / 2^32
-        // D >= 0 up to rounding (|D| ~ 1e-15 nu for duplicate points): no clamp needed, the
-        // exp below is exact in form for small negative arguments, and a NaN stays NaN
-        double p;
-        if (EPI == KV_POLY) {
-          p = pk.value((-0.5 * ai) * sC[buf][jj] * g);  // <x_i, x_j> (power-of-two scales)
-        } else {
-          const double D = fma(ai * sC[buf][jj], g, nui + sN[buf][jj]);
-          p = exp_neg_tab(D * c, sE);
-          if (EPI == KV_DSIGMA) p *= D * dscale;
-        }
-        if (VPV) {
-          const double* vr = &sV[buf][jj * LV];
-#pragma unroll
-          for (int cc = 0; cc < 8; ++cc) accv[cc] = fma(p, vr[cc], accv[cc]);
-        } else {
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct)
-            acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(p, sV[buf][jj * LV + 16 * ct + li],
-                                                           acc[ct], 0, 0, 0);
-        }
-      }
+      i8_block(buf, jb, E);
+      i8_epi(buf, jb, E);
     }
     if (more) lstore(t + 1, buf ^ 1);
     __syncthreads();
