@@ -558,8 +558,9 @@ const char* krr_tune_digest(void);
  * until every column of every problem has converged, with one host read of the active count
  * per replay (iterations therefore run in groups of check_every: a converged column is left
  * unchanged by the rest of its group, and max_iter is reached rounded up to a multiple of
- * check_every). The product's work items run the register-resident small-d body where
- * Kp <= 128 and the LDS-streamed body above; the work-item granularity is chosen by timing
+ * check_every). The product's work items run the register-resident small-d body for
+ * d <= 128 (operands round_up(d, 32) wide, the exponent's norm terms added in FP32 in its
+ * epilogue) and the LDS-streamed body above; the work-item granularity is chosen by timing
  * candidates when the plan is created.
  * Products use KRR_PREC_F16X3. The plan owns device memory (allocated at creation, freed by
  * krr_batch_plan_destroy); krr_batch_solve allocates nothing.

@@ -2194,17 +2194,25 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
   PLAN_HIP(plan_alloc(P, &P->S.live, count));
   PLAN_HIP(fill_i32(P->S.live, count, 1, st));
   PLAN_HIP(plan_alloc(P, &P->S.tol, cm));
-  // per-problem prepared points (F16X3, augmented, scaled)
+  // per-problem prepared points (F16X3, scaled). Up to d = 128 the norm terms of the
+  // exponent are added in the epilogue of the register-resident body, so the operands hold
+  // only the coordinates (width round_up(d, 32), the same array on both sides); larger d
+  // keeps the two augmented norm columns for the large-d body.
   for (int i = 0; i < count; ++i) {
     const krr_batch_problem& b = probs[i];
     const int64_t rows_pad = round_up(b.n, ROW_PAD);
-    const int64_t Kp = kp_for(b.d);
-    _Float16 *ah, *al, *bh, *bl;
-    float* stats;
+    const bool ne = round_up(b.d, K_STEP) <= 128;
+    const int64_t Kp = ne ? round_up(b.d, K_STEP) : kp_for(b.d);
+    _Float16 *ah, *al, *bh = nullptr, *bl = nullptr;
+    float *stats, *nrm = nullptr;
     PLAN_HIP(plan_alloc(P, &ah, rows_pad * Kp));
     PLAN_HIP(plan_alloc(P, &al, rows_pad * Kp));
-    PLAN_HIP(plan_alloc(P, &bh, rows_pad * Kp));
-    PLAN_HIP(plan_alloc(P, &bl, rows_pad * Kp));
+    if (ne) {
+      PLAN_HIP(plan_alloc(P, &nrm, rows_pad));
+    } else {
+      PLAN_HIP(plan_alloc(P, &bh, rows_pad * Kp));
+      PLAN_HIP(plan_alloc(P, &bl, rows_pad * Kp));
+    }
     PLAN_HIP(plan_alloc(P, &stats, 64));
     const double c2 = 1.4426950408889634 / (2.0 * b.sigma * b.sigma);
     PLAN_HIP(fill_f32(stats, 4, 0.0f, st));
@@ -2212,11 +2220,15 @@ krr_status krr_batch_plan_create(const krr_batch_problem* probs, int32_t count,
     RowSpec rs;
     rs.c2 = c2;
     PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, rs, stats, 0, 0, ah, al,
-                                   stats + 2, st));
-    PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, rs, stats, 1, 0, bh, bl,
-                                   nullptr, st));
+                                   stats + 2, st, nrm));
+    if (!ne)
+      PLAN_HIP(prep_points<_Float16>(b.X, b.n, b.d, b.ldx, rows_pad, Kp, rs, stats, 1, 0, bh, bl,
+                                     nullptr, st));
     BatchInst& I = P->inst_h[i];
-    I.Ahi = ah; I.Alo = al; I.Bhi = bh; I.Blo = bl;
+    I.Ahi = ah; I.Alo = al;
+    I.Bhi = ne ? ah : bh;
+    I.Blo = ne ? al : bl;
+    I.nrm = nrm;
     I.Vth = P->Vth + P->meta_h[i].off;
     I.Vtl = P->Vtl + P->meta_h[i].off;
     I.vscale = P->vscale + 16 * i;

@@ -57,7 +57,7 @@ struct RowSpec {
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                        int64_t Kp, const RowSpec& rs, const float* stats, int side, int pshift,
-                       T* hi, T* lo, float* kpar, hipStream_t st);
+                       T* hi, T* lo, float* kpar, hipStream_t st, float* nrm = nullptr);
 hipError_t vec_split_t(float* V, int64_t n, int64_t m, int64_t ldv, int64_t rows_pad, int64_t mpad,
                        float* colmax, int pshift, bool packed, _Float16* hi, _Float16* lo,
                        float* vscale, hipStream_t st);
@@ -153,6 +153,8 @@ hipError_t matmat_finalize(const double* part, int64_t part_stride, int nsplit, 
 // batched kernel product (matmat.hip)
 struct BatchInst {          // one problem of a batch, prepared for the F16X3 product
   const _Float16 *Ahi, *Alo, *Bhi, *Blo;   // rows padded to ROW_PAD, Kp wide
+  const float* nrm;                        // Kp <= 128: the norm terms of the exponent
+                                           // (rows_pad), added in the epilogue
   const _Float16 *Vth, *Vtl;              // [16][ldvt] split V^T
   const float* vscale;                     // [16]
   const float* qinv2;                      // device scalar

@@ -329,23 +329,28 @@ __device__ inline void pack_combine(double (&acc64)[2][NCT][4]) {
     for (int r = 0; r < 4; ++r) acc64[ib][0][r] += __shfl_down(acc64[ib][0][r], 8, 16);
 }
 
-template <int KS, int NCT, bool PACK>
+template <int KS, int NCT, bool PACK, bool NE = false>
 struct PVSmem {
   static constexpr int KP = KS * 32;
   _Float16 Bh[2][MM_BN * KP];
   _Float16 Bl[2][MM_BN * KP];
   _Float16 Vh[2][NCT * 16 * MM_BN];
   _Float16 Vl[2][PACK ? 8 : NCT * 16 * MM_BN];  // unused with packed V^T
+  float Nb[2][NE ? MM_BN : 4];                  // norm terms of the column tile
 };
 
-template <int KS, int NCT, bool UNIT, int EPI, bool PACK>
+// NE (norms in the epilogue): the operands hold only the scaled coordinates (Kp >= d
+// instead of d + 2) and the exponent is completed in FP32 as S + (nA_i + nB_j), with the
+// row terms in registers and the column terms staged with their tile.
+template <int KS, int NCT, bool UNIT, int EPI, bool PACK, bool NE = false>
 __device__ __forceinline__ void f16pv_body(
-    PVSmem<KS, NCT, PACK>& sm, const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
-    const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
-    const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
-    const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
-    float qinv2, float dscale, int deg, double pmul, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split, int64_t rb, int64_t split) {
+    PVSmem<KS, NCT, PACK, NE>& sm, const _Float16* __restrict__ Ahi,
+    const _Float16* __restrict__ Alo, const _Float16* __restrict__ Bhi,
+    const _Float16* __restrict__ Blo, const _Float16* __restrict__ Vth,
+    const _Float16* __restrict__ Vtl, const float* __restrict__ vscale, int64_t ldvt, int64_t n1,
+    int64_t n2, int64_t m, float qinv2, float dscale, int deg, double pmul,
+    double* __restrict__ part, int64_t ldp, int64_t part_stride, int tiles_per_split, int64_t rb,
+    int64_t split, const float* __restrict__ nA = nullptr, const float* __restrict__ nB = nullptr) {
   constexpr int KP = KS * 32;
   constexpr int CPR = KP / 8;                 // 16-byte chunks per B row
   constexpr int SWZ = (KS == 1 || KS == 3) ? 3 : 7;
@@ -371,6 +376,12 @@ __device__ __forceinline__ void f16pv_body(
       ah[ib][ks] = *reinterpret_cast<const half8*>(Ahi + off);
       al[ib][ks] = *reinterpret_cast<const half8*>(Alo + off);
     }
+
+  float na[2] = {0.0f, 0.0f};  // NE: row terms (rows are padded, so always in range)
+  if constexpr (NE) {
+    na[0] = nA[i0 + li];
+    na[1] = nA[i0 + 16 + li];
+  }
 
   f32x4 acc[2][NCT];
   double acc64[2][NCT][4];
@@ -414,6 +425,10 @@ __device__ __forceinline__ void f16pv_body(
   // struct is left in scratch memory by the compiler)
   u32x4 rbh0 = {}, rbh1 = {}, rbh2 = {}, rbh3 = {}, rbl0 = {}, rbl1 = {}, rbl2 = {}, rbl3 = {};
   u32x4 rvh = {}, rvl = {};
+  // NE: the tile's 64 column terms, one 16-byte piece for each of threads 0..15
+  u32x4 rnb = {};
+  const bool nload = NE && tid < MM_BN / 4;
+  int64_t nbo = t_begin * MM_BN + 4 * (tid & (MM_BN / 4 - 1));
 #define KRR_PV_LD(u)                                                       \
   if (u < BCPT) {                                                          \
     rbh##u = *reinterpret_cast<const u32x4*>(gbh + gbo[u]);                \
@@ -465,6 +480,12 @@ __device__ __forceinline__ void f16pv_body(
       vh[ct] = *reinterpret_cast<const half8*>(&sm.Vh[buf][u]);
       if (!PACK) vl[ct] = *reinterpret_cast<const half8*>(&sm.Vl[buf][u]);
     }
+    f32x4 nb[2] = {f32x4{0.0f, 0.0f, 0.0f, 0.0f}, f32x4{0.0f, 0.0f, 0.0f, 0.0f}};
+    if constexpr (NE) {
+#pragma unroll
+      for (int jb = 0; jb < 2; ++jb)
+        nb[jb] = *reinterpret_cast<const f32x4*>(&sm.Nb[buf][32 * jp + 16 * jb + 4 * lg]);
+    }
 #pragma unroll
     for (int ib = 0; ib < 2; ++ib) {
       half8 ph, pl;
@@ -473,6 +494,10 @@ __device__ __forceinline__ void f16pv_body(
 #pragma unroll
         for (int r = 0; r < 4; r += 2) {
           float l2a = S[jb][ib][r], l2b = S[jb][ib][r + 1];
+          if constexpr (NE) {
+            l2a += na[ib] + nb[jb][r];
+            l2b += na[ib] + nb[jb][r + 1];
+          }
           if (!UNIT) { l2a *= qinv2; l2b *= qinv2; }
           const float pa = epi_value<EPI>(l2a, dscale, deg);
           const float pb = epi_value<EPI>(l2b, dscale, deg);
@@ -505,7 +530,10 @@ __device__ __forceinline__ void f16pv_body(
     }
     gvh += MM_BN;
     gvl += MM_BN;
+    if (nload) rnb = *reinterpret_cast<const u32x4*>(nB + nbo);
+    nbo += MM_BN;
     KRR_PV_ST(0, 0) KRR_PV_ST(1, 0) KRR_PV_ST(2, 0) KRR_PV_ST(3, 0)
+    if (nload) *reinterpret_cast<u32x4*>(&sm.Nb[0][4 * tid]) = rnb;
     if (vload) {
       *reinterpret_cast<u32x2*>(&sm.Vh[0][svo0]) = u32x2{rvh.x, rvh.y};
       *reinterpret_cast<u32x2*>(&sm.Vh[0][svo1]) = u32x2{rvh.z, rvh.w};
@@ -535,6 +563,8 @@ __device__ __forceinline__ void f16pv_body(
     }
     gvh += MM_BN;
     gvl += MM_BN;
+    if (nload) rnb = *reinterpret_cast<const u32x4*>(nB + nbo);
+    nbo += MM_BN;
     }
     f32x4 S0[2][2];
     // raised wave priority while issuing the distance MFMAs lets the waves of a SIMD
@@ -559,6 +589,7 @@ __device__ __forceinline__ void f16pv_body(
     }
     if (more) {
     KRR_PV_ST(0, buf ^ 1) KRR_PV_ST(1, buf ^ 1) KRR_PV_ST(2, buf ^ 1) KRR_PV_ST(3, buf ^ 1)
+    if (nload) *reinterpret_cast<u32x4*>(&sm.Nb[buf ^ 1][4 * tid]) = rnb;
     if (vload) {
       *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo0]) = u32x2{rvh.x, rvh.y};
       *reinterpret_cast<u32x2*>(&sm.Vh[buf ^ 1][svo1]) = u32x2{rvh.z, rvh.w};
@@ -1327,8 +1358,8 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
 // whose columns have all converged (live[inst] == 0) are skipped.
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int BATCH_SMEM_BYTES =
-    cmax(cmax(2 * bigd_smem_halves<1, 4>(), (int)sizeof(PVSmem<4, 1, true>)),
-         (int)sizeof(PVSmem<4, 1, false>));
+    cmax(cmax(2 * bigd_smem_halves<1, 4>(), (int)sizeof(PVSmem<4, 1, true, true>)),
+         (int)sizeof(PVSmem<4, 1, false, true>));
 __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* __restrict__ items,
                                                               const int* __restrict__ list,
                                                               const int* __restrict__ nlist,
@@ -1348,7 +1379,12 @@ __global__ __launch_bounds__(256, 2) void matmat_batch_kernel(const BatchItem* _
     const BatchInst I = inst[wi.inst];
     const float qinv2 = *I.qinv2;
     if (I.Kp <= 128) {
-#define KRR_BATCH_SMALL(KS, U, PK)                                                               f16pv_body<KS, 1, U, KV_GAUSS, PK>(*reinterpret_cast<PVSmem<KS, 1, PK>*>(smem), I.Ahi, I.Alo,                                       I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale, I.ldvt, I.n, I.n,                                          I.m, qinv2, 0.0f, 1, 1.0, I.part, I.ldp, I.part_stride,                                          wi.tiles_per_split, wi.rb, wi.split)
+#define KRR_BATCH_SMALL(KS, U, PK)                                                          \
+  f16pv_body<KS, 1, U, KV_GAUSS, PK, true>(*reinterpret_cast<PVSmem<KS, 1, PK, true>*>(smem), \
+                                           I.Ahi, I.Alo, I.Bhi, I.Blo, I.Vth, I.Vtl, I.vscale,  \
+                                           I.ldvt, I.n, I.n, I.m, qinv2, 0.0f, 1, 1.0, I.part,  \
+                                           I.ldp, I.part_stride, wi.tiles_per_split, wi.rb,     \
+                                           wi.split, I.nrm, I.nrm)
 #define KRR_BATCH_KS(U, PK)                                      switch (I.Kp) {                                                  case 32: KRR_BATCH_SMALL(1, U, PK); break;                     case 64: KRR_BATCH_SMALL(2, U, PK); break;                     case 96: KRR_BATCH_SMALL(3, U, PK); break;                     default: KRR_BATCH_SMALL(4, U, PK); break;                   }
       if (packed) {
         if (qinv2 == 1.0f) { KRR_BATCH_KS(true, true) }

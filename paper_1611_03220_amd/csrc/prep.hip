@@ -99,6 +99,9 @@ hipError_t point_stats(const float* X, int64_t n, int64_t d, int64_t ldx, float*
 // even power of two at or above t_max = gamma max ||x||^2 + c (the Cauchy-Schwarz bound of
 // |gamma x^T z + c|): the scaled value lies in [-1, 1] and its deg-th power cannot overflow;
 // the products are multiplied back by T^deg.
+// With nrm (Gaussian rows only), the two norm columns are left out (Kp >= d) and
+// nrm[row] = -q^2 c nu_row is written instead, the same for both sides; the product then
+// adds nrm_i + nrm_j to the accumulated q^2 2c <x_i, x_j> in FP32 (rows n..rows_pad-1: 0).
 // Rows n..rows_pad-1 and the remaining columns up to Kp are zero. Thread 0 of block 0 of
 // side 0 also stores the kernel parameters kpar[0] = 1/q^2, kpar[1] = log2 T^deg and
 // kpar[2] = deg (identical for both sides: they depend only on the shared stats).
@@ -106,7 +109,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void prep_points_kernel(
     const float* __restrict__ X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad, int64_t Kp,
     RowSpec rs, const float* __restrict__ stats, int side, int pshift, T* __restrict__ hi,
-    T* __restrict__ lo, float* __restrict__ kpar) {
+    T* __restrict__ lo, float* __restrict__ kpar, float* __restrict__ nrm) {
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   double t, cterm = 0.0;
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
   T* l = lo + row * Kp;
   if (row >= n) {
     for (int64_t k = lane; k < Kp; k += 64) { h[k] = (T)0.0f; l[k] = (T)0.0f; }
+    if (nrm && lane == 0) nrm[row] = 0.0f;
     return;
   }
   const float* x = X + row * ldx;
@@ -146,9 +150,11 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
   }
   const double qt = (double)q * t;
   const double qnu = -(double)q * rs.c2 * nu;
+  if (nrm && lane == 0) nrm[row] = (float)((double)q * qnu);
   for (int64_t k = lane; k < Kp; k += 64) {
     double v;
     if (k < d) v = qt * (double)x[k];
+    else if (nrm) v = 0.0;
     else if (rs.poly) v = k == d ? (double)q * cterm : 0.0;
     else if (k == d) v = side == 0 ? qnu : (double)q;
     else if (k == d + 1) v = side == 0 ? (double)q : qnu;
@@ -164,18 +170,20 @@ __global__ __launch_bounds__(256) void prep_points_kernel(
 template <typename T>
 hipError_t prep_points(const float* X, int64_t n, int64_t d, int64_t ldx, int64_t rows_pad,
                        int64_t Kp, const RowSpec& rs, const float* stats, int side, int pshift,
-                       T* hi, T* lo, float* kpar, hipStream_t st) {
+                       T* hi, T* lo, float* kpar, hipStream_t st, float* nrm) {
+  if (nrm && (rs.poly || pshift != 0 || Kp < d)) return hipErrorInvalidValue;
   prep_points_kernel<T><<<ceil_div(rows_pad, 4), 256, 0, st>>>(X, n, d, ldx, rows_pad, Kp, rs,
-                                                               stats, side, pshift, hi, lo, kpar);
+                                                               stats, side, pshift, hi, lo, kpar,
+                                                               nrm);
   KRR_LAUNCH_CHECK();
   return hipSuccess;
 }
 template hipError_t prep_points<_Float16>(const float*, int64_t, int64_t, int64_t, int64_t,
                                           int64_t, const RowSpec&, const float*, int, int,
-                                          _Float16*, _Float16*, float*, hipStream_t);
+                                          _Float16*, _Float16*, float*, hipStream_t, float*);
 template hipError_t prep_points<__bf16>(const float*, int64_t, int64_t, int64_t, int64_t, int64_t,
                                         const RowSpec&, const float*, int, int, __bf16*, __bf16*,
-                                        float*, hipStream_t);
+                                        float*, hipStream_t, float*);
 
 // ------------------------------------------- right-hand sides for the MFMA accumulation
 // colmax[c] = max_i |V[i, c]| (atomic max on the float bit pattern; colmax starts at 0).

@@ -67,11 +67,14 @@ def test_batch_reduced_uneven_instances(dev):
 
 def test_batch_edge_shapes(dev):
     """Degenerate members: n = 2 without a preconditioner, a ragged n = 70 with s = 8, the
-    widest m = 16, d = 1 and d = 200 (several 32-wide feature chunks), one column only."""
+    widest m = 16, d = 1 and d = 200 (several 32-wide feature chunks), one column only;
+    widths at the 32-column steps (d = 31, 32, 127, 128: the norm terms added in the
+    epilogue keep them at round_up(d, 32)) next to d = 129 (large-d body, augmented)."""
     rng = np.random.default_rng(7)
     ws = []
     for n, d, m, s in [(2, 3, 1, 0), (70, 5, 2, 8), (1000, 16, 16, 125), (513, 1, 1, 64),
-                       (600, 200, 3, 75), (129, 64, 4, 0)]:
+                       (600, 200, 3, 75), (129, 64, 4, 0), (300, 31, 2, 40), (333, 32, 1, 0),
+                       (257, 127, 3, 32), (400, 128, 2, 50), (300, 129, 2, 0)]:
         X = rng.standard_normal((n, d)).astype(np.float32)
         Y = rng.standard_normal((n, m))
         sigma = math.sqrt(d)
