@@ -156,6 +156,9 @@ krr_status krr_precond_apply(const float* Ut, int64_t n, int64_t s, int64_t ldu,
  *   prec  : a krr_prec. Squared distances are not clamped at zero: where rounding leaves one
  *           slightly negative (coincident points), k comes out slightly above 1, within the
  *           product's error bound; a NaN coordinate propagates to every output it meets.
+ *           With KRR_PREC_F16X3 and d + 2 past a multiple of 32 (d = 31, 32, 63, 64, 95, 96)
+ *           the squared norms are added to the exponent in FP32 after the split inner
+ *           products instead of through two extra operand columns.
  * When X1 and X2 are the same array (same pointer, n1 == n2, ldx1 == ldx2) the product is
  * K(X, X) V and K is symmetric: with KRR_PREC_F16X3, d > 126 and passes of up to 16
  * columns, each off-diagonal pair of 128-row blocks is formed once and serves both

@@ -89,6 +89,12 @@ struct MatmatCtx {
   int64_t mpad = 0;
   int64_t n1 = 0, n2 = 0, d = 0, m = 0;
   int64_t rp1 = 0, rp2 = 0, Kp = 0, dp = 0;
+  // Gaussian F16X3 products whose d + 2 crosses a 32-column step: the norm terms of the
+  // exponent go to the epilogue (nrmA/nrmB, -q^2 c nu per row) and the operands are Kp_run =
+  // round_up(d, 32) wide; Kp stays the augmented width (workspace and tuning key)
+  float *nrmA = nullptr, *nrmB = nullptr;
+  bool ne = false;
+  int64_t Kp_run = 0;
   int nsplit = 1;
   int nsplit_max = 1;       // splits the partial buffer holds (tuned choices stay within it)
   int pass_w = 0;           // right-hand-side pass width (0: pv_pass_width)
@@ -170,6 +176,10 @@ void layout_matmat(Bump& b, MatmatCtx& c, int64_t n1, int64_t n2, int64_t d, int
       c.fx = b.take<unsigned long long>(c.rp1 * 32);
       c.fxflag = b.take<unsigned>(c.rp1);
     }
+    if (c.pv && c.Kp <= 128 && round_up(d, K_STEP) < c.Kp) {
+      c.nrmA = b.take<float>(c.rp1);
+      c.nrmB = b.take<float>(c.rp2);
+    }
     c.Ahi = b.take<uint16_t>(c.rp1 * c.Kp);
     c.Alo = b.take<uint16_t>(c.rp1 * c.Kp);
     c.Bhi = b.take<uint16_t>(c.rp2 * c.Kp);
@@ -220,12 +230,16 @@ hipError_t prepare_points(MatmatCtx& c, const float* X1, int64_t ldx1, const flo
   const float* Xb = X2 ? X2 : X1;
   const int64_t ldb = X2 ? ldx2 : ldx1;
   const int ps = c.pv ? PSHIFT : 0;
+  c.ne = c.nrmA && !c.poly && ps == 0;
+  c.Kp_run = c.ne ? round_up(c.d, K_STEP) : c.Kp;
   if (c.prec == KRR_PREC_F16X3) {
-    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, rs, c.stats, 0, ps,
-                                   (_Float16*)c.Ahi, (_Float16*)c.Alo, c.stats + 2, st)))
+    if ((e = prep_points<_Float16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp_run, rs, c.stats, 0, ps,
+                                   (_Float16*)c.Ahi, (_Float16*)c.Alo, c.stats + 2, st,
+                                   c.ne ? c.nrmA : nullptr)))
       return e;
-    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp, rs, c.stats, 1, ps,
-                                 (_Float16*)c.Bhi, (_Float16*)c.Blo, nullptr, st);
+    return prep_points<_Float16>(Xb, c.n2, c.d, ldb, c.rp2, c.Kp_run, rs, c.stats, 1, ps,
+                                 (_Float16*)c.Bhi, (_Float16*)c.Blo, nullptr, st,
+                                 c.ne ? c.nrmB : nullptr);
   }
   if (c.poly) return hipErrorInvalidValue;  // BF16X3 products are Gaussian only
   if ((e = prep_points<__bf16>(X1, c.n1, c.d, ldx1, c.rp1, c.Kp, rs, c.stats, 0, 0,
@@ -258,8 +272,12 @@ hipError_t run_matmat(const MatmatCtx& c, float* Vf, const double* V64, int64_t 
   }
   const float dscale = (float)(1.0 / (c.c2 * sig3));  // dk/dsigma = k * (-log2 k) / (c2 sigma^3)
   if (c.prec == KRR_PREC_F16X3) {
-    MixedPoints<_Float16> A{(const _Float16*)c.Ahi, (const _Float16*)c.Alo, c.n1, c.Kp, c.stats + 2};
-    MixedPoints<_Float16> B{(const _Float16*)c.Bhi, (const _Float16*)c.Blo, c.n2, c.Kp, c.stats + 2};
+    const bool ne = c.ne && c.Kp_run > 0;
+    const int64_t kpr = ne ? c.Kp_run : c.Kp;
+    MixedPoints<_Float16> A{(const _Float16*)c.Ahi, (const _Float16*)c.Alo, c.n1, kpr, c.stats + 2,
+                            ne ? c.nrmA : nullptr};
+    MixedPoints<_Float16> B{(const _Float16*)c.Bhi, (const _Float16*)c.Blo, c.n2, kpr, c.stats + 2,
+                            ne ? c.nrmB : nullptr};
     if (c.pv) {
       const int64_t W = c.Kp > 128 && c.pass_w ? c.pass_w : pv_pass_width(c.Kp);
       for (int64_t c0 = 0; c0 < c.m; c0 += W) {

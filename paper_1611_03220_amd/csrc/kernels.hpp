@@ -13,6 +13,8 @@ template <typename T> struct MixedPoints {
   int64_t Kp;     // padded augmented width (multiple of 32)
   const float* qinv2;  // device kernel parameters: 1/q^2, then (polynomial rows) log2 of the
                        // output multiplier and the degree
+  const float* nrm = nullptr;  // Gaussian rows without the two norm columns: -q^2 c nu per
+                               // row, added to the exponent in the product's epilogue
 };
 
 struct F64Points {

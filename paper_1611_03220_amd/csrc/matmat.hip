@@ -622,27 +622,30 @@ __device__ __forceinline__ void f16pv_body(
   }
 }
 
-template <int KS, int NCT, int EPI, bool PACK>
-__global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? 4 : 2) void matmat_f16pv_kernel(
+template <int KS, int NCT, int EPI, bool PACK, bool NE = false>
+__global__ __launch_bounds__(256, (NCT == 1 && KS <= 2) ? (NE ? 3 : 4) : 2) void matmat_f16pv_kernel(
     const _Float16* __restrict__ Ahi, const _Float16* __restrict__ Alo,
     const _Float16* __restrict__ Bhi, const _Float16* __restrict__ Blo,
     const _Float16* __restrict__ Vth, const _Float16* __restrict__ Vtl,
     const float* __restrict__ vscale, int64_t ldvt, int64_t n1, int64_t n2, int64_t m,
     const float* __restrict__ qinv2_ptr, float dscale, double* __restrict__ part, int64_t ldp,
-    int64_t part_stride, int tiles_per_split) {
-  __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT, PACK> sm;
+    int64_t part_stride, int tiles_per_split, const float* __restrict__ nA,
+    const float* __restrict__ nB) {
+  __shared__ __attribute__((aligned(16))) PVSmem<KS, NCT, PACK, NE> sm;
   const float qinv2 = qinv2_ptr[0];
   int deg;
   double pmul;
   epi_params<EPI>(qinv2_ptr, deg, pmul);
   if (qinv2 == 1.0f)
-    f16pv_body<KS, NCT, true, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                     qinv2, dscale, deg, pmul, part, ldp, part_stride,
-                                     tiles_per_split, blockIdx.x, blockIdx.y);
+    f16pv_body<KS, NCT, true, EPI, PACK, NE>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1,
+                                             n2, m, qinv2, dscale, deg, pmul, part, ldp,
+                                             part_stride, tiles_per_split, blockIdx.x,
+                                             blockIdx.y, nA, nB);
   else
-    f16pv_body<KS, NCT, false, EPI, PACK>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1, n2, m,
-                                      qinv2, dscale, deg, pmul, part, ldp, part_stride,
-                                      tiles_per_split, blockIdx.x, blockIdx.y);
+    f16pv_body<KS, NCT, false, EPI, PACK, NE>(sm, Ahi, Alo, Bhi, Blo, Vth, Vtl, vscale, ldvt, n1,
+                                              n2, m, qinv2, dscale, deg, pmul, part, ldp,
+                                              part_stride, tiles_per_split, blockIdx.x,
+                                              blockIdx.y, nA, nB);
 }
 
 // Large-d variant: the row operands no longer fit in registers, so both operands stream
@@ -1266,6 +1269,9 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
   if (A.Kp > 128 ? !(V.mpad <= 32 || V.mpad == 64 || V.mpad == 160) : V.mpad > 32)
     return hipErrorInvalidValue;
   if (V.packed && (m > 8 || V.mpad != 16)) return hipErrorInvalidValue;
+  // norm terms in the epilogue: Gaussian products of the register-resident kernel only
+  if ((A.nrm != nullptr) != (B.nrm != nullptr) || (A.nrm && (A.Kp > 128 || epi == KV_POLY)))
+    return hipErrorInvalidValue;
   if (part_stride < round_up(A.n, MM2_BM) * ldp) return hipErrorInvalidValue;
   const int64_t ntiles = ceil_div(B.n, MM_BN);
   const int tps = (int)ceil_div(ntiles, nsplit);
@@ -1329,15 +1335,18 @@ hipError_t matmat_f16pv(const MixedPoints<_Float16>& A, const MixedPoints<_Float
     KRR_LAUNCH_CHECK();
     return symm ? sym_end(so, inv_fxs, A.n, m, V, A.qinv2, epi, part, ldp, st) : hipSuccess;
   }
-#define KRR_PV1(KS_, NCT_, E_, PK_)                                                           \
-  matmat_f16pv_kernel<KS_, NCT_, E_, PK_><<<grid, 256, 0, st>>>(                              \
+#define KRR_PV1(KS_, NCT_, E_, PK_, NE_)                                                      \
+  matmat_f16pv_kernel<KS_, NCT_, E_, PK_, NE_><<<grid, 256, 0, st>>>(                         \
       A.hi, A.lo, B.hi, B.lo, V.hi, V.lo, V.vscale, V.rows_pad, A.n, B.n, m, A.qinv2, dscale,  \
-      part, ldp, part_stride, tps)
+      part, ldp, part_stride, tps, A.nrm, B.nrm)
 #define KRR_PV(KS_, NCT_, PK_)                                                                \
   if (A.Kp == KS_ * 32 && nct == NCT_ && V.packed == PK_) {                                   \
-    if (epi == KV_DSIGMA) KRR_PV1(KS_, NCT_, KV_DSIGMA, PK_);                              \
-    else if (epi == KV_POLY) KRR_PV1(KS_, NCT_, KV_POLY, PK_);                             \
-    else KRR_PV1(KS_, NCT_, KV_GAUSS, PK_);                                                  \
+    if (A.nrm) {                                                                              \
+      if (epi == KV_DSIGMA) KRR_PV1(KS_, NCT_, KV_DSIGMA, PK_, true);                        \
+      else KRR_PV1(KS_, NCT_, KV_GAUSS, PK_, true);                                          \
+    } else if (epi == KV_DSIGMA) KRR_PV1(KS_, NCT_, KV_DSIGMA, PK_, false);                  \
+    else if (epi == KV_POLY) KRR_PV1(KS_, NCT_, KV_POLY, PK_, false);                        \
+    else KRR_PV1(KS_, NCT_, KV_GAUSS, PK_, false);                                           \
     KRR_LAUNCH_CHECK();                                                                       \
     return hipSuccess;                                                                        \
   }

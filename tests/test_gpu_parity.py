@@ -64,6 +64,13 @@ MATMAT_CASES = [
     (100, 2000, 126, 3, False),  # Kp = 128
     (70, 90, 254, 1, False),     # largest d of the register-resident mixed kernel
     (129, 65, 1, 5, False),
+    # d + 2 past a 32-column step: Gaussian F16X3 rows without the norm columns (the norm
+    # terms added in the epilogue), one, two and three 32-column steps, packed, split and
+    # 32-column right-hand-side passes
+    (300, 411, 64, 7, False),
+    (257, 257, 32, 9, True),
+    (190, 333, 96, 3, False),
+    (150, 260, 63, 20, False),
 ]
 
 
@@ -87,17 +94,18 @@ def test_matmat_parity(dev, prec, case):
 
 
 @pytest.mark.parametrize("prec", ["f16x3", "fp64"])
-def test_matmat_deriv_parity(dev, prec):
+@pytest.mark.parametrize("d", [20, 64])
+def test_matmat_deriv_parity(dev, prec, d):
     rng = np.random.default_rng(5)
-    X1 = rng.standard_normal((200, 20)).astype(np.float32)
-    X2 = rng.standard_normal((333, 20)).astype(np.float32)
+    X1 = rng.standard_normal((200, d)).astype(np.float32)
+    X2 = rng.standard_normal((333, d)).astype(np.float32)
     V = rng.standard_normal((333, 4))
-    sigma = 3.1
+    sigma = 3.1 * math.sqrt(d / 20)
     got = krr.kernel_matmat(_t(X1, dev), _t(X2, dev), sigma, _t(V, dev), deriv=True, prec=prec).cpu().numpy()
     ref = O.kernel_matmat(X1, X2, sigma, V, deriv=True)
     # dk/dsigma = k * D / sigma^3: the relative error of D adds to that of k; D is formed as
     # -log2(k)/c, so its absolute error is that of S (bounded as in _tau) divided by c
-    tau = _tau(prec, X1, X2, sigma, 20)
+    tau = _tau(prec, X1, X2, sigma, d)
     c = math.log2(math.e) / (2 * sigma ** 2)
     D = O.sq_dists(X1, X2)
     Kd = np.exp(-D / (2 * sigma ** 2))
